@@ -1,0 +1,185 @@
+"""ORACLE -- test infrastructure, not part of the product.
+
+ctypes front end of the plain CPU reference in wh_oracle.cpp (and the
+brute-force Gragg-Bulirsch-Stoer pin in gbs.cpp).  Only the test suite, the
+smoke check and the CPU-baseline leg of the benchmark may import this package.
+
+Arrays follow the input generator's layout: n_planets int32 [S], m0 [S],
+m [S, 8], Q [S, 8, 3], V [S, 8, 3], dt [S].  Long double is the parity
+precision; double is the timing precision.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+LD = np.longdouble
+_PLD = np.ctypeslib.ndpointer(dtype=LD, flags="C_CONTIGUOUS")
+_PD = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_PI = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_PL = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+
+
+def lib():
+    """Load the oracle library, building it first if it is not there."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        i, l, ld, d = C.c_int, C.c_long, C.c_longdouble, C.c_double
+        sig = {
+            "or_max_threads": ([], i),
+            "or_set_series_recur": ([i], None),
+            "or_set_guess": ([i], None),
+            "or_kepler_ld": ([i, _PLD, _PLD, _PLD, _PLD, _PLD], None),
+            "or_kepler_fixed_ld": ([i, _PLD, _PLD, _PLD, _PLD, i, i, i, i], None),
+            "or_kepler_fixed_d": ([i, _PD, _PD, _PD, _PD, i, i, i, i], None),
+            "or_substep_ld": ([i, i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, ld], None),
+            "or_integrate_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, l, i, ld, i], None),
+            "or_integrate_d": ([i, i, _PI, _PD, _PD, _PD, _PD, _PD, l, i, d, i], None),
+            "or_energy_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld, _PLD], None),
+            "or_angmom_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD], None),
+            "or_tangent_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, l, i, ld, _PLD, _PLD, _PLD, _PLD, i], None),
+            "or_count_ops": ([i, i, i, i, i, i, _PL], None),
+            "or_gbs_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld, l], ld),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _ld(a):
+    return np.ascontiguousarray(a, dtype=LD)
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+SCHEMES = {"dkd": 0, "kdk": 1}
+
+
+def kepler(Q, V, mu, tau, return_X=False):
+    """Exact Kepler drift of n particles: Q, V [n, 3]; mu, tau [n]."""
+    Q = _ld(Q).copy(); V = _ld(V).copy()
+    n = Q.shape[0]
+    X = np.zeros(n, dtype=LD)
+    lib().or_kepler_ld(n, Q, V, _ld(np.broadcast_to(mu, (n,))), _ld(np.broadcast_to(tau, (n,))), X)
+    return (Q, V, X) if return_X else (Q, V)
+
+
+def kepler_fixed(Q, V, mu, tau, n_halley=2, n_newton=2, terms_halley=4, terms_newton=8, precision="ld", recur=0, guess=0):
+    """Fixed-iteration Kepler solve (App. A sweep mode).
+
+    recur selects the series arrangement: `terms` terms are summed for
+    c_{2+2r}, c_{3+2r} and r downward recurrences give c2, c3.
+    """
+    n = np.asarray(Q).shape[0]
+    lib().or_set_series_recur(int(recur))
+    lib().or_set_guess(int(guess))
+    if precision == "ld":
+        Q = _ld(Q).copy(); V = _ld(V).copy()
+        lib().or_kepler_fixed_ld(n, Q, V, _ld(np.broadcast_to(mu, (n,))), _ld(np.broadcast_to(tau, (n,))),
+                                 n_halley, n_newton, terms_halley, terms_newton)
+    else:
+        Q = _d(Q).copy(); V = _d(V).copy()
+        lib().or_kepler_fixed_d(n, Q, V, _d(np.broadcast_to(mu, (n,))), _d(np.broadcast_to(tau, (n,))),
+                                n_halley, n_newton, terms_halley, terms_newton)
+    return Q, V
+
+
+def _unpack(sysm):
+    S = sysm.S
+    return S, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), _ld(sysm.Q).copy(), _ld(sysm.V).copy()
+
+
+SUBSTEPS = {"kepler": 0, "jump": 1, "interaction": 2, "gr": 3}
+
+
+def substep(which, sysm, tau, gr_c=0.0, Q=None, V=None):
+    """Apply one sub-flow to every system; returns (Q, V) in long double."""
+    S, np_, m0, m, Q0, V0 = _unpack(sysm)
+    if Q is not None:
+        Q0 = _ld(Q).copy()
+    if V is not None:
+        V0 = _ld(V).copy()
+    lib().or_substep_ld(SUBSTEPS[which], S, 8, np_, m0, m, Q0, V0, _ld(np.broadcast_to(tau, (S,))), LD(gr_c))
+    return Q0, V0
+
+
+def integrate(sysm, n_steps, scheme="dkd", gr_c=0.0, precision="ld", nthreads=0, Q=None, V=None, dt=None):
+    """n_steps plain-composition steps; returns final (Q, V)."""
+    S = sysm.S
+    dtv = sysm.dt if dt is None else dt
+    if precision == "ld":
+        Qa = _ld(sysm.Q if Q is None else Q).copy(); Va = _ld(sysm.V if V is None else V).copy()
+        lib().or_integrate_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), Qa, Va, _ld(dtv),
+                              int(n_steps), SCHEMES[scheme], LD(gr_c), nthreads)
+    else:
+        Qa = _d(sysm.Q if Q is None else Q).copy(); Va = _d(sysm.V if V is None else V).copy()
+        lib().or_integrate_d(S, 8, _i(sysm.n_planets), _d(sysm.m0), _d(sysm.m), Qa, Va, _d(dtv),
+                             int(n_steps), SCHEMES[scheme], float(gr_c), nthreads)
+    return Qa, Va
+
+
+def energy(sysm, Q=None, V=None, gr_c=0.0, m=None, m0=None):
+    S = sysm.S
+    E = np.zeros(S, dtype=LD)
+    lib().or_energy_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m0 if m0 is None else m0), _ld(sysm.m if m is None else m),
+                       _ld(sysm.Q if Q is None else Q), _ld(sysm.V if V is None else V), LD(gr_c), E)
+    return E
+
+
+def angmom(sysm, Q=None, V=None):
+    S = sysm.S
+    L = np.zeros((S, 3), dtype=LD)
+    lib().or_angmom_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m), _ld(sysm.Q if Q is None else Q),
+                       _ld(sysm.V if V is None else V), L)
+    return L
+
+
+def tangent(sysm, n_steps, dQ, dV, dm, dm0, scheme="dkd", gr_c=0.0, nthreads=0):
+    """Forward tangent map along one direction per system.
+
+    Returns (Q_T, V_T, dQ_T, dV_T) with dX_T = (d x_T / d x_0) . direction.
+    """
+    S = sysm.S
+    Q = _ld(sysm.Q).copy(); V = _ld(sysm.V).copy()
+    dQ = _ld(dQ).copy(); dV = _ld(dV).copy()
+    lib().or_tangent_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), Q, V, _ld(sysm.dt), int(n_steps),
+                        SCHEMES[scheme], LD(gr_c), _ld(dm0), _ld(dm), dQ, dV, nthreads)
+    return Q, V, dQ, dV
+
+
+def count_ops(n_planets=8, gr=False, n_halley=2, n_newton=2, terms_halley=4, terms_newton=8):
+    """Operation count of one step of the method: dict add/mul/div/sqrt/flops."""
+    c = np.zeros(4, dtype=np.int64)
+    lib().or_count_ops(n_planets, int(gr), n_halley, n_newton, terms_halley, terms_newton, c)
+    d = dict(add=int(c[0]), mul=int(c[1]), div=int(c[2]), sqrt=int(c[3]))
+    d["flops"] = d["add"] + d["mul"] + d["div"] + d["sqrt"]
+    return d
+
+
+def gbs(sysm, t_total, n_macro, Q=None, V=None):
+    """Brute-force N-body solution (Gragg-Bulirsch-Stoer); returns (Q, V, err)."""
+    S = sysm.S
+    Qa = _ld(sysm.Q if Q is None else Q).copy(); Va = _ld(sysm.V if V is None else V).copy()
+    err = lib().or_gbs_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), Qa, Va, LD(t_total), int(n_macro))
+    return Qa, Va, err
+
+
+def max_threads() -> int:
+    return int(lib().or_max_threads())
