@@ -1,0 +1,176 @@
+"""Benchmark: Wisdom-Holman ensemble throughput on one MI355X.
+
+Default workload: 4096 independent systems of 8 planets (star mass 1,
+planet masses log-uniform in [1e-7, 1e-3], semi-major axes log-uniform in
+[0.4, 30] with >= 10 mutual Hill radii spacing, e and i uniform in
+[0, 0.05], dt = P_inner/20, drift-kick-drift, no GR), seeded and synthetic.
+A "step" is one Wisdom-Holman timestep of every system of the batch (the
+Kepler drift, interaction kick and jump of every planet); the metric is
+system-steps per second.  The state is resident in device memory before
+the timed region starts.
+
+Printed: one JSON line with the metric, a roofline object for the step
+kernel (algorithmic FP64 flops per launch / average launch time, against
+the 78.6 TFLOP/s FP64 vector peak) and a CPU baseline (the oracle timed on
+the host's cores on a bounded sample of the same workload).
+
+Other workloads: --workload uneven2to8 (16384 systems, 2..8 planets,
+per-system dt) also times the per-size reference path; --workload large8gr
+(65536 systems with GR).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+
+WORKLOAD_TEXT = {
+    "uniform8": "4096 systems x 8 planets, dt = P_inner/20, drift-kick-drift, no GR",
+    "uneven2to8": "16384 systems x 2..8 planets (uniform), dt uniform in [P_inner/30, P_inner/15], drift-kick-drift",
+    "large8gr": "65536 systems x 8 planets, GR (c = 10065), dt = P_inner/20, drift-kick-drift",
+    "single8": "1 system x 8 planets, dt = P_inner/20, kick-drift-kick",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1_000_000, help="timed Wisdom-Holman steps")
+    ap.add_argument("--warmup", type=int, default=4096, help="untimed steps before the timed region")
+    ap.add_argument("--workload", default="uniform8", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--packing", default="auto")
+    ap.add_argument("--block-waves", type=int, default=1)
+    ap.add_argument("--chunk", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
+    ap.add_argument("--cpu-steps", type=int, default=80000)
+    ap.add_argument("--cpu-systems", type=int, default=256)
+    ap.add_argument("--plain-steps", type=int, default=2000, help="steps of the per-size reference path")
+    return ap.parse_args()
+
+
+def flops_per_system_step(n_planets: np.ndarray, gr: bool) -> float:
+    from paper_2307_05683_amd.flops import ALGO_FLOPS, ALGO_FLOPS_GR
+    table = ALGO_FLOPS_GR if gr else ALGO_FLOPS
+    return float(sum(table[int(n)] for n in n_planets))
+
+
+def cpu_baseline(systems, args, gr_c):
+    import oracle
+    sub = systems.subset(np.arange(min(args.cpu_systems, systems.S)))
+    threads = oracle.max_threads()
+    t0 = time.perf_counter()
+    oracle.integrate(sub, args.cpu_steps, scheme="dkd", gr_c=gr_c, precision="d", nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {
+        "value": sub.S * args.cpu_steps / dt,
+        "unit": "system-steps/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "%d systems of the same workload x %d steps, FP64, converged Kepler solves, OpenMP over systems "
+                  "(%.1f s wall)" % (sub.S, args.cpu_steps, dt),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (systems are independent; "
+              "see the sharding design notes). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2307_05683_amd import inputs
+    from paper_2307_05683_amd.ensemble import Ensemble
+
+    gr_c = inputs.GR_C if args.workload == "large8gr" else 0.0
+    scheme = "kdk" if args.workload == "single8" else "dkd"
+    systems = inputs.workload(args.workload)
+    dev = torch.device("cuda:0")
+    ens = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, packing=args.packing,
+                                block_waves=args.block_waves, chunk_steps=args.chunk, device=dev)
+    print("[bench] %s: S=%d, warmup %d steps" % (args.workload, systems.S, args.warmup), file=sys.stderr, flush=True)
+    if args.warmup:
+        ens.step(args.warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    ens.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    print("[bench] timed %d steps: %.3f s (events), %.3f s (wall)" % (args.steps, gpu_s, wall), file=sys.stderr,
+          flush=True)
+    flags = ens.flags().cpu().numpy()
+    sys_steps = systems.S * args.steps
+    value = sys_steps / gpu_s
+    n_launch = -(-args.steps // args.chunk)
+    flops_step = flops_per_system_step(systems.n_planets, gr_c > 0)
+    achieved = flops_step * args.steps / gpu_s / 1e12
+    out = {
+        "metric": "system-steps/s (8-planet FP64)" if "8" in args.workload else "system-steps/s (FP64)",
+        "value": value,
+        "unit": "system-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": gpu_s * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: %s" % (args.workload, WORKLOAD_TEXT[args.workload]),
+            "systems": systems.S,
+            "planets_total": int(systems.n_planets.sum()),
+            "packing": args.packing,
+            "chunk_steps": args.chunk,
+            "block_waves": args.block_waves,
+            "flagged_systems": int((flags != 0).sum()),
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": None,
+            "kernel": "k_step (persistent step kernel)",
+            "algorithmic_flops_per_step": flops_step,
+            "avg_launch_ms": gpu_s * 1e3 / n_launch,
+            "launches": n_launch,
+        },
+    }
+    if args.workload == "uneven2to8" and args.plain_steps > 0:
+        plain = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, packing="g8", device=dev)
+        plain.step_plain(10)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        plain.step_plain(args.plain_steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ps = ev0.elapsed_time(ev1) / 1e3
+        out["plain_per_size"] = {"value": systems.S * args.plain_steps / ps, "steps": args.plain_steps,
+                                 "speedup_fused_over_plain": value / (systems.S * args.plain_steps / ps)}
+        plain.close()
+    ens.close()
+    if not args.no_cpu:
+        print("[bench] CPU baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(systems, args, gr_c)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

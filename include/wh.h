@@ -1,0 +1,161 @@
+/*
+ * wh.h -- C interface of the MI355X Wisdom-Holman ensemble integrator.
+ *
+ * The library integrates many independent planetary systems (a star of mass
+ * m0 and 1..8 planets each) with the Wisdom-Holman map in democratic
+ * heliocentric coordinates of the WHFast512 paper (Javaheri, Rein & Tamayo
+ * 2023, Sec. 3): per step a Kepler drift of every planet about the star
+ * (Sec. 3.2), the planet-planet interaction kick (Sec. 3.3, acceleration
+ * equation), the jump step (Sec. 3.4, jump equation) and an optional 1/r^2
+ * GR kick (Sec. 3.3, final paragraphs), composed drift-kick-drift as in
+ * Sec. 3.1 with combined drifts and "keep unsynchronized" output (Sec. 3.5).
+ *
+ * Conventions (Sec. 3.5 assumptions):
+ *   - G = 1; masses constant; dt fixed per system and > 0 (integrate
+ *     backwards by flipping the velocities).  Changing dt or masses needs a
+ *     new wh_init.
+ *   - Q = planet position relative to the star (heliocentric), V = P/m =
+ *     barycentric velocity.  All floating point is IEEE binary64.
+ *
+ * Memory: every device buffer (inputs, outputs, workspace, tape) is owned by
+ * the caller; the library never allocates device memory.  Host pointers are
+ * marked "host"; every other pointer is a device pointer.  Array layouts:
+ *   m0[S], dt[S], E[S], flags[S]               one value per system
+ *   m[S*8]            planet p of system s at  m[s*8 + p]
+ *   Q[S*8*3], V[...]  component c at          Q[(s*8 + p)*3 + c]
+ * Entries of planets p >= n_planets[s] are ignored on input and left
+ * untouched on output.
+ *
+ * Streams: every call is enqueued on `stream` and returns once enqueued;
+ * buffers must stay valid until the stream has passed the call.  One context
+ * is driven by one stream at a time; calls that overlap on one context race.
+ *
+ * Errors: calls return WH_OK (0) or a negative code; they validate their
+ * arguments before enqueueing anything and never abort.  wh_last_error()
+ * gives a message for the calling thread's last failure.  Numerical trouble
+ * inside a system (non-finite state, an unbound orbit, a Kepler step outside
+ * the validated range) is not an error: it sets sticky per-system flag bits
+ * and the integration continues without branching.
+ */
+#ifndef WH_H
+#define WH_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wh_ctx wh_ctx;
+typedef int32_t wh_status;
+
+enum {
+  WH_OK = 0,
+  WH_EINVAL = -1,     /* invalid argument (sizes, dt <= 0, G != 1, null pointer) */
+  WH_EWORKSPACE = -2, /* workspace or tape smaller than required */
+  WH_EHIP = -3,       /* HIP runtime error (text in wh_last_error) */
+  WH_ESTATE = -4      /* call not valid in the context's current state */
+};
+
+/* Step composition (Sec. 3.1). */
+enum {
+  WH_DKD = 0, /* K(dt/2) J(dt/2) I(dt) J(dt/2) K(dt/2): the paper's step */
+  WH_KDK = 1  /* I(dt/2) J(dt/2) K(dt) J(dt/2) I(dt/2)  (I includes GR) */
+};
+
+/* Lane packings of systems onto 64-lane wavefronts. */
+enum {
+  WH_PACK_AUTO = -1, /* WH_PACK_POW2 (an autotuner may pass an explicit id) */
+  WH_PACK_POW2 = 0,  /* one group of 1/2/4/8 lanes per system (next power of 2 >= N) */
+  WH_PACK_G8 = 1     /* one 8-lane group per system whatever N */
+};
+
+/* Sticky per-system status bits. */
+enum {
+  WH_F_NONFINITE = 1u,  /* a position or velocity became NaN or infinite */
+  WH_F_HYPERBOLIC = 2u, /* a Kepler drift saw an unbound orbit (beta <= 0) */
+  WH_F_ZMAX = 4u        /* a Kepler drift's Stumpff argument exceeded z_max */
+};
+
+typedef struct {
+  int32_t n_systems;   /* S >= 1 */
+  double G;            /* must be 1.0 (Sec. 3.5) */
+  double gr_c;         /* speed of light for the GR kick; <= 0 turns GR off */
+  int32_t scheme;      /* WH_DKD or WH_KDK */
+  int32_t packing;     /* WH_PACK_* */
+  int32_t block_waves; /* wavefronts per workgroup: 1, 2 or 4 (0 = 1) */
+  int32_t chunk_steps; /* steps per kernel launch (0 = 4096) */
+  int32_t graph_launches; /* launches per replayed HIP graph (0 = 8, < 0 = no graph) */
+  double z_max;        /* WH_F_ZMAX threshold on the Stumpff argument (0 = 1.0) */
+} wh_config;
+
+/* Fills *cfg with the defaults above (DKD, no GR, auto packing). */
+void wh_config_default(wh_config* cfg, int32_t n_systems);
+
+/* Device workspace the context needs for this configuration and these planet
+ * counts (n_planets: host array [S], each in 1..8).  0 on invalid input. */
+size_t wh_workspace_bytes(const wh_config* cfg, const int32_t* n_planets);
+
+/* Create a context and load the initial state.  n_planets is host memory;
+ * m0, m, Q, V, dt are device arrays in the layout above; workspace is
+ * caller-owned device memory of at least wh_workspace_bytes(), 256-byte
+ * aligned, kept alive until wh_destroy.  The state starts synchronized. */
+wh_status wh_init(wh_ctx** out, const wh_config* cfg, const int32_t* n_planets, const double* m0,
+                  const double* m, const double* Q, const double* V, const double* dt, void* workspace,
+                  size_t workspace_bytes, hipStream_t stream);
+
+/* Advance every system by n_steps >= 0 steps of the fused persistent kernel.
+ * Drifts are combined across steps (Sec. 3.1, 3.5): the stored state stays
+ * unsynchronized until a reader synchronizes a copy of it. */
+wh_status wh_step_n(wh_ctx* ctx, int64_t n_steps, hipStream_t stream);
+
+/* Reference path with the same device math: one 8-lane group per system,
+ * one launch per planet count per step, state read from and written to
+ * device memory every step, no graph.  Results equal wh_step_n's up to
+ * rounding order. */
+wh_status wh_step_n_plain(wh_ctx* ctx, int64_t n_steps, hipStream_t stream);
+
+/* Synchronized copy of the state (Q_out, V_out: device [S*8*3]); the
+ * context keeps integrating the unsynchronized state (Sec. 3.5). */
+wh_status wh_get_state(wh_ctx* ctx, double* Q_out, double* V_out, hipStream_t stream);
+
+/* Energy of the synchronized copy, E_out device [S]:
+ *   sum_i [m_i V_i^2/2 - m0 m_i/|Q_i|] - sum_{i<j} m_i m_j/|Q_i - Q_j|
+ *   + |sum_i m_i V_i|^2/(2 m0)  [- sum_i 3 m0^2 m_i/(c^2 |Q_i|^2) with GR]
+ * (the Hamiltonian of Sec. 3.1 without the constant barycentre term). */
+wh_status wh_energy(wh_ctx* ctx, double* E_out, hipStream_t stream);
+
+/* Copy the sticky WH_F_* bits (flags_out: device uint32 [S]). */
+wh_status wh_status_flags(wh_ctx* ctx, uint32_t* flags_out, hipStream_t stream);
+
+/* Steps taken so far by every system (identical for all systems). */
+int64_t wh_steps_done(const wh_ctx* ctx);
+
+/* ---- reverse mode ------------------------------------------------------
+ * Gradients of a loss of the synchronized final state with respect to the
+ * initial synchronized state (Q0, V0), the planet masses and the star mass.
+ * Usage: wh_init; wh_forward_ckpt(n, K, tape) (advances the context like
+ * wh_step_n and stores a checkpoint every K steps in the tape);
+ * wh_adjoint_n(tape, dL/dQ_T, dL/dV_T) -> dL/dQ_0, dL/dV_0, dL/dm, dL/dm0.
+ * The adjoint re-runs each K-step segment from its checkpoint, records the
+ * segment's per-step states and converged Kepler anomalies in the tape, and
+ * sweeps it backwards with the hand-written transposed Jacobian of every
+ * sub-step (the Kepler drift through the implicit function theorem). */
+size_t wh_tape_bytes(const wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every);
+wh_status wh_forward_ckpt(wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every, void* tape, size_t tape_bytes,
+                          hipStream_t stream);
+wh_status wh_adjoint_n(wh_ctx* ctx, void* tape, size_t tape_bytes, const double* gQ_T, const double* gV_T,
+                       double* gQ_0, double* gV_0, double* gm, double* gm0, hipStream_t stream);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char* wh_last_error(void);
+
+/* Free the host context (the caller frees the workspace). */
+void wh_destroy(wh_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WH_H */

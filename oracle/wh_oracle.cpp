@@ -251,7 +251,8 @@ template <class T> void stumpff_trunc(const T& z, int terms, int recur, T c[4]) 
 int g_recur = 0;   // series arrangement of the fixed-iteration solver
 int g_guess = 0;   // initial guess of the fixed-iteration solver
 
-template <class T> void kep_trunc_eval(const KepEq<T>& e, const T& X, int terms, T& F, T& dF, T& ddF, T G[4]) {
+template <class T> void kep_trunc_eval(const KepEq<T>& e, const T& X, int terms, T& F, T& dF, T& ddF, T G[4],
+                                       bool need_dd) {
   T c[4];
   T X2 = X * X;
   stumpff_trunc(e.beta * X2, terms, g_recur, c);
@@ -261,7 +262,7 @@ template <class T> void kep_trunc_eval(const KepEq<T>& e, const T& X, int terms,
   G[3] = X2 * X * c[3];
   F = e.r0 * X + e.eta0 * G[2] + e.zeta0 * G[3] - e.tau;
   dF = e.r0 + e.eta0 * G[1] + e.zeta0 * G[2];
-  ddF = e.eta0 * G[0] + e.zeta0 * G[1];
+  if (need_dd) ddF = e.eta0 * G[0] + e.zeta0 * G[1];
 }
 
 // Initial guess (the paper does not print one): second-order Taylor expansion
@@ -282,14 +283,14 @@ template <class T> void kepler_fixed(T Q[3], T V[3], const T& mu, const T& tau,
   if (g_guess == 0) X = X - eta0 * tau * tau * ir0 * ir0 * ir0 * T(R(0.5));
   T F, dF, ddF, G[4];
   for (int k = 0; k < n_halley; ++k) {
-    kep_trunc_eval(e, X, terms_halley, F, dF, ddF, G);
+    kep_trunc_eval(e, X, terms_halley, F, dF, ddF, G, true);
     X = X - T(R(2)) * F * dF / (T(R(2)) * dF * dF - F * ddF);
   }
   for (int k = 0; k < n_newton; ++k) {
-    kep_trunc_eval(e, X, terms_newton, F, dF, ddF, G);
+    kep_trunc_eval(e, X, terms_newton, F, dF, ddF, G, false);
     X = X - F / dF;
   }
-  kep_trunc_eval(e, X, terms_newton, F, dF, ddF, G);
+  kep_trunc_eval(e, X, terms_newton, F, dF, ddF, G, false);
   T r = dF;
   T f = T(R(1)) - mu * G[2] * ir0;
   T g = tau - mu * G[3];

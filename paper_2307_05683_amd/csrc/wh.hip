@@ -1,0 +1,834 @@
+// MI355X (gfx950) Wisdom-Holman ensemble integrator: kernels and the C ABI
+// declared in include/wh.h.
+//
+// Hot path: one persistent kernel advances every system by a chunk of steps
+// with the state held in VGPRs; each lane carries one planet, each aligned
+// group of G lanes one system, each 64-lane wavefront 64/G systems.  The
+// step is the drift-kick-drift composition of the WHFast512 paper (Sec. 3.1)
+// with the drifts of consecutive steps merged and, without GR, the two half
+// jumps merged (they commute with the interaction kick then).  Output reads
+// synchronize a register copy (Sec. 3.5, "keep unsynchronized").
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <cmath>
+#include <stdint.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "wh.h"
+#include "wh_device.h"
+
+using namespace wh;
+
+// ===========================================================================
+// Device side
+// ===========================================================================
+namespace {
+
+// State arrays, structure of arrays over lane slots: rows 0-2 Q, 3-5 V,
+// 6 m, 7-9 and 10-12 the compensation terms of Q and V (the low-order parts
+// that rounding dropped from earlier increments).
+constexpr int ROWS = 13;
+
+struct StepParams {
+  double* st;            // [ROWS][ns]
+  int ns;                // number of lane slots (multiple of 64)
+  const double* m0s;     // [ns] star mass of the slot's system
+  const double* dts;     // [ns] timestep of the slot's system
+  const int* slot_sys;   // [ns] system index, -1 for an empty group
+  const int* slot_pl;    // [ns] planet index, -1 for a padding lane
+  uint32_t* flags;       // [S]
+  int* synced;           // [S] 1 while the stored state is synchronized
+  int wave0;             // first wave of this launch
+  int w1, w2, w4, w8;    // wave ranges [0,w1) G=1, [w1,w2) G=2, [w2,w4) G=4, [w4,w8) G=8
+  int n_steps;
+  double kgr;            // 6 / c^2, or 0 without GR
+  double zlim;           // WH_F_ZMAX threshold
+};
+
+struct Lane {
+  double qx, qy, qz, vx, vy, vz, m, m0, dt;
+  double cqx, cqy, cqz, cvx, cvy, cvz;
+  int sys, pl, first;
+};
+
+__device__ __forceinline__ Lane load_lane(const StepParams& p, int slot) {
+  Lane L;
+  const double* st = p.st;
+  const int ns = p.ns;
+  L.qx = st[slot];
+  L.qy = st[ns + slot];
+  L.qz = st[2 * ns + slot];
+  L.vx = st[3 * ns + slot];
+  L.vy = st[4 * ns + slot];
+  L.vz = st[5 * ns + slot];
+  L.m = st[6 * ns + slot];
+  L.cqx = st[7 * ns + slot];
+  L.cqy = st[8 * ns + slot];
+  L.cqz = st[9 * ns + slot];
+  L.cvx = st[10 * ns + slot];
+  L.cvy = st[11 * ns + slot];
+  L.cvz = st[12 * ns + slot];
+  L.m0 = p.m0s[slot];
+  L.dt = p.dts[slot];
+  L.sys = p.slot_sys[slot];
+  L.pl = p.slot_pl[slot];
+  L.first = L.sys >= 0 ? p.synced[L.sys] : 1;
+  return L;
+}
+
+__device__ __forceinline__ void store_lane(const StepParams& p, int slot, const Lane& L) {
+  double* st = p.st;
+  const int ns = p.ns;
+  st[slot] = L.qx;
+  st[ns + slot] = L.qy;
+  st[2 * ns + slot] = L.qz;
+  st[3 * ns + slot] = L.vx;
+  st[4 * ns + slot] = L.vy;
+  st[5 * ns + slot] = L.vz;
+  st[7 * ns + slot] = L.cqx;
+  st[8 * ns + slot] = L.cqy;
+  st[9 * ns + slot] = L.cqz;
+  st[10 * ns + slot] = L.cvx;
+  st[11 * ns + slot] = L.cvy;
+  st[12 * ns + slot] = L.cvz;
+}
+
+// Working copy of one step: the current rounded position and velocity used
+// by the operators, and the small increments of the kicks and jumps of the
+// step, which are added to the low-order part of the state at the end.
+struct Work {
+  double qx, qy, qz, vx, vy, vz;
+  double sqx, sqy, sqz, svx, svy, svz;
+};
+
+__device__ __forceinline__ void work_begin(Work& w, const Lane& L) {
+  w.qx = L.qx; w.qy = L.qy; w.qz = L.qz;
+  w.vx = L.vx; w.vy = L.vy; w.vz = L.vz;
+  w.sqx = w.sqy = w.sqz = 0.0;
+  w.svx = w.svy = w.svz = 0.0;
+}
+__device__ __forceinline__ void work_dq(Work& w, double x, double y, double z) {
+  w.qx += x; w.qy += y; w.qz += z;
+  w.sqx += x; w.sqy += y; w.sqz += z;
+}
+__device__ __forceinline__ void work_dv(Work& w, double x, double y, double z) {
+  w.vx += x; w.vy += y; w.vz += z;
+  w.svx += x; w.svy += y; w.svz += z;
+}
+
+// Kepler drift K(tau) of the lane's compensated state (Q + cQ, V + cV).
+// The coefficients come from the rounded state; the increment is formed in
+// double-double (product and sum errors kept), the low-order parts are
+// carried through the same linear map, (cQ, cV) -> (f-1, g; f', g'-1)(cQ, cV),
+// and the extra terms ex (small increments of the same step) join the low
+// part.  Returns the increments' high parts in dq/dv for the working copy.
+struct DriftInc {
+  double qx, qy, qz, vx, vy, vz;      // high parts
+  double lqx, lqy, lqz, lvx, lvy, lvz;  // low parts
+};
+
+__device__ __forceinline__ double drift_inc(const Lane& L, double mu, double tau, KepDiag& dg, DriftInc& d) {
+  KepCoef k;
+  double X = kepler_coeffs<KEP_NH, KEP_NN, KEP_KH, KEP_KN>(L.qx, L.qy, L.qz, L.vx, L.vy, L.vz, mu, tau, dg, k);
+  lin2_dd(k.fm1, L.qx, k.g, L.vx, d.qx, d.lqx);
+  lin2_dd(k.fm1, L.qy, k.g, L.vy, d.qy, d.lqy);
+  lin2_dd(k.fm1, L.qz, k.g, L.vz, d.qz, d.lqz);
+  lin2_dd(k.gdm1, L.vx, k.fd, L.qx, d.vx, d.lvx);
+  lin2_dd(k.gdm1, L.vy, k.fd, L.qy, d.vy, d.lvy);
+  lin2_dd(k.gdm1, L.vz, k.fd, L.qz, d.vz, d.lvz);
+  d.lqx += fma(k.fm1, L.cqx, k.g * L.cvx);
+  d.lqy += fma(k.fm1, L.cqy, k.g * L.cvy);
+  d.lqz += fma(k.fm1, L.cqz, k.g * L.cvz);
+  d.lvx += fma(k.fd, L.cqx, k.gdm1 * L.cvx);
+  d.lvy += fma(k.fd, L.cqy, k.gdm1 * L.cvy);
+  d.lvz += fma(k.fd, L.cqz, k.gdm1 * L.cvz);
+  return X;
+}
+
+// State += drift increment + the step's small increments.
+__device__ __forceinline__ void commit(Lane& L, const DriftInc& d, const Work& w) {
+  dd_add(L.qx, L.cqx, d.qx, d.lqx + w.sqx);
+  dd_add(L.qy, L.cqy, d.qy, d.lqy + w.sqy);
+  dd_add(L.qz, L.cqz, d.qz, d.lqz + w.sqz);
+  dd_add(L.vx, L.cvx, d.vx, d.lvx + w.svx);
+  dd_add(L.vy, L.cvy, d.vy, d.lvy + w.svy);
+  dd_add(L.vz, L.cvz, d.vz, d.lvz + w.svz);
+}
+// State += the small increments only.
+__device__ __forceinline__ void commit_small(Lane& L, const Work& w) {
+  dd_add(L.qx, L.cqx, w.sqx, 0.0);
+  dd_add(L.qy, L.cqy, w.sqy, 0.0);
+  dd_add(L.qz, L.cqz, w.sqz, 0.0);
+  dd_add(L.vx, L.cvx, w.svx, 0.0);
+  dd_add(L.vy, L.cvy, w.svy, 0.0);
+  dd_add(L.vz, L.cvz, w.svz, 0.0);
+}
+
+// Working copy after a drift: rounded state + high part of the increment.
+__device__ __forceinline__ void work_after_drift(Work& w, const Lane& L, const DriftInc& d) {
+  w.qx = L.qx + d.qx; w.qy = L.qy + d.qy; w.qz = L.qz + d.qz;
+  w.vx = L.vx + d.vx; w.vy = L.vy + d.vy; w.vz = L.vz + d.vz;
+  w.sqx = w.sqy = w.sqz = 0.0;
+  w.svx = w.svy = w.svz = 0.0;
+}
+
+// Jump J(tau): kj = tau / m0.
+template <int G> __device__ __forceinline__ void jump(Work& w, double m, double kj) {
+  double sx, sy, sz;
+  group_momentum<G>(m, w.vx, w.vy, w.vz, sx, sy, sz);
+  work_dq(w, kj * sx, kj * sy, kj * sz);
+}
+
+// Interaction kick I(tau), plus the GR kick when GR is on (both depend on
+// the positions only, so they share one velocity update).
+template <int G, bool GR>
+__device__ __forceinline__ void kick(Work& w, const GroupTopo<G>& topo, double m, double kg, double tau) {
+  double ax, ay, az;
+  interaction_accel<G>(topo, w.qx, w.qy, w.qz, m, ax, ay, az);
+  if (GR) {
+    double gx, gy, gz;
+    gr_accel(w.qx, w.qy, w.qz, kg, gx, gy, gz);
+    ax += gx; ay += gy; az += gz;
+  }
+  work_dv(w, tau * ax, tau * ay, tau * az);
+}
+
+// Combined kick block of the loop.  With GR: J(ta) [I + GR](ti) J(tc).
+// Without GR the jumps commute with I and merge: I(ti) J(ta + tc).
+template <int G, bool GR>
+__device__ __forceinline__ void kick_block(Work& w, const GroupTopo<G>& topo, double m, double inv_m0, double kg,
+                                           double ta, double ti, double tc) {
+  if (GR) {
+    jump<G>(w, m, ta * inv_m0);
+    kick<G, GR>(w, topo, m, kg, ti);
+    jump<G>(w, m, tc * inv_m0);
+  } else {
+    kick<G, GR>(w, topo, m, kg, ti);
+    jump<G>(w, m, (ta + tc) * inv_m0);
+  }
+}
+
+// n_steps steps for one lane.  The stored state X_u is "after a kick block,
+// before its closing drift" (DKD) or "after a drift" (KDK):
+//   DKD loop body: K(tk) . J(h) I(dt) J(h)        tk = h on the first step out
+//                                                 of a synchronized state
+//   KDK loop body: J(ta) I(ti) J(h) . K(dt)       (ta, ti) = (0, h) first,
+//                                                 (h, dt) afterwards
+// (operators in the order they act).  The state is kept as a double-double
+// (rounded value + compensation); see drift_inc and commit.
+template <int G, bool GR, int SCHEME>
+__device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane) {
+  GroupTopo<G> topo;
+  make_topo<G>(topo, lane, L.m);
+  const double dt = L.dt;
+  const double h = 0.5 * dt;
+  const double inv_m0 = 1.0 / L.m0;
+  const double kg = GR ? p.kgr * L.m0 * L.m0 : 0.0;
+  KepDiag dg{0.0, 1.0e300};
+  Work w;
+  DriftInc d;
+  if (SCHEME == WH_DKD) {
+    double tk = L.first ? h : dt;
+    for (int s = 0; s < p.n_steps; ++s) {
+      drift_inc(L, L.m0, tk, dg, d);
+      tk = dt;
+      work_after_drift(w, L, d);
+      kick_block<G, GR>(w, topo, L.m, inv_m0, kg, h, dt, h);
+      commit(L, d, w);
+    }
+  } else {
+    double ta = L.first ? 0.0 : h;
+    double ti = L.first ? h : dt;
+    for (int s = 0; s < p.n_steps; ++s) {
+      work_begin(w, L);
+      kick_block<G, GR>(w, topo, L.m, inv_m0, kg, ta, ti, h);
+      ta = h;
+      ti = dt;
+      commit_small(L, w);
+      drift_inc(L, L.m0, dt, dg, d);
+      work_begin(w, L);
+      commit(L, d, w);
+    }
+  }
+  int f = 0;
+  if (L.pl >= 0) {
+    bool fin = __builtin_isfinite(L.qx) && __builtin_isfinite(L.qy) && __builtin_isfinite(L.qz) &&
+               __builtin_isfinite(L.vx) && __builtin_isfinite(L.vy) && __builtin_isfinite(L.vz);
+    if (!fin) f |= WH_F_NONFINITE;
+    if (!(dg.bmin > 0.0)) f |= WH_F_HYPERBOLIC;
+    if (!(dg.zmax <= p.zlim)) f |= WH_F_ZMAX;
+  }
+  f = group_or<G>(f);
+  if ((lane & (G - 1)) == 0 && L.sys >= 0) {
+    p.flags[L.sys] |= (uint32_t)f;
+    p.synced[L.sys] = 0;
+  }
+}
+
+template <int G, bool GR, int SCHEME> __device__ void step_group(const StepParams& p, int slot, int lane) {
+  Lane L = load_lane(p, slot);
+  step_lane<G, GR, SCHEME>(p, L, lane);
+  store_lane(p, slot, L);
+}
+
+template <bool GR, int SCHEME>
+__global__ __launch_bounds__(256) void k_step(StepParams p) {
+  const int lane = threadIdx.x & 63;
+  const int wave = p.wave0 + (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  const int slot = wave * 64 + lane;
+  if (wave < p.w1) step_group<1, GR, SCHEME>(p, slot, lane);
+  else if (wave < p.w2) step_group<2, GR, SCHEME>(p, slot, lane);
+  else if (wave < p.w4) step_group<4, GR, SCHEME>(p, slot, lane);
+  else step_group<8, GR, SCHEME>(p, slot, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Synchronized copy: DKD applies the pending half drift K(h); KDK applies the
+// pending half kick J(h) [I + GR](h).  A synchronized state is left as is.
+// The result is the compensated state plus the half step's increments.
+struct SyncParams {
+  StepParams sp;
+  double* Q_out;    // [S*8*3] or null
+  double* V_out;
+  double* E_out;    // [S] or null
+};
+
+template <int G, bool GR, int SCHEME> __device__ void sync_lane(const StepParams& p, Lane& L, int lane) {
+  if (!L.first) {   // uniform over the group: one system, one flag
+    const double h = 0.5 * L.dt;
+    Work w;
+    if (SCHEME == WH_DKD) {
+      KepDiag dg{0.0, 1.0e300};
+      DriftInc d;
+      drift_inc(L, L.m0, h, dg, d);
+      work_begin(w, L);
+      commit(L, d, w);
+    } else {
+      GroupTopo<G> topo;
+      make_topo<G>(topo, lane, L.m);
+      work_begin(w, L);
+      jump<G>(w, L.m, h / L.m0);
+      kick<G, GR>(w, topo, L.m, GR ? p.kgr * L.m0 * L.m0 : 0.0, h);
+      commit_small(L, w);
+    }
+  }
+  L.qx += L.cqx; L.qy += L.cqy; L.qz += L.cqz;
+  L.vx += L.cvx; L.vy += L.cvy; L.vz += L.cvz;
+}
+
+// Energy of the lane's system (every lane of the group gets it).
+template <int G, bool GR> __device__ double group_energy(const StepParams& p, const Lane& L, int lane) {
+  const double r2 = L.qx * L.qx + L.qy * L.qy + L.qz * L.qz;
+  const double r = sqrt(r2);
+  double e = 0.5 * L.m * (L.vx * L.vx + L.vy * L.vy + L.vz * L.vz) - L.m0 * L.m / r;
+  if (GR) e -= 0.5 * p.kgr * L.m0 * L.m0 * L.m / r2;   // 3 m0^2 m / (c^2 r^2)
+  double pair = 0.0;
+#pragma unroll
+  for (int k = 1; k < G; ++k) {
+    int src = (lane ^ k) << 2;
+    double px = bperm(src, L.qx), py = bperm(src, L.qy), pz = bperm(src, L.qz), pm = bperm(src, L.m);
+    double dx = L.qx - px, dy = L.qy - py, dz = L.qz - pz;
+    pair += pm / sqrt(dx * dx + dy * dy + dz * dz);
+  }
+  e -= 0.5 * L.m * pair;
+  e = group_sum<G>(e);
+  double sx = group_sum<G>(L.m * L.vx), sy = group_sum<G>(L.m * L.vy), sz = group_sum<G>(L.m * L.vz);
+  return e + (sx * sx + sy * sy + sz * sz) / (2.0 * L.m0);
+}
+
+template <int G, bool GR, int SCHEME> __device__ void sync_group(const SyncParams& q, int slot, int lane) {
+  const StepParams& p = q.sp;
+  Lane L = load_lane(p, slot);
+  sync_lane<G, GR, SCHEME>(p, L, lane);
+  if (q.Q_out && L.sys >= 0 && L.pl >= 0) {
+    size_t o = ((size_t)L.sys * 8 + L.pl) * 3;
+    q.Q_out[o] = L.qx; q.Q_out[o + 1] = L.qy; q.Q_out[o + 2] = L.qz;
+    q.V_out[o] = L.vx; q.V_out[o + 1] = L.vy; q.V_out[o + 2] = L.vz;
+  }
+  if (q.E_out) {
+    double E = group_energy<G, GR>(p, L, lane);
+    if ((lane & (G - 1)) == 0 && L.sys >= 0) q.E_out[L.sys] = E;
+  }
+}
+
+template <bool GR, int SCHEME>
+__global__ __launch_bounds__(256) void k_sync(SyncParams q) {
+  const StepParams& p = q.sp;
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  const int slot = wave * 64 + lane;
+  if (wave < p.w1) sync_group<1, GR, SCHEME>(q, slot, lane);
+  else if (wave < p.w2) sync_group<2, GR, SCHEME>(q, slot, lane);
+  else if (wave < p.w4) sync_group<4, GR, SCHEME>(q, slot, lane);
+  else sync_group<8, GR, SCHEME>(q, slot, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Load the caller's arrays into the slot layout.  Padding lanes get a zero
+// mass and a distinct circular orbit far outside the system, so their
+// Kepler solves stay finite and their positions never coincide with another
+// lane's (their zero mass keeps them out of every other lane's sums).
+__global__ void k_gather(double* st, int ns, double* m0s, double* dts, const int* slot_sys, const int* slot_pl,
+                         const double* m0, const double* m, const double* Q, const double* V, const double* dt) {
+  int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= ns) return;
+  int s = slot_sys[slot], pl = slot_pl[slot];
+  double M0 = s >= 0 ? m0[s] : 1.0;
+  m0s[slot] = M0;
+  dts[slot] = s >= 0 ? dt[s] : 1.0e-3;
+  if (s >= 0 && pl >= 0) {
+    size_t o = ((size_t)s * 8 + pl) * 3;
+    for (int c = 0; c < 3; ++c) {
+      st[c * ns + slot] = Q[o + c];
+      st[(3 + c) * ns + slot] = V[o + c];
+    }
+    st[6 * ns + slot] = m[(size_t)s * 8 + pl];
+  } else {
+    int k = slot & 7;
+    double a = 1.0e4 * (1.0 + 0.25 * k);
+    double ph = 0.3 + 0.7 * k;
+    double vc = sqrt(M0 / a);
+    st[slot] = a * cos(ph);
+    st[ns + slot] = a * sin(ph);
+    st[2 * ns + slot] = 0.0;
+    st[3 * ns + slot] = -vc * sin(ph);
+    st[4 * ns + slot] = vc * cos(ph);
+    st[5 * ns + slot] = 0.0;
+    st[6 * ns + slot] = 0.0;
+  }
+  for (int r = 7; r < ROWS; ++r) st[r * ns + slot] = 0.0;
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_copy_u32(uint32_t* dst, const uint32_t* src, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+}  // namespace
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+namespace {
+
+thread_local std::string g_err;
+
+wh_status fail(wh_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+wh_status hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(WH_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return WH_OK;
+}
+
+struct Packing {
+  int ns = 0, nwaves = 0;
+  int w1 = 0, w2 = 0, w4 = 0, w8 = 0;
+  int plain_begin[9] = {0}, plain_end[9] = {0};   // G8 packing: waves of each planet count
+  std::vector<int32_t> slot_sys, slot_pl;
+};
+
+int group_size(int n, int packing) {
+  if (packing == WH_PACK_G8) return 8;
+  return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : 8;
+}
+
+// Lay systems out on lanes.  Systems of one group size fill whole waves; G8
+// packing also keeps each planet count on waves of its own (for the
+// per-size reference path).  Within a class systems keep their index order.
+bool make_packing(int S, const int32_t* np, int packing, Packing& P) {
+  for (int s = 0; s < S; ++s)
+    if (np[s] < 1 || np[s] > 8) return false;
+  auto add_wave_block = [&](const std::vector<int>& systems, int G) {
+    int per_wave = 64 / G;
+    int nw = ((int)systems.size() + per_wave - 1) / per_wave;
+    for (int w = 0; w < nw; ++w)
+      for (int j = 0; j < per_wave; ++j) {
+        int idx = w * per_wave + j;
+        int s = idx < (int)systems.size() ? systems[idx] : -1;
+        for (int l = 0; l < G; ++l) {
+          P.slot_sys.push_back(s);
+          P.slot_pl.push_back(s >= 0 && l < np[s] ? l : -1);
+        }
+      }
+    P.nwaves += nw;
+  };
+  if (packing == WH_PACK_G8) {
+    for (int n = 1; n <= 8; ++n) {
+      std::vector<int> cls;
+      for (int s = 0; s < S; ++s)
+        if (np[s] == n) cls.push_back(s);
+      P.plain_begin[n] = P.nwaves;
+      add_wave_block(cls, 8);
+      P.plain_end[n] = P.nwaves;
+    }
+    P.w1 = P.w2 = P.w4 = 0;
+    P.w8 = P.nwaves;
+  } else {
+    int ends[4];
+    const int Gs[4] = {1, 2, 4, 8};
+    for (int gi = 0; gi < 4; ++gi) {
+      std::vector<int> cls;
+      for (int s = 0; s < S; ++s)
+        if (group_size(np[s], packing) == Gs[gi]) cls.push_back(s);
+      add_wave_block(cls, Gs[gi]);
+      ends[gi] = P.nwaves;
+    }
+    P.w1 = ends[0]; P.w2 = ends[1]; P.w4 = ends[2]; P.w8 = ends[3];
+  }
+  P.ns = P.nwaves * 64;
+  return true;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t st, m0s, dts, slot_sys, slot_pl, flags, synced, total;
+};
+
+Layout make_layout(int S, int ns) {
+  Layout L;
+  size_t o = 0;
+  L.st = o; o = align256(o + sizeof(double) * ROWS * (size_t)ns);
+  L.m0s = o; o = align256(o + sizeof(double) * (size_t)ns);
+  L.dts = o; o = align256(o + sizeof(double) * (size_t)ns);
+  L.slot_sys = o; o = align256(o + sizeof(int) * (size_t)ns);
+  L.slot_pl = o; o = align256(o + sizeof(int) * (size_t)ns);
+  L.flags = o; o = align256(o + sizeof(uint32_t) * (size_t)S);
+  L.synced = o; o = align256(o + sizeof(int) * (size_t)S);
+  L.total = o;
+  return L;
+}
+
+bool config_ok(const wh_config* c, std::string& why) {
+  if (!c) { why = "null config"; return false; }
+  if (c->n_systems < 1) { why = "n_systems must be >= 1"; return false; }
+  if (c->G != 1.0) { why = "G must be 1 (units with G = 1)"; return false; }
+  if (c->scheme != WH_DKD && c->scheme != WH_KDK) { why = "scheme must be WH_DKD or WH_KDK"; return false; }
+  if (c->packing < WH_PACK_AUTO || c->packing > WH_PACK_G8) { why = "unknown packing"; return false; }
+  if (c->block_waves != 0 && c->block_waves != 1 && c->block_waves != 2 && c->block_waves != 4) {
+    why = "block_waves must be 0, 1, 2 or 4"; return false;
+  }
+  if (c->chunk_steps < 0) { why = "chunk_steps must be >= 0"; return false; }
+  if (!(c->z_max >= 0.0)) { why = "z_max must be >= 0"; return false; }
+  if (!(c->gr_c == c->gr_c)) { why = "gr_c is NaN"; return false; }
+  return true;
+}
+
+int eff_packing(const wh_config* c) { return c->packing == WH_PACK_AUTO ? WH_PACK_POW2 : c->packing; }
+
+}  // namespace
+
+struct wh_ctx {
+  wh_config cfg;
+  int S = 0;
+  Packing P;
+  Layout lay;
+  char* ws = nullptr;
+  double* st = nullptr;
+  double* m0s = nullptr;
+  double* dts = nullptr;
+  int* slot_sys = nullptr;
+  int* slot_pl = nullptr;
+  uint32_t* flags = nullptr;
+  int* synced = nullptr;
+  int64_t steps_done = 0;
+  int block_waves = 1;
+  int chunk = 4096;
+  int graph_launches = 8;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+StepParams step_params(const wh_ctx* c, int n_steps) {
+  StepParams p;
+  p.st = c->st;
+  p.ns = c->P.ns;
+  p.m0s = c->m0s;
+  p.dts = c->dts;
+  p.slot_sys = c->slot_sys;
+  p.slot_pl = c->slot_pl;
+  p.flags = c->flags;
+  p.synced = c->synced;
+  p.wave0 = 0;
+  p.w1 = c->P.w1; p.w2 = c->P.w2; p.w4 = c->P.w4; p.w8 = c->P.w8;
+  p.n_steps = n_steps;
+  p.kgr = c->cfg.gr_c > 0 ? 6.0 / (c->cfg.gr_c * c->cfg.gr_c) : 0.0;
+  p.zlim = c->cfg.z_max > 0 ? c->cfg.z_max : 1.0;
+  return p;
+}
+
+void launch_step_kernel(const wh_ctx* c, const StepParams& p, int n_waves, hipStream_t st) {
+  const int bw = c->block_waves;
+  dim3 block(64 * bw), grid((n_waves + bw - 1) / bw);
+  const bool gr = c->cfg.gr_c > 0;
+  if (c->cfg.scheme == WH_DKD) {
+    if (gr) hipLaunchKernelGGL((k_step<true, WH_DKD>), grid, block, 0, st, p);
+    else hipLaunchKernelGGL((k_step<false, WH_DKD>), grid, block, 0, st, p);
+  } else {
+    if (gr) hipLaunchKernelGGL((k_step<true, WH_KDK>), grid, block, 0, st, p);
+    else hipLaunchKernelGGL((k_step<false, WH_KDK>), grid, block, 0, st, p);
+  }
+}
+
+void launch_step(const wh_ctx* c, int n_steps, hipStream_t st) {
+  StepParams p = step_params(c, n_steps);
+  launch_step_kernel(c, p, c->P.nwaves, st);
+}
+
+wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st) {
+  SyncParams q;
+  q.sp = step_params(c, 0);
+  q.Q_out = Q;
+  q.V_out = V;
+  q.E_out = E;
+  dim3 block(64), grid(c->P.nwaves);
+  const bool gr = c->cfg.gr_c > 0;
+  if (c->cfg.scheme == WH_DKD) {
+    if (gr) hipLaunchKernelGGL((k_sync<true, WH_DKD>), grid, block, 0, st, q);
+    else hipLaunchKernelGGL((k_sync<false, WH_DKD>), grid, block, 0, st, q);
+  } else {
+    if (gr) hipLaunchKernelGGL((k_sync<true, WH_KDK>), grid, block, 0, st, q);
+    else hipLaunchKernelGGL((k_sync<false, WH_KDK>), grid, block, 0, st, q);
+  }
+  return hip_check(hipGetLastError(), "sync kernel launch");
+}
+
+wh_status ensure_graph(wh_ctx* c) {
+  if (c->gexec) return WH_OK;
+  wh_status s;
+  if ((s = hip_check(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate"))) return s;
+  if ((s = hip_check(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture")))
+    return s;
+  for (int i = 0; i < c->graph_launches; ++i) launch_step(c, c->chunk, c->cap_stream);
+  hipError_t le = hipGetLastError();
+  hipError_t ee = hipStreamEndCapture(c->cap_stream, &c->graph);
+  if ((s = hip_check(le, "launch during capture"))) return s;
+  if ((s = hip_check(ee, "end capture"))) return s;
+  if ((s = hip_check(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0), "graph instantiate"))) return s;
+  return WH_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void wh_config_default(wh_config* cfg, int32_t n_systems) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->n_systems = n_systems;
+  cfg->G = 1.0;
+  cfg->gr_c = 0.0;
+  cfg->scheme = WH_DKD;
+  cfg->packing = WH_PACK_AUTO;
+  cfg->block_waves = 1;
+  cfg->chunk_steps = 4096;
+  cfg->graph_launches = 8;
+  cfg->z_max = 1.0;
+}
+
+size_t wh_workspace_bytes(const wh_config* cfg, const int32_t* n_planets) {
+  std::string why;
+  if (!config_ok(cfg, why) || !n_planets) return 0;
+  Packing P;
+  if (!make_packing(cfg->n_systems, n_planets, eff_packing(cfg), P)) return 0;
+  return make_layout(cfg->n_systems, P.ns).total;
+}
+
+wh_status wh_init(wh_ctx** out, const wh_config* cfg, const int32_t* n_planets, const double* m0, const double* m,
+                  const double* Q, const double* V, const double* dt, void* workspace, size_t workspace_bytes,
+                  hipStream_t stream) {
+  std::string why;
+  if (!out) return fail(WH_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!config_ok(cfg, why)) return fail(WH_EINVAL, why);
+  if (!n_planets || !m0 || !m || !Q || !V || !dt || !workspace)
+    return fail(WH_EINVAL, "null array pointer");
+  if (((uintptr_t)workspace & 255) != 0) return fail(WH_EINVAL, "workspace must be 256-byte aligned");
+  const int S = cfg->n_systems;
+  wh_ctx* c = new wh_ctx();
+  c->cfg = *cfg;
+  c->S = S;
+  if (!make_packing(S, n_planets, eff_packing(cfg), c->P)) {
+    delete c;
+    return fail(WH_EINVAL, "planet counts must be in 1..8");
+  }
+  c->lay = make_layout(S, c->P.ns);
+  if (workspace_bytes < c->lay.total) {
+    delete c;
+    return fail(WH_EWORKSPACE, "workspace too small: need " + std::to_string(c->lay.total) + " bytes");
+  }
+  // Validate the physical inputs (Sec. 3.5: dt > 0, positive star mass,
+  // non-negative constant planet masses) before anything is enqueued.
+  std::vector<double> h_m0(S), h_dt(S), h_m((size_t)S * 8);
+  wh_status st;
+  if ((st = hip_check(hipMemcpyAsync(h_m0.data(), m0, sizeof(double) * S, hipMemcpyDeviceToHost, stream), "copy m0")) ||
+      (st = hip_check(hipMemcpyAsync(h_dt.data(), dt, sizeof(double) * S, hipMemcpyDeviceToHost, stream), "copy dt")) ||
+      (st = hip_check(hipMemcpyAsync(h_m.data(), m, sizeof(double) * 8 * S, hipMemcpyDeviceToHost, stream), "copy m")) ||
+      (st = hip_check(hipStreamSynchronize(stream), "synchronize"))) {
+    delete c;
+    return st;
+  }
+  for (int s = 0; s < S; ++s) {
+    if (!(h_dt[s] > 0.0) || !std::isfinite(h_dt[s])) {
+      delete c;
+      return fail(WH_EINVAL, "dt must be finite and > 0 (system " + std::to_string(s) + ")");
+    }
+    if (!(h_m0[s] > 0.0) || !std::isfinite(h_m0[s])) {
+      delete c;
+      return fail(WH_EINVAL, "star mass must be finite and > 0 (system " + std::to_string(s) + ")");
+    }
+    for (int p = 0; p < n_planets[s]; ++p)
+      if (!(h_m[(size_t)s * 8 + p] >= 0.0) || !std::isfinite(h_m[(size_t)s * 8 + p])) {
+        delete c;
+        return fail(WH_EINVAL, "planet masses must be finite and >= 0 (system " + std::to_string(s) + ")");
+      }
+  }
+  c->ws = (char*)workspace;
+  c->st = (double*)(c->ws + c->lay.st);
+  c->m0s = (double*)(c->ws + c->lay.m0s);
+  c->dts = (double*)(c->ws + c->lay.dts);
+  c->slot_sys = (int*)(c->ws + c->lay.slot_sys);
+  c->slot_pl = (int*)(c->ws + c->lay.slot_pl);
+  c->flags = (uint32_t*)(c->ws + c->lay.flags);
+  c->synced = (int*)(c->ws + c->lay.synced);
+  c->block_waves = cfg->block_waves > 0 ? cfg->block_waves : 1;
+  c->chunk = cfg->chunk_steps > 0 ? cfg->chunk_steps : 4096;
+  c->graph_launches = cfg->graph_launches == 0 ? 8 : cfg->graph_launches;
+  const int ns = c->P.ns;
+  if ((st = hip_check(hipMemcpyAsync(c->slot_sys, c->P.slot_sys.data(), sizeof(int) * ns, hipMemcpyHostToDevice,
+                                     stream), "upload slot table")) ||
+      (st = hip_check(hipMemcpyAsync(c->slot_pl, c->P.slot_pl.data(), sizeof(int) * ns, hipMemcpyHostToDevice,
+                                     stream), "upload slot table"))) {
+    delete c;
+    return st;
+  }
+  hipLaunchKernelGGL(k_gather, dim3((ns + 255) / 256), dim3(256), 0, stream, c->st, ns, c->m0s, c->dts, c->slot_sys,
+                     c->slot_pl, m0, m, Q, V, dt);
+  hipLaunchKernelGGL(k_fill_u32, dim3((S + 255) / 256), dim3(256), 0, stream, c->flags, 0u, S);
+  hipLaunchKernelGGL(k_fill_u32, dim3((S + 255) / 256), dim3(256), 0, stream, (uint32_t*)c->synced, 1u, S);
+  if ((st = hip_check(hipGetLastError(), "init kernels"))) {
+    delete c;
+    return st;
+  }
+  // the slot tables live in the context and must outlive the async copies;
+  // synchronize so the caller may free the input arrays right away
+  if ((st = hip_check(hipStreamSynchronize(stream), "synchronize"))) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return WH_OK;
+}
+
+wh_status wh_step_n(wh_ctx* c, int64_t n_steps, hipStream_t stream) {
+  if (!c) return fail(WH_EINVAL, "null context");
+  if (n_steps < 0) return fail(WH_EINVAL, "n_steps must be >= 0");
+  if (n_steps == 0) return WH_OK;
+  int64_t full = n_steps / c->chunk;
+  int rem = (int)(n_steps % c->chunk);
+  wh_status st;
+  if (c->graph_launches > 0 && full >= c->graph_launches) {
+    if ((st = ensure_graph(c))) return st;
+    int64_t reps = full / c->graph_launches;
+    for (int64_t r = 0; r < reps; ++r)
+      if ((st = hip_check(hipGraphLaunch(c->gexec, stream), "graph launch"))) return st;
+    full -= reps * c->graph_launches;
+  }
+  for (int64_t i = 0; i < full; ++i) launch_step(c, c->chunk, stream);
+  if (rem) launch_step(c, rem, stream);
+  if ((st = hip_check(hipGetLastError(), "step kernel launch"))) return st;
+  c->steps_done += n_steps;
+  return WH_OK;
+}
+
+wh_status wh_step_n_plain(wh_ctx* c, int64_t n_steps, hipStream_t stream) {
+  if (!c) return fail(WH_EINVAL, "null context");
+  if (n_steps < 0) return fail(WH_EINVAL, "n_steps must be >= 0");
+  if (eff_packing(&c->cfg) != WH_PACK_G8)
+    return fail(WH_ESTATE, "the per-size reference path needs a context created with WH_PACK_G8");
+  for (int64_t s = 0; s < n_steps; ++s)
+    for (int n = 1; n <= 8; ++n) {
+      int b = c->P.plain_begin[n], e = c->P.plain_end[n];
+      if (e <= b) continue;
+      StepParams p = step_params(c, 1);
+      p.wave0 = b;
+      p.w1 = p.w2 = p.w4 = 0;
+      p.w8 = e;
+      launch_step_kernel(c, p, e - b, stream);
+    }
+  wh_status st = hip_check(hipGetLastError(), "step kernel launch");
+  if (st) return st;
+  c->steps_done += n_steps;
+  return WH_OK;
+}
+
+wh_status wh_get_state(wh_ctx* c, double* Q_out, double* V_out, hipStream_t stream) {
+  if (!c) return fail(WH_EINVAL, "null context");
+  if (!Q_out || !V_out) return fail(WH_EINVAL, "null output pointer");
+  return launch_sync(c, Q_out, V_out, nullptr, stream);
+}
+
+wh_status wh_energy(wh_ctx* c, double* E_out, hipStream_t stream) {
+  if (!c) return fail(WH_EINVAL, "null context");
+  if (!E_out) return fail(WH_EINVAL, "null output pointer");
+  return launch_sync(c, nullptr, nullptr, E_out, stream);
+}
+
+wh_status wh_status_flags(wh_ctx* c, uint32_t* flags_out, hipStream_t stream) {
+  if (!c) return fail(WH_EINVAL, "null context");
+  if (!flags_out) return fail(WH_EINVAL, "null output pointer");
+  hipLaunchKernelGGL(k_copy_u32, dim3((c->S + 255) / 256), dim3(256), 0, stream, flags_out, c->flags, c->S);
+  return hip_check(hipGetLastError(), "flags copy");
+}
+
+int64_t wh_steps_done(const wh_ctx* c) { return c ? c->steps_done : -1; }
+
+size_t wh_tape_bytes(const wh_ctx* c, int64_t n_steps, int64_t ckpt_every) {
+  (void)c; (void)n_steps; (void)ckpt_every;
+  return 0;
+}
+
+wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* tape, size_t tape_bytes,
+                          hipStream_t stream) {
+  (void)c; (void)n_steps; (void)ckpt_every; (void)tape; (void)tape_bytes; (void)stream;
+  return fail(WH_ESTATE, "reverse mode not available in this build");
+}
+
+wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* gQ_T, const double* gV_T,
+                       double* gQ_0, double* gV_0, double* gm, double* gm0, hipStream_t stream) {
+  (void)c; (void)tape; (void)tape_bytes; (void)gQ_T; (void)gV_T; (void)gQ_0; (void)gV_0; (void)gm; (void)gm0;
+  (void)stream;
+  return fail(WH_ESTATE, "reverse mode not available in this build");
+}
+
+const char* wh_last_error(void) { return g_err.c_str(); }
+
+void wh_destroy(wh_ctx* c) {
+  if (!c) return;
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  delete c;
+}
+
+}  // extern "C"

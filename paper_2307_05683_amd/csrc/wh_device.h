@@ -1,0 +1,276 @@
+// Device math of the Wisdom-Holman step for CDNA4 (gfx950), FP64 throughout.
+//
+// One lane holds one planet.  A system of N planets occupies an aligned group
+// of G = 1, 2, 4 or 8 lanes of a 64-lane wavefront; lanes of the group beyond
+// N are inert padding (zero mass).  Cross-lane traffic never leaves the
+// group: sums use DPP row operations, partner exchange uses ds_bpermute (the
+// LDS crossbar, no LDS storage and no barrier).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wh {
+
+// ---------------------------------------------------------------------------
+// Reciprocal and reciprocal square root.  The hardware seeds (v_rcp_f64,
+// v_rsq_f64) are good to about 2^-24; one Newton step with the second-order
+// term, y (1 + e + e^2) for 1/x and y (1 + e/2 + 3e^2/8) for 1/sqrt(x), leaves
+// an O(e^3) error below the final rounding.
+__device__ __forceinline__ double rcp_seed(double x) { return __builtin_amdgcn_rcp(x); }
+__device__ __forceinline__ double rcp_full(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  return fma(y, fma(e, e, e), y);
+}
+__device__ __forceinline__ double rsqrt_full(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = x * y;
+  double e = fma(-h, y, 1.0);
+  double c = fma(0.375, e, 0.5);
+  return fma(y * e, c, y);
+}
+
+// ---------------------------------------------------------------------------
+// Cross-lane moves of 64-bit values (two 32-bit moves each).
+template <int CTRL> __device__ __forceinline__ double dpp(double v) {
+  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL> __device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+// DPP controls: quad_perm [1,0,3,2] (xor 1), [2,3,0,1] (xor 2), row_half_mirror
+// (lane i of each 8-lane half-row reads lane 7-i).
+constexpr int DPP_XOR1 = 0xB1;
+constexpr int DPP_XOR2 = 0x4E;
+constexpr int DPP_HALF_MIRROR = 0x141;
+
+__device__ __forceinline__ double bperm(int src_byte_addr, double v) {
+  int lo = __builtin_amdgcn_ds_bpermute(src_byte_addr, __double2loint(v));
+  int hi = __builtin_amdgcn_ds_bpermute(src_byte_addr, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over an aligned group of G lanes; every lane receives the same bits.
+// Butterfly: after stage s each lane holds the sum of its 2^s-lane block
+// (the GPU form of the three shuffle-and-add stages of Sec. 3.4).
+template <int G> __device__ __forceinline__ double group_sum(double v) {
+  if (G >= 2) v += dpp<DPP_XOR1>(v);
+  if (G >= 4) v += dpp<DPP_XOR2>(v);
+  if (G >= 8) v += dpp<DPP_HALF_MIRROR>(v);
+  return v;
+}
+template <int G> __device__ __forceinline__ int group_or(int v) {
+  if (G >= 2) v |= dpp_i<DPP_XOR1>(v);
+  if (G >= 4) v |= dpp_i<DPP_XOR2>(v);
+  if (G >= 8) v |= dpp_i<DPP_HALF_MIRROR>(v);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Stumpff functions by truncated series (Sec. 3.2): K terms of
+//   c2(z) = sum_k (-z)^k / (2k+2)!,   c3(z) = sum_k (-z)^k / (2k+3)!
+// evaluated by Horner's rule with exact inverse factorials.
+__host__ __device__ constexpr double inv_factorial(int n) {
+  double f = 1.0;
+  for (int k = 2; k <= n; ++k) f *= k;   // exact up to 18!
+  return 1.0 / f;
+}
+template <int K, int N0> __device__ __forceinline__ double stumpff_series(double z) {
+  double s = inv_factorial(N0 + 2 * (K - 1));
+#pragma unroll
+  for (int k = K - 2; k >= 0; --k) s = fma(-z, s, inv_factorial(N0 + 2 * k));
+  return s;
+}
+
+// Per-lane running diagnostics of the Kepler solves.
+struct KepDiag {
+  double zmax;   // largest Stumpff argument of a final evaluation
+  double bmin;   // smallest beta = 2 mu / r0 - v^2 (<= 0: unbound)
+};
+
+// Lagrange coefficients of a Kepler drift: the drift maps (Q, V) to
+// (f Q + g V, f' Q + g' V); kept as f - 1, g, f', g' - 1 so increments are
+// formed without cancellation.
+struct KepCoef {
+  double fm1, g, fd, gdm1;
+};
+
+// Kepler drift of one planet over tau about a star with mu = G m0 (Sec. 3.2),
+// in universal variables: with r0 = |Q|, eta = Q.V, beta = 2mu/r0 - V^2,
+// zeta = mu - beta r0, solve
+//   F(X) = r0 X + eta G2(X) + zeta G3(X) - tau = 0,  G_n = X^n c_n(beta X^2),
+// with a fixed NH Halley steps (KH series terms) and NN Newton steps (KN
+// terms), no convergence test and no branch, then form the Lagrange
+// coefficients.  Initial guess: X = tau/r0 - eta tau^2 / (2 r0^3).
+// g' - 1 is taken from the Wronskian identity f g' - f' g = 1, which keeps
+// the discrete map area-preserving to rounding.  Returns the anomaly X.
+template <int NH, int NN, int KH, int KN>
+__device__ __forceinline__ double kepler_coeffs(double qx, double qy, double qz, double vx, double vy, double vz,
+                                                double mu, double tau, KepDiag& dg, KepCoef& k) {
+  double r2 = fma(qx, qx, fma(qy, qy, qz * qz));
+  double v2 = fma(vx, vx, fma(vy, vy, vz * vz));
+  double eta = fma(qx, vx, fma(qy, vy, qz * vz));
+  double ir0 = rsqrt_full(r2);
+  double r0 = r2 * ir0;
+  double beta = fma(2.0 * mu, ir0, -v2);
+  double zeta = fma(-beta, r0, mu);
+  dg.bmin = fmin(dg.bmin, beta);
+  double a = tau * ir0;
+  double X = a * fma(-0.5 * eta * ir0, a, 1.0);
+#pragma unroll
+  for (int it = 0; it < NH; ++it) {
+    double X2 = X * X;
+    double z = beta * X2;
+    double c2 = stumpff_series<KH, 2>(z);
+    double c3 = stumpff_series<KH, 3>(z);
+    double c0 = fma(-z, c2, 1.0);
+    double c1 = fma(-z, c3, 1.0);
+    double G1 = X * c1, G2 = X2 * c2, G3 = X2 * X * c3;
+    double F = fma(r0, X, fma(eta, G2, fma(zeta, G3, -tau)));
+    double Fp = fma(eta, G1, fma(zeta, G2, r0));
+    double Fpp = fma(eta, c0, zeta * G1);
+    // Halley: X -= 2 F F' / (2 F'^2 - F F'')
+    double den = fma(-0.5 * F, Fpp, Fp * Fp);
+    X = fma(-F * Fp, rcp_seed(den), X);
+  }
+#pragma unroll
+  for (int it = 0; it < NN; ++it) {
+    double X2 = X * X;
+    double z = beta * X2;
+    double c2 = stumpff_series<KN, 2>(z);
+    double c3 = stumpff_series<KN, 3>(z);
+    double c1 = fma(-z, c3, 1.0);
+    double G1 = X * c1, G2 = X2 * c2, G3 = X2 * X * c3;
+    double F = fma(r0, X, fma(eta, G2, fma(zeta, G3, -tau)));
+    double Fp = fma(eta, G1, fma(zeta, G2, r0));
+    X = fma(-F, rcp_seed(Fp), X);
+  }
+  // G functions at the final anomaly, then the Lagrange coefficients.
+  double X2 = X * X;
+  double z = beta * X2;
+  dg.zmax = fmax(dg.zmax, z);
+  double c2 = stumpff_series<KN, 2>(z);
+  double c3 = stumpff_series<KN, 3>(z);
+  double c1 = fma(-z, c3, 1.0);
+  double G1 = X * c1, G2 = X2 * c2, G3 = X2 * X * c3;
+  double r = fma(eta, G1, fma(zeta, G2, r0));
+  double ir = rcp_full(r);
+  k.fm1 = -mu * G2 * ir0;
+  k.g = fma(-mu, G3, tau);
+  k.fd = -mu * G1 * ir0 * ir;
+  k.gdm1 = fma(k.fd, k.g, -k.fm1) * rcp_full(1.0 + k.fm1);
+  return X;
+}
+
+// Increment a x + b y of one coordinate as an unevaluated sum hi + lo, with
+// the rounding errors of the product b y and of the sum kept in lo (b y is
+// the larger term: g V for positions, f' Q for velocities).  Contraction is
+// off: fusing b*y into p - t would count the product error twice.
+__device__ __forceinline__ void lin2_dd(double a, double x, double b, double y, double& hi, double& lo) {
+#pragma clang fp contract(off)
+  double p = b * y;
+  double pe = fma(b, y, -p);
+  double t = fma(a, x, p);
+  double te = fma(a, x, p - t);
+  hi = t;
+  lo = pe + te;
+}
+
+// Double-double accumulation (s, c) += (d, e), where s + c is the state with
+// |c| <= ulp(s)/2: an exact two-sum of s and d, the low parts added, then
+// renormalized.
+__device__ __forceinline__ void dd_add(double& s, double& c, double d, double e) {
+#pragma clang fp contract(off)
+  double t = s + d;
+  double bp = t - s;
+  double err = (s - (t - bp)) + (d - bp);
+  double lo = (c + e) + err;
+  s = t + lo;
+  c = lo - (s - t);
+}
+
+// The paper's solver: 2 Halley steps with 4 series terms, 2 Newton steps
+// with 8 terms (Sec. 3.2).
+constexpr int KEP_NH = 2, KEP_NN = 2, KEP_KH = 4, KEP_KN = 8;
+
+// ---------------------------------------------------------------------------
+// Interaction kick (Sec. 3.3, acceleration equation) inside a G-lane group,
+// using Newton's third law: round k = 1..G/2 pairs lane p with lane
+// (p + k) mod G.  For k < G/2 the G pairs of the round are distinct, so the
+// lane also computes its partner's reaction and returns it (the partner
+// reads it back from lane (p - k) mod G); the round k = G/2 pairs lanes
+// symmetrically and each side computes its own half.  Every unordered pair
+// is evaluated exactly once per side that needs it, with one reciprocal
+// square root per lane per round (G/2 per lane in all, 28 per 8-planet
+// system for the two-sided rounds and 4 for the symmetric one).
+template <int G> struct GroupTopo {
+  int fetch[G / 2 > 0 ? G / 2 : 1];   // byte address of the round-k partner
+  int back[G / 2 > 0 ? G / 2 : 1];    // byte address of the lane whose partner I am
+  double mp[G / 2 > 0 ? G / 2 : 1];   // partner masses (constant, Sec. 3.5)
+};
+
+template <int G> __device__ __forceinline__ void make_topo(GroupTopo<G>& t, int lane, double m) {
+#pragma unroll
+  for (int k = 1; k <= G / 2; ++k) {
+    int base = lane & ~(G - 1);
+    int p = lane & (G - 1);
+    t.fetch[k - 1] = (base | ((p + k) & (G - 1))) << 2;
+    t.back[k - 1] = (base | ((p - k) & (G - 1))) << 2;
+    t.mp[k - 1] = bperm(t.fetch[k - 1], m);
+  }
+}
+
+// Acceleration a_i of the lane's planet from the other planets of its group.
+template <int G> __device__ __forceinline__ void interaction_accel(const GroupTopo<G>& t, double qx, double qy,
+                                                                   double qz, double m, double& ax, double& ay,
+                                                                   double& az) {
+  ax = 0.0; ay = 0.0; az = 0.0;
+#pragma unroll
+  for (int k = 1; k <= G / 2; ++k) {
+    double px = bperm(t.fetch[k - 1], qx);
+    double py = bperm(t.fetch[k - 1], qy);
+    double pz = bperm(t.fetch[k - 1], qz);
+    double dx = qx - px, dy = qy - py, dz = qz - pz;
+    double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    double ir = rsqrt_full(r2);
+    double ir3 = ir * ir * ir;
+    double wj = t.mp[k - 1] * ir3;
+    ax = fma(-wj, dx, ax);
+    ay = fma(-wj, dy, ay);
+    az = fma(-wj, dz, az);
+    if (2 * k < G) {
+      double wi = m * ir3;   // partner's acceleration is +wi * d
+      double rx = bperm(t.back[k - 1], wi * dx);
+      double ry = bperm(t.back[k - 1], wi * dy);
+      double rz = bperm(t.back[k - 1], wi * dz);
+      ax += rx;
+      ay += ry;
+      az += rz;
+    }
+  }
+}
+
+// Jump (Sec. 3.4): every planet of the group moves by (tau/m0) sum_j m_j V_j;
+// velocities are unchanged.  Returns the group's total planetary momentum.
+template <int G> __device__ __forceinline__ void group_momentum(double m, double vx, double vy, double vz,
+                                                                double& sx, double& sy, double& sz) {
+  sx = group_sum<G>(m * vx);
+  sy = group_sum<G>(m * vy);
+  sz = group_sum<G>(m * vz);
+}
+
+// GR acceleration -6 mu^2/c^2 * Q/|Q|^4, from the potential -3 mu^2 m/(c^2 |Q|^2)
+// centred on the star.  kg = 6 mu^2 / c^2.
+__device__ __forceinline__ void gr_accel(double qx, double qy, double qz, double kg, double& ax, double& ay,
+                                         double& az) {
+  double r2 = fma(qx, qx, fma(qy, qy, qz * qz));
+  double ir2 = rcp_full(r2);
+  double w = -kg * ir2 * ir2;
+  ax = w * qx;
+  ay = w * qy;
+  az = w * qz;
+}
+
+}  // namespace wh

@@ -1,0 +1,123 @@
+"""Python front end: an ensemble of planetary systems integrated on the GPU.
+
+PyTorch provides device memory and the stream; every computation runs in
+libwh.so through the C interface (include/wh.h).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+SCHEMES = {"dkd": _lib.WH_DKD, "kdk": _lib.WH_KDK}
+PACKINGS = {"auto": _lib.WH_PACK_AUTO, "pow2": _lib.WH_PACK_POW2, "g8": _lib.WH_PACK_G8}
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev_f64(x, device):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=device)
+
+
+class Ensemble:
+    """S independent systems (star + 1..8 planets) in democratic heliocentric
+    coordinates; see include/wh.h for the conventions.
+
+    Arrays: n_planets [S] (host ints), m0 [S], m [S, 8], Q [S, 8, 3],
+    V [S, 8, 3], dt [S] (float64; numpy or torch).
+    """
+
+    def __init__(self, n_planets, m0, m, Q, V, dt, *, gr_c=0.0, scheme="dkd", packing="auto", block_waves=1,
+                 chunk_steps=4096, graph_launches=8, z_max=1.0, device="cuda"):
+        L = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("Ensemble needs a GPU (no CPU path exists)")
+        self.device = torch.device(device)
+        np_ = np.ascontiguousarray(np.asarray(n_planets), dtype=np.int32)
+        S = int(np_.shape[0])
+        self.S = S
+        self.n_planets = np_
+        cfg = _lib.default_config(S)
+        cfg.gr_c = float(gr_c)
+        cfg.scheme = SCHEMES[scheme]
+        cfg.packing = PACKINGS[packing] if isinstance(packing, str) else int(packing)
+        cfg.block_waves = int(block_waves)
+        cfg.chunk_steps = int(chunk_steps)
+        cfg.graph_launches = int(graph_launches)
+        cfg.z_max = float(z_max)
+        self.cfg = cfg
+        self.gr_c = float(gr_c)
+        self.scheme = scheme
+        nptr = np_.ctypes.data_as(C.POINTER(C.c_int32))
+        nbytes = L.wh_workspace_bytes(C.byref(cfg), nptr)
+        if nbytes == 0:
+            raise _lib.WHError(_lib.WH_EINVAL, "invalid configuration or planet counts")
+        self.workspace = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self.m0 = _dev_f64(m0, self.device)
+        self.m = _dev_f64(m, self.device)
+        Qd, Vd = _dev_f64(Q, self.device), _dev_f64(V, self.device)
+        self.dt = _dev_f64(dt, self.device)
+        for name, t, shape in (("m0", self.m0, (S,)), ("m", self.m, (S, 8)), ("Q", Qd, (S, 8, 3)),
+                               ("V", Vd, (S, 8, 3)), ("dt", self.dt, (S,))):
+            if tuple(t.shape) != shape:
+                raise ValueError("%s must have shape %s, got %s" % (name, shape, tuple(t.shape)))
+        ctx = C.c_void_p()
+        check(L.wh_init(C.byref(ctx), C.byref(cfg), nptr, self.m0.data_ptr(), self.m.data_ptr(), Qd.data_ptr(),
+                        Vd.data_ptr(), self.dt.data_ptr(), self._ws_ptr, int(nbytes), _stream(self.device)))
+        self._ctx = ctx
+
+    @classmethod
+    def from_systems(cls, systems, **kw):
+        return cls(systems.n_planets, systems.m0, systems.m, systems.Q, systems.V, systems.dt, **kw)
+
+    # ---- integration -----------------------------------------------------
+    def step(self, n_steps: int):
+        check(_lib.load().wh_step_n(self._ctx, int(n_steps), _stream(self.device)))
+        return self
+
+    def step_plain(self, n_steps: int):
+        check(_lib.load().wh_step_n_plain(self._ctx, int(n_steps), _stream(self.device)))
+        return self
+
+    @property
+    def steps_done(self) -> int:
+        return int(_lib.load().wh_steps_done(self._ctx))
+
+    # ---- outputs (synchronized copies) -------------------------------------
+    def state(self):
+        Q = torch.zeros((self.S, 8, 3), dtype=torch.float64, device=self.device)
+        V = torch.zeros((self.S, 8, 3), dtype=torch.float64, device=self.device)
+        check(_lib.load().wh_get_state(self._ctx, Q.data_ptr(), V.data_ptr(), _stream(self.device)))
+        return Q, V
+
+    def energy(self):
+        E = torch.zeros(self.S, dtype=torch.float64, device=self.device)
+        check(_lib.load().wh_energy(self._ctx, E.data_ptr(), _stream(self.device)))
+        return E
+
+    def flags(self):
+        f = torch.zeros(self.S, dtype=torch.int32, device=self.device)
+        check(_lib.load().wh_status_flags(self._ctx, f.data_ptr(), _stream(self.device)))
+        return f
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            torch.cuda.synchronize(self.device)      # nothing of this context may still be in flight
+            _lib.load().wh_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,59 @@
+"""Host-side checks of the C-ABI library (no GPU call is made here)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2307_05683_amd import _lib
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.load()
+    names = _lib.header_symbols()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+    # the binding declares exactly the header's functions
+    assert sorted(_lib._SIGS) == names
+
+
+def _ws(cfg, n):
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    return _lib.load().wh_workspace_bytes(C.byref(cfg), n.ctypes.data_as(C.POINTER(C.c_int32)))
+
+
+def test_workspace_size_follows_packing():
+    n = np.array([2, 3, 5, 8, 1, 4, 7], dtype=np.int32)
+    cfg = _lib.default_config(len(n))
+    cfg.packing = _lib.WH_PACK_POW2
+    a = _ws(cfg, n)
+    cfg.packing = _lib.WH_PACK_G8
+    b = _ws(cfg, n)
+    assert a > 0 and b > 0
+    # G8 keeps every planet count on its own waves: 7 counts -> 7 waves of 64 lanes
+    per_slot = 7 * 8 + 2 * 8 + 2 * 4
+    assert b >= 7 * 64 * per_slot
+    # pow2 packs groups of 1/2/4/8 lanes: one wave per group size here
+    assert a < b
+
+
+@pytest.mark.parametrize("bad", [
+    dict(G=2.0), dict(scheme=5), dict(packing=7), dict(block_waves=3), dict(chunk_steps=-1), dict(n_systems=0),
+])
+def test_invalid_configs_rejected(bad):
+    cfg = _lib.default_config(3)
+    for k, v in bad.items():
+        setattr(cfg, k, v)
+    assert _ws(cfg, [2, 2, 2]) == 0
+
+
+@pytest.mark.parametrize("counts", [[0, 2], [9], [3, -1]])
+def test_invalid_planet_counts_rejected(counts):
+    cfg = _lib.default_config(len(counts))
+    assert _ws(cfg, counts) == 0
+
+
+def test_defaults():
+    cfg = _lib.default_config(4)
+    assert cfg.G == 1.0 and cfg.scheme == _lib.WH_DKD and cfg.gr_c == 0.0
+    assert cfg.chunk_steps > 0 and cfg.z_max > 0

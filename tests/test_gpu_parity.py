@@ -1,0 +1,242 @@
+"""GPU path vs the CPU oracle on the same seeded inputs (parity tests).
+
+Tolerance: 1e-12 relative, per planet and norm-wise,
+  |Q_gpu - Q_oracle| / |Q_oracle| and |V_gpu - V_oracle| / |V_oracle|,
+after 1e3 steps.  The oracle runs the plain composition in long double with
+converged Kepler solves; the GPU runs the fixed-iteration solver in double
+with combined drifts (and combined jumps without GR), so the two agree up to
+the accumulated double rounding of the GPU path.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2307_05683_amd import inputs
+from paper_2307_05683_amd.ensemble import Ensemble
+from paper_2307_05683_amd import _lib
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def live(s):
+    return np.arange(8)[None, :] < s.n_planets[:, None]
+
+
+def rel_err(s, Qg, Vg, Qo, Vo):
+    lm = live(s)
+    Qo = Qo.astype(np.float64); Vo = Vo.astype(np.float64)
+    eq = np.linalg.norm(Qg - Qo, axis=2) / np.linalg.norm(Qo, axis=2)
+    ev = np.linalg.norm(Vg - Vo, axis=2) / np.linalg.norm(Vo, axis=2)
+    per_sys = np.where(lm, np.maximum(eq, ev), 0).max(axis=1)
+    print("relative error per system: median %.2e  p90 %.2e  max %.2e" % (np.median(per_sys), np.percentile(per_sys, 90),
+                                                                          per_sys.max()), flush=True)
+    return eq[lm].max(), ev[lm].max()
+
+
+def gpu_run(s, n_steps, **kw):
+    e = Ensemble.from_systems(s, **kw)
+    e.step(n_steps)
+    Q, V = e.state()
+    torch.cuda.synchronize()
+    out = Q.cpu().numpy(), V.cpu().numpy()
+    e.close()
+    return out
+
+
+def check(s, n_steps, scheme="dkd", gr_c=0.0, tol=TOL, **kw):
+    print("case: S=%d n_steps=%d scheme=%s gr_c=%g %s" % (s.S, n_steps, scheme, gr_c, kw), flush=True)
+    Qg, Vg = gpu_run(s, n_steps, scheme=scheme, gr_c=gr_c, **kw)
+    Qo, Vo = oracle.integrate(s, n_steps, scheme=scheme, gr_c=gr_c)
+    eq, ev = rel_err(s, Qg, Vg, Qo, Vo)
+    assert eq < tol and ev < tol, (eq, ev)
+    return eq, ev
+
+
+@pytest.mark.parametrize("scheme", ["dkd", "kdk"])
+def test_single_system_1000_steps(scheme):
+    check(inputs.workload("single8"), 1000, scheme)
+
+
+@pytest.mark.parametrize("scheme", ["dkd", "kdk"])
+def test_uniform_ensemble_1000_steps(scheme):
+    check(inputs.workload("uniform8", S=72), 1000, scheme)
+
+
+@pytest.mark.parametrize("packing", ["pow2", "g8"])
+@pytest.mark.parametrize("scheme", ["dkd", "kdk"])
+def test_uneven_batch_1000_steps(packing, scheme):
+    s = inputs.make_systems(150, 2, n_planets=None, n_range=(1, 8), dt_mode="u15_30")
+    check(s, 1000, scheme, packing=packing)
+
+
+@pytest.mark.parametrize("scheme", ["dkd", "kdk"])
+@pytest.mark.parametrize("gr_c", [10065.0, 40.0])
+def test_gr_1000_steps(scheme, gr_c):
+    s = inputs.make_systems(40, 4, n_planets=None, n_range=(2, 8))
+    check(s, 1000, scheme, gr_c=gr_c)
+
+
+@pytest.mark.parametrize("n_steps", [1, 2, 3, 17])
+@pytest.mark.parametrize("scheme,gr_c", [("dkd", 0.0), ("kdk", 0.0), ("dkd", 40.0), ("kdk", 40.0)])
+def test_few_steps(n_steps, scheme, gr_c):
+    s = inputs.make_systems(20, 7, n_planets=None, n_range=(1, 8))
+    check(s, n_steps, scheme, gr_c=gr_c, tol=1e-14)
+
+
+def test_zero_steps_returns_input():
+    s = inputs.make_systems(9, 8, n_planets=None, n_range=(1, 8))
+    Qg, Vg = gpu_run(s, 0)
+    lm = live(s)
+    assert np.array_equal(Qg[lm], s.Q[lm]) and np.array_equal(Vg[lm], s.V[lm])
+
+
+def test_keep_unsynchronized_is_bitwise_reproducible():
+    """Sec. 3.5: outputs synchronize a copy; the run itself does not depend on
+    how many outputs were taken."""
+    s = inputs.make_systems(40, 9, n_planets=None, n_range=(2, 8))
+    a = Ensemble.from_systems(s, chunk_steps=32)
+    a.step(200)
+    Qa, Va = a.state()
+    b = Ensemble.from_systems(s, chunk_steps=32)
+    for _ in range(20):
+        b.step(10)
+        b.state()
+        b.energy()
+    Qb, Vb = b.state()
+    assert torch.equal(Qa, Qb) and torch.equal(Va, Vb)
+    a.close(); b.close()
+
+
+def test_graph_replay_matches_direct_launches_bitwise():
+    s = inputs.make_systems(40, 10, n_planets=None, n_range=(2, 8))
+    a = Ensemble.from_systems(s, chunk_steps=16, graph_launches=4)
+    b = Ensemble.from_systems(s, chunk_steps=16, graph_launches=-1)
+    for e in (a, b):
+        e.step(3 * 64 + 21)
+        e.step(64)
+    Qa, Va = a.state()
+    Qb, Vb = b.state()
+    assert torch.equal(Qa, Qb) and torch.equal(Va, Vb)
+    a.close(); b.close()
+
+
+@pytest.mark.parametrize("scheme,gr_c", [("dkd", 0.0), ("kdk", 40.0)])
+def test_plain_per_size_path_matches_fused_bitwise(scheme, gr_c):
+    s = inputs.make_systems(70, 11, n_planets=None, n_range=(1, 8), dt_mode="u15_30")
+    a = Ensemble.from_systems(s, packing="g8", scheme=scheme, gr_c=gr_c, chunk_steps=50)
+    b = Ensemble.from_systems(s, packing="g8", scheme=scheme, gr_c=gr_c)
+    a.step(120)
+    b.step_plain(120)
+    Qa, Va = a.state()
+    Qb, Vb = b.state()
+    assert torch.equal(Qa, Qb) and torch.equal(Va, Vb)
+    a.close(); b.close()
+
+
+def test_packings_agree_and_eight_planet_systems_bitwise():
+    s = inputs.make_systems(60, 12, n_planets=None, n_range=(1, 8))
+    Qa, Va = gpu_run(s, 300, packing="pow2")
+    Qb, Vb = gpu_run(s, 300, packing="g8")
+    lm = live(s)
+    assert np.abs(Qa - Qb)[lm].max() < 1e-13 * np.abs(Qb)[lm].max()
+    eight = s.n_planets == 8
+    assert np.array_equal(Qa[eight], Qb[eight]) and np.array_equal(Va[eight], Vb[eight])
+
+
+@pytest.mark.parametrize("scheme,gr_c", [("dkd", 0.0), ("kdk", 0.0), ("dkd", 10065.0)])
+def test_energy_matches_oracle(scheme, gr_c):
+    s = inputs.make_systems(33, 13, n_planets=None, n_range=(1, 8))
+    e = Ensemble.from_systems(s, scheme=scheme, gr_c=gr_c)
+    E0 = e.energy().cpu().numpy()
+    Eo0 = oracle.energy(s, gr_c=gr_c).astype(float)
+    assert np.abs((E0 - Eo0) / Eo0).max() < 1e-14
+    e.step(500)
+    Q, V = e.state()
+    E1 = e.energy().cpu().numpy()
+    Eo1 = oracle.energy(s, Q.cpu().numpy(), V.cpu().numpy(), gr_c=gr_c).astype(float)
+    assert np.abs((E1 - Eo1) / Eo1).max() < 1e-14
+    e.close()
+
+
+def test_flags_isolated_and_healthy_systems_unaffected():
+    s = inputs.make_systems(24, 14, n_planets=None, n_range=(2, 8))
+    bad = s.copy()
+    # system 3: one planet on an unbound orbit; system 7: a NaN velocity
+    bad.V[3, 0] *= 3.0
+    bad.V[7, 1, 0] = np.nan
+    e = Ensemble.from_systems(bad)
+    e.step(50)
+    f = e.flags().cpu().numpy()
+    Qb, Vb = e.state()
+    e.close()
+    assert f[3] & _lib.WH_F_HYPERBOLIC
+    assert f[7] & _lib.WH_F_NONFINITE
+    others = [k for k in range(s.S) if k not in (3, 7)]
+    assert np.all(f[others] == 0)
+    good = s.subset(others)
+    g = Ensemble.from_systems(good)
+    g.step(50)
+    Qg, Vg = g.state()
+    g.close()
+    assert torch.equal(Qb[others], Qg) and torch.equal(Vb[others], Vg)
+
+
+def test_zmax_flag_on_large_step():
+    s = inputs.make_systems(8, 15, n_planets=3)
+    s.dt[2] *= 8.0            # z ~ (2 pi 8 / 20)^2 ~ 6 for the inner planet
+    e = Ensemble.from_systems(s)
+    e.step(5)
+    f = e.flags().cpu().numpy()
+    e.close()
+    assert f[2] & _lib.WH_F_ZMAX
+    assert np.all(f[[0, 1, 3, 4, 5, 6, 7]] == 0)
+
+
+@pytest.mark.parametrize("field,value", [("dt", 0.0), ("dt", -1.0), ("m0", 0.0), ("m", -1e-5)])
+def test_invalid_inputs_rejected(field, value):
+    s = inputs.make_systems(4, 16, n_planets=3)
+    getattr(s, field)[1] = value
+    with pytest.raises(_lib.WHError) as ei:
+        Ensemble.from_systems(s)
+    assert ei.value.code == _lib.WH_EINVAL
+
+
+def test_uniform_full_size_sampled():
+    """The benchmark's workload (4096 eight-planet systems, its launch
+    configuration): sampled systems checked one by one against the oracle."""
+    s = inputs.workload("uniform8")
+    e = Ensemble.from_systems(s)
+    e.step(1000)
+    Q, V = e.state()
+    Q = Q.cpu().numpy(); V = V.cpu().numpy()
+    e.close()
+    idx = np.random.default_rng(0).choice(s.S, 48, replace=False)
+    sub = s.subset(idx)
+    Qo, Vo = oracle.integrate(sub, 1000)
+    eq, ev = rel_err(sub, Q[idx], V[idx], Qo, Vo)
+    assert eq < TOL and ev < TOL, (eq, ev)
+
+
+def test_energy_error_statistics_match_oracle():
+    """Over a longer run the per-system maximum relative energy error of the
+    GPU path matches the oracle's (ratio within [0.5, 2] for >= 95% of the
+    systems, medians within 10%)."""
+    s = inputs.workload("uniform8", S=64)
+    e = Ensemble.from_systems(s)
+    E0 = e.energy().cpu().numpy()
+    Q, V = s.Q.astype(np.longdouble), s.V.astype(np.longdouble)
+    Eo0 = oracle.energy(s).astype(float)
+    worst_g = np.zeros(s.S); worst_o = np.zeros(s.S)
+    for _ in range(20):
+        e.step(1000)
+        Eg = e.energy().cpu().numpy()
+        worst_g = np.maximum(worst_g, np.abs((Eg - E0) / E0))
+        Q, V = oracle.integrate(s, 1000, Q=Q, V=V)
+        Eo = oracle.energy(s, Q, V).astype(float)
+        worst_o = np.maximum(worst_o, np.abs((Eo - Eo0) / Eo0))
+    e.close()
+    ratio = worst_g / worst_o
+    assert np.mean((ratio > 0.5) & (ratio < 2.0)) >= 0.95
+    assert abs(np.median(worst_g) / np.median(worst_o) - 1) < 0.1
