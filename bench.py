@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--packing", default="auto")
     ap.add_argument("--block-waves", type=int, default=1)
     ap.add_argument("--chunk", type=int, default=4096)
+    ap.add_argument("--exchange", default="auto", choices=["auto", "dpp", "lds"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--cpu-steps", type=int, default=80000)
     ap.add_argument("--cpu-systems", type=int, default=256)
@@ -95,7 +96,8 @@ def main():
     systems = inputs.workload(args.workload)
     dev = torch.device("cuda:0")
     ens = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, packing=args.packing,
-                                block_waves=args.block_waves, chunk_steps=args.chunk, device=dev)
+                                block_waves=args.block_waves, chunk_steps=args.chunk, exchange=args.exchange,
+                                device=dev)
     print("[bench] %s: S=%d, warmup %d steps" % (args.workload, systems.S, args.warmup), file=sys.stderr, flush=True)
     if args.warmup:
         ens.step(args.warmup)
@@ -138,6 +140,7 @@ def main():
             "packing": args.packing,
             "chunk_steps": args.chunk,
             "block_waves": args.block_waves,
+            "exchange": args.exchange,
             "flagged_systems": int((flags != 0).sum()),
         },
         "roofline": {

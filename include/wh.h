@@ -72,6 +72,13 @@ enum {
   WH_PACK_G8 = 1     /* one 8-lane group per system whatever N */
 };
 
+/* Partner exchange of the interaction kick inside a lane group. */
+enum {
+  WH_EXCH_AUTO = 0, /* WH_EXCH_DPP */
+  WH_EXCH_LDS = 1,  /* third-law rotation rounds through the LDS crossbar (ds_bpermute) */
+  WH_EXCH_DPP = 2   /* DPP row moves only (one more pair round for 8-lane groups) */
+};
+
 /* Sticky per-system status bits. */
 enum {
   WH_F_NONFINITE = 1u,  /* a position or velocity became NaN or infinite */
@@ -89,6 +96,7 @@ typedef struct {
   int32_t chunk_steps; /* steps per kernel launch (0 = 4096) */
   int32_t graph_launches; /* launches per replayed HIP graph (0 = 8, < 0 = no graph) */
   double z_max;        /* WH_F_ZMAX threshold on the Stumpff argument (0 = 1.0) */
+  int32_t exchange;    /* WH_EXCH_* */
 } wh_config;
 
 /* Fills *cfg with the defaults above (DKD, no GR, auto packing). */

@@ -286,12 +286,21 @@ template <class T> void kepler_fixed(T Q[3], T V[3], const T& mu, const T& tau,
     kep_trunc_eval(e, X, terms_halley, F, dF, ddF, G, true);
     X = X - T(R(2)) * F * dF / (T(R(2)) * dF * dF - F * ddF);
   }
+  // Newton steps; the G functions at the final anomaly follow from those of
+  // the last iterate by G_n(X + d) = G_n(X) + d G_{n-1}(X) (d is at rounding
+  // level once converged; with no Newton step they are evaluated afresh).
   for (int k = 0; k < n_newton; ++k) {
     kep_trunc_eval(e, X, terms_newton, F, dF, ddF, G, false);
-    X = X - F / dF;
+    T d = -(F / dF);
+    X = X + d;
+    if (k == n_newton - 1) {
+      G[3] = G[3] + d * G[2];
+      G[2] = G[2] + d * G[1];
+      G[1] = G[1] + d * G[0];
+    }
   }
-  kep_trunc_eval(e, X, terms_newton, F, dF, ddF, G, false);
-  T r = dF;
+  if (n_newton == 0) kep_trunc_eval(e, X, terms_newton, F, dF, ddF, G, false);
+  T r = e.r0 + e.eta0 * G[1] + e.zeta0 * G[2];
   T f = T(R(1)) - mu * G[2] * ir0;
   T g = tau - mu * G[3];
   T ir = T(R(1)) / r;

@@ -18,6 +18,7 @@ WH_OK, WH_EINVAL, WH_EWORKSPACE, WH_EHIP, WH_ESTATE = 0, -1, -2, -3, -4
 WH_DKD, WH_KDK = 0, 1
 WH_PACK_AUTO, WH_PACK_POW2, WH_PACK_G8 = -1, 0, 1
 WH_F_NONFINITE, WH_F_HYPERBOLIC, WH_F_ZMAX = 1, 2, 4
+WH_EXCH_AUTO, WH_EXCH_LDS, WH_EXCH_DPP = 0, 1, 2
 ERRORS = {WH_EINVAL: "WH_EINVAL", WH_EWORKSPACE: "WH_EWORKSPACE", WH_EHIP: "WH_EHIP", WH_ESTATE: "WH_ESTATE"}
 
 
@@ -38,6 +39,7 @@ class Config(C.Structure):
         ("chunk_steps", C.c_int32),
         ("graph_launches", C.c_int32),
         ("z_max", C.c_double),
+        ("exchange", C.c_int32),
     ]
 
 

@@ -176,6 +176,26 @@ __device__ __forceinline__ void work_after_drift(Work& w, const Lane& L, const D
   w.svx = w.svy = w.svz = 0.0;
 }
 
+// Partner exchange of the interaction kick: EXCH 0 = rotation rounds over the
+// LDS crossbar (ds_bpermute), EXCH 1 = DPP rounds.
+template <int G, int EXCH> struct Exch;
+template <int G> struct Exch<G, 0> {
+  GroupTopo<G> t;
+  __device__ __forceinline__ void init(int lane, double m) { make_topo<G>(t, lane, m); }
+  __device__ __forceinline__ void accel(double qx, double qy, double qz, double m, double& ax, double& ay,
+                                        double& az) const {
+    interaction_accel<G>(t, qx, qy, qz, m, ax, ay, az);
+  }
+};
+template <int G> struct Exch<G, 1> {
+  DppMass t;
+  __device__ __forceinline__ void init(int, double m) { make_dpp_mass<G>(t, m); }
+  __device__ __forceinline__ void accel(double qx, double qy, double qz, double m, double& ax, double& ay,
+                                        double& az) const {
+    interaction_accel_dpp<G>(t, qx, qy, qz, m, ax, ay, az);
+  }
+};
+
 // Jump J(tau): kj = tau / m0.
 template <int G> __device__ __forceinline__ void jump(Work& w, double m, double kj) {
   double sx, sy, sz;
@@ -185,10 +205,10 @@ template <int G> __device__ __forceinline__ void jump(Work& w, double m, double 
 
 // Interaction kick I(tau), plus the GR kick when GR is on (both depend on
 // the positions only, so they share one velocity update).
-template <int G, bool GR>
-__device__ __forceinline__ void kick(Work& w, const GroupTopo<G>& topo, double m, double kg, double tau) {
+template <int G, bool GR, int EXCH>
+__device__ __forceinline__ void kick(Work& w, const Exch<G, EXCH>& ex, double m, double kg, double tau) {
   double ax, ay, az;
-  interaction_accel<G>(topo, w.qx, w.qy, w.qz, m, ax, ay, az);
+  ex.accel(w.qx, w.qy, w.qz, m, ax, ay, az);
   if (GR) {
     double gx, gy, gz;
     gr_accel(w.qx, w.qy, w.qz, kg, gx, gy, gz);
@@ -199,15 +219,15 @@ __device__ __forceinline__ void kick(Work& w, const GroupTopo<G>& topo, double m
 
 // Combined kick block of the loop.  With GR: J(ta) [I + GR](ti) J(tc).
 // Without GR the jumps commute with I and merge: I(ti) J(ta + tc).
-template <int G, bool GR>
-__device__ __forceinline__ void kick_block(Work& w, const GroupTopo<G>& topo, double m, double inv_m0, double kg,
+template <int G, bool GR, int EXCH>
+__device__ __forceinline__ void kick_block(Work& w, const Exch<G, EXCH>& ex, double m, double inv_m0, double kg,
                                            double ta, double ti, double tc) {
   if (GR) {
     jump<G>(w, m, ta * inv_m0);
-    kick<G, GR>(w, topo, m, kg, ti);
+    kick<G, GR, EXCH>(w, ex, m, kg, ti);
     jump<G>(w, m, tc * inv_m0);
   } else {
-    kick<G, GR>(w, topo, m, kg, ti);
+    kick<G, GR, EXCH>(w, ex, m, kg, ti);
     jump<G>(w, m, (ta + tc) * inv_m0);
   }
 }
@@ -220,10 +240,10 @@ __device__ __forceinline__ void kick_block(Work& w, const GroupTopo<G>& topo, do
 //                                                 (h, dt) afterwards
 // (operators in the order they act).  The state is kept as a double-double
 // (rounded value + compensation); see drift_inc and commit.
-template <int G, bool GR, int SCHEME>
+template <int G, bool GR, int SCHEME, int EXCH>
 __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane) {
-  GroupTopo<G> topo;
-  make_topo<G>(topo, lane, L.m);
+  Exch<G, EXCH> ex;
+  ex.init(lane, L.m);
   const double dt = L.dt;
   const double h = 0.5 * dt;
   const double inv_m0 = 1.0 / L.m0;
@@ -237,7 +257,7 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
       drift_inc(L, L.m0, tk, dg, d);
       tk = dt;
       work_after_drift(w, L, d);
-      kick_block<G, GR>(w, topo, L.m, inv_m0, kg, h, dt, h);
+      kick_block<G, GR, EXCH>(w, ex, L.m, inv_m0, kg, h, dt, h);
       commit(L, d, w);
     }
   } else {
@@ -245,7 +265,7 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
     double ti = L.first ? h : dt;
     for (int s = 0; s < p.n_steps; ++s) {
       work_begin(w, L);
-      kick_block<G, GR>(w, topo, L.m, inv_m0, kg, ta, ti, h);
+      kick_block<G, GR, EXCH>(w, ex, L.m, inv_m0, kg, ta, ti, h);
       ta = h;
       ti = dt;
       commit_small(L, w);
@@ -269,22 +289,23 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
   }
 }
 
-template <int G, bool GR, int SCHEME> __device__ void step_group(const StepParams& p, int slot, int lane) {
+template <int G, bool GR, int SCHEME, int EXCH>
+__device__ void step_group(const StepParams& p, int slot, int lane) {
   Lane L = load_lane(p, slot);
-  step_lane<G, GR, SCHEME>(p, L, lane);
+  step_lane<G, GR, SCHEME, EXCH>(p, L, lane);
   store_lane(p, slot, L);
 }
 
-template <bool GR, int SCHEME>
+template <bool GR, int SCHEME, int EXCH>
 __global__ __launch_bounds__(256) void k_step(StepParams p) {
   const int lane = threadIdx.x & 63;
   const int wave = p.wave0 + (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (wave >= p.w8) return;
   const int slot = wave * 64 + lane;
-  if (wave < p.w1) step_group<1, GR, SCHEME>(p, slot, lane);
-  else if (wave < p.w2) step_group<2, GR, SCHEME>(p, slot, lane);
-  else if (wave < p.w4) step_group<4, GR, SCHEME>(p, slot, lane);
-  else step_group<8, GR, SCHEME>(p, slot, lane);
+  if (wave < p.w1) step_group<1, GR, SCHEME, EXCH>(p, slot, lane);
+  else if (wave < p.w2) step_group<2, GR, SCHEME, EXCH>(p, slot, lane);
+  else if (wave < p.w4) step_group<4, GR, SCHEME, EXCH>(p, slot, lane);
+  else step_group<8, GR, SCHEME, EXCH>(p, slot, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -309,11 +330,11 @@ template <int G, bool GR, int SCHEME> __device__ void sync_lane(const StepParams
       work_begin(w, L);
       commit(L, d, w);
     } else {
-      GroupTopo<G> topo;
-      make_topo<G>(topo, lane, L.m);
+      Exch<G, 0> ex;
+      ex.init(lane, L.m);
       work_begin(w, L);
       jump<G>(w, L.m, h / L.m0);
-      kick<G, GR>(w, topo, L.m, GR ? p.kgr * L.m0 * L.m0 : 0.0, h);
+      kick<G, GR, 0>(w, ex, L.m, GR ? p.kgr * L.m0 * L.m0 : 0.0, h);
       commit_small(L, w);
     }
   }
@@ -524,6 +545,7 @@ bool config_ok(const wh_config* c, std::string& why) {
   }
   if (c->chunk_steps < 0) { why = "chunk_steps must be >= 0"; return false; }
   if (!(c->z_max >= 0.0)) { why = "z_max must be >= 0"; return false; }
+  if (c->exchange < WH_EXCH_AUTO || c->exchange > WH_EXCH_DPP) { why = "unknown exchange"; return false; }
   if (!(c->gr_c == c->gr_c)) { why = "gr_c is NaN"; return false; }
   return true;
 }
@@ -547,6 +569,7 @@ struct wh_ctx {
   int* synced = nullptr;
   int64_t steps_done = 0;
   int block_waves = 1;
+  int exchange = WH_EXCH_DPP;
   int chunk = 4096;
   int graph_launches = 8;
   hipStream_t cap_stream = nullptr;
@@ -574,17 +597,23 @@ StepParams step_params(const wh_ctx* c, int n_steps) {
   return p;
 }
 
+template <int EXCH>
+void launch_step_exch(const wh_ctx* c, const StepParams& p, dim3 grid, dim3 block, hipStream_t st) {
+  const bool gr = c->cfg.gr_c > 0;
+  if (c->cfg.scheme == WH_DKD) {
+    if (gr) hipLaunchKernelGGL((k_step<true, WH_DKD, EXCH>), grid, block, 0, st, p);
+    else hipLaunchKernelGGL((k_step<false, WH_DKD, EXCH>), grid, block, 0, st, p);
+  } else {
+    if (gr) hipLaunchKernelGGL((k_step<true, WH_KDK, EXCH>), grid, block, 0, st, p);
+    else hipLaunchKernelGGL((k_step<false, WH_KDK, EXCH>), grid, block, 0, st, p);
+  }
+}
+
 void launch_step_kernel(const wh_ctx* c, const StepParams& p, int n_waves, hipStream_t st) {
   const int bw = c->block_waves;
   dim3 block(64 * bw), grid((n_waves + bw - 1) / bw);
-  const bool gr = c->cfg.gr_c > 0;
-  if (c->cfg.scheme == WH_DKD) {
-    if (gr) hipLaunchKernelGGL((k_step<true, WH_DKD>), grid, block, 0, st, p);
-    else hipLaunchKernelGGL((k_step<false, WH_DKD>), grid, block, 0, st, p);
-  } else {
-    if (gr) hipLaunchKernelGGL((k_step<true, WH_KDK>), grid, block, 0, st, p);
-    else hipLaunchKernelGGL((k_step<false, WH_KDK>), grid, block, 0, st, p);
-  }
+  if (c->exchange == WH_EXCH_LDS) launch_step_exch<0>(c, p, grid, block, st);
+  else launch_step_exch<1>(c, p, grid, block, st);
 }
 
 void launch_step(const wh_ctx* c, int n_steps, hipStream_t st) {
@@ -644,6 +673,7 @@ void wh_config_default(wh_config* cfg, int32_t n_systems) {
   cfg->chunk_steps = 4096;
   cfg->graph_launches = 8;
   cfg->z_max = 1.0;
+  cfg->exchange = WH_EXCH_AUTO;
 }
 
 size_t wh_workspace_bytes(const wh_config* cfg, const int32_t* n_planets) {
@@ -712,6 +742,7 @@ wh_status wh_init(wh_ctx** out, const wh_config* cfg, const int32_t* n_planets, 
   c->flags = (uint32_t*)(c->ws + c->lay.flags);
   c->synced = (int*)(c->ws + c->lay.synced);
   c->block_waves = cfg->block_waves > 0 ? cfg->block_waves : 1;
+  c->exchange = cfg->exchange == WH_EXCH_LDS ? WH_EXCH_LDS : WH_EXCH_DPP;
   c->chunk = cfg->chunk_steps > 0 ? cfg->chunk_steps : 4096;
   c->graph_launches = cfg->graph_launches == 0 ? 8 : cfg->graph_launches;
   const int ns = c->P.ns;

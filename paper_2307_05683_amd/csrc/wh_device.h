@@ -32,13 +32,15 @@ __device__ __forceinline__ double rsqrt_full(double x) {
 
 // ---------------------------------------------------------------------------
 // Cross-lane moves of 64-bit values (two 32-bit moves each).
+// Every pattern used here reads a lane of the same row, so no lane ever
+// reads an invalid source and the "old" operand is never used.
 template <int CTRL> __device__ __forceinline__ double dpp(double v) {
-  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 template <int CTRL> __device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 // DPP controls: quad_perm [1,0,3,2] (xor 1), [2,3,0,1] (xor 2), row_half_mirror
 // (lane i of each 8-lane half-row reads lane 7-i).
@@ -135,26 +137,30 @@ __device__ __forceinline__ double kepler_coeffs(double qx, double qy, double qz,
     double den = fma(-0.5 * F, Fpp, Fp * Fp);
     X = fma(-F * Fp, rcp_seed(den), X);
   }
+  // Newton steps.  The G functions of the final anomaly come from those of
+  // the last iterate: G_n(X + d) = G_n(X) + d G_{n-1}(X) + O(d^2), and d is at
+  // rounding level once the iteration has converged.
+  double G1 = 0.0, G2 = 0.0, G3 = 0.0;
 #pragma unroll
   for (int it = 0; it < NN; ++it) {
     double X2 = X * X;
     double z = beta * X2;
+    if (it == NN - 1) dg.zmax = fmax(dg.zmax, z);
     double c2 = stumpff_series<KN, 2>(z);
     double c3 = stumpff_series<KN, 3>(z);
     double c1 = fma(-z, c3, 1.0);
-    double G1 = X * c1, G2 = X2 * c2, G3 = X2 * X * c3;
+    G1 = X * c1; G2 = X2 * c2; G3 = X2 * X * c3;
     double F = fma(r0, X, fma(eta, G2, fma(zeta, G3, -tau)));
     double Fp = fma(eta, G1, fma(zeta, G2, r0));
-    X = fma(-F, rcp_seed(Fp), X);
+    double d = -F * rcp_seed(Fp);
+    X += d;
+    if (it == NN - 1) {
+      double G0 = fma(-z, c2, 1.0);
+      G3 = fma(d, G2, G3);
+      G2 = fma(d, G1, G2);
+      G1 = fma(d, G0, G1);
+    }
   }
-  // G functions at the final anomaly, then the Lagrange coefficients.
-  double X2 = X * X;
-  double z = beta * X2;
-  dg.zmax = fmax(dg.zmax, z);
-  double c2 = stumpff_series<KN, 2>(z);
-  double c3 = stumpff_series<KN, 3>(z);
-  double c1 = fma(-z, c3, 1.0);
-  double G1 = X * c1, G2 = X2 * c2, G3 = X2 * X * c3;
   double r = fma(eta, G1, fma(zeta, G2, r0));
   double ir = rcp_full(r);
   k.fm1 = -mu * G2 * ir0;
@@ -249,6 +255,92 @@ template <int G> __device__ __forceinline__ void interaction_accel(const GroupTo
       ay += ry;
       az += rz;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same kick with every exchange done by DPP row moves (VALU, no LDS
+// latency), for groups of 2, 4 or 8 lanes.  Lane p = 4 q + r (quad q,
+// position r).  Rounds:
+//   R1  partner (r+1) mod 4 in the quad, reaction returned (4 distinct pairs
+//       per quad);
+//   R2  partner r xor 2 in the quad, each side its own half (2 pairs/quad);
+//   R3  partner (r+1) mod 4 of the other quad, reaction returned: quad 0 lane
+//       r pairs with quad 1 lane r+1, quad 1 lane r with quad 0 lane r+1, so
+//       the 8 pairs are distinct;
+//   R4  partner r of the other quad (one-sided), R5 partner r xor 2 of the
+//       other quad (one-sided).
+// G = 8 uses R1-R5 (12 intra-quad + 16 cross-quad pairs = 28, five reciprocal
+// square roots per lane), G = 4 uses R1-R2, G = 2 pairs lanes r xor 1.
+// Cross-quad reads are a row_half_mirror (lane p reads 7 - p) followed by a
+// quad_perm.
+constexpr int QP_NEXT = 0x39;     // quad_perm [1,2,3,0]: r reads (r+1)&3
+constexpr int QP_PREV = 0x93;     // quad_perm [3,0,1,2]: r reads (r-1)&3
+constexpr int QP_R3 = 0xC6;       // after mirror: other quad's (r+1)&3
+constexpr int QP_R3_BACK = 0x6C;  // after mirror: other quad's (r-1)&3
+constexpr int QP_R4 = 0x1B;       // after mirror: other quad's r
+constexpr int QP_R5 = 0xB1;       // after mirror: other quad's r^2
+
+struct DppMass {
+  double m[5];   // partner mass of each round
+};
+
+template <int G> __device__ __forceinline__ void make_dpp_mass(DppMass& t, double m) {
+  if (G == 2) t.m[0] = dpp<DPP_XOR1>(m);
+  if (G >= 4) {
+    t.m[0] = dpp<QP_NEXT>(m);
+    t.m[1] = dpp<DPP_XOR2>(m);
+  }
+  if (G == 8) {
+    double mm = dpp<DPP_HALF_MIRROR>(m);
+    t.m[2] = dpp<QP_R3>(mm);
+    t.m[3] = dpp<QP_R4>(mm);
+    t.m[4] = dpp<QP_R5>(mm);
+  }
+}
+
+// One pair: a -= m_j ir^3 d with d = q - p; returns ir^3 (for the reaction).
+__device__ __forceinline__ double pair_accel(double qx, double qy, double qz, double px, double py, double pz,
+                                             double mj, double& ax, double& ay, double& az, double& dx, double& dy,
+                                             double& dz) {
+  dx = qx - px; dy = qy - py; dz = qz - pz;
+  double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+  double ir = rsqrt_full(r2);
+  double ir3 = ir * ir * ir;
+  double w = mj * ir3;
+  ax = fma(-w, dx, ax);
+  ay = fma(-w, dy, ay);
+  az = fma(-w, dz, az);
+  return ir3;
+}
+
+template <int G> __device__ __forceinline__ void interaction_accel_dpp(const DppMass& t, double qx, double qy,
+                                                                       double qz, double m, double& ax, double& ay,
+                                                                       double& az) {
+  ax = 0.0; ay = 0.0; az = 0.0;
+  double dx, dy, dz;
+  if (G == 2) {
+    pair_accel(qx, qy, qz, dpp<DPP_XOR1>(qx), dpp<DPP_XOR1>(qy), dpp<DPP_XOR1>(qz), t.m[0], ax, ay, az, dx, dy, dz);
+  }
+  if (G >= 4) {
+    double ir3 = pair_accel(qx, qy, qz, dpp<QP_NEXT>(qx), dpp<QP_NEXT>(qy), dpp<QP_NEXT>(qz), t.m[0], ax, ay, az,
+                            dx, dy, dz);
+    double wi = m * ir3;
+    ax += dpp<QP_PREV>(wi * dx);
+    ay += dpp<QP_PREV>(wi * dy);
+    az += dpp<QP_PREV>(wi * dz);
+    pair_accel(qx, qy, qz, dpp<DPP_XOR2>(qx), dpp<DPP_XOR2>(qy), dpp<DPP_XOR2>(qz), t.m[1], ax, ay, az, dx, dy, dz);
+  }
+  if (G == 8) {
+    double mx = dpp<DPP_HALF_MIRROR>(qx), my = dpp<DPP_HALF_MIRROR>(qy), mz = dpp<DPP_HALF_MIRROR>(qz);
+    double ir3 = pair_accel(qx, qy, qz, dpp<QP_R3>(mx), dpp<QP_R3>(my), dpp<QP_R3>(mz), t.m[2], ax, ay, az, dx,
+                            dy, dz);
+    double wi = m * ir3;
+    ax += dpp<QP_R3_BACK>(dpp<DPP_HALF_MIRROR>(wi * dx));
+    ay += dpp<QP_R3_BACK>(dpp<DPP_HALF_MIRROR>(wi * dy));
+    az += dpp<QP_R3_BACK>(dpp<DPP_HALF_MIRROR>(wi * dz));
+    pair_accel(qx, qy, qz, dpp<QP_R4>(mx), dpp<QP_R4>(my), dpp<QP_R4>(mz), t.m[3], ax, ay, az, dx, dy, dz);
+    pair_accel(qx, qy, qz, dpp<QP_R5>(mx), dpp<QP_R5>(my), dpp<QP_R5>(mz), t.m[4], ax, ay, az, dx, dy, dz);
   }
 }
 

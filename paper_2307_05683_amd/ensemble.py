@@ -15,6 +15,7 @@ from ._lib import check
 
 SCHEMES = {"dkd": _lib.WH_DKD, "kdk": _lib.WH_KDK}
 PACKINGS = {"auto": _lib.WH_PACK_AUTO, "pow2": _lib.WH_PACK_POW2, "g8": _lib.WH_PACK_G8}
+EXCHANGES = {"auto": _lib.WH_EXCH_AUTO, "lds": _lib.WH_EXCH_LDS, "dpp": _lib.WH_EXCH_DPP}
 
 
 def _stream(device) -> int:
@@ -36,7 +37,7 @@ class Ensemble:
     """
 
     def __init__(self, n_planets, m0, m, Q, V, dt, *, gr_c=0.0, scheme="dkd", packing="auto", block_waves=1,
-                 chunk_steps=4096, graph_launches=8, z_max=1.0, device="cuda"):
+                 chunk_steps=4096, graph_launches=8, z_max=1.0, exchange="auto", device="cuda"):
         L = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("Ensemble needs a GPU (no CPU path exists)")
@@ -53,6 +54,7 @@ class Ensemble:
         cfg.chunk_steps = int(chunk_steps)
         cfg.graph_launches = int(graph_launches)
         cfg.z_max = float(z_max)
+        cfg.exchange = EXCHANGES[exchange] if isinstance(exchange, str) else int(exchange)
         self.cfg = cfg
         self.gr_c = float(gr_c)
         self.scheme = scheme

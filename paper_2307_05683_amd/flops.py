@@ -6,5 +6,5 @@ fixed-iteration Kepler solve of Sec. 3.2 (2 Halley steps with 4 series terms,
 (third law, Sec. 3.3) and the jump(s).  add/sub, mul, div and sqrt count one
 each; an FMA counts two.  Written by oracle/write_flops.py.
 """
-ALGO_FLOPS = {1: 313, 2: 650, 3: 1012, 4: 1399, 5: 1811, 6: 2248, 7: 2710, 8: 3197}
-ALGO_FLOPS_GR = {1: 348, 2: 713, 3: 1103, 4: 1518, 5: 1958, 6: 2423, 7: 2913, 8: 3428}
+ALGO_FLOPS = {1: 275, 2: 574, 3: 898, 4: 1247, 5: 1621, 6: 2020, 7: 2444, 8: 2893}
+ALGO_FLOPS_GR = {1: 310, 2: 637, 3: 989, 4: 1366, 5: 1768, 6: 2195, 7: 2647, 8: 3124}

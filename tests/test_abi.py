@@ -39,6 +39,7 @@ def test_workspace_size_follows_packing():
 
 @pytest.mark.parametrize("bad", [
     dict(G=2.0), dict(scheme=5), dict(packing=7), dict(block_waves=3), dict(chunk_steps=-1), dict(n_systems=0),
+    dict(exchange=9),
 ])
 def test_invalid_configs_rejected(bad):
     cfg = _lib.default_config(3)

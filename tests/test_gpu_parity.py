@@ -64,11 +64,12 @@ def test_uniform_ensemble_1000_steps(scheme):
     check(inputs.workload("uniform8", S=72), 1000, scheme)
 
 
+@pytest.mark.parametrize("exchange", ["dpp", "lds"])
 @pytest.mark.parametrize("packing", ["pow2", "g8"])
 @pytest.mark.parametrize("scheme", ["dkd", "kdk"])
-def test_uneven_batch_1000_steps(packing, scheme):
+def test_uneven_batch_1000_steps(packing, scheme, exchange):
     s = inputs.make_systems(150, 2, n_planets=None, n_range=(1, 8), dt_mode="u15_30")
-    check(s, 1000, scheme, packing=packing)
+    check(s, 1000, scheme, packing=packing, exchange=exchange)
 
 
 @pytest.mark.parametrize("scheme", ["dkd", "kdk"])
@@ -78,11 +79,12 @@ def test_gr_1000_steps(scheme, gr_c):
     check(s, 1000, scheme, gr_c=gr_c)
 
 
+@pytest.mark.parametrize("exchange", ["dpp", "lds"])
 @pytest.mark.parametrize("n_steps", [1, 2, 3, 17])
 @pytest.mark.parametrize("scheme,gr_c", [("dkd", 0.0), ("kdk", 0.0), ("dkd", 40.0), ("kdk", 40.0)])
-def test_few_steps(n_steps, scheme, gr_c):
+def test_few_steps(n_steps, scheme, gr_c, exchange):
     s = inputs.make_systems(20, 7, n_planets=None, n_range=(1, 8))
-    check(s, n_steps, scheme, gr_c=gr_c, tol=1e-14)
+    check(s, n_steps, scheme, gr_c=gr_c, tol=1e-14, exchange=exchange)
 
 
 def test_zero_steps_returns_input():
@@ -133,6 +135,18 @@ def test_plain_per_size_path_matches_fused_bitwise(scheme, gr_c):
     Qb, Vb = b.state()
     assert torch.equal(Qa, Qb) and torch.equal(Va, Vb)
     a.close(); b.close()
+
+
+def test_exchanges_agree():
+    """The DPP and LDS-crossbar schedules pair the planets in a different order
+    and so differ only by rounding."""
+    s = inputs.make_systems(60, 17, n_planets=None, n_range=(1, 8))
+    Qa, Va = gpu_run(s, 300, exchange="dpp")
+    Qb, Vb = gpu_run(s, 300, exchange="lds")
+    lm = live(s)
+    assert np.abs(Qa - Qb)[lm].max() < 1e-13 * np.abs(Qb)[lm].max()
+    one = s.n_planets == 1          # no partner: identical arithmetic
+    assert np.array_equal(Qa[one], Qb[one])
 
 
 def test_packings_agree_and_eight_planet_systems_bitwise():
