@@ -38,6 +38,8 @@ WORKLOAD_TEXT = {
     "uneven2to8": "16384 systems x 2..8 planets (uniform), dt uniform in [P_inner/30, P_inner/15], drift-kick-drift",
     "large8gr": "65536 systems x 8 planets, GR (c = 10065), dt = P_inner/20, drift-kick-drift",
     "single8": "1 system x 8 planets, dt = P_inner/20, kick-drift-kick",
+    "adjoint8": "1024 systems x 8 planets, dt = P_inner/20, drift-kick-drift; reverse mode with checkpoints "
+                "every 1000 steps, loss sum |Q(T)|^2",
 }
 
 
@@ -55,6 +57,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=80000)
     ap.add_argument("--cpu-systems", type=int, default=256)
     ap.add_argument("--plain-steps", type=int, default=2000, help="steps of the per-size reference path")
+    ap.add_argument("--ckpt-every", type=int, default=1000, help="checkpoint interval of the adjoint workload")
     return ap.parse_args()
 
 
@@ -79,6 +82,29 @@ def cpu_baseline(systems, args, gr_c):
         "sample": "%d systems of the same workload x %d steps, FP64, converged Kepler solves, OpenMP over systems "
                   "(%.1f s wall)" % (sub.S, args.cpu_steps, dt),
     }
+
+
+def adjoint_cost(systems, args, dev, stream, t_plain):
+    """Forward with checkpoints + adjoint, against the plain forward of the
+    same steps (the cost ratio of reverse mode)."""
+    import torch
+    from paper_2307_05683_amd.ensemble import Ensemble
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e = Ensemble.from_systems(systems, device=dev)
+    ev[0].record(stream)
+    e.forward_ckpt(args.steps, args.ckpt_every)
+    ev[1].record(stream)
+    QT, VT = e.state()
+    g = e.adjoint(2 * QT, torch.zeros_like(VT))
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    t_ckpt = ev[0].elapsed_time(ev[1]) / 1e3
+    t_adj = ev[1].elapsed_time(ev[2]) / 1e3
+    finite = bool(all(torch.isfinite(x).all().item() for x in g))
+    e.close()
+    return {"steps": args.steps, "ckpt_every": args.ckpt_every, "forward_s": t_plain, "forward_ckpt_s": t_ckpt,
+            "adjoint_s": t_adj, "cost_ratio": (t_ckpt + t_adj) / t_plain, "backward_over_forward": t_adj / t_plain,
+            "gradients_finite": finite}
 
 
 def main():
@@ -156,6 +182,8 @@ def main():
             "launches": n_launch,
         },
     }
+    if args.workload == "adjoint8":
+        out["adjoint"] = adjoint_cost(systems, args, dev, stream, gpu_s)
     if args.workload == "uneven2to8" and args.plain_steps > 0:
         plain = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, packing="g8", device=dev)
         plain.step_plain(10)

@@ -15,11 +15,13 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
 #include "wh.h"
 #include "wh_device.h"
+#include "wh_adjoint.h"
 
 using namespace wh;
 
@@ -391,6 +393,222 @@ __global__ __launch_bounds__(256) void k_sync(SyncParams q) {
 }
 
 // ---------------------------------------------------------------------------
+// Reverse mode (drift-kick-drift).  Checkpoints hold the double-double state
+// [12][ns] (Q, V, then their compensation); the segment tape holds, per step,
+// the rounded state entering the step and the step's Kepler anomaly,
+// [step][7][ns]; the adjoint state is [8][ns]: gQ, gV, gm, and the lane's
+// share of gm0.
+struct AdjParams {
+  StepParams sp;
+  const double* ck;    // checkpoint the segment starts from
+  double* ck_out;      // checkpoint to write (forward pass)
+  double* tape;        // segment tape
+  double* grad;        // adjoint state
+  const double* gQ_T;  // caller layout [S*8*3]
+  const double* gV_T;
+  double* gQ_0;
+  double* gV_0;
+  double* gm;          // [S*8]
+  double* gm0;         // [S]
+  int n_seg;           // steps of the segment
+  int first_synced;    // the segment starts from the synchronized initial state
+};
+
+__device__ __forceinline__ void load_ck(const double* ck, int ns, int slot, Lane& L) {
+  L.qx = ck[slot]; L.qy = ck[ns + slot]; L.qz = ck[2 * ns + slot];
+  L.vx = ck[3 * ns + slot]; L.vy = ck[4 * ns + slot]; L.vz = ck[5 * ns + slot];
+  L.cqx = ck[6 * ns + slot]; L.cqy = ck[7 * ns + slot]; L.cqz = ck[8 * ns + slot];
+  L.cvx = ck[9 * ns + slot]; L.cvy = ck[10 * ns + slot]; L.cvz = ck[11 * ns + slot];
+}
+
+__global__ void k_save_ck(const double* st, double* ck, int ns) {
+  int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= ns) return;
+  for (int r = 0; r < 6; ++r) ck[r * ns + slot] = st[r * ns + slot];
+  for (int r = 0; r < 6; ++r) ck[(6 + r) * ns + slot] = st[(7 + r) * ns + slot];
+}
+
+struct Grad {
+  double qx, qy, qz, vx, vy, vz, m, m0;
+};
+
+__device__ __forceinline__ void load_grad(const double* g, int ns, int slot, Grad& a) {
+  a.qx = g[slot]; a.qy = g[ns + slot]; a.qz = g[2 * ns + slot];
+  a.vx = g[3 * ns + slot]; a.vy = g[4 * ns + slot]; a.vz = g[5 * ns + slot];
+  a.m = g[6 * ns + slot]; a.m0 = g[7 * ns + slot];
+}
+__device__ __forceinline__ void store_grad(double* g, int ns, int slot, const Grad& a) {
+  g[slot] = a.qx; g[ns + slot] = a.qy; g[2 * ns + slot] = a.qz;
+  g[3 * ns + slot] = a.vx; g[4 * ns + slot] = a.vy; g[5 * ns + slot] = a.vz;
+  g[6 * ns + slot] = a.m; g[7 * ns + slot] = a.m0;
+}
+
+// Adjoint of the jump Q += kj sum_j m_j V_j (kj = tau/m0) given the group's
+// momentum S = sum_j m_j V_j: gV_i += kj m_i sum_k gQ_k, gm_i += kj V_i .
+// sum_k gQ_k, and gm0 gets -(kj/m0) S . sum_k gQ_k once per group.
+template <int G>
+__device__ __forceinline__ void jump_vjp(Grad& a, double m, double vx, double vy, double vz, double kj, double m0,
+                                         double sx, double sy, double sz, bool leader) {
+  double Gx = group_sum<G>(a.qx), Gy = group_sum<G>(a.qy), Gz = group_sum<G>(a.qz);
+  double km = kj * m;
+  a.vx = fma(km, Gx, a.vx);
+  a.vy = fma(km, Gy, a.vy);
+  a.vz = fma(km, Gz, a.vz);
+  a.m += kj * (vx * Gx + vy * Gy + vz * Gz);
+  if (leader) a.m0 -= kj / m0 * (sx * Gx + sy * Gy + sz * Gz);
+}
+
+// Forward recompute of a segment from its checkpoint, writing the tape, then
+// the reverse sweep.  Same arithmetic as the step kernel (DPP exchange).
+template <int G, bool GR>
+__device__ void adj_segment_lane(const AdjParams& q, int slot, int lane) {
+  const StepParams& p = q.sp;
+  const int ns = p.ns;
+  Lane L;
+  load_ck(q.ck, ns, slot, L);
+  L.m = p.st[6 * ns + slot];
+  L.m0 = p.m0s[slot];
+  L.dt = p.dts[slot];
+  L.sys = p.slot_sys[slot];
+  L.pl = p.slot_pl[slot];
+  L.first = q.first_synced;
+  Exch<G, 1> ex;
+  ex.init(lane, L.m);
+  const double dt = L.dt, h = 0.5 * dt;
+  const double inv_m0 = 1.0 / L.m0;
+  const double kg = GR ? p.kgr * L.m0 * L.m0 : 0.0;
+  KepDiag dg{0.0, 1.0e300};
+  Work w;
+  DriftInc d;
+  double tk = L.first ? h : dt;
+  for (int s = 0; s < q.n_seg; ++s) {
+    double* row = q.tape + (size_t)s * 7 * ns + slot;
+    row[0] = L.qx; row[ns] = L.qy; row[2 * ns] = L.qz;
+    row[3 * ns] = L.vx; row[4 * ns] = L.vy; row[5 * ns] = L.vz;
+    row[6 * ns] = drift_inc(L, L.m0, tk, dg, d);
+    tk = dt;
+    work_after_drift(w, L, d);
+    kick_block<G, GR, 1>(w, ex, L.m, inv_m0, kg, h, dt, h);
+    commit(L, d, w);
+  }
+  // reverse sweep
+  Grad a;
+  load_grad(q.grad, ns, slot, a);
+  const bool leader = (lane & (G - 1)) == 0;
+  const double m = L.m, m0 = L.m0;
+  for (int s = q.n_seg - 1; s >= 0; --s) {
+    const double* row = q.tape + (size_t)s * 7 * ns + slot;
+    double q0x = row[0], q0y = row[ns], q0z = row[2 * ns];
+    double v0x = row[3 * ns], v0y = row[4 * ns], v0z = row[5 * ns];
+    double X = row[6 * ns];
+    double tau = (q.first_synced && s == 0) ? h : dt;
+    KepFwd k;
+    kepler_at_X(q0x, q0y, q0z, v0x, v0y, v0z, m0, tau, X, k);
+    double q1x = k.f * q0x + k.g * v0x, q1y = k.f * q0y + k.g * v0y, q1z = k.f * q0z + k.g * v0z;
+    double v1x = k.fd * q0x + k.gd * v0x, v1y = k.fd * q0y + k.gd * v0y, v1z = k.fd * q0z + k.gd * v0z;
+    if (GR) {
+      double s1x, s1y, s1z;
+      group_momentum<G>(m, v1x, v1y, v1z, s1x, s1y, s1z);
+      double kj = h * inv_m0;
+      double q2x = q1x + kj * s1x, q2y = q1y + kj * s1y, q2z = q1z + kj * s1z;
+      double ax, ay, az, gx, gy, gz;
+      ex.accel(q2x, q2y, q2z, m, ax, ay, az);
+      gr_accel(q2x, q2y, q2z, kg, gx, gy, gz);
+      double v3x = v1x + dt * (ax + gx), v3y = v1y + dt * (ay + gy), v3z = v1z + dt * (az + gz);
+      double s3x, s3y, s3z;
+      group_momentum<G>(m, v3x, v3y, v3z, s3x, s3y, s3z);
+      jump_vjp<G>(a, m, v3x, v3y, v3z, kj, m0, s3x, s3y, s3z, leader);
+      double gmu = 0.0;
+      interaction_vjp_dpp<G>(ex.t, q2x, q2y, q2z, m, dt, a.vx, a.vy, a.vz, a.qx, a.qy, a.qz, a.m);
+      gr_vjp(q2x, q2y, q2z, kg, m0, dt, a.vx, a.vy, a.vz, a.qx, a.qy, a.qz, gmu);
+      a.m0 += gmu;
+      jump_vjp<G>(a, m, v1x, v1y, v1z, kj, m0, s1x, s1y, s1z, leader);
+    } else {
+      double ax, ay, az;
+      ex.accel(q1x, q1y, q1z, m, ax, ay, az);
+      double v2x = v1x + dt * ax, v2y = v1y + dt * ay, v2z = v1z + dt * az;
+      double s2x, s2y, s2z;
+      group_momentum<G>(m, v2x, v2y, v2z, s2x, s2y, s2z);
+      jump_vjp<G>(a, m, v2x, v2y, v2z, dt * inv_m0, m0, s2x, s2y, s2z, leader);
+      interaction_vjp_dpp<G>(ex.t, q1x, q1y, q1z, m, dt, a.vx, a.vy, a.vz, a.qx, a.qy, a.qz, a.m);
+    }
+    double gmu = 0.0;
+    kepler_vjp(k, q0x, q0y, q0z, v0x, v0y, v0z, m0, a.qx, a.qy, a.qz, a.vx, a.vy, a.vz, gmu);
+    a.m0 += gmu;
+  }
+  store_grad(q.grad, ns, slot, a);
+}
+
+template <bool GR> __global__ __launch_bounds__(256) void k_adj_segment(AdjParams q) {
+  const StepParams& p = q.sp;
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  const int slot = wave * 64 + lane;
+  if (wave < p.w1) adj_segment_lane<1, GR>(q, slot, lane);
+  else if (wave < p.w2) adj_segment_lane<2, GR>(q, slot, lane);
+  else if (wave < p.w4) adj_segment_lane<4, GR>(q, slot, lane);
+  else adj_segment_lane<8, GR>(q, slot, lane);
+}
+
+// Adjoint of the closing half drift K(h) of the synchronized output (or the
+// identity when no step was taken), from the caller's dL/dQ_T, dL/dV_T.
+__global__ void k_adj_init(AdjParams q, int synced) {
+  const StepParams& p = q.sp;
+  const int ns = p.ns;
+  int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= ns) return;
+  int sys = p.slot_sys[slot], pl = p.slot_pl[slot];
+  Grad a{0, 0, 0, 0, 0, 0, 0, 0};
+  if (sys >= 0 && pl >= 0) {
+    size_t o = ((size_t)sys * 8 + pl) * 3;
+    a.qx = q.gQ_T[o]; a.qy = q.gQ_T[o + 1]; a.qz = q.gQ_T[o + 2];
+    a.vx = q.gV_T[o]; a.vy = q.gV_T[o + 1]; a.vz = q.gV_T[o + 2];
+    if (!synced) {
+      double qx = q.ck[slot], qy = q.ck[ns + slot], qz = q.ck[2 * ns + slot];
+      double vx = q.ck[3 * ns + slot], vy = q.ck[4 * ns + slot], vz = q.ck[5 * ns + slot];
+      double m0 = p.m0s[slot], h = 0.5 * p.dts[slot];
+      KepDiag dg{0.0, 1.0e300};
+      KepCoef kc;
+      double X = kepler_coeffs<KEP_NH, KEP_NN, KEP_KH, KEP_KN>(qx, qy, qz, vx, vy, vz, m0, h, dg, kc);
+      KepFwd k;
+      kepler_at_X(qx, qy, qz, vx, vy, vz, m0, h, X, k);
+      double gmu = 0.0;
+      kepler_vjp(k, qx, qy, qz, vx, vy, vz, m0, a.qx, a.qy, a.qz, a.vx, a.vy, a.vz, gmu);
+      a.m0 = gmu;
+    }
+  }
+  store_grad(q.grad, ns, slot, a);
+}
+
+template <int G> __device__ void adj_finish_lane(const AdjParams& q, int slot, int lane) {
+  const StepParams& p = q.sp;
+  Grad a;
+  load_grad(q.grad, p.ns, slot, a);
+  double g0 = group_sum<G>(a.m0);
+  int sys = p.slot_sys[slot], pl = p.slot_pl[slot];
+  if (sys >= 0 && pl >= 0) {
+    size_t o = ((size_t)sys * 8 + pl) * 3;
+    q.gQ_0[o] = a.qx; q.gQ_0[o + 1] = a.qy; q.gQ_0[o + 2] = a.qz;
+    q.gV_0[o] = a.vx; q.gV_0[o + 1] = a.vy; q.gV_0[o + 2] = a.vz;
+    q.gm[(size_t)sys * 8 + pl] = a.m;
+  }
+  if ((lane & (G - 1)) == 0 && sys >= 0) q.gm0[sys] = g0;
+}
+
+__global__ __launch_bounds__(256) void k_adj_finish(AdjParams q) {
+  const StepParams& p = q.sp;
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  const int slot = wave * 64 + lane;
+  if (wave < p.w1) adj_finish_lane<1>(q, slot, lane);
+  else if (wave < p.w2) adj_finish_lane<2>(q, slot, lane);
+  else if (wave < p.w4) adj_finish_lane<4>(q, slot, lane);
+  else adj_finish_lane<8>(q, slot, lane);
+}
+
+// ---------------------------------------------------------------------------
 // Load the caller's arrays into the slot layout.  Padding lanes get a zero
 // mass and a distinct circular orbit far outside the system, so their
 // Kepler solves stay finite and their positions never coincide with another
@@ -572,6 +790,10 @@ struct wh_ctx {
   int exchange = WH_EXCH_DPP;
   int chunk = 4096;
   int graph_launches = 8;
+  // reverse mode: the tape the last wh_forward_ckpt filled
+  const void* tape = nullptr;
+  size_t tape_bytes = 0;
+  int64_t tape_steps = 0, tape_every = 0, tape_end = -1;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -652,6 +874,25 @@ wh_status ensure_graph(wh_ctx* c) {
   if ((s = hip_check(ee, "end capture"))) return s;
   if ((s = hip_check(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0), "graph instantiate"))) return s;
   return WH_OK;
+}
+
+struct TapeLayout {
+  int64_t n_seg = 0;       // segments
+  size_t ck = 0;           // checkpoints: (n_seg + 1) x [12][ns]
+  size_t seg = 0;          // segment tape: ckpt_every x [7][ns]
+  size_t grad = 0;         // adjoint state: [8][ns]
+  size_t total = 0;
+};
+
+TapeLayout tape_layout(int ns, int64_t n_steps, int64_t every) {
+  TapeLayout T;
+  T.n_seg = (n_steps + every - 1) / every;
+  size_t o = 0;
+  T.ck = o; o = align256(o + sizeof(double) * 12 * (size_t)ns * (size_t)(T.n_seg + 1));
+  T.seg = o; o = align256(o + sizeof(double) * 7 * (size_t)ns * (size_t)every);
+  T.grad = o; o = align256(o + sizeof(double) * 8 * (size_t)ns);
+  T.total = o;
+  return T;
 }
 
 }  // namespace
@@ -835,21 +1076,76 @@ wh_status wh_status_flags(wh_ctx* c, uint32_t* flags_out, hipStream_t stream) {
 int64_t wh_steps_done(const wh_ctx* c) { return c ? c->steps_done : -1; }
 
 size_t wh_tape_bytes(const wh_ctx* c, int64_t n_steps, int64_t ckpt_every) {
-  (void)c; (void)n_steps; (void)ckpt_every;
-  return 0;
+  if (!c || n_steps < 0 || ckpt_every < 1 || ckpt_every > (1 << 30)) return 0;
+  return tape_layout(c->P.ns, n_steps, ckpt_every).total;
 }
 
 wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* tape, size_t tape_bytes,
                           hipStream_t stream) {
-  (void)c; (void)n_steps; (void)ckpt_every; (void)tape; (void)tape_bytes; (void)stream;
-  return fail(WH_ESTATE, "reverse mode not available in this build");
+  if (!c) return fail(WH_EINVAL, "null context");
+  if (!tape) return fail(WH_EINVAL, "null tape");
+  if (n_steps < 0 || ckpt_every < 1 || ckpt_every > (1 << 30)) return fail(WH_EINVAL, "bad n_steps or ckpt_every");
+  if (((uintptr_t)tape & 255) != 0) return fail(WH_EINVAL, "tape must be 256-byte aligned");
+  if (c->cfg.scheme != WH_DKD) return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD");
+  if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
+  TapeLayout T = tape_layout(c->P.ns, n_steps, ckpt_every);
+  if (tape_bytes < T.total) return fail(WH_EWORKSPACE, "tape too small: need " + std::to_string(T.total) + " bytes");
+  const int ns = c->P.ns;
+  double* ck = (double*)((char*)tape + T.ck);
+  dim3 blk(256), grd((ns + 255) / 256);
+  int64_t done = 0;
+  for (int64_t k = 0; k <= T.n_seg; ++k) {
+    hipLaunchKernelGGL(k_save_ck, grd, blk, 0, stream, c->st, ck + (size_t)k * 12 * ns, ns);
+    if (k == T.n_seg) break;
+    int64_t n = std::min(ckpt_every, n_steps - done);
+    while (n > 0) {
+      int m = (int)std::min<int64_t>(n, c->chunk);
+      launch_step(c, m, stream);
+      n -= m;
+      done += m;
+    }
+  }
+  wh_status st = hip_check(hipGetLastError(), "forward checkpoint launch");
+  if (st) return st;
+  c->steps_done += n_steps;
+  c->tape = tape;
+  c->tape_bytes = tape_bytes;
+  c->tape_steps = n_steps;
+  c->tape_every = ckpt_every;
+  c->tape_end = c->steps_done;
+  return WH_OK;
 }
 
 wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* gQ_T, const double* gV_T,
                        double* gQ_0, double* gV_0, double* gm, double* gm0, hipStream_t stream) {
-  (void)c; (void)tape; (void)tape_bytes; (void)gQ_T; (void)gV_T; (void)gQ_0; (void)gV_0; (void)gm; (void)gm0;
-  (void)stream;
-  return fail(WH_ESTATE, "reverse mode not available in this build");
+  if (!c) return fail(WH_EINVAL, "null context");
+  if (!tape || !gQ_T || !gV_T || !gQ_0 || !gV_0 || !gm || !gm0) return fail(WH_EINVAL, "null pointer");
+  if (tape != c->tape || tape_bytes != c->tape_bytes || c->steps_done != c->tape_end)
+    return fail(WH_ESTATE, "no matching wh_forward_ckpt for this tape (or steps taken since)");
+  const int ns = c->P.ns;
+  TapeLayout T = tape_layout(ns, c->tape_steps, c->tape_every);
+  double* ck = (double*)((char*)tape + T.ck);
+  AdjParams q;
+  q.sp = step_params(c, 0);
+  q.tape = (double*)((char*)tape + T.seg);
+  q.grad = (double*)((char*)tape + T.grad);
+  q.gQ_T = gQ_T; q.gV_T = gV_T;
+  q.gQ_0 = gQ_0; q.gV_0 = gV_0; q.gm = gm; q.gm0 = gm0;
+  q.ck_out = nullptr;
+  q.ck = ck + (size_t)T.n_seg * 12 * ns;
+  q.n_seg = 0;
+  q.first_synced = 0;
+  hipLaunchKernelGGL(k_adj_init, dim3((ns + 255) / 256), dim3(256), 0, stream, q, (int)(c->tape_steps == 0));
+  const bool gr = c->cfg.gr_c > 0;
+  for (int64_t k = T.n_seg - 1; k >= 0; --k) {
+    q.ck = ck + (size_t)k * 12 * ns;
+    q.n_seg = (int)std::min<int64_t>(c->tape_every, c->tape_steps - k * c->tape_every);
+    q.first_synced = (k == 0);
+    if (gr) hipLaunchKernelGGL(k_adj_segment<true>, dim3(c->P.nwaves), dim3(64), 0, stream, q);
+    else hipLaunchKernelGGL(k_adj_segment<false>, dim3(c->P.nwaves), dim3(64), 0, stream, q);
+  }
+  hipLaunchKernelGGL(k_adj_finish, dim3(c->P.nwaves), dim3(64), 0, stream, q);
+  return hip_check(hipGetLastError(), "adjoint launch");
 }
 
 const char* wh_last_error(void) { return g_err.c_str(); }

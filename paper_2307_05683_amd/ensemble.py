@@ -112,6 +112,36 @@ class Ensemble:
         check(_lib.load().wh_status_flags(self._ctx, f.data_ptr(), _stream(self.device)))
         return f
 
+    # ---- reverse mode ------------------------------------------------------
+    def forward_ckpt(self, n_steps: int, ckpt_every: int):
+        """Advance n_steps from the initial state, storing a checkpoint every
+        ckpt_every steps; returns the tape (a device byte tensor)."""
+        L = _lib.load()
+        nbytes = int(L.wh_tape_bytes(self._ctx, int(n_steps), int(ckpt_every)))
+        if nbytes == 0:
+            raise _lib.WHError(_lib.WH_EINVAL, "bad n_steps or ckpt_every")
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (buf.data_ptr() + 255) & ~255
+        check(L.wh_forward_ckpt(self._ctx, int(n_steps), int(ckpt_every), ptr, nbytes, _stream(self.device)))
+        self._tape = (buf, ptr, nbytes)
+        return buf
+
+    def adjoint(self, gQ_T, gV_T):
+        """dL/d(Q0, V0, m, m0) from dL/d(Q_T, V_T) of the synchronized final
+        state, for the run recorded by forward_ckpt."""
+        if getattr(self, "_tape", None) is None:
+            raise _lib.WHError(_lib.WH_ESTATE, "call forward_ckpt first")
+        _, ptr, nbytes = self._tape
+        gQ_T = _dev_f64(gQ_T, self.device)
+        gV_T = _dev_f64(gV_T, self.device)
+        gQ0 = torch.zeros((self.S, 8, 3), dtype=torch.float64, device=self.device)
+        gV0 = torch.zeros_like(gQ0)
+        gm = torch.zeros((self.S, 8), dtype=torch.float64, device=self.device)
+        gm0 = torch.zeros(self.S, dtype=torch.float64, device=self.device)
+        check(_lib.load().wh_adjoint_n(self._ctx, ptr, nbytes, gQ_T.data_ptr(), gV_T.data_ptr(), gQ0.data_ptr(),
+                                       gV0.data_ptr(), gm.data_ptr(), gm0.data_ptr(), _stream(self.device)))
+        return gQ0, gV0, gm, gm0
+
     def close(self):
         if getattr(self, "_ctx", None):
             torch.cuda.synchronize(self.device)      # nothing of this context may still be in flight
@@ -123,3 +153,38 @@ class Ensemble:
             self.close()
         except Exception:
             pass
+
+
+class _Integrate(torch.autograd.Function):
+    """(Q0, V0, m, m0) -> (Q_T, V_T) after n_steps; backward by the
+    hand-written adjoint with checkpoint recomputation."""
+
+    @staticmethod
+    def forward(ctx, Q0, V0, m, m0, dt, n_planets, n_steps, ckpt_every, gr_c, opts):
+        ens = Ensemble(n_planets, m0.detach(), m.detach(), Q0.detach(), V0.detach(), dt.detach(), gr_c=gr_c,
+                       device=Q0.device, **opts)
+        ens.forward_ckpt(n_steps, ckpt_every)
+        QT, VT = ens.state()
+        ctx.ens = ens
+        return QT, VT
+
+    @staticmethod
+    def backward(ctx, gQ, gV):
+        ens = ctx.ens
+        if gQ is None:
+            gQ = torch.zeros((ens.S, 8, 3), dtype=torch.float64, device=ens.device)
+        if gV is None:
+            gV = torch.zeros((ens.S, 8, 3), dtype=torch.float64, device=ens.device)
+        gQ0, gV0, gm, gm0 = ens.adjoint(gQ.contiguous(), gV.contiguous())
+        return gQ0, gV0, gm, gm0, None, None, None, None, None, None
+
+
+def integrate(Q0, V0, m, m0, dt, n_planets, n_steps, ckpt_every=1000, gr_c=0.0, **opts):
+    """Differentiable ensemble integration (drift-kick-drift).
+
+    Q0, V0: [S, 8, 3], m: [S, 8], m0, dt: [S] float64 CUDA tensors;
+    n_planets: host ints [S].  Returns the synchronized (Q_T, V_T).
+    Gradients flow to Q0, V0, m and m0.
+    """
+    return _Integrate.apply(Q0, V0, m, m0, dt, np.asarray(n_planets), int(n_steps), int(ckpt_every), float(gr_c),
+                            opts)

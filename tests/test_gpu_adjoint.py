@@ -1,0 +1,204 @@
+"""Reverse mode of the GPU path.
+
+The adjoint is checked against what does not share its arithmetic:
+  * the oracle's forward tangent map (dual numbers in long double) through
+    the dot-product identity <g_in, u> = <g_out, M u>, per system;
+  * central finite differences of the GPU forward map (h = 1e-7 relative) on
+    the loss sum_i |Q_i(T)|^2;
+  * torch.autograd.gradcheck on a tiny case.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2307_05683_amd import inputs, _lib
+from paper_2307_05683_amd.ensemble import Ensemble, integrate
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def live(s):
+    return np.arange(8)[None, :] < s.n_planets[:, None]
+
+
+def adjoint_run(s, n_steps, every, gQ_T, gV_T, gr_c=0.0):
+    e = Ensemble.from_systems(s, gr_c=gr_c)
+    e.forward_ckpt(n_steps, every)
+    QT, VT = e.state()
+    g = e.adjoint(gQ_T, gV_T)
+    out = [x.cpu().numpy() for x in (QT, VT) + g]
+    e.close()
+    return out
+
+
+def random_dirs(s, seed):
+    rng = np.random.default_rng(seed)
+    lm = live(s)
+    dQ = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None]
+    dV = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None] * 0.1
+    dm = rng.normal(size=(s.S, 8)) * lm * s.m
+    dm0 = rng.normal(size=s.S) * 0.01
+    return dQ, dV, dm, dm0
+
+
+@pytest.mark.parametrize("n_steps,every,gr_c", [(200, 64, 0.0), (200, 64, 40.0), (150, 1000, 0.0), (64, 64, 0.0),
+                                                 (1, 1, 0.0), (97, 10, 10065.0)])
+def test_dot_product_vs_oracle_tangent(n_steps, every, gr_c):
+    s = inputs.make_systems(16, 31, n_planets=None, n_range=(1, 8))
+    print("case: n_steps=%d every=%d gr_c=%g" % (n_steps, every, gr_c), flush=True)
+    rng = np.random.default_rng(5)
+    lm = live(s)
+    gQ_T = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None]
+    gV_T = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None]
+    QT, VT, gQ0, gV0, gm, gm0 = adjoint_run(s, n_steps, every, gQ_T, gV_T, gr_c)
+    dQ, dV, dm, dm0 = random_dirs(s, 6)
+    _, _, tQ, tV = oracle.tangent(s, n_steps, dQ, dV, dm, dm0, gr_c=gr_c)
+    lhs = (gQ0 * dQ).sum((1, 2)) + (gV0 * dV).sum((1, 2)) + (gm * dm).sum(1) + gm0 * dm0
+    rhs = (gQ_T * tQ.astype(float)).sum((1, 2)) + (gV_T * tV.astype(float)).sum((1, 2))
+    scale = np.abs(gQ_T * tQ.astype(float)).sum((1, 2)) + np.abs(gV_T * tV.astype(float)).sum((1, 2))
+    rel = np.abs(lhs - rhs) / scale
+    print("dot-product relative mismatch: max %.2e" % rel.max(), flush=True)
+    assert rel.max() < 1e-9
+
+
+def test_zero_steps_is_identity():
+    s = inputs.make_systems(5, 32, n_planets=None, n_range=(1, 8))
+    rng = np.random.default_rng(1)
+    gQ_T = rng.normal(size=(s.S, 8, 3)) * live(s)[:, :, None]
+    gV_T = rng.normal(size=(s.S, 8, 3)) * live(s)[:, :, None]
+    _, _, gQ0, gV0, gm, gm0 = adjoint_run(s, 0, 10, gQ_T, gV_T)
+    assert np.array_equal(gQ0, gQ_T) and np.array_equal(gV0, gV_T)
+    assert not gm.any() and not gm0.any()
+
+
+def loss_np(Q, s):
+    return (Q ** 2 * live(s)[:, :, None]).sum((1, 2))
+
+
+def test_gradients_match_central_differences():
+    """Loss L = sum_i |Q_i(T)|^2 per system; perturb one input coordinate in
+    every system at once (systems are independent) with h = 1e-7 relative."""
+    s = inputs.make_systems(32, 33, n_planets=8)
+    n_steps, every = 400, 100
+    e = Ensemble.from_systems(s)
+    e.forward_ckpt(n_steps, every)
+    QT, VT = e.state()
+    gQ0, gV0, gm, gm0 = [x.cpu().numpy() for x in e.adjoint(2 * QT, torch.zeros_like(VT))]
+    e.close()
+
+    def run(mod):
+        t = s.copy()
+        mod(t)
+        f = Ensemble.from_systems(t)
+        f.step(n_steps)
+        Q, _ = f.state()
+        f.close()
+        return loss_np(Q.cpu().numpy(), s)
+
+    # R14: h = 1e-7 |Q_i| (or |V_i|) for a state component, 1e-7 m for a mass;
+    # compared norm-wise: |fd - adjoint| <= tol * |gradient block of the system|
+    nQ = np.linalg.norm(gQ0.reshape(s.S, -1), axis=1)
+    nV = np.linalg.norm(gV0.reshape(s.S, -1), axis=1)
+    nm = np.linalg.norm(gm, axis=1)
+    for arr, idx, ref, norm in [("Q", (slice(None), 0, 0), gQ0[:, 0, 0], nQ), ("Q", (slice(None), 5, 2), gQ0[:, 5, 2], nQ),
+                                ("V", (slice(None), 2, 1), gV0[:, 2, 1], nV), ("V", (slice(None), 7, 0), gV0[:, 7, 0], nV),
+                                ("m", (slice(None), 1), gm[:, 1], nm), ("m", (slice(None), 6), gm[:, 6], nm)]:
+        base = getattr(s, arr)[idx].copy()
+        if arr == "m":
+            h = 1e-7 * base
+        else:
+            h = 1e-7 * np.linalg.norm(getattr(s, arr)[:, idx[1], :], axis=1)
+
+        def plus(t, sign):
+            getattr(t, arr)[idx] = base + sign * h
+        fd = (run(lambda t: plus(t, 1)) - run(lambda t: plus(t, -1))) / (2 * h)
+        rel = np.abs(fd - ref) / norm
+        print("FD check %s%s: median %.2e max %.2e (relative to the block norm)" % (arr, idx[1:], np.median(rel),
+                                                                                   rel.max()), flush=True)
+        assert rel.max() < 1e-6
+    # star mass
+    h = 1e-7 * s.m0
+    fd = (run(lambda t: setattr(t, "m0", s.m0 + h)) - run(lambda t: setattr(t, "m0", s.m0 - h))) / (2 * h)
+    rel = np.abs(fd - gm0) / np.abs(gm0)
+    print("FD check m0: median %.2e max %.2e" % (np.median(rel), rel.max()), flush=True)
+    assert rel.max() < 1e-6
+
+
+def test_autograd_function_and_gradcheck():
+    s = inputs.make_systems(2, 34, n_planets=None, n_range=(2, 3))
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device=DEV, requires_grad=True)
+    Q0, V0, m, m0 = t(s.Q), t(s.V), t(s.m), t(s.m0)
+    dt = torch.tensor(s.dt, dtype=torch.float64, device=DEV)
+
+    def f(Q0, V0, m, m0):
+        QT, VT = integrate(Q0, V0, m, m0, dt, s.n_planets, 6, ckpt_every=4)
+        return QT, VT
+
+    assert torch.autograd.gradcheck(f, (Q0, V0, m, m0), eps=1e-7, atol=1e-6, rtol=1e-5)
+    QT, VT = f(Q0, V0, m, m0)
+    L = (QT ** 2).sum()
+    L.backward()
+    assert Q0.grad is not None and torch.isfinite(Q0.grad).all()
+    assert torch.isfinite(m0.grad).all() and torch.isfinite(m.grad).all()
+
+
+def test_tape_validation():
+    s = inputs.make_systems(4, 35, n_planets=3)
+    e = Ensemble.from_systems(s)
+    with pytest.raises(_lib.WHError):
+        e.adjoint(np.zeros((4, 8, 3)), np.zeros((4, 8, 3)))
+    e.forward_ckpt(10, 5)
+    e.step(1)                      # the tape no longer matches the state
+    with pytest.raises(_lib.WHError) as ei:
+        e.adjoint(np.zeros((4, 8, 3)), np.zeros((4, 8, 3)))
+    assert ei.value.code == _lib.WH_ESTATE
+    e.close()
+    k = Ensemble.from_systems(s, scheme="kdk")
+    with pytest.raises(_lib.WHError):
+        k.forward_ckpt(10, 5)
+    k.close()
+
+
+def test_adjoint_workload_sampled():
+    """The adjoint workload shape (1024 eight-planet systems, checkpoints
+    every 1000 steps), shortened to 3000 steps: sampled systems pass the
+    dot-product test against the oracle tangent."""
+    s = inputs.workload("adjoint8")
+    n_steps, every = 3000, 1000
+    rng = np.random.default_rng(9)
+    gQ_T = rng.normal(size=(s.S, 8, 3))
+    gV_T = rng.normal(size=(s.S, 8, 3))
+    _, _, gQ0, gV0, gm, gm0 = adjoint_run(s, n_steps, every, gQ_T, gV_T)
+    idx = np.random.default_rng(2).choice(s.S, 6, replace=False)
+    sub = s.subset(idx)
+    dQ, dV, dm, dm0 = random_dirs(sub, 7)
+    _, _, tQ, tV = oracle.tangent(sub, n_steps, dQ, dV, dm, dm0)
+    lhs = (gQ0[idx] * dQ).sum((1, 2)) + (gV0[idx] * dV).sum((1, 2)) + (gm[idx] * dm).sum(1) + gm0[idx] * dm0
+    rhs = (gQ_T[idx] * tQ.astype(float)).sum((1, 2)) + (gV_T[idx] * tV.astype(float)).sum((1, 2))
+    scale = np.abs(gQ_T[idx] * tQ.astype(float)).sum((1, 2)) + np.abs(gV_T[idx] * tV.astype(float)).sum((1, 2))
+    rel = np.abs(lhs - rhs) / scale
+    print("dot-product relative mismatch (adjoint workload): max %.2e" % rel.max(), flush=True)
+    assert rel.max() < 1e-9
+
+
+def test_adjoint_workload_full_length_sampled():
+    """Full length of the adjoint workload (1e5 steps, checkpoints every
+    1000): 4 sampled systems against the oracle tangent."""
+    s = inputs.workload("adjoint8")
+    n_steps, every = 100000, 1000
+    rng = np.random.default_rng(11)
+    gQ_T = rng.normal(size=(s.S, 8, 3))
+    gV_T = np.zeros((s.S, 8, 3))
+    _, _, gQ0, gV0, gm, gm0 = adjoint_run(s, n_steps, every, gQ_T, gV_T)
+    idx = np.array([0, 311, 650, 1023])
+    sub = s.subset(idx)
+    dQ, dV, dm, dm0 = random_dirs(sub, 12)
+    _, _, tQ, tV = oracle.tangent(sub, n_steps, dQ, dV, dm, dm0)
+    lhs = (gQ0[idx] * dQ).sum((1, 2)) + (gV0[idx] * dV).sum((1, 2)) + (gm[idx] * dm).sum(1) + gm0[idx] * dm0
+    rhs = (gQ_T[idx] * tQ.astype(float)).sum((1, 2))
+    scale = np.abs(gQ_T[idx] * tQ.astype(float)).sum((1, 2))
+    rel = np.abs(lhs - rhs) / scale
+    print("dot-product relative mismatch (1e5 steps): %s" % np.array2string(rel, precision=2), flush=True)
+    assert rel.max() < 1e-6
