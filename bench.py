@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--cpu-systems", type=int, default=256)
     ap.add_argument("--plain-steps", type=int, default=2000, help="steps of the per-size reference path")
     ap.add_argument("--ckpt-every", type=int, default=1000, help="checkpoint interval of the adjoint workload")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (calibrates memory counters)")
     return ap.parse_args()
 
 
@@ -121,10 +123,22 @@ def main():
     scheme = "kdk" if args.workload == "single8" else "dkd"
     systems = inputs.workload(args.workload)
     dev = torch.device("cuda:0")
-    ens = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, packing=args.packing,
-                                block_waves=args.block_waves, chunk_steps=args.chunk, exchange=args.exchange,
-                                device=dev)
+    opts = dict(packing=args.packing, block_waves=args.block_waves, chunk_steps=args.chunk, exchange=args.exchange)
+    tune_table = None
+    if args.packing == "tuned":
+        from paper_2307_05683_amd.autotune import autotune
+        print("[bench] autotuning the lane packing ...", file=sys.stderr, flush=True)
+        best, tune_table = autotune(systems, gr_c=gr_c, scheme=scheme, device=dev)
+        opts.update(best)
+        print("[bench] chosen: %s" % best, file=sys.stderr, flush=True)
+    ens = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, device=dev, **opts)
     print("[bench] %s: S=%d, warmup %d steps" % (args.workload, systems.S, args.warmup), file=sys.stderr, flush=True)
+    if args.copy_probe_mb:
+        x = torch.ones(args.copy_probe_mb << 17, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     if args.warmup:
         ens.step(args.warmup)
     torch.cuda.synchronize()
@@ -143,7 +157,7 @@ def main():
     flags = ens.flags().cpu().numpy()
     sys_steps = systems.S * args.steps
     value = sys_steps / gpu_s
-    n_launch = -(-args.steps // args.chunk)
+    n_launch = -(-args.steps // opts["chunk_steps"])
     flops_step = flops_per_system_step(systems.n_planets, gr_c > 0)
     achieved = flops_step * args.steps / gpu_s / 1e12
     out = {
@@ -163,10 +177,10 @@ def main():
             "workload": "%s: %s" % (args.workload, WORKLOAD_TEXT[args.workload]),
             "systems": systems.S,
             "planets_total": int(systems.n_planets.sum()),
-            "packing": args.packing,
-            "chunk_steps": args.chunk,
-            "block_waves": args.block_waves,
-            "exchange": args.exchange,
+            "packing": opts["packing"],
+            "chunk_steps": opts["chunk_steps"],
+            "block_waves": opts["block_waves"],
+            "exchange": opts["exchange"],
             "flagged_systems": int((flags != 0).sum()),
         },
         "roofline": {
@@ -182,6 +196,8 @@ def main():
             "launches": n_launch,
         },
     }
+    if tune_table is not None:
+        out["config"]["autotune"] = [dict(r["opts"], rate=r["system_steps_per_s"]) for r in tune_table]
     if args.workload == "adjoint8":
         out["adjoint"] = adjoint_cost(systems, args, dev, stream, gpu_s)
     if args.workload == "uneven2to8" and args.plain_steps > 0:

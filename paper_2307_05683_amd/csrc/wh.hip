@@ -395,9 +395,10 @@ __global__ __launch_bounds__(256) void k_sync(SyncParams q) {
 // ---------------------------------------------------------------------------
 // Reverse mode (drift-kick-drift).  Checkpoints hold the double-double state
 // [12][ns] (Q, V, then their compensation); the segment tape holds, per step,
-// the rounded state entering the step and the step's Kepler anomaly,
-// [step][7][ns]; the adjoint state is [8][ns]: gQ, gV, gm, and the lane's
-// share of gm0.
+// the rounded state entering the step, the step's Kepler anomaly and the
+// velocity after the step's kick, [step][TAPE_ROWS][ns]; the adjoint state is
+// [8][ns]: gQ, gV, gm, and the lane's share of gm0.
+constexpr int TAPE_ROWS = 10;
 struct AdjParams {
   StepParams sp;
   const double* ck;    // checkpoint the segment starts from
@@ -482,13 +483,14 @@ __device__ void adj_segment_lane(const AdjParams& q, int slot, int lane) {
   DriftInc d;
   double tk = L.first ? h : dt;
   for (int s = 0; s < q.n_seg; ++s) {
-    double* row = q.tape + (size_t)s * 7 * ns + slot;
+    double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
     row[0] = L.qx; row[ns] = L.qy; row[2 * ns] = L.qz;
     row[3 * ns] = L.vx; row[4 * ns] = L.vy; row[5 * ns] = L.vz;
     row[6 * ns] = drift_inc(L, L.m0, tk, dg, d);
     tk = dt;
     work_after_drift(w, L, d);
     kick_block<G, GR, 1>(w, ex, L.m, inv_m0, kg, h, dt, h);
+    row[7 * ns] = w.vx; row[8 * ns] = w.vy; row[9 * ns] = w.vz;   // V after the kick
     commit(L, d, w);
   }
   // reverse sweep
@@ -497,10 +499,11 @@ __device__ void adj_segment_lane(const AdjParams& q, int slot, int lane) {
   const bool leader = (lane & (G - 1)) == 0;
   const double m = L.m, m0 = L.m0;
   for (int s = q.n_seg - 1; s >= 0; --s) {
-    const double* row = q.tape + (size_t)s * 7 * ns + slot;
+    const double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
     double q0x = row[0], q0y = row[ns], q0z = row[2 * ns];
     double v0x = row[3 * ns], v0y = row[4 * ns], v0z = row[5 * ns];
     double X = row[6 * ns];
+    double vkx = row[7 * ns], vky = row[8 * ns], vkz = row[9 * ns];
     double tau = (q.first_synced && s == 0) ? h : dt;
     KepFwd k;
     kepler_at_X(q0x, q0y, q0z, v0x, v0y, v0z, m0, tau, X, k);
@@ -511,10 +514,7 @@ __device__ void adj_segment_lane(const AdjParams& q, int slot, int lane) {
       group_momentum<G>(m, v1x, v1y, v1z, s1x, s1y, s1z);
       double kj = h * inv_m0;
       double q2x = q1x + kj * s1x, q2y = q1y + kj * s1y, q2z = q1z + kj * s1z;
-      double ax, ay, az, gx, gy, gz;
-      ex.accel(q2x, q2y, q2z, m, ax, ay, az);
-      gr_accel(q2x, q2y, q2z, kg, gx, gy, gz);
-      double v3x = v1x + dt * (ax + gx), v3y = v1y + dt * (ay + gy), v3z = v1z + dt * (az + gz);
+      double v3x = vkx, v3y = vky, v3z = vkz;   // V after the kick, from the tape
       double s3x, s3y, s3z;
       group_momentum<G>(m, v3x, v3y, v3z, s3x, s3y, s3z);
       jump_vjp<G>(a, m, v3x, v3y, v3z, kj, m0, s3x, s3y, s3z, leader);
@@ -524,9 +524,7 @@ __device__ void adj_segment_lane(const AdjParams& q, int slot, int lane) {
       a.m0 += gmu;
       jump_vjp<G>(a, m, v1x, v1y, v1z, kj, m0, s1x, s1y, s1z, leader);
     } else {
-      double ax, ay, az;
-      ex.accel(q1x, q1y, q1z, m, ax, ay, az);
-      double v2x = v1x + dt * ax, v2y = v1y + dt * ay, v2z = v1z + dt * az;
+      double v2x = vkx, v2y = vky, v2z = vkz;   // V after the kick, from the tape
       double s2x, s2y, s2z;
       group_momentum<G>(m, v2x, v2y, v2z, s2x, s2y, s2z);
       jump_vjp<G>(a, m, v2x, v2y, v2z, dt * inv_m0, m0, s2x, s2y, s2z, leader);
@@ -879,7 +877,7 @@ wh_status ensure_graph(wh_ctx* c) {
 struct TapeLayout {
   int64_t n_seg = 0;       // segments
   size_t ck = 0;           // checkpoints: (n_seg + 1) x [12][ns]
-  size_t seg = 0;          // segment tape: ckpt_every x [7][ns]
+  size_t seg = 0;          // segment tape: ckpt_every x [TAPE_ROWS][ns]
   size_t grad = 0;         // adjoint state: [8][ns]
   size_t total = 0;
 };
@@ -889,7 +887,7 @@ TapeLayout tape_layout(int ns, int64_t n_steps, int64_t every) {
   T.n_seg = (n_steps + every - 1) / every;
   size_t o = 0;
   T.ck = o; o = align256(o + sizeof(double) * 12 * (size_t)ns * (size_t)(T.n_seg + 1));
-  T.seg = o; o = align256(o + sizeof(double) * 7 * (size_t)ns * (size_t)every);
+  T.seg = o; o = align256(o + sizeof(double) * TAPE_ROWS * (size_t)ns * (size_t)every);
   T.grad = o; o = align256(o + sizeof(double) * 8 * (size_t)ns);
   T.total = o;
   return T;
