@@ -99,83 +99,64 @@ __device__ __forceinline__ void store_lane(const StepParams& p, int slot, const 
   st[12 * ns + slot] = L.cvz;
 }
 
-// Working copy of one step: the current rounded position and velocity used
-// by the operators, and the small increments of the kicks and jumps of the
-// step, which are added to the low-order part of the state at the end.
-struct Work {
-  double qx, qy, qz, vx, vy, vz;
-  double sqx, sqy, sqz, svx, svy, svz;
-};
-
-__device__ __forceinline__ void work_begin(Work& w, const Lane& L) {
-  w.qx = L.qx; w.qy = L.qy; w.qz = L.qz;
-  w.vx = L.vx; w.vy = L.vy; w.vz = L.vz;
-  w.sqx = w.sqy = w.sqz = 0.0;
-  w.svx = w.svy = w.svz = 0.0;
+// The state of a coordinate is the unevaluated sum s + c (rounded value and
+// compensation).  Operators read the rounded values.  A Kepler drift adds
+// its increment to s by an exact two-sum and sends the two-sum's error, the
+// increment's own low part and the image of c under the drift to c; kicks and
+// jumps add their (small) increments to c; one renormalization per step
+// moves c back to at most half an ulp of s.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  double bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
 }
-__device__ __forceinline__ void work_dq(Work& w, double x, double y, double z) {
-  w.qx += x; w.qy += y; w.qz += z;
-  w.sqx += x; w.sqy += y; w.sqz += z;
+__device__ __forceinline__ void renorm(double& s, double& c) {
+#pragma clang fp contract(off)
+  double t = s + c;
+  c = c - (t - s);
+  s = t;
 }
-__device__ __forceinline__ void work_dv(Work& w, double x, double y, double z) {
-  w.vx += x; w.vy += y; w.vz += z;
-  w.svx += x; w.svy += y; w.svz += z;
+__device__ __forceinline__ void add_hi(double& s, double& c, double h, double l) {
+#pragma clang fp contract(off)
+  double t, e;
+  two_sum(s, h, t, e);
+  s = t;
+  c = (c + l) + e;
 }
 
-// Kepler drift K(tau) of the lane's compensated state (Q + cQ, V + cV).
-// The coefficients come from the rounded state; the increment is formed in
-// double-double (product and sum errors kept), the low-order parts are
-// carried through the same linear map, (cQ, cV) -> (f-1, g; f', g'-1)(cQ, cV),
-// and the extra terms ex (small increments of the same step) join the low
-// part.  Returns the increments' high parts in dq/dv for the working copy.
-struct DriftInc {
-  double qx, qy, qz, vx, vy, vz;      // high parts
-  double lqx, lqy, lqz, lvx, lvy, lvz;  // low parts
-};
-
-__device__ __forceinline__ double drift_inc(const Lane& L, double mu, double tau, KepDiag& dg, DriftInc& d) {
+// Kepler drift K(tau) of the compensated state.  The coefficients come from
+// the rounded values; the increment (f-1)Q + gV, f'Q + (g'-1)V is formed in
+// double-double (lin2_dd) and c is carried through the same linear map.
+// Returns the anomaly X.
+__device__ __forceinline__ double drift(Lane& L, double mu, double tau, KepDiag& dg) {
   KepCoef k;
   double X = kepler_coeffs<KEP_NH, KEP_NN, KEP_KH, KEP_KN>(L.qx, L.qy, L.qz, L.vx, L.vy, L.vz, mu, tau, dg, k);
-  lin2_dd(k.fm1, L.qx, k.g, L.vx, d.qx, d.lqx);
-  lin2_dd(k.fm1, L.qy, k.g, L.vy, d.qy, d.lqy);
-  lin2_dd(k.fm1, L.qz, k.g, L.vz, d.qz, d.lqz);
-  lin2_dd(k.gdm1, L.vx, k.fd, L.qx, d.vx, d.lvx);
-  lin2_dd(k.gdm1, L.vy, k.fd, L.qy, d.vy, d.lvy);
-  lin2_dd(k.gdm1, L.vz, k.fd, L.qz, d.vz, d.lvz);
-  d.lqx += fma(k.fm1, L.cqx, k.g * L.cvx);
-  d.lqy += fma(k.fm1, L.cqy, k.g * L.cvy);
-  d.lqz += fma(k.fm1, L.cqz, k.g * L.cvz);
-  d.lvx += fma(k.fd, L.cqx, k.gdm1 * L.cvx);
-  d.lvy += fma(k.fd, L.cqy, k.gdm1 * L.cvy);
-  d.lvz += fma(k.fd, L.cqz, k.gdm1 * L.cvz);
+  double hqx, hqy, hqz, hvx, hvy, hvz, lqx, lqy, lqz, lvx, lvy, lvz;
+  lin2_dd(k.fm1, L.qx, k.g, L.vx, hqx, lqx);
+  lin2_dd(k.fm1, L.qy, k.g, L.vy, hqy, lqy);
+  lin2_dd(k.fm1, L.qz, k.g, L.vz, hqz, lqz);
+  lin2_dd(k.gdm1, L.vx, k.fd, L.qx, hvx, lvx);
+  lin2_dd(k.gdm1, L.vy, k.fd, L.qy, hvy, lvy);
+  lin2_dd(k.gdm1, L.vz, k.fd, L.qz, hvz, lvz);
+  lqx += fma(k.fm1, L.cqx, k.g * L.cvx);
+  lqy += fma(k.fm1, L.cqy, k.g * L.cvy);
+  lqz += fma(k.fm1, L.cqz, k.g * L.cvz);
+  lvx += fma(k.fd, L.cqx, k.gdm1 * L.cvx);
+  lvy += fma(k.fd, L.cqy, k.gdm1 * L.cvy);
+  lvz += fma(k.fd, L.cqz, k.gdm1 * L.cvz);
+  add_hi(L.qx, L.cqx, hqx, lqx);
+  add_hi(L.qy, L.cqy, hqy, lqy);
+  add_hi(L.qz, L.cqz, hqz, lqz);
+  add_hi(L.vx, L.cvx, hvx, lvx);
+  add_hi(L.vy, L.cvy, hvy, lvy);
+  add_hi(L.vz, L.cvz, hvz, lvz);
   return X;
 }
 
-// State += drift increment + the step's small increments.
-__device__ __forceinline__ void commit(Lane& L, const DriftInc& d, const Work& w) {
-  dd_add(L.qx, L.cqx, d.qx, d.lqx + w.sqx);
-  dd_add(L.qy, L.cqy, d.qy, d.lqy + w.sqy);
-  dd_add(L.qz, L.cqz, d.qz, d.lqz + w.sqz);
-  dd_add(L.vx, L.cvx, d.vx, d.lvx + w.svx);
-  dd_add(L.vy, L.cvy, d.vy, d.lvy + w.svy);
-  dd_add(L.vz, L.cvz, d.vz, d.lvz + w.svz);
-}
-// State += the small increments only.
-__device__ __forceinline__ void commit_small(Lane& L, const Work& w) {
-  dd_add(L.qx, L.cqx, w.sqx, 0.0);
-  dd_add(L.qy, L.cqy, w.sqy, 0.0);
-  dd_add(L.qz, L.cqz, w.sqz, 0.0);
-  dd_add(L.vx, L.cvx, w.svx, 0.0);
-  dd_add(L.vy, L.cvy, w.svy, 0.0);
-  dd_add(L.vz, L.cvz, w.svz, 0.0);
-}
-
-// Working copy after a drift: rounded state + high part of the increment.
-__device__ __forceinline__ void work_after_drift(Work& w, const Lane& L, const DriftInc& d) {
-  w.qx = L.qx + d.qx; w.qy = L.qy + d.qy; w.qz = L.qz + d.qz;
-  w.vx = L.vx + d.vx; w.vy = L.vy + d.vy; w.vz = L.vz + d.vz;
-  w.sqx = w.sqy = w.sqz = 0.0;
-  w.svx = w.svy = w.svz = 0.0;
+__device__ __forceinline__ void renorm_all(Lane& L) {
+  renorm(L.qx, L.cqx); renorm(L.qy, L.cqy); renorm(L.qz, L.cqz);
+  renorm(L.vx, L.cvx); renorm(L.vy, L.cvy); renorm(L.vz, L.cvz);
 }
 
 // Partner exchange of the interaction kick: EXCH 0 = rotation rounds over the
@@ -198,40 +179,35 @@ template <int G> struct Exch<G, 1> {
   }
 };
 
-// Jump J(tau): kj = tau / m0.
-template <int G> __device__ __forceinline__ void jump(Work& w, double m, double kj) {
-  double sx, sy, sz;
-  group_momentum<G>(m, w.vx, w.vy, w.vz, sx, sy, sz);
-  work_dq(w, kj * sx, kj * sy, kj * sz);
-}
-
-// Interaction kick I(tau), plus the GR kick when GR is on (both depend on
-// the positions only, so they share one velocity update).
+// Kick block of the loop on the compensated state.  With GR:
+// J(ta) [I + GR](ti) J(tc); without GR the jumps commute with I and merge:
+// I(ti) J(ta + tc).  Increments go to the low parts; the state is
+// renormalized at the end.  (vkx, vky, vkz) receive the velocity after the
+// kick (kept by the adjoint).  kj = tau/m0 for the jumps (Sec. 3.4).
 template <int G, bool GR, int EXCH>
-__device__ __forceinline__ void kick(Work& w, const Exch<G, EXCH>& ex, double m, double kg, double tau) {
-  double ax, ay, az;
-  ex.accel(w.qx, w.qy, w.qz, m, ax, ay, az);
+__device__ __forceinline__ void kick_block(Lane& L, const Exch<G, EXCH>& ex, double inv_m0, double kg, double ta,
+                                           double ti, double tc, double& vkx, double& vky, double& vkz) {
+  double ax, ay, az, sx, sy, sz;
   if (GR) {
+    group_momentum<G>(L.m, L.vx, L.vy, L.vz, sx, sy, sz);
+    double k1 = ta * inv_m0;
+    double dqx = k1 * sx, dqy = k1 * sy, dqz = k1 * sz;
+    L.cqx += dqx; L.cqy += dqy; L.cqz += dqz;
+    double qx = L.qx + dqx, qy = L.qy + dqy, qz = L.qz + dqz;
+    ex.accel(qx, qy, qz, L.m, ax, ay, az);
     double gx, gy, gz;
-    gr_accel(w.qx, w.qy, w.qz, kg, gx, gy, gz);
+    gr_accel(qx, qy, qz, kg, gx, gy, gz);
     ax += gx; ay += gy; az += gz;
-  }
-  work_dv(w, tau * ax, tau * ay, tau * az);
-}
-
-// Combined kick block of the loop.  With GR: J(ta) [I + GR](ti) J(tc).
-// Without GR the jumps commute with I and merge: I(ti) J(ta + tc).
-template <int G, bool GR, int EXCH>
-__device__ __forceinline__ void kick_block(Work& w, const Exch<G, EXCH>& ex, double m, double inv_m0, double kg,
-                                           double ta, double ti, double tc) {
-  if (GR) {
-    jump<G>(w, m, ta * inv_m0);
-    kick<G, GR, EXCH>(w, ex, m, kg, ti);
-    jump<G>(w, m, tc * inv_m0);
   } else {
-    kick<G, GR, EXCH>(w, ex, m, kg, ti);
-    jump<G>(w, m, (ta + tc) * inv_m0);
+    ex.accel(L.qx, L.qy, L.qz, L.m, ax, ay, az);
   }
+  double dvx = ti * ax, dvy = ti * ay, dvz = ti * az;
+  L.cvx += dvx; L.cvy += dvy; L.cvz += dvz;
+  vkx = L.vx + dvx; vky = L.vy + dvy; vkz = L.vz + dvz;
+  group_momentum<G>(L.m, vkx, vky, vkz, sx, sy, sz);
+  double k2 = (GR ? tc : ta + tc) * inv_m0;
+  L.cqx += k2 * sx; L.cqy += k2 * sy; L.cqz += k2 * sz;
+  renorm_all(L);
 }
 
 // n_steps steps for one lane.  The stored state X_u is "after a kick block,
@@ -241,7 +217,7 @@ __device__ __forceinline__ void kick_block(Work& w, const Exch<G, EXCH>& ex, dou
 //   KDK loop body: J(ta) I(ti) J(h) . K(dt)       (ta, ti) = (0, h) first,
 //                                                 (h, dt) afterwards
 // (operators in the order they act).  The state is kept as a double-double
-// (rounded value + compensation); see drift_inc and commit.
+// (rounded value + compensation); see drift and kick_block.
 template <int G, bool GR, int SCHEME, int EXCH>
 __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane) {
   Exch<G, EXCH> ex;
@@ -251,29 +227,22 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
   const double inv_m0 = 1.0 / L.m0;
   const double kg = GR ? p.kgr * L.m0 * L.m0 : 0.0;
   KepDiag dg{0.0, 1.0e300};
-  Work w;
-  DriftInc d;
+  double vkx, vky, vkz;
   if (SCHEME == WH_DKD) {
     double tk = L.first ? h : dt;
     for (int s = 0; s < p.n_steps; ++s) {
-      drift_inc(L, L.m0, tk, dg, d);
+      drift(L, L.m0, tk, dg);
       tk = dt;
-      work_after_drift(w, L, d);
-      kick_block<G, GR, EXCH>(w, ex, L.m, inv_m0, kg, h, dt, h);
-      commit(L, d, w);
+      kick_block<G, GR, EXCH>(L, ex, inv_m0, kg, h, dt, h, vkx, vky, vkz);
     }
   } else {
     double ta = L.first ? 0.0 : h;
     double ti = L.first ? h : dt;
     for (int s = 0; s < p.n_steps; ++s) {
-      work_begin(w, L);
-      kick_block<G, GR, EXCH>(w, ex, L.m, inv_m0, kg, ta, ti, h);
+      kick_block<G, GR, EXCH>(L, ex, inv_m0, kg, ta, ti, h, vkx, vky, vkz);
       ta = h;
       ti = dt;
-      commit_small(L, w);
-      drift_inc(L, L.m0, dt, dg, d);
-      work_begin(w, L);
-      commit(L, d, w);
+      drift(L, L.m0, dt, dg);
     }
   }
   int f = 0;
@@ -298,6 +267,8 @@ __device__ void step_group(const StepParams& p, int slot, int lane) {
   store_lane(p, slot, L);
 }
 
+// At most 128 VGPRs (4 wavefronts per SIMD): large ensembles then run in
+// whole rounds of resident waves.
 template <bool GR, int SCHEME, int EXCH>
 __global__ __launch_bounds__(256) void k_step(StepParams p) {
   const int lane = threadIdx.x & 63;
@@ -324,20 +295,14 @@ struct SyncParams {
 template <int G, bool GR, int SCHEME> __device__ void sync_lane(const StepParams& p, Lane& L, int lane) {
   if (!L.first) {   // uniform over the group: one system, one flag
     const double h = 0.5 * L.dt;
-    Work w;
     if (SCHEME == WH_DKD) {
       KepDiag dg{0.0, 1.0e300};
-      DriftInc d;
-      drift_inc(L, L.m0, h, dg, d);
-      work_begin(w, L);
-      commit(L, d, w);
+      drift(L, L.m0, h, dg);
     } else {
       Exch<G, 0> ex;
       ex.init(lane, L.m);
-      work_begin(w, L);
-      jump<G>(w, L.m, h / L.m0);
-      kick<G, GR, 0>(w, ex, L.m, GR ? p.kgr * L.m0 * L.m0 : 0.0, h);
-      commit_small(L, w);
+      double vkx, vky, vkz;
+      kick_block<G, GR, 0>(L, ex, 1.0 / L.m0, GR ? p.kgr * L.m0 * L.m0 : 0.0, h, h, 0.0, vkx, vky, vkz);
     }
   }
   L.qx += L.cqx; L.qy += L.cqy; L.qz += L.cqz;
@@ -479,19 +444,16 @@ __device__ void adj_segment_lane(const AdjParams& q, int slot, int lane) {
   const double inv_m0 = 1.0 / L.m0;
   const double kg = GR ? p.kgr * L.m0 * L.m0 : 0.0;
   KepDiag dg{0.0, 1.0e300};
-  Work w;
-  DriftInc d;
   double tk = L.first ? h : dt;
   for (int s = 0; s < q.n_seg; ++s) {
     double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
     row[0] = L.qx; row[ns] = L.qy; row[2 * ns] = L.qz;
     row[3 * ns] = L.vx; row[4 * ns] = L.vy; row[5 * ns] = L.vz;
-    row[6 * ns] = drift_inc(L, L.m0, tk, dg, d);
+    row[6 * ns] = drift(L, L.m0, tk, dg);
     tk = dt;
-    work_after_drift(w, L, d);
-    kick_block<G, GR, 1>(w, ex, L.m, inv_m0, kg, h, dt, h);
-    row[7 * ns] = w.vx; row[8 * ns] = w.vy; row[9 * ns] = w.vz;   // V after the kick
-    commit(L, d, w);
+    double vkx, vky, vkz;
+    kick_block<G, GR, 1>(L, ex, inv_m0, kg, h, dt, h, vkx, vky, vkz);
+    row[7 * ns] = vkx; row[8 * ns] = vky; row[9 * ns] = vkz;   // V after the kick
   }
   // reverse sweep
   Grad a;
