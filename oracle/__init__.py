@@ -37,6 +37,7 @@ def lib():
             "or_max_threads": ([], i),
             "or_set_series_recur": ([i], None),
             "or_set_guess": ([i], None),
+            "or_set_gd_form": ([i], None),
             "or_kepler_ld": ([i, _PLD, _PLD, _PLD, _PLD, _PLD], None),
             "or_kepler_fixed_ld": ([i, _PLD, _PLD, _PLD, _PLD, i, i, i, i], None),
             "or_kepler_fixed_d": ([i, _PD, _PD, _PD, _PD, i, i, i, i], None),
@@ -81,15 +82,18 @@ def kepler(Q, V, mu, tau, return_X=False):
     return (Q, V, X) if return_X else (Q, V)
 
 
-def kepler_fixed(Q, V, mu, tau, n_halley=2, n_newton=2, terms_halley=4, terms_newton=8, precision="ld", recur=0, guess=0):
+def kepler_fixed(Q, V, mu, tau, n_halley=2, n_newton=2, terms_halley=4, terms_newton=8, precision="ld", recur=0, guess=0,
+                 gd_form="direct"):
     """Fixed-iteration Kepler solve (App. A sweep mode).
 
     recur selects the series arrangement: `terms` terms are summed for
     c_{2+2r}, c_{3+2r} and r downward recurrences give c2, c3.
+    gd_form: "direct" g' = 1 - mu G2 / r, or "wronskian" g' = (1 + f' g) / f.
     """
     n = np.asarray(Q).shape[0]
     lib().or_set_series_recur(int(recur))
     lib().or_set_guess(int(guess))
+    lib().or_set_gd_form({"direct": 0, "wronskian": 1}[gd_form])
     if precision == "ld":
         Q = _ld(Q).copy(); V = _ld(V).copy()
         lib().or_kepler_fixed_ld(n, Q, V, _ld(np.broadcast_to(mu, (n,))), _ld(np.broadcast_to(tau, (n,))),
@@ -167,6 +171,9 @@ def tangent(sysm, n_steps, dQ, dV, dm, dm0, scheme="dkd", gr_c=0.0, nthreads=0):
 def count_ops(n_planets=8, gr=False, n_halley=2, n_newton=2, terms_halley=4, terms_newton=8):
     """Operation count of one step of the method: dict add/mul/div/sqrt/flops."""
     c = np.zeros(4, dtype=np.int64)
+    lib().or_set_series_recur(0)
+    lib().or_set_guess(0)
+    lib().or_set_gd_form(0)
     lib().or_count_ops(n_planets, int(gr), n_halley, n_newton, terms_halley, terms_newton, c)
     d = dict(add=int(c[0]), mul=int(c[1]), div=int(c[2]), sqrt=int(c[3]))
     d["flops"] = d["add"] + d["mul"] + d["div"] + d["sqrt"]
@@ -183,3 +190,27 @@ def gbs(sysm, t_total, n_macro, Q=None, V=None):
 
 def max_threads() -> int:
     return int(lib().or_max_threads())
+
+
+def elements(sysm, Q=None, V=None):
+    """Osculating heliocentric semi-major axis and eccentricity, [S, 8] each.
+
+    Two-body problem of the star and planet i: mu = G (m0 + m_i), position
+    Q_i, velocity u_i = V_i + sum_j m_j V_j / m0 (heliocentric velocity from
+    the barycentric one, Sec. 3.1: the star moves with -sum_j m_j V_j / m0);
+    a = 1 / (2/r - u^2/mu), e = |u x (Q x u) / mu - Q / r|.  Slots beyond
+    n_planets are NaN.
+    """
+    Q = _ld(sysm.Q if Q is None else Q); V = _ld(sysm.V if V is None else V)
+    m = _ld(sysm.m); m0 = _ld(sysm.m0)
+    live = np.arange(8)[None, :] < np.asarray(sysm.n_planets)[:, None]
+    P = (np.where(live, m, 0)[..., None] * V).sum(axis=1)             # [S, 3]
+    u = V + (P / m0[:, None])[:, None, :]
+    mu = m0[:, None] + m
+    with np.errstate(divide="ignore", invalid="ignore"):      # empty slots have r = 0
+        r = np.sqrt((Q * Q).sum(-1))
+        a = 1 / (2 / r - (u * u).sum(-1) / mu)
+        h = np.cross(Q, u)
+        evec = np.cross(u, h) / mu[..., None] - Q / r[..., None]
+        e = np.sqrt((evec * evec).sum(-1))
+    return np.where(live, a, np.nan), np.where(live, e, np.nan)

@@ -250,6 +250,11 @@ template <class T> void stumpff_trunc(const T& z, int terms, int recur, T c[4]) 
 
 int g_recur = 0;   // series arrangement of the fixed-iteration solver
 int g_guess = 0;   // initial guess of the fixed-iteration solver
+// Form of g' in the fixed-iteration solver: 0 = its definition 1 - mu G2 / r;
+// 1 = from the Wronskian identity f g' - f' g = 1 of the Lagrange
+// coefficients, g' = (1 + f' g) / f.  Both equal the exact g' once the solve
+// has converged; they differ where it has not (the envelope of Fig. 1).
+int g_gd_form = 0;
 
 template <class T> void kep_trunc_eval(const KepEq<T>& e, const T& X, int terms, T& F, T& dF, T& ddF, T G[4],
                                        bool need_dd) {
@@ -305,7 +310,7 @@ template <class T> void kepler_fixed(T Q[3], T V[3], const T& mu, const T& tau,
   T g = tau - mu * G[3];
   T ir = T(R(1)) / r;
   T fd = -mu * G[1] * ir0 * ir;
-  T gd = T(R(1)) - mu * G[2] * ir;
+  T gd = g_gd_form == 0 ? T(R(1)) - mu * G[2] * ir : T(R(1)) + (fd * g - (f - T(R(1)))) / f;
   T Qn[3], Vn[3];
   for (int a = 0; a < 3; ++a) {
     Qn[a] = f * Q[a] + g * V[a];
@@ -480,6 +485,8 @@ int or_max_threads() { return omp_get_max_threads(); }
 void or_set_series_recur(int r) { g_recur = r; }
 // Initial guess of the fixed-iteration solver: 0 second order, 1 first order.
 void or_set_guess(int g) { g_guess = g; }
+
+void or_set_gd_form(int g) { g_gd_form = g; }
 
 // Exact Kepler drift of n independent particles, in place.
 void or_kepler_ld(int n, ld* Q, ld* V, const ld* mu, const ld* tau, ld* X) {

@@ -218,3 +218,42 @@ def test_fixed_solver_agrees_with_exact_inside_envelope():
     rq = np.linalg.norm((Qf - Qe).astype(float), axis=1) / np.linalg.norm(Qe.astype(float), axis=1)
     rv = np.linalg.norm((Vf - Ve).astype(float), axis=1) / np.linalg.norm(Ve.astype(float), axis=1)
     assert rq.max() < 1e-17 and rv.max() < 1e-17
+
+
+def test_wronskian_form_equals_direct_where_converged():
+    """g' from the Wronskian identity equals its definition once the solve
+    has converged (both are identities of the exact Lagrange coefficients)."""
+    rng = np.random.default_rng(8)
+    n = 128
+    a = rng.uniform(0.4, 30, n)
+    e = rng.uniform(0, 0.3, n)
+    pos, vel = elements_to_cartesian(1.0, a, e, rng.uniform(0, 0.5, n), rng.uniform(0, 6.28, n),
+                                     rng.uniform(0, 6.28, n), rng.uniform(0, 6.28, n))
+    dt = 2 * np.pi * np.sqrt(a ** 3) / 40
+    Qw, Vw = oracle.kepler_fixed(pos, vel, 1.0, dt, gd_form="wronskian")
+    Qe, Ve = oracle.kepler(pos, vel, 1.0, dt)
+    rv = np.linalg.norm((Vw - Ve).astype(float), axis=1) / np.linalg.norm(Ve.astype(float), axis=1)
+    rq = np.linalg.norm((Qw - Qe).astype(float), axis=1) / np.linalg.norm(Qe.astype(float), axis=1)
+    assert rq.max() < 1e-17 and rv.max() < 1e-17
+
+
+def test_wronskian_form_conserves_angular_momentum_outside_envelope():
+    """Q' x V' = (f g' - f' g) Q x V: with g' from the Wronskian identity the
+    drift keeps the specific angular momentum to rounding even where the
+    fixed solve has not converged (while the orbit stays bounded); with the
+    direct g' it does not."""
+    dt = 2 * np.pi * 5 / 365.25
+    a, e = 0.1, 0.3                         # about one step per pericentre timescale
+    pos, vel = elements_to_cartesian(1.0, np.full(8, a), np.full(8, e), np.full(8, 0.3), np.zeros(8),
+                                     np.zeros(8), np.linspace(0, 6, 8))
+    L0 = np.cross(pos, vel)
+    for form, expect_kept in (("wronskian", True), ("direct", False)):
+        Q, V = pos, vel
+        for _ in range(20):
+            Q, V = oracle.kepler_fixed(Q, V, 1.0, dt, gd_form=form)
+        Qe, Ve = pos, vel
+        for _ in range(20):
+            Qe, Ve = oracle.kepler(Qe, Ve, 1.0, dt)
+        assert np.abs((Q - Qe).astype(float)).max() > 1e-6        # not converged
+        dL = np.abs(np.cross(Q.astype(float), V.astype(float)) - L0).max() / np.abs(L0).max()
+        assert (dL < 1e-13) == expect_kept, (form, dL)

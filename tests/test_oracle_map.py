@@ -224,3 +224,45 @@ def test_operation_count_structure():
     pair_flops = ((c8["flops"] - c6["flops"]) - (c4["flops"] - c2["flops"])) / 8.0
     assert 15 < pair_flops < 40
     assert oracle.count_ops(8, gr=True)["flops"] > c8["flops"]
+
+
+def test_osculating_elements_recover_drawn_elements():
+    """The oracle's osculating (a, e) invert the generator's element-to-
+    Cartesian conversion (an independent construction: Kepler's equation
+    and rotations, then V = u - sum_j m_j u_j / M_tot)."""
+    rng = np.random.default_rng(3)
+    S, n = 6, 5
+    m = np.zeros((S, 8)); m[:, :n] = 10 ** rng.uniform(-7, -3, (S, n))
+    a = rng.uniform(0.3, 20, (S, n)); e = rng.uniform(0, 0.9, (S, n))
+    inc = rng.uniform(0, 1.0, (S, n)); ang = rng.uniform(0, 2 * np.pi, (3, S, n))
+    mu = 1.0 + m[:, :n]
+    pos, vel = inputs.elements_to_cartesian(mu, a, e, inc, ang[0], ang[1], ang[2])
+    Q = np.zeros((S, 8, 3)); U = np.zeros((S, 8, 3))
+    Q[:, :n] = pos; U[:, :n] = vel
+    Mtot = 1.0 + m.sum(1)
+    V = U - ((m[..., None] * U).sum(1) / Mtot[:, None])[:, None, :]
+    sysm = inputs.Systems(np.full(S, n, dtype=np.int32), np.ones(S), m, Q, V, np.full(S, 0.01))
+    ao, eo = oracle.elements(sysm)
+    assert np.allclose(ao[:, :n].astype(float), a, rtol=1e-12, atol=0)
+    assert np.allclose(eo[:, :n].astype(float), e, rtol=0, atol=1e-12)
+    assert np.all(np.isnan(ao[:, n:].astype(float)))
+
+
+def test_osculating_elements_closed_forms():
+    """Circular orbit: a = r, e = 0; at pericentre with speed
+    sqrt(mu (1 + e) / (a (1 - e))): the given a and e."""
+    m = np.zeros((1, 8)); m[0, :2] = [1e-9, 1e-9]
+    Q = np.zeros((1, 8, 3)); V = np.zeros((1, 8, 3))
+    a1, e1 = 2.0, 0.0
+    a2, e2 = 3.0, 0.4
+    mu1, mu2 = 1 + 1e-9, 1 + 1e-9
+    Q[0, 0] = [a1, 0, 0]; V[0, 0] = [0, np.sqrt(mu1 / a1), 0]
+    rp = a2 * (1 - e2)
+    Q[0, 1] = [0, 0, rp]; V[0, 1] = [np.sqrt(mu2 * (1 + e2) / rp), 0, 0]
+    # barycentric velocities of these heliocentric ones (star mass 1)
+    U = V.copy()
+    V = U - ((m[..., None] * U).sum(1) / (1 + m.sum()))[:, None, :]
+    sysm = inputs.Systems(np.array([2], dtype=np.int32), np.ones(1), m, Q, V, np.ones(1))
+    ao, eo = oracle.elements(sysm)
+    assert abs(float(ao[0, 0]) - a1) < 1e-14 and float(eo[0, 0]) < 1e-14
+    assert abs(float(ao[0, 1]) - a2) < 1e-14 and abs(float(eo[0, 1]) - e2) < 1e-14
