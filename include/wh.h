@@ -135,6 +135,14 @@ wh_status wh_get_state(wh_ctx* ctx, double* Q_out, double* V_out, hipStream_t st
  * (the Hamiltonian of Sec. 3.1 without the constant barycentre term). */
 wh_status wh_energy(wh_ctx* ctx, double* E_out, hipStream_t stream);
 
+/* Osculating heliocentric semi-major axis and eccentricity of every planet
+ * of the synchronized copy (a_out, e_out: device [S*8]), for the two-body
+ * problem of star and planet (mu = G (m0 + m_i)) with the heliocentric
+ * velocity u_i = V_i + sum_j m_j V_j / m0.  The paper's Sec. 5 declares a
+ * Solar-System run unstable once Mercury's eccentricity exceeds 0.65.
+ * a < 0 marks an unbound orbit. */
+wh_status wh_elements(wh_ctx* ctx, double* a_out, double* e_out, hipStream_t stream);
+
 /* Copy the sticky WH_F_* bits (flags_out: device uint32 [S]). */
 wh_status wh_status_flags(wh_ctx* ctx, uint32_t* flags_out, hipStream_t stream);
 
@@ -156,6 +164,28 @@ wh_status wh_forward_ckpt(wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every, void
                           hipStream_t stream);
 wh_status wh_adjoint_n(wh_ctx* ctx, void* tape, size_t tape_bytes, const double* gQ_T, const double* gV_T,
                        double* gQ_0, double* gV_0, double* gm, double* gm0, hipStream_t stream);
+
+/* ---- Kepler-solver envelope (Sec. 3.2, Fig. 1; App. A) ------------------
+ * Advances n massless test particles, each about its own star (mu[i] = G m0)
+ * with its own step tau[i] > 0, through n_steps Kepler drifts of the fixed
+ * solver with n_halley Halley steps (terms_halley series terms) then
+ * n_newton Newton steps (terms_newton terms), and writes the relative change
+ * of the osculating semi-major axis, a_err[i] = (a_end - a_0) / a_0 with
+ * a = 1 / (2/|Q| - |V|^2/mu) (zero for the exact flow; NaN where the solve
+ * broke down).  The integrator's own solver is n_halley = 2, n_newton = 2,
+ * terms 4 and 8.  With n_newton = 0 the series are evaluated once more at
+ * the last Halley iterate.
+ *   Q, V: device [n*3] initial positions / velocities, Q[i*3 + c];
+ *   mu, tau: device [n];  a_err: device [n] (required);
+ *   Q_out, V_out: device [n*3] final state, both or neither (may alias Q, V);
+ *   zmax_out: device [n] or null, largest Stumpff argument beta X^2 of a
+ *   final evaluation (the series assume it small).
+ * Limits: 0 <= n_halley, n_newton <= 8, n_halley + n_newton >= 1, series
+ * lengths 1..14; otherwise WH_EINVAL.  n = 0 enqueues nothing. */
+wh_status wh_kepler_envelope(int64_t n, const double* Q, const double* V, const double* mu, const double* tau,
+                             int64_t n_steps, int32_t n_halley, int32_t n_newton, int32_t terms_halley,
+                             int32_t terms_newton, double* Q_out, double* V_out, double* a_err, double* zmax_out,
+                             hipStream_t stream);
 
 /* Message of the calling thread's last failed call ("" if none). */
 const char* wh_last_error(void);

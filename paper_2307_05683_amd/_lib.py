@@ -54,10 +54,12 @@ _SIGS = {
     "wh_get_state": ([vp, vp, vp, vp], i32),
     "wh_energy": ([vp, vp, vp], i32),
     "wh_status_flags": ([vp, vp, vp], i32),
+    "wh_elements": ([vp, vp, vp, vp], i32),
     "wh_steps_done": ([vp], i64),
     "wh_tape_bytes": ([vp, i64, i64], sz),
     "wh_forward_ckpt": ([vp, i64, i64, vp, sz, vp], i32),
     "wh_adjoint_n": ([vp, vp, sz, vp, vp, vp, vp, vp, vp, vp], i32),
+    "wh_kepler_envelope": ([i64, vp, vp, vp, vp, i64, i32, i32, i32, i32, vp, vp, vp, vp, vp], i32),
     "wh_last_error": ([], C.c_char_p),
     "wh_destroy": ([vp], None),
 }

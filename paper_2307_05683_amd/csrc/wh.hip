@@ -290,6 +290,8 @@ struct SyncParams {
   double* Q_out;    // [S*8*3] or null
   double* V_out;
   double* E_out;    // [S] or null
+  double* a_out;    // [S*8] or null
+  double* e_out;
 };
 
 template <int G, bool GR, int SCHEME> __device__ void sync_lane(const StepParams& p, Lane& L, int lane) {
@@ -341,6 +343,25 @@ template <int G, bool GR, int SCHEME> __device__ void sync_group(const SyncParam
   if (q.E_out) {
     double E = group_energy<G, GR>(p, L, lane);
     if ((lane & (G - 1)) == 0 && L.sys >= 0) q.E_out[L.sys] = E;
+  }
+  if (q.a_out) {
+    // heliocentric velocity u = V + sum_j m_j V_j / m0, two-body elements
+    double sx, sy, sz;
+    group_momentum<G>(L.m, L.vx, L.vy, L.vz, sx, sy, sz);
+    double ux = L.vx + sx / L.m0, uy = L.vy + sy / L.m0, uz = L.vz + sz / L.m0;
+    double mu = L.m0 + L.m;
+    double r = sqrt(L.qx * L.qx + L.qy * L.qy + L.qz * L.qz);
+    double u2 = ux * ux + uy * uy + uz * uz;
+    double a = 1.0 / (2.0 / r - u2 / mu);
+    double hx = L.qy * uz - L.qz * uy, hy = L.qz * ux - L.qx * uz, hz = L.qx * uy - L.qy * ux;
+    double ex = (uy * hz - uz * hy) / mu - L.qx / r;
+    double ey = (uz * hx - ux * hz) / mu - L.qy / r;
+    double ez = (ux * hy - uy * hx) / mu - L.qz / r;
+    if (L.sys >= 0 && L.pl >= 0) {
+      size_t o = (size_t)L.sys * 8 + L.pl;
+      q.a_out[o] = a;
+      q.e_out[o] = sqrt(ex * ex + ey * ey + ez * ez);
+    }
   }
 }
 
@@ -617,6 +638,64 @@ __global__ void k_copy_u32(uint32_t* dst, const uint32_t* src, int n) {
 }  // namespace
 
 // ===========================================================================
+// Kepler-solver envelope (Sec. 3.2 test of Fig. 1, App. A search): massless
+// test particles about a star, each advanced n_steps Kepler drifts of its own
+// tau with run-time iteration counts, and the relative change of the
+// osculating semi-major axis a = 1 / (2/r - v^2/mu), which the exact flow
+// conserves.  One lane per particle; the state is plain binary64, the update
+// Q' = Q + ((f - 1) Q + g V), V' = V + (f' Q + (g' - 1) V).
+// ===========================================================================
+struct EnvParams {
+  const double* Q;   // [n*3]
+  const double* V;
+  const double* mu;  // [n]
+  const double* tau; // [n]
+  double* Q_out;     // [n*3] or null (may alias Q)
+  double* V_out;
+  double* a_err;     // [n]
+  double* zmax_out;  // [n] or null
+  int64_t n;
+  int64_t n_steps;
+  KepCountsRun counts;
+};
+
+__device__ __forceinline__ double semi_major(double qx, double qy, double qz, double vx, double vy, double vz,
+                                             double mu) {
+  double r = sqrt(qx * qx + qy * qy + qz * qz);
+  double v2 = vx * vx + vy * vy + vz * vz;
+  return 1.0 / (2.0 / r - v2 / mu);
+}
+
+__global__ __launch_bounds__(256) void k_envelope(EnvParams p) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < p.n; i += (int64_t)gridDim.x * 256) {
+    double qx = p.Q[3 * i], qy = p.Q[3 * i + 1], qz = p.Q[3 * i + 2];
+    double vx = p.V[3 * i], vy = p.V[3 * i + 1], vz = p.V[3 * i + 2];
+    const double mu = p.mu[i], tau = p.tau[i];
+    const double a0 = semi_major(qx, qy, qz, vx, vy, vz, mu);
+    KepDiag dg{0.0, 1e300};
+    for (int64_t s = 0; s < p.n_steps; ++s) {
+      KepCoef k;
+      kepler_coeffs_p(p.counts, qx, qy, qz, vx, vy, vz, mu, tau, dg, k);
+      double nqx = qx + fma(k.fm1, qx, k.g * vx);
+      double nqy = qy + fma(k.fm1, qy, k.g * vy);
+      double nqz = qz + fma(k.fm1, qz, k.g * vz);
+      vx = vx + fma(k.fd, qx, k.gdm1 * vx);
+      vy = vy + fma(k.fd, qy, k.gdm1 * vy);
+      vz = vz + fma(k.fd, qz, k.gdm1 * vz);
+      qx = nqx; qy = nqy; qz = nqz;
+    }
+    p.a_err[i] = (semi_major(qx, qy, qz, vx, vy, vz, mu) - a0) / a0;
+    if (p.zmax_out) p.zmax_out[i] = dg.zmax;
+    if (p.Q_out) {
+      p.Q_out[3 * i] = qx; p.Q_out[3 * i + 1] = qy; p.Q_out[3 * i + 2] = qz;
+    }
+    if (p.V_out) {
+      p.V_out[3 * i] = vx; p.V_out[3 * i + 1] = vy; p.V_out[3 * i + 2] = vz;
+    }
+  }
+}
+
+// ===========================================================================
 // Host side
 // ===========================================================================
 namespace {
@@ -803,12 +882,15 @@ void launch_step(const wh_ctx* c, int n_steps, hipStream_t st) {
   launch_step_kernel(c, p, c->P.nwaves, st);
 }
 
-wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st) {
+wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st, double* a = nullptr,
+                      double* e = nullptr) {
   SyncParams q;
   q.sp = step_params(c, 0);
   q.Q_out = Q;
   q.V_out = V;
   q.E_out = E;
+  q.a_out = a;
+  q.e_out = e;
   dim3 block(64), grid(c->P.nwaves);
   const bool gr = c->cfg.gr_c > 0;
   if (c->cfg.scheme == WH_DKD) {
@@ -1026,6 +1108,12 @@ wh_status wh_energy(wh_ctx* c, double* E_out, hipStream_t stream) {
   return launch_sync(c, nullptr, nullptr, E_out, stream);
 }
 
+wh_status wh_elements(wh_ctx* c, double* a_out, double* e_out, hipStream_t stream) {
+  if (!c) return fail(WH_EINVAL, "null context");
+  if (!a_out || !e_out) return fail(WH_EINVAL, "null output pointer");
+  return launch_sync(c, nullptr, nullptr, nullptr, stream, a_out, e_out);
+}
+
 wh_status wh_status_flags(wh_ctx* c, uint32_t* flags_out, hipStream_t stream) {
   if (!c) return fail(WH_EINVAL, "null context");
   if (!flags_out) return fail(WH_EINVAL, "null output pointer");
@@ -1106,6 +1194,29 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
   }
   hipLaunchKernelGGL(k_adj_finish, dim3(c->P.nwaves), dim3(64), 0, stream, q);
   return hip_check(hipGetLastError(), "adjoint launch");
+}
+
+wh_status wh_kepler_envelope(int64_t n, const double* Q, const double* V, const double* mu, const double* tau,
+                             int64_t n_steps, int32_t n_halley, int32_t n_newton, int32_t terms_halley,
+                             int32_t terms_newton, double* Q_out, double* V_out, double* a_err, double* zmax_out,
+                             hipStream_t stream) {
+  if (n < 0 || n_steps < 0) return fail(WH_EINVAL, "n and n_steps must be >= 0");
+  if (n_halley < 0 || n_halley > KEP_RT_MAX_NH || n_newton < 0 || n_newton > KEP_RT_MAX_NN ||
+      n_halley + n_newton < 1)
+    return fail(WH_EINVAL, "iteration counts must satisfy 0 <= n_halley, n_newton <= 8 and n_halley + n_newton >= 1");
+  if (terms_halley < 1 || terms_halley > KEP_RT_MAX_TERMS || terms_newton < 1 || terms_newton > KEP_RT_MAX_TERMS)
+    return fail(WH_EINVAL, "series lengths must be in 1..14");
+  if (n == 0) return WH_OK;
+  if (!Q || !V || !mu || !tau || !a_err) return fail(WH_EINVAL, "null array pointer");
+  if ((Q_out == nullptr) != (V_out == nullptr)) return fail(WH_EINVAL, "Q_out and V_out must both be given or both null");
+  EnvParams p;
+  p.Q = Q; p.V = V; p.mu = mu; p.tau = tau;
+  p.Q_out = Q_out; p.V_out = V_out; p.a_err = a_err; p.zmax_out = zmax_out;
+  p.n = n; p.n_steps = n_steps;
+  p.counts = KepCountsRun{n_halley, n_newton, terms_halley, terms_newton};
+  int64_t blocks = std::min<int64_t>((n + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_envelope, dim3((unsigned)blocks), dim3(256), 0, stream, p);
+  return hip_check(hipGetLastError(), "envelope launch");
 }
 
 const char* wh_last_error(void) { return g_err.c_str(); }

@@ -99,18 +99,54 @@ struct KepCoef {
   double fm1, g, fd, gdm1;
 };
 
+// Iteration counts of the fixed Kepler solve: NH Halley steps with KH series
+// terms, then NN Newton steps with KN terms.  KepCountsFixed bakes them in at
+// compile time (the integrator); KepCountsRun takes them at run time, uniform
+// over a launch (the envelope explorer of App. A).
+template <int NH, int NN, int KH, int KN> struct KepCountsFixed {
+  __device__ static constexpr int nh() { return NH; }
+  __device__ static constexpr int nn() { return NN; }
+  template <int N0> __device__ static double series_h(double z) { return stumpff_series<KH, N0>(z); }
+  template <int N0> __device__ static double series_n(double z) { return stumpff_series<KN, N0>(z); }
+};
+
+// 1/n! for n = 0..31 (exact to n = 18, correctly rounded products beyond).
+struct InvFactTable {
+  double v[32];
+  __host__ __device__ constexpr InvFactTable() : v() {
+    for (int n = 0; n < 32; ++n) v[n] = inv_factorial(n);
+  }
+};
+__constant__ constexpr InvFactTable kInvFact{};
+
+template <int N0> __device__ __forceinline__ double stumpff_series_rt(double z, int K) {
+  double s = kInvFact.v[N0 + 2 * (K - 1)];
+  for (int k = K - 2; k >= 0; --k) s = fma(-z, s, kInvFact.v[N0 + 2 * k]);
+  return s;
+}
+
+// Run-time counts; limits keep every table index in range.
+constexpr int KEP_RT_MAX_NH = 8, KEP_RT_MAX_NN = 8, KEP_RT_MAX_TERMS = 14;
+struct KepCountsRun {
+  int h, n, kh, kn;
+  __device__ int nh() const { return h; }
+  __device__ int nn() const { return n; }
+  template <int N0> __device__ double series_h(double z) const { return stumpff_series_rt<N0>(z, kh); }
+  template <int N0> __device__ double series_n(double z) const { return stumpff_series_rt<N0>(z, kn); }
+};
+
 // Kepler drift of one planet over tau about a star with mu = G m0 (Sec. 3.2),
 // in universal variables: with r0 = |Q|, eta = Q.V, beta = 2mu/r0 - V^2,
 // zeta = mu - beta r0, solve
 //   F(X) = r0 X + eta G2(X) + zeta G3(X) - tau = 0,  G_n = X^n c_n(beta X^2),
-// with a fixed NH Halley steps (KH series terms) and NN Newton steps (KN
-// terms), no convergence test and no branch, then form the Lagrange
-// coefficients.  Initial guess: X = tau/r0 - eta tau^2 / (2 r0^3).
+// with a fixed number of Halley steps then Newton steps (counts and series
+// lengths from P), no convergence test and no branch on the data, then form
+// the Lagrange coefficients.  Initial guess: X = tau/r0 - eta tau^2 / (2 r0^3).
 // g' - 1 is taken from the Wronskian identity f g' - f' g = 1, which keeps
 // the discrete map area-preserving to rounding.  Returns the anomaly X.
-template <int NH, int NN, int KH, int KN>
-__device__ __forceinline__ double kepler_coeffs(double qx, double qy, double qz, double vx, double vy, double vz,
-                                                double mu, double tau, KepDiag& dg, KepCoef& k) {
+template <class P>
+__device__ __forceinline__ double kepler_coeffs_p(const P& p, double qx, double qy, double qz, double vx, double vy,
+                                                  double vz, double mu, double tau, KepDiag& dg, KepCoef& k) {
   double r2 = fma(qx, qx, fma(qy, qy, qz * qz));
   double v2 = fma(vx, vx, fma(vy, vy, vz * vz));
   double eta = fma(qx, vx, fma(qy, vy, qz * vz));
@@ -122,11 +158,11 @@ __device__ __forceinline__ double kepler_coeffs(double qx, double qy, double qz,
   double a = tau * ir0;
   double X = a * fma(-0.5 * eta * ir0, a, 1.0);
 #pragma unroll
-  for (int it = 0; it < NH; ++it) {
+  for (int it = 0; it < p.nh(); ++it) {
     double X2 = X * X;
     double z = beta * X2;
-    double c2 = stumpff_series<KH, 2>(z);
-    double c3 = stumpff_series<KH, 3>(z);
+    double c2 = p.template series_h<2>(z);
+    double c3 = p.template series_h<3>(z);
     double c0 = fma(-z, c2, 1.0);
     double c1 = fma(-z, c3, 1.0);
     double G1 = X * c1, G2 = X2 * c2, G3 = X2 * X * c3;
@@ -142,24 +178,34 @@ __device__ __forceinline__ double kepler_coeffs(double qx, double qy, double qz,
   // rounding level once the iteration has converged.
   double G1 = 0.0, G2 = 0.0, G3 = 0.0;
 #pragma unroll
-  for (int it = 0; it < NN; ++it) {
+  for (int it = 0; it < p.nn(); ++it) {
     double X2 = X * X;
     double z = beta * X2;
-    if (it == NN - 1) dg.zmax = fmax(dg.zmax, z);
-    double c2 = stumpff_series<KN, 2>(z);
-    double c3 = stumpff_series<KN, 3>(z);
+    if (it == p.nn() - 1) dg.zmax = fmax(dg.zmax, z);
+    double c2 = p.template series_n<2>(z);
+    double c3 = p.template series_n<3>(z);
     double c1 = fma(-z, c3, 1.0);
     G1 = X * c1; G2 = X2 * c2; G3 = X2 * X * c3;
     double F = fma(r0, X, fma(eta, G2, fma(zeta, G3, -tau)));
     double Fp = fma(eta, G1, fma(zeta, G2, r0));
     double d = -F * rcp_seed(Fp);
     X += d;
-    if (it == NN - 1) {
+    if (it == p.nn() - 1) {
       double G0 = fma(-z, c2, 1.0);
       G3 = fma(d, G2, G3);
       G2 = fma(d, G1, G2);
       G1 = fma(d, G0, G1);
     }
+  }
+  if (p.nn() == 0) {
+    // no Newton step: the G functions are evaluated afresh at the last
+    // Halley iterate with the final series length
+    double X2 = X * X;
+    double z = beta * X2;
+    dg.zmax = fmax(dg.zmax, z);
+    double c2 = p.template series_n<2>(z);
+    double c3 = p.template series_n<3>(z);
+    G1 = X * fma(-z, c3, 1.0); G2 = X2 * c2; G3 = X2 * X * c3;
   }
   double r = fma(eta, G1, fma(zeta, G2, r0));
   double ir = rcp_full(r);
@@ -168,6 +214,12 @@ __device__ __forceinline__ double kepler_coeffs(double qx, double qy, double qz,
   k.fd = -mu * G1 * ir0 * ir;
   k.gdm1 = fma(k.fd, k.g, -k.fm1) * rcp_full(1.0 + k.fm1);
   return X;
+}
+
+template <int NH, int NN, int KH, int KN>
+__device__ __forceinline__ double kepler_coeffs(double qx, double qy, double qz, double vx, double vy, double vz,
+                                                double mu, double tau, KepDiag& dg, KepCoef& k) {
+  return kepler_coeffs_p(KepCountsFixed<NH, NN, KH, KN>{}, qx, qy, qz, vx, vy, vz, mu, tau, dg, k);
 }
 
 // Increment a x + b y of one coordinate as an unevaluated sum hi + lo, with

@@ -107,6 +107,13 @@ class Ensemble:
         check(_lib.load().wh_energy(self._ctx, E.data_ptr(), _stream(self.device)))
         return E
 
+    def elements(self):
+        """Osculating heliocentric (a, e) of every planet: [S, 8] each."""
+        a = torch.zeros((self.S, 8), dtype=torch.float64, device=self.device)
+        e = torch.zeros((self.S, 8), dtype=torch.float64, device=self.device)
+        check(_lib.load().wh_elements(self._ctx, a.data_ptr(), e.data_ptr(), _stream(self.device)))
+        return a, e
+
     def flags(self):
         f = torch.zeros(self.S, dtype=torch.int32, device=self.device)
         check(_lib.load().wh_status_flags(self._ctx, f.data_ptr(), _stream(self.device)))

@@ -21,12 +21,19 @@ paper's performance and long-term tests, Sec. 4-5, which is not available):
 * dt = P_inner / 20 with P_inner = 2 pi sqrt(a_1^3 / (m0 + m_1)), or, for
   uneven batches, dt uniform in [P_inner/30, P_inner/15].
 
+Kepler-envelope test particles (Sec. 3.2, Fig. 1): massless particles about
+a unit-mass star (mu = 1) on a grid of semi-major axis and eccentricity, in
+the reference plane (i = node = pericentre argument = 0), with mean anomalies
+uniform in [0, 2pi) from domain 4 of a per-cell key; the step is 5 days,
+dt = 2pi * 5 / 365.25 in these units.
+
 Randomness: a counter-based SplitMix64.  System i of base seed s owns the
 stream key = mix((s << 32) | i); draw k of domain d is
 mix(mix(key + d * 0x632BE59BD9B4E019) + (k + 1) * 0x9E3779B97F4A7C15) and its
 top 53 bits give a uniform double in [0, 1).  Domains: 0 planet count,
 1 masses and semi-major axes (16 draws per rejection attempt), 2 angles and
-shape, 3 timestep.  A system's values therefore do not depend on how many
+shape, 3 timestep, 4 test-particle phases (keyed by grid cell instead of
+system).  A system's values therefore do not depend on how many
 systems are drawn with it.
 """
 from __future__ import annotations
@@ -239,3 +246,24 @@ def workload(name: str, S: int | None = None) -> Systems:
     if S is not None:
         kw["S"] = S
     return make_systems(**kw)
+
+
+DT_5_DAYS = 2.0 * np.pi * 5.0 / 365.25
+
+
+def make_test_particles(a_values, e_values, n_phase: int, base_seed: int = 7):
+    """Test particles on the (a, e) grid, n_phase random phases per cell.
+
+    Returns (Q, V, a, e) with Q, V [n_a, n_e, n_phase, 3] and the per-particle
+    a, e [n_a, n_e, n_phase] (heliocentric, mu = 1)."""
+    a_values = np.asarray(a_values, dtype=np.float64)
+    e_values = np.asarray(e_values, dtype=np.float64)
+    na, ne = len(a_values), len(e_values)
+    cells = np.arange(na * ne, dtype=np.int64)
+    M = 2.0 * np.pi * uniform(_keys(base_seed, cells), 4, np.arange(n_phase)[None, :])
+    A = np.broadcast_to(a_values[:, None, None], (na, ne, n_phase)).reshape(-1)
+    E = np.broadcast_to(e_values[None, :, None], (na, ne, n_phase)).reshape(-1)
+    z = np.zeros_like(A)
+    Q, V = elements_to_cartesian(1.0, A, E, z, z, z, M.reshape(-1))
+    shp = (na, ne, n_phase)
+    return Q.reshape(shp + (3,)), V.reshape(shp + (3,)), A.reshape(shp), E.reshape(shp)
