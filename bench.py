@@ -43,10 +43,17 @@ WORKLOAD_TEXT = {
 }
 
 
+# Steps of each workload's run; large8gr's 1e7-step run is timed over 1e6
+# steps to keep the GPU held for seconds, not a minute.
+DEFAULT_STEPS = {"uniform8": 1_000_000, "uneven2to8": 1_000_000, "large8gr": 1_000_000, "single8": 100_000,
+                 "adjoint8": 100_000}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1_000_000, help="timed Wisdom-Holman steps")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed Wisdom-Holman steps (default: 1e5 for adjoint8 and single8, 1e6 otherwise)")
     ap.add_argument("--warmup", type=int, default=4096, help="untimed steps before the timed region")
     ap.add_argument("--workload", default="uniform8", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--packing", default="auto")
@@ -61,6 +68,25 @@ def parse():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates memory counters)")
     return ap.parse_args()
+
+
+def measured_traffic(workload: str, chunk: int):
+    """HBM bytes per launch from the committed counter summary, if the kernel
+    sources are still the ones it was taken on (else None)."""
+    import hashlib
+    import re
+    try:
+        text = open(os.path.join(ROOT, "profiles", "k_step_hbm_traffic.md")).read()
+        rec = json.loads(re.search(r"```json\n(.*?)```", text, re.S).group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    for name, digest in rec["sources"].items():
+        with open(os.path.join(ROOT, "paper_2307_05683_amd", "csrc", name), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    if chunk != rec["chunk_steps"]:
+        return None
+    return rec["bytes_per_launch"].get(workload)
 
 
 def flops_per_system_step(n_planets: np.ndarray, gr: bool) -> float:
@@ -88,20 +114,31 @@ def cpu_baseline(systems, args, gr_c):
 
 def adjoint_cost(systems, args, dev, stream, t_plain):
     """Forward with checkpoints + adjoint, against the plain forward of the
-    same steps (the cost ratio of reverse mode)."""
+    same steps (the cost ratio of reverse mode).  A short run first loads
+    every kernel involved; the loss seed dL/dQ_T = 2 Q_T is formed outside
+    the timed intervals."""
     import torch
     from paper_2307_05683_amd.ensemble import Ensemble
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    w = Ensemble.from_systems(systems.subset(np.arange(min(64, systems.S))), device=dev)
+    w.forward_ckpt(4, 2)
+    QT, VT = w.state()
+    w.adjoint(2 * QT, torch.zeros_like(VT))
+    torch.cuda.synchronize()
+    w.close()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     e = Ensemble.from_systems(systems, device=dev)
     ev[0].record(stream)
     e.forward_ckpt(args.steps, args.ckpt_every)
     ev[1].record(stream)
     QT, VT = e.state()
-    g = e.adjoint(2 * QT, torch.zeros_like(VT))
+    gQ, gV = 2 * QT, torch.zeros_like(VT)
+    torch.cuda.synchronize()
     ev[2].record(stream)
+    g = e.adjoint(gQ, gV)
+    ev[3].record(stream)
     torch.cuda.synchronize()
     t_ckpt = ev[0].elapsed_time(ev[1]) / 1e3
-    t_adj = ev[1].elapsed_time(ev[2]) / 1e3
+    t_adj = ev[2].elapsed_time(ev[3]) / 1e3
     finite = bool(all(torch.isfinite(x).all().item() for x in g))
     e.close()
     return {"steps": args.steps, "ckpt_every": args.ckpt_every, "forward_s": t_plain, "forward_ckpt_s": t_ckpt,
@@ -111,6 +148,8 @@ def adjoint_cost(systems, args, dev, stream, t_plain):
 
 def main():
     args = parse()
+    if args.steps is None:
+        args.steps = DEFAULT_STEPS.get(args.workload, 1_000_000)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (systems are independent; "
               "see the sharding design notes). Use --gpus 1.", file=sys.stderr)
@@ -189,7 +228,8 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, opts["chunk_steps"]),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
             "kernel": "k_step (persistent step kernel)",
             "algorithmic_flops_per_step": flops_step,
             "avg_launch_ms": gpu_s * 1e3 / n_launch,

@@ -267,8 +267,9 @@ __device__ void step_group(const StepParams& p, int slot, int lane) {
   store_lane(p, slot, L);
 }
 
-// At most 128 VGPRs (4 wavefronts per SIMD): large ensembles then run in
-// whole rounds of resident waves.
+// The compiler fits every variant in 128 VGPRs without spills, so four
+// wavefronts stay resident per SIMD; a launch holds one wave per 64 lanes of
+// the packed ensemble and each wave runs its whole chunk of steps.
 template <bool GR, int SCHEME, int EXCH>
 __global__ __launch_bounds__(256) void k_step(StepParams p) {
   const int lane = threadIdx.x & 63;
@@ -768,6 +769,8 @@ bool make_packing(int S, const int32_t* np, int packing, Packing& P) {
     P.w1 = ends[0]; P.w2 = ends[1]; P.w4 = ends[2]; P.w8 = ends[3];
   }
   P.ns = P.nwaves * 64;
+  // every wave holds exactly 64 slots; the device tables are copied at ns
+  if ((int)P.slot_sys.size() != P.ns || (int)P.slot_pl.size() != P.ns) return false;
   return true;
 }
 
