@@ -49,6 +49,12 @@ def lib():
             "or_tangent_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, l, i, ld, _PLD, _PLD, _PLD, _PLD, i], None),
             "or_count_ops": ([i, i, i, i, i, i, _PL], None),
             "or_gbs_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld, l], ld),
+            "or_jacobi_integrate_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, l, i, i], None),
+            "or_jacobi_integrate_d": ([i, i, _PI, _PD, _PD, _PD, _PD, _PD, l, i, i], None),
+            "or_jacobi_from_dhc_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, _PLD], None),
+            "or_jacobi_to_dhc_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, _PLD], None),
+            "or_jacobi_parts_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD], None),
+            "or_jacobi_kick_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -214,3 +220,51 @@ def elements(sysm, Q=None, V=None):
         evec = np.cross(u, h) / mu[..., None] - Q / r[..., None]
         e = np.sqrt((evec * evec).sum(-1))
     return np.where(live, a, np.nan), np.where(live, e, np.nan)
+
+
+# ---- Wisdom-Holman map in Jacobi coordinates (Wisdom & Holman 1991) --------
+
+def jacobi_integrate(sysm, n_steps, scheme="dkd", precision="ld", nthreads=0, Q=None, V=None, dt=None):
+    """n_steps of the Jacobi-coordinate map; DHC (Q, V) in and out."""
+    S = sysm.S
+    dtv = sysm.dt if dt is None else dt
+    if precision == "ld":
+        Qa = _ld(sysm.Q if Q is None else Q).copy(); Va = _ld(sysm.V if V is None else V).copy()
+        lib().or_jacobi_integrate_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), Qa, Va, _ld(dtv),
+                                     int(n_steps), SCHEMES[scheme], nthreads)
+    else:
+        Qa = _d(sysm.Q if Q is None else Q).copy(); Va = _d(sysm.V if V is None else V).copy()
+        lib().or_jacobi_integrate_d(S, 8, _i(sysm.n_planets), _d(sysm.m0), _d(sysm.m), Qa, Va, _d(dtv),
+                                    int(n_steps), SCHEMES[scheme], nthreads)
+    return Qa, Va
+
+
+def jacobi_from_dhc(sysm, Q=None, V=None):
+    S = sysm.S
+    xp = np.zeros((S, 8, 3), dtype=LD); vp = np.zeros((S, 8, 3), dtype=LD)
+    lib().or_jacobi_from_dhc_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), _ld(sysm.Q if Q is None else Q),
+                                _ld(sysm.V if V is None else V), xp, vp)
+    return xp, vp
+
+
+def jacobi_to_dhc(sysm, xp, vp):
+    S = sysm.S
+    Q = np.zeros((S, 8, 3), dtype=LD); V = np.zeros((S, 8, 3), dtype=LD)
+    lib().or_jacobi_to_dhc_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), _ld(xp), _ld(vp), Q, V)
+    return Q, V
+
+
+def jacobi_parts(sysm, Q=None, V=None):
+    """Per system (kinetic energy in Jacobi form, H_K, H_I)."""
+    S = sysm.S
+    out = np.zeros((S, 3), dtype=LD)
+    lib().or_jacobi_parts_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), _ld(sysm.Q if Q is None else Q),
+                             _ld(sysm.V if V is None else V), out)
+    return out[:, 0], out[:, 1], out[:, 2]
+
+
+def jacobi_kick(sysm, tau, Q=None, V=None):
+    S = sysm.S
+    Qa = _ld(sysm.Q if Q is None else Q).copy(); Va = _ld(sysm.V if V is None else V).copy()
+    lib().or_jacobi_kick_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), Qa, Va, LD(tau))
+    return Qa, Va

@@ -473,6 +473,185 @@ template <class T> void integrate_arrays(int S, int nmax, const int* np, const T
   }
 }
 
+// ---------------------------------------------------------------------------
+// Wisdom-Holman map in Jacobi coordinates (Wisdom & Holman 1991), the
+// alternative the paper names for systems of two or four planets (Sec. 3.5,
+// footnote on Jacobi coordinates; Sec. 6 outlook).  Bodies 0 (the star) .. n,
+// interior masses M_i = m_0 + m_1 + ... + m_i.  Jacobi coordinates of body
+// i >= 1 are measured from the centre of mass of the bodies inside it:
+//   x'_i = x_i - (m_0 x_0 + ... + m_{i-1} x_{i-1}) / M_{i-1}   (same for v),
+// translation invariant, so computable from heliocentric positions Q_j =
+// x_j - x_0 (Q_0 = 0) and heliocentric velocities u_j.  With reduced masses
+// m'_i = m_i M_{i-1} / M_i the barycentric kinetic energy is
+// sum_i m'_i |v'_i|^2 / 2, and the Hamiltonian splits as
+//   H_K = sum_i [ m'_i |v'_i|^2 / 2 - G M_i m'_i / |x'_i| ]  (Kepler, mu_i = G M_i)
+//   H_I = U + sum_i G M_i m'_i / |x'_i|,
+//   U   = - sum_{i>=1} G m_0 m_i / |Q_i| - sum_{1<=i<j} G m_i m_j / |Q_i - Q_j|.
+// The kick is v'_i -= tau (1/m'_i) dH_I/dx'_i with the gradient taken by
+// dual numbers through this definition of H_I (no hand-derived force).
+template <class T> struct JSys {
+  int n;
+  T m0;
+  T m[8];
+  T M[9];        // M[i] = m_0 + ... + m_i over bodies 0..n (M[0] = m0)
+  T x[8][3];     // Jacobi position of planet k (body k + 1)
+  T v[8][3];     // Jacobi velocity
+};
+
+template <class T> void jac_masses(JSys<T>& s) {
+  s.M[0] = s.m0;
+  for (int k = 0; k < s.n; ++k) s.M[k + 1] = s.M[k] + s.m[k];
+}
+
+// Heliocentric -> Jacobi for one vector field (positions or heliocentric
+// velocities): x'_k = h_k - (sum_{j<k} m_j h_j) / M_k  (star at h = 0).
+template <class T, class A> void helio_to_jacobi(const JSys<T>& s, const A h[8][3], T out[8][3]) {
+  T acc[3] = {T(0), T(0), T(0)};
+  for (int k = 0; k < s.n; ++k) {
+    for (int a = 0; a < 3; ++a) out[k][a] = T(h[k][a]) - acc[a] / s.M[k];
+    for (int a = 0; a < 3; ++a) acc[a] += s.m[k] * T(h[k][a]);
+  }
+}
+// Jacobi -> heliocentric: h_k = x'_k + (sum_{j<k} m_j h_j) / M_k.
+template <class T, class U> void jacobi_to_helio(const JSys<T>& s, const U xp[8][3], U h[8][3]) {
+  U acc[3] = {U(0), U(0), U(0)};
+  for (int k = 0; k < s.n; ++k) {
+    for (int a = 0; a < 3; ++a) h[k][a] = xp[k][a] + acc[a] / U(s.M[k]);
+    for (int a = 0; a < 3; ++a) acc[a] += U(s.m[k]) * h[k][a];
+  }
+}
+
+// From democratic heliocentric Q (heliocentric) and V (barycentric): the
+// star's barycentric velocity is -sum_j m_j V_j / m0, so u_j = V_j + sum m V / m0.
+template <class T> void jac_from_dhc(JSys<T>& s, const T Q[8][3], const T V[8][3]) {
+  jac_masses(s);
+  T P[3] = {T(0), T(0), T(0)};
+  for (int k = 0; k < s.n; ++k)
+    for (int a = 0; a < 3; ++a) P[a] += s.m[k] * V[k][a];
+  T u[8][3];
+  for (int k = 0; k < s.n; ++k)
+    for (int a = 0; a < 3; ++a) u[k][a] = V[k][a] + P[a] / s.m0;
+  helio_to_jacobi(s, Q, s.x);
+  helio_to_jacobi(s, u, s.v);
+}
+// Back: heliocentric Q from x', heliocentric u from v', and V = u + v_0 with
+// the star's barycentric velocity v_0 = -sum_j m_j u_j / M_n.
+template <class T> void jac_to_dhc(const JSys<T>& s, T Q[8][3], T V[8][3]) {
+  jacobi_to_helio(s, s.x, Q);
+  T u[8][3];
+  jacobi_to_helio(s, s.v, u);
+  T P[3] = {T(0), T(0), T(0)};
+  for (int k = 0; k < s.n; ++k)
+    for (int a = 0; a < 3; ++a) P[a] += s.m[k] * u[k][a];
+  for (int k = 0; k < s.n; ++k)
+    for (int a = 0; a < 3; ++a) V[k][a] = u[k][a] - P[a] / s.M[s.n];
+}
+
+template <class T> T jac_reduced_mass(const JSys<T>& s, int k) { return s.m[k] * s.M[k] / s.M[k + 1]; }
+
+// H_I at Jacobi positions xp (scalar type U: long double, or dual numbers
+// for the gradient).
+template <class T, class U> U jac_hint(const JSys<T>& s, const U xp[8][3]) {
+  using std::sqrt;
+  U Q[8][3];
+  jacobi_to_helio(s, xp, Q);
+  U H = U(0);
+  for (int i = 0; i < s.n; ++i) {
+    U r = sqrt(Q[i][0] * Q[i][0] + Q[i][1] * Q[i][1] + Q[i][2] * Q[i][2]);
+    H -= U(s.m0 * s.m[i]) / r;
+    for (int j = i + 1; j < s.n; ++j) {
+      U d[3] = {Q[i][0] - Q[j][0], Q[i][1] - Q[j][1], Q[i][2] - Q[j][2]};
+      H -= U(s.m[i] * s.m[j]) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    }
+    U rp = sqrt(xp[i][0] * xp[i][0] + xp[i][1] * xp[i][1] + xp[i][2] * xp[i][2]);
+    H += U(s.M[i + 1] * jac_reduced_mass(s, i)) / rp;
+  }
+  return H;
+}
+
+template <class T> T jac_hk(const JSys<T>& s) {
+  using std::sqrt;
+  T H = T(0);
+  for (int i = 0; i < s.n; ++i) {
+    T mp = jac_reduced_mass(s, i);
+    T v2 = s.v[i][0] * s.v[i][0] + s.v[i][1] * s.v[i][1] + s.v[i][2] * s.v[i][2];
+    T r = sqrt(s.x[i][0] * s.x[i][0] + s.x[i][1] * s.x[i][1] + s.x[i][2] * s.x[i][2]);
+    H += T(0.5L) * mp * v2 - s.M[i + 1] * mp / r;
+  }
+  return H;
+}
+
+// Kick of H_I over tau: one dual-number evaluation of H_I per coordinate.
+void jac_kick(JSys<ld>& s, ld tau) {
+  typedef Dual<ld> D;
+  ld g[8][3];
+  for (int i = 0; i < s.n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      D xp[8][3];
+      for (int k = 0; k < s.n; ++k)
+        for (int b = 0; b < 3; ++b) xp[k][b] = D(s.x[k][b], (k == i && b == a) ? 1.0L : 0.0L);
+      g[i][a] = jac_hint(s, xp).d;
+    }
+  for (int i = 0; i < s.n; ++i) {
+    ld mp = jac_reduced_mass(s, i);
+    for (int a = 0; a < 3; ++a) s.v[i][a] -= tau * g[i][a] / mp;
+  }
+}
+
+void jac_drift(JSys<ld>& s, ld tau) {
+  for (int i = 0; i < s.n; ++i) kepler_exact(s.x[i], s.v[i], s.M[i + 1], tau, (ld*)0);
+}
+
+// scheme 0: K(dt/2) I(dt) K(dt/2); scheme 1: I(dt/2) K(dt) I(dt/2).
+void jac_step(JSys<ld>& s, ld dt, int scheme) {
+  ld h = dt * 0.5L;
+  if (scheme == 0) {
+    jac_drift(s, h);
+    jac_kick(s, dt);
+    jac_drift(s, h);
+  } else {
+    jac_kick(s, h);
+    jac_drift(s, dt);
+    jac_kick(s, h);
+  }
+}
+
+template <class A> void jac_load(JSys<ld>& s, int idx, int nmax, const int* np, const A* m0, const A* m, const A* Q,
+                                 const A* V) {
+  s.n = np[idx];
+  s.m0 = m0[idx];
+  ld q[8][3], vv[8][3];
+  for (int i = 0; i < s.n; ++i) {
+    s.m[i] = m[idx * nmax + i];
+    for (int a = 0; a < 3; ++a) {
+      q[i][a] = Q[(idx * nmax + i) * 3 + a];
+      vv[i][a] = V[(idx * nmax + i) * 3 + a];
+    }
+  }
+  jac_from_dhc(s, q, vv);
+}
+template <class A> void jac_store(const JSys<ld>& s, int idx, int nmax, A* Q, A* V) {
+  ld q[8][3], vv[8][3];
+  jac_to_dhc(s, q, vv);
+  for (int i = 0; i < s.n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      Q[(idx * nmax + i) * 3 + a] = (A)q[i][a];
+      V[(idx * nmax + i) * 3 + a] = (A)vv[i][a];
+    }
+}
+
+template <class A> void jac_integrate_arrays(int S, int nmax, const int* np, const A* m0, const A* m, A* Q, A* V,
+                                             const A* dt, long n_steps, int scheme, int nthreads) {
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+  for (int k = 0; k < S; ++k) {
+    JSys<ld> s;
+    jac_load(s, k, nmax, np, m0, m, Q, V);
+    for (long t = 0; t < n_steps; ++t) jac_step(s, (ld)dt[k], scheme);
+    jac_store(s, k, nmax, Q, V);
+  }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -527,6 +706,70 @@ void or_integrate_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, 
 void or_integrate_d(int S, int nmax, const int* np, const double* m0, const double* m, double* Q, double* V,
                     const double* dt, long n_steps, int scheme, double gr_c, int nthreads) {
   integrate_arrays<double>(S, nmax, np, m0, m, Q, V, dt, n_steps, scheme, gr_c, nthreads);
+}
+
+// ---- Jacobi-coordinate map (Wisdom & Holman 1991) ----------------------
+// DHC in, DHC out; the state is carried in Jacobi coordinates in between.
+void or_jacobi_integrate_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, ld* Q, ld* V, const ld* dt,
+                            long n_steps, int scheme, int nthreads) {
+  jac_integrate_arrays(S, nmax, np, m0, m, Q, V, dt, n_steps, scheme, nthreads);
+}
+void or_jacobi_integrate_d(int S, int nmax, const int* np, const double* m0, const double* m, double* Q, double* V,
+                           const double* dt, long n_steps, int scheme, int nthreads) {
+  jac_integrate_arrays(S, nmax, np, m0, m, Q, V, dt, n_steps, scheme, nthreads);
+}
+// Jacobi coordinates of DHC states (xp, vp: [S][nmax][3]).
+void or_jacobi_from_dhc_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, const ld* Q, const ld* V,
+                           ld* xp, ld* vp) {
+  for (int k = 0; k < S; ++k) {
+    JSys<ld> s;
+    jac_load(s, k, nmax, np, m0, m, Q, V);
+    for (int i = 0; i < s.n; ++i)
+      for (int a = 0; a < 3; ++a) {
+        xp[(k * nmax + i) * 3 + a] = s.x[i][a];
+        vp[(k * nmax + i) * 3 + a] = s.v[i][a];
+      }
+  }
+}
+// DHC states of Jacobi coordinates.
+void or_jacobi_to_dhc_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, const ld* xp, const ld* vp,
+                         ld* Q, ld* V) {
+  for (int k = 0; k < S; ++k) {
+    JSys<ld> s;
+    s.n = np[k];
+    s.m0 = m0[k];
+    for (int i = 0; i < s.n; ++i) s.m[i] = m[k * nmax + i];
+    jac_masses(s);
+    for (int i = 0; i < s.n; ++i)
+      for (int a = 0; a < 3; ++a) {
+        s.x[i][a] = xp[(k * nmax + i) * 3 + a];
+        s.v[i][a] = vp[(k * nmax + i) * 3 + a];
+      }
+    jac_store(s, k, nmax, Q, V);
+  }
+}
+// Per system: [kinetic energy sum m'|v'|^2/2, H_K, H_I] of DHC states.
+void or_jacobi_parts_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, const ld* Q, const ld* V,
+                        ld* out) {
+  for (int k = 0; k < S; ++k) {
+    JSys<ld> s;
+    jac_load(s, k, nmax, np, m0, m, Q, V);
+    ld T = 0;
+    for (int i = 0; i < s.n; ++i)
+      T += 0.5L * jac_reduced_mass(s, i) * (s.v[i][0] * s.v[i][0] + s.v[i][1] * s.v[i][1] + s.v[i][2] * s.v[i][2]);
+    out[3 * k] = T;
+    out[3 * k + 1] = jac_hk(s);
+    out[3 * k + 2] = jac_hint(s, s.x);
+  }
+}
+// One kick of H_I over tau applied to DHC states (converted to Jacobi and back).
+void or_jacobi_kick_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, ld* Q, ld* V, ld tau) {
+  for (int k = 0; k < S; ++k) {
+    JSys<ld> s;
+    jac_load(s, k, nmax, np, m0, m, Q, V);
+    jac_kick(s, tau);
+    jac_store(s, k, nmax, Q, V);
+  }
 }
 
 void or_energy_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, const ld* Q, const ld* V, ld gr_c,
