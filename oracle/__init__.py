@@ -55,6 +55,8 @@ def lib():
             "or_jacobi_to_dhc_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, _PLD], None),
             "or_jacobi_parts_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD], None),
             "or_jacobi_kick_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld], None),
+            "or_jacobi_kick_direct_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld], None),
+            "or_count_ops_jacobi": ([i, i, i, i, i, _PL], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -263,8 +265,23 @@ def jacobi_parts(sysm, Q=None, V=None):
     return out[:, 0], out[:, 1], out[:, 2]
 
 
-def jacobi_kick(sysm, tau, Q=None, V=None):
+def jacobi_kick(sysm, tau, Q=None, V=None, form="gradient"):
+    """One kick of H_I: "gradient" = dual-number gradient of H_I, "direct" =
+    the closed-form Jacobi acceleration."""
     S = sysm.S
     Qa = _ld(sysm.Q if Q is None else Q).copy(); Va = _ld(sysm.V if V is None else V).copy()
-    lib().or_jacobi_kick_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), Qa, Va, LD(tau))
+    f = lib().or_jacobi_kick_ld if form == "gradient" else lib().or_jacobi_kick_direct_ld
+    f(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), Qa, Va, LD(tau))
     return Qa, Va
+
+
+def count_ops_jacobi(n_planets=8, n_halley=2, n_newton=2, terms_halley=4, terms_newton=8):
+    """Operation count of one step of the Jacobi map."""
+    c = np.zeros(4, dtype=np.int64)
+    lib().or_set_series_recur(0)
+    lib().or_set_guess(0)
+    lib().or_set_gd_form(0)
+    lib().or_count_ops_jacobi(n_planets, n_halley, n_newton, terms_halley, terms_newton, c)
+    d = dict(add=int(c[0]), mul=int(c[1]), div=int(c[2]), sqrt=int(c[3]))
+    d["flops"] = d["add"] + d["mul"] + d["div"] + d["sqrt"]
+    return d

@@ -598,6 +598,50 @@ void jac_kick(JSys<ld>& s, ld tau) {
   }
 }
 
+// The same kick from the closed form of the gradient (for the operation
+// count; a test checks it against the dual-number gradient above):
+//   a'_i = a_i - A_{i-1} + G M_i x'_i / |x'_i|^3,
+// with a_i the Newtonian acceleration of planet i and A_{i-1} that of the
+// centre of mass of the bodies inside it; the mutual forces of those bodies
+// cancel, leaving  M_{i-1} A_{i-1} = G m_0 sum_{k>=i} m_k Q_k/|Q_k|^3 +
+// sum_{j<i} m_j a^pl_j  (a^pl: the planet-planet part, each pair once).
+template <class T> void jac_kick_direct(JSys<T>& s, const T& tau) {
+  typedef typename Real<T>::type R;
+  using std::sqrt;
+  T Q[8][3], apl[8][3], g[8][3];
+  jacobi_to_helio(s, s.x, Q);
+  for (int i = 0; i < s.n; ++i)
+    for (int a = 0; a < 3; ++a) apl[i][a] = T(R(0));
+  for (int i = 0; i < s.n; ++i)
+    for (int j = i + 1; j < s.n; ++j) {
+      T d[3] = {Q[i][0] - Q[j][0], Q[i][1] - Q[j][1], Q[i][2] - Q[j][2]};
+      T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      T ir3 = T(R(1)) / (r2 * sqrt(r2));
+      T wi = s.m[j] * ir3, wj = s.m[i] * ir3;
+      for (int a = 0; a < 3; ++a) { apl[i][a] -= wi * d[a]; apl[j][a] += wj * d[a]; }
+    }
+  for (int i = 0; i < s.n; ++i) {
+    T r2 = Q[i][0] * Q[i][0] + Q[i][1] * Q[i][1] + Q[i][2] * Q[i][2];
+    T ir3 = T(R(1)) / (r2 * sqrt(r2));
+    for (int a = 0; a < 3; ++a) g[i][a] = Q[i][a] * ir3;
+  }
+  // running sums: suf[i] = sum_{k>=i} m_k g_k, pre[i] = sum_{j<i} m_j a^pl_j
+  T suf[9][3], pre[9][3];
+  for (int a = 0; a < 3; ++a) { suf[s.n][a] = T(R(0)); pre[0][a] = T(R(0)); }
+  for (int k = s.n - 1; k >= 0; --k)
+    for (int a = 0; a < 3; ++a) suf[k][a] = suf[k + 1][a] + s.m[k] * g[k][a];
+  for (int j = 0; j < s.n; ++j)
+    for (int a = 0; a < 3; ++a) pre[j + 1][a] = pre[j][a] + s.m[j] * apl[j][a];
+  for (int i = 0; i < s.n; ++i) {
+    T rp2 = s.x[i][0] * s.x[i][0] + s.x[i][1] * s.x[i][1] + s.x[i][2] * s.x[i][2];
+    T kp = s.M[i + 1] / (rp2 * sqrt(rp2));
+    for (int a = 0; a < 3; ++a) {
+      T A = (s.m0 * suf[i][a] + pre[i][a]) / s.M[i];
+      s.v[i][a] += tau * (apl[i][a] - s.m0 * g[i][a] - A + kp * s.x[i][a]);
+    }
+  }
+}
+
 void jac_drift(JSys<ld>& s, ld tau) {
   for (int i = 0; i < s.n; ++i) kepler_exact(s.x[i], s.v[i], s.M[i + 1], tau, (ld*)0);
 }
@@ -748,6 +792,15 @@ void or_jacobi_to_dhc_ld(int S, int nmax, const int* np, const ld* m0, const ld*
     jac_store(s, k, nmax, Q, V);
   }
 }
+// The closed-form kick (jac_kick_direct) on DHC states.
+void or_jacobi_kick_direct_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, ld* Q, ld* V, ld tau) {
+  for (int k = 0; k < S; ++k) {
+    JSys<ld> s;
+    jac_load(s, k, nmax, np, m0, m, Q, V);
+    jac_kick_direct(s, tau);
+    jac_store(s, k, nmax, Q, V);
+  }
+}
 // Per system: [kinetic energy sum m'|v'|^2/2, H_K, H_I] of DHC states.
 void or_jacobi_parts_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, const ld* Q, const ld* V,
                         ld* out) {
@@ -872,6 +925,28 @@ void or_count_ops(int n, int gr, int nh, int nn, int th, int tn, long* counts) {
     for (int i = 0; i < n; ++i) for (int a = 0; a < 3; ++a) s.V[i][a] += dt * acc[i][a];
   }
   if (gr) { gr_kick(s, dt, c); jump(s, dt * C(0.5)); }
+  counts[0] = g_ops.add; counts[1] = g_ops.mul; counts[2] = g_ops.div; counts[3] = g_ops.sqrt;
+}
+
+
+// Operation count of one step of the Jacobi map: the fixed-iteration drift of
+// every planet about mu = G M_i and the closed-form kick (no jump).  The
+// interior masses are per-system constants and are not counted.
+void or_count_ops_jacobi(int n, int nh, int nn, int th, int tn, long* counts) {
+  typedef Counted C;
+  JSys<C> s;
+  s.n = n;
+  s.m0 = C(1.0);
+  for (int i = 0; i < n; ++i) {
+    s.m[i] = C(1e-5);
+    s.x[i][0] = C(1.0 + i); s.x[i][1] = C(0.01 * i); s.x[i][2] = C(0.0);
+    s.v[i][0] = C(0.0); s.v[i][1] = C(1.0 / std::sqrt(1.0 + i)); s.v[i][2] = C(0.001);
+  }
+  jac_masses(s);
+  C dt(0.01);
+  g_ops = OpCount{0, 0, 0, 0};
+  for (int i = 0; i < n; ++i) kepler_fixed<C>(s.x[i], s.v[i], s.M[i + 1], dt, nh, nn, th, tn);
+  jac_kick_direct(s, dt);
   counts[0] = g_ops.add; counts[1] = g_ops.mul; counts[2] = g_ops.div; counts[3] = g_ops.sqrt;
 }
 

@@ -16,16 +16,20 @@ OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 
 def main():
     plain = {n: oracle.count_ops(n)["flops"] for n in range(1, 9)}
     gr = {n: oracle.count_ops(n, gr=True)["flops"] for n in range(1, 9)}
+    jac = {n: oracle.count_ops_jacobi(n)["flops"] for n in range(1, 9)}
     with open(OUT, "w") as f:
         f.write('"""Algorithmic FP64 operations per system-step, by planet count.\n\n'
                 'Counted on one step of the method as the paper states it (Sec. 3.1-3.4): the\n'
                 'fixed-iteration Kepler solve of Sec. 3.2 (2 Halley steps with 4 series terms,\n'
                 '2 Newton steps with 8), the combined drift, one evaluation per planet pair\n'
                 '(third law, Sec. 3.3) and the jump(s).  add/sub, mul, div and sqrt count one\n'
-                'each; an FMA counts two.  Written by oracle/write_flops.py.\n"""\n')
+                'each; an FMA counts two.  ALGO_FLOPS_JACOBI: the same drifts about the Jacobi\n'
+                'Kepler masses and the closed-form Jacobi kick (no jump).  Written by\n'
+                'oracle/write_flops.py.\n"""\n')
         f.write("ALGO_FLOPS = %r\n" % plain)
         f.write("ALGO_FLOPS_GR = %r\n" % gr)
-    print(OUT, plain, gr)
+        f.write("ALGO_FLOPS_JACOBI = %r\n" % jac)
+    print(OUT, plain, gr, jac)
 
 
 if __name__ == "__main__":

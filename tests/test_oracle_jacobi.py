@@ -212,3 +212,31 @@ def test_converges_to_brute_force_at_second_order():
         Q, V = oracle.jacobi_integrate(s, nst, dt=np.array([T / nst]))
         errs.append(np.abs((Q - Qg)[0, :2].astype(float)).max())
     assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
+
+
+def test_closed_form_kick_equals_gradient_kick():
+    """The closed-form Jacobi acceleration a_i - A_{i-1} + G M_i x'_i/|x'_i|^3
+    (used for the operation count and by the GPU kernel) is the gradient of
+    H_I: the two kicks agree to long-double rounding of V."""
+    s = inputs.make_systems(16, 48, n_planets=None, n_range=(1, 8))
+    s.m[:, :] *= 10.0          # heavier planets: larger interaction terms
+    lm = live(s)
+    Qa, Va = oracle.jacobi_kick(s, 0.05)
+    Qb, Vb = oracle.jacobi_kick(s, 0.05, form="direct")
+    dv = np.abs((Va - s.V.astype(LD))[lm]).max()
+    assert dv > 1e-7                                          # the kick is not negligible
+    assert np.abs((Va - Vb)[lm].astype(float)).max() < 2e-18
+    assert np.abs((Qa - Qb)[lm].astype(float)).max() < 2e-18
+
+
+def test_operation_count_of_the_jacobi_step():
+    """One Jacobi step = the drifts (as in the DHC step) plus a kick whose
+    extra work over the DHC interaction is linear in N (the coordinate sums
+    and the star terms); no jump."""
+    d = [oracle.count_ops(n)["flops"] for n in range(1, 9)]
+    j = [oracle.count_ops_jacobi(n)["flops"] for n in range(1, 9)]
+    extra = [jj - dd for jj, dd in zip(j, d)]
+    steps = np.diff(extra)
+    assert all(e > 0 for e in extra)
+    assert np.all(steps == steps[0])          # exactly linear in N
+    assert oracle.count_ops_jacobi(2)["div"] > 0 and oracle.count_ops_jacobi(2)["sqrt"] > 0
