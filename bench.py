@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--block-waves", type=int, default=1)
     ap.add_argument("--chunk", type=int, default=4096)
     ap.add_argument("--exchange", default="auto", choices=["auto", "dpp", "lds"])
+    ap.add_argument("--coords", default="dhc", choices=["dhc", "jacobi"],
+                    help="splitting coordinates: democratic heliocentric (the paper's) or Jacobi")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--cpu-steps", type=int, default=80000)
     ap.add_argument("--cpu-systems", type=int, default=256)
@@ -70,7 +72,7 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(workload: str, chunk: int):
+def measured_traffic(workload: str, chunk: int, coords: str = "dhc"):
     """HBM bytes per launch from the committed counter summary, if the kernel
     sources are still the ones it was taken on (else None)."""
     import hashlib
@@ -84,14 +86,14 @@ def measured_traffic(workload: str, chunk: int):
         with open(os.path.join(ROOT, "paper_2307_05683_amd", "csrc", name), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return None
-    if chunk != rec["chunk_steps"]:
+    if chunk != rec["chunk_steps"] or coords != "dhc":
         return None
     return rec["bytes_per_launch"].get(workload)
 
 
-def flops_per_system_step(n_planets: np.ndarray, gr: bool) -> float:
-    from paper_2307_05683_amd.flops import ALGO_FLOPS, ALGO_FLOPS_GR
-    table = ALGO_FLOPS_GR if gr else ALGO_FLOPS
+def flops_per_system_step(n_planets: np.ndarray, gr: bool, coords: str = "dhc") -> float:
+    from paper_2307_05683_amd.flops import ALGO_FLOPS, ALGO_FLOPS_GR, ALGO_FLOPS_JACOBI
+    table = ALGO_FLOPS_JACOBI if coords == "jacobi" else (ALGO_FLOPS_GR if gr else ALGO_FLOPS)
     return float(sum(table[int(n)] for n in n_planets))
 
 
@@ -100,7 +102,10 @@ def cpu_baseline(systems, args, gr_c):
     sub = systems.subset(np.arange(min(args.cpu_systems, systems.S)))
     threads = oracle.max_threads()
     t0 = time.perf_counter()
-    oracle.integrate(sub, args.cpu_steps, scheme="dkd", gr_c=gr_c, precision="d", nthreads=threads)
+    if args.coords == "jacobi":
+        oracle.jacobi_integrate(sub, args.cpu_steps, scheme="dkd", precision="d", nthreads=threads)
+    else:
+        oracle.integrate(sub, args.cpu_steps, scheme="dkd", gr_c=gr_c, precision="d", nthreads=threads)
     dt = time.perf_counter() - t0
     return {
         "value": sub.S * args.cpu_steps / dt,
@@ -162,12 +167,16 @@ def main():
     scheme = "kdk" if args.workload == "single8" else "dkd"
     systems = inputs.workload(args.workload)
     dev = torch.device("cuda:0")
-    opts = dict(packing=args.packing, block_waves=args.block_waves, chunk_steps=args.chunk, exchange=args.exchange)
+    if args.coords == "jacobi" and gr_c > 0:
+        print("the GR kick is implemented in democratic heliocentric coordinates only", file=sys.stderr)
+        sys.exit(2)
+    opts = dict(packing=args.packing, block_waves=args.block_waves, chunk_steps=args.chunk, exchange=args.exchange,
+                coords=args.coords)
     tune_table = None
     if args.packing == "tuned":
         from paper_2307_05683_amd.autotune import autotune
         print("[bench] autotuning the lane packing ...", file=sys.stderr, flush=True)
-        best, tune_table = autotune(systems, gr_c=gr_c, scheme=scheme, device=dev)
+        best, tune_table = autotune(systems, gr_c=gr_c, scheme=scheme, device=dev, coords=args.coords)
         opts.update(best)
         print("[bench] chosen: %s" % best, file=sys.stderr, flush=True)
     ens = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, device=dev, **opts)
@@ -197,7 +206,7 @@ def main():
     sys_steps = systems.S * args.steps
     value = sys_steps / gpu_s
     n_launch = -(-args.steps // opts["chunk_steps"])
-    flops_step = flops_per_system_step(systems.n_planets, gr_c > 0)
+    flops_step = flops_per_system_step(systems.n_planets, gr_c > 0, args.coords)
     achieved = flops_step * args.steps / gpu_s / 1e12
     out = {
         "metric": "system-steps/s (8-planet FP64)" if "8" in args.workload else "system-steps/s (FP64)",
@@ -220,6 +229,7 @@ def main():
             "chunk_steps": opts["chunk_steps"],
             "block_waves": opts["block_waves"],
             "exchange": opts["exchange"],
+            "coords": args.coords,
             "flagged_systems": int((flags != 0).sum()),
         },
         "roofline": {
@@ -228,7 +238,7 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": measured_traffic(args.workload, opts["chunk_steps"]),
+            "traffic": measured_traffic(args.workload, opts["chunk_steps"], args.coords),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
             "kernel": "k_step (persistent step kernel)",
             "algorithmic_flops_per_step": flops_step,
@@ -241,7 +251,8 @@ def main():
     if args.workload == "adjoint8":
         out["adjoint"] = adjoint_cost(systems, args, dev, stream, gpu_s)
     if args.workload == "uneven2to8" and args.plain_steps > 0:
-        plain = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, packing="g8", device=dev)
+        plain = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, packing="g8", coords=args.coords,
+                                      device=dev)
         plain.step_plain(10)
         torch.cuda.synchronize()
         ev0.record(stream)

@@ -79,6 +79,16 @@ enum {
   WH_EXCH_DPP = 2   /* DPP row moves only (one more pair round for 8-lane groups) */
 };
 
+/* Coordinates of the splitting. */
+enum {
+  WH_COORDS_DHC = 0,    /* democratic heliocentric (the paper's, Sec. 3) */
+  WH_COORDS_JACOBI = 1  /* Jacobi coordinates (Wisdom & Holman 1991; the paper names them for systems of
+                           two or four planets, Sec. 3.5 footnote and Sec. 6): planets in lane order, each
+                           drifting about the centre of mass of the star and the planets inside it with
+                           mu = G (m0 + m_1 + ... + m_i), and a kick of the remaining Hamiltonian; no jump.
+                           Inputs and outputs stay in the DHC layout; no GR, no reverse mode. */
+};
+
 /* Sticky per-system status bits. */
 enum {
   WH_F_NONFINITE = 1u,  /* a position or velocity became NaN or infinite */
@@ -97,9 +107,10 @@ typedef struct {
   int32_t graph_launches; /* launches per replayed HIP graph (0 = 8, < 0 = no graph) */
   double z_max;        /* WH_F_ZMAX threshold on the Stumpff argument (0 = 1.0) */
   int32_t exchange;    /* WH_EXCH_* */
+  int32_t coords;      /* WH_COORDS_* */
 } wh_config;
 
-/* Fills *cfg with the defaults above (DKD, no GR, auto packing). */
+/* Fills *cfg with the defaults above (DKD, no GR, auto packing, DHC). */
 void wh_config_default(wh_config* cfg, int32_t n_systems);
 
 /* Device workspace the context needs for this configuration and these planet

@@ -19,6 +19,7 @@ WH_DKD, WH_KDK = 0, 1
 WH_PACK_AUTO, WH_PACK_POW2, WH_PACK_G8 = -1, 0, 1
 WH_F_NONFINITE, WH_F_HYPERBOLIC, WH_F_ZMAX = 1, 2, 4
 WH_EXCH_AUTO, WH_EXCH_LDS, WH_EXCH_DPP = 0, 1, 2
+WH_COORDS_DHC, WH_COORDS_JACOBI = 0, 1
 ERRORS = {WH_EINVAL: "WH_EINVAL", WH_EWORKSPACE: "WH_EWORKSPACE", WH_EHIP: "WH_EHIP", WH_ESTATE: "WH_ESTATE"}
 
 
@@ -40,6 +41,7 @@ class Config(C.Structure):
         ("graph_launches", C.c_int32),
         ("z_max", C.c_double),
         ("exchange", C.c_int32),
+        ("coords", C.c_int32),
     ]
 
 

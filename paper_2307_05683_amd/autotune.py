@@ -2,9 +2,10 @@
 
 Candidates: packing (1/2/4/8-lane groups or always 8 lanes), partner
 exchange (DPP or LDS crossbar), wavefronts per workgroup and steps per
-launch.  Each candidate integrates the real batch for a short run; the
+launch (the splitting coordinates are the caller's choice, not a candidate:
+they change the results, not just the speed).  Each candidate integrates the real batch for a short run; the
 fastest (system-steps per second, GPU event time) wins.  Results are cached
-in a JSON file keyed by GPU architecture, scheme, GR on/off, the batch size
+in a JSON file keyed by GPU architecture, coordinates, scheme, GR on/off, the batch size
 bucket and the planet-count histogram bucket, so a repeated shape reuses
 the choice without timing again.
 
@@ -34,7 +35,7 @@ def cache_path() -> str:
     return os.environ.get("WH_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "wh_autotune.json"))
 
 
-def shape_key(n_planets, gr: bool, scheme: str) -> str:
+def shape_key(n_planets, gr: bool, scheme: str, coords: str = "dhc") -> str:
     n = np.asarray(n_planets)
     S = len(n)
     s_bucket = 1 << int(np.ceil(np.log2(max(S, 1))))
@@ -44,7 +45,7 @@ def shape_key(n_planets, gr: bool, scheme: str) -> str:
         arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     except Exception:
         arch = "unknown"
-    return "%s|%s|gr%d|S%d|%s" % (arch, scheme, int(gr), s_bucket, h_bucket)
+    return "%s|%s|%s|gr%d|S%d|%s" % (arch, coords, scheme, int(gr), s_bucket, h_bucket)
 
 
 def _load():
@@ -64,9 +65,10 @@ def _save(d):
     os.replace(tmp, p)
 
 
-def time_candidate(systems, opts, gr_c, scheme, steps, warmup, device) -> float:
+def time_candidate(systems, opts, gr_c, scheme, steps, warmup, device, coords="dhc") -> float:
     """System-steps per second of one configuration on a short run."""
-    e = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, device=device, graph_launches=-1, **opts)
+    e = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, device=device, graph_launches=-1, coords=coords,
+                              **opts)
     try:
         e.step(warmup)
         stream = torch.cuda.current_stream(device)
@@ -82,10 +84,10 @@ def time_candidate(systems, opts, gr_c, scheme, steps, warmup, device) -> float:
 
 
 def autotune(systems, gr_c: float = 0.0, scheme: str = "dkd", steps: int = 1024, warmup: int = 64,
-             device="cuda", use_cache: bool = True, candidates=None, verbose: bool = False):
+             device="cuda", use_cache: bool = True, candidates=None, verbose: bool = False, coords: str = "dhc"):
     """Return (best_options, table) for this batch; best_options can be passed
     to Ensemble(...) as keyword arguments."""
-    key = shape_key(systems.n_planets, gr_c > 0, scheme)
+    key = shape_key(systems.n_planets, gr_c > 0, scheme, coords)
     cache = _load() if use_cache else {}
     if use_cache and key in cache:
         return cache[key]["best"], cache[key]["table"]
@@ -96,7 +98,7 @@ def autotune(systems, gr_c: float = 0.0, scheme: str = "dkd", steps: int = 1024,
         opts = dict(zip(names, values))
         # the steps of a probe must cover a few launches of the candidate's chunk
         n = max(steps, 2 * opts.get("chunk_steps", 0)) if "chunk_steps" in opts else steps
-        rate = time_candidate(systems, opts, gr_c, scheme, n, warmup, device)
+        rate = time_candidate(systems, opts, gr_c, scheme, n, warmup, device, coords)
         table.append({"opts": opts, "system_steps_per_s": rate})
         if verbose:
             print("autotune %s: %.4g system-steps/s" % (opts, rate), flush=True)

@@ -210,6 +210,111 @@ __device__ __forceinline__ void kick_block(Lane& L, const Exch<G, EXCH>& ex, dou
   renorm_all(L);
 }
 
+// ---------------------------------------------------------------------------
+// Jacobi coordinates (Wisdom & Holman 1991; the paper names them for systems
+// of two or four planets).  In a Jacobi context the state rows hold each
+// planet's Jacobi position and velocity, measured from the centre of mass of
+// the star and the planets inside it (planet order = lane order of the group).
+// Per lane: M_i = m0 + m_1 + ... + m_i (the Kepler mass of its drift),
+// 1/M_{i-1}, and w_i = m_i / M_i, with which heliocentric vectors follow as
+//   h_i = x'_i + sum_{j<i} w_j x'_j.
+struct JacConst {
+  double Mi, inv_Mim1, w, ratio;   // ratio = m0 / M_{i-1} (exactly 1 for the innermost planet)
+};
+template <int G> __device__ __forceinline__ JacConst jac_const(double m0, double m, int p) {
+  JacConst c;
+  const double Mim1 = m0 + group_scan_excl<G>(m, p);
+  c.Mi = Mim1 + m;
+  c.inv_Mim1 = 1.0 / Mim1;
+  c.w = m / c.Mi;
+  c.ratio = m0 / Mim1;
+  return c;
+}
+template <int G> __device__ __forceinline__ double jac_to_helio(double x, double w, int p) {
+  return x + group_scan_excl<G>(w * x, p);
+}
+
+// Interaction kick over tau in Jacobi coordinates.  With H_I = U + sum_i G
+// M_i m'_i / |x'_i| (m'_i = m_i M_{i-1} / M_i) the Jacobi acceleration is
+//   a'_i = a_i - A_{i-1} + G M_i x'_i / |x'_i|^3,
+// a_i the Newtonian acceleration of planet i, A_{i-1} that of the centre of
+// mass of the bodies inside it; the mutual forces of those bodies cancel, so
+//   M_{i-1} A_{i-1} = G m0 sum_{k>=i} m_k Q_k / |Q_k|^3 + sum_{j<i} m_j a^pl_j
+// (Q heliocentric, a^pl the planet-planet part of a).  The star terms of
+// planet i itself are grouped as
+//   G M_i (x'_i / |x'_i|^3 - (m0 / M_{i-1}) Q_i / |Q_i|^3),
+// which is exactly zero for the innermost planet (x'_1 = Q_1, M_0 = m0) and
+// small for the others, leaving
+//   a'_i = a^pl_i - (m0 / M_{i-1}) sum_{k>i} m_k Q_k / |Q_k|^3
+//          - (1 / M_{i-1}) sum_{j<i} m_j a^pl_j + [the grouped star terms].
+// Prefix and suffix sums run as group scans.  Increments go to the low
+// parts, as in kick_block.
+// a x - b y with both products rounded (no contraction), so that equal
+// products cancel exactly.
+__device__ __forceinline__ double diff_of_products(double a, double x, double b, double y) {
+#pragma clang fp contract(off)
+  return a * x - b * y;
+}
+
+template <int G, int EXCH>
+__device__ __forceinline__ void kick_jacobi(Lane& L, const Exch<G, EXCH>& ex, const JacConst& jc, int p, double tau,
+                                            double& vkx, double& vky, double& vkz) {
+  const double qx = jac_to_helio<G>(L.qx, jc.w, p);
+  const double qy = jac_to_helio<G>(L.qy, jc.w, p);
+  const double qz = jac_to_helio<G>(L.qz, jc.w, p);
+  double ax, ay, az;
+  ex.accel(qx, qy, qz, L.m, ax, ay, az);
+  const double irq = rsqrt_full(fma(qx, qx, fma(qy, qy, qz * qz)));
+  const double irq3 = irq * irq * irq;
+  const double irp = rsqrt_full(fma(L.qx, L.qx, fma(L.qy, L.qy, L.qz * L.qz)));
+  const double kp = jc.Mi * (irp * irp * irp);
+  const double kq = (jc.Mi * jc.ratio) * irq3;
+  const double wq = L.m * irq3;
+  const double cx = fma(jc.ratio, group_suffix_excl<G>(wq * qx, p), group_scan_excl<G>(L.m * ax, p) * jc.inv_Mim1);
+  const double cy = fma(jc.ratio, group_suffix_excl<G>(wq * qy, p), group_scan_excl<G>(L.m * ay, p) * jc.inv_Mim1);
+  const double cz = fma(jc.ratio, group_suffix_excl<G>(wq * qz, p), group_scan_excl<G>(L.m * az, p) * jc.inv_Mim1);
+  const double dvx = tau * ((ax - cx) + diff_of_products(kp, L.qx, kq, qx));
+  const double dvy = tau * ((ay - cy) + diff_of_products(kp, L.qy, kq, qy));
+  const double dvz = tau * ((az - cz) + diff_of_products(kp, L.qz, kq, qz));
+  L.cvx += dvx; L.cvy += dvy; L.cvz += dvz;
+  vkx = L.vx + dvx; vky = L.vy + dvy; vkz = L.vz + dvz;
+  renorm_all(L);
+}
+
+// Jacobi state of the lane -> democratic heliocentric (Q heliocentric, V
+// barycentric): heliocentric u from v', then V = u - sum_j m_j u_j / M_n.
+template <int G> __device__ __forceinline__ void jacobi_to_dhc(Lane& L, int p) {
+  const JacConst jc = jac_const<G>(L.m0, L.m, p);
+  const double Mn = L.m0 + group_sum<G>(L.m);
+  const double ux = jac_to_helio<G>(L.vx, jc.w, p);
+  const double uy = jac_to_helio<G>(L.vy, jc.w, p);
+  const double uz = jac_to_helio<G>(L.vz, jc.w, p);
+  L.qx = jac_to_helio<G>(L.qx, jc.w, p);
+  L.qy = jac_to_helio<G>(L.qy, jc.w, p);
+  L.qz = jac_to_helio<G>(L.qz, jc.w, p);
+  double px, py, pz;
+  group_momentum<G>(L.m, ux, uy, uz, px, py, pz);
+  L.vx = ux - px / Mn;
+  L.vy = uy - py / Mn;
+  L.vz = uz - pz / Mn;
+}
+
+// Democratic heliocentric -> Jacobi: u = V + sum_j m_j V_j / m0 (heliocentric
+// velocity), x'_i = h_i - sum_{j<i} m_j h_j / M_{i-1} for h = Q and u.
+template <int G> __device__ __forceinline__ void dhc_to_jacobi(Lane& L, int p) {
+  const JacConst jc = jac_const<G>(L.m0, L.m, p);
+  double px, py, pz;
+  group_momentum<G>(L.m, L.vx, L.vy, L.vz, px, py, pz);
+  const double ux = L.vx + px / L.m0, uy = L.vy + py / L.m0, uz = L.vz + pz / L.m0;
+  L.vx = ux - group_scan_excl<G>(L.m * ux, p) * jc.inv_Mim1;
+  L.vy = uy - group_scan_excl<G>(L.m * uy, p) * jc.inv_Mim1;
+  L.vz = uz - group_scan_excl<G>(L.m * uz, p) * jc.inv_Mim1;
+  const double qx = L.qx, qy = L.qy, qz = L.qz;
+  L.qx = qx - group_scan_excl<G>(L.m * qx, p) * jc.inv_Mim1;
+  L.qy = qy - group_scan_excl<G>(L.m * qy, p) * jc.inv_Mim1;
+  L.qz = qz - group_scan_excl<G>(L.m * qz, p) * jc.inv_Mim1;
+}
+
 // n_steps steps for one lane.  The stored state X_u is "after a kick block,
 // before its closing drift" (DKD) or "after a drift" (KDK):
 //   DKD loop body: K(tk) . J(h) I(dt) J(h)        tk = h on the first step out
@@ -218,7 +323,10 @@ __device__ __forceinline__ void kick_block(Lane& L, const Exch<G, EXCH>& ex, dou
 //                                                 (h, dt) afterwards
 // (operators in the order they act).  The state is kept as a double-double
 // (rounded value + compensation); see drift and kick_block.
-template <int G, bool GR, int SCHEME, int EXCH>
+//
+// In Jacobi coordinates (JAC) the loop bodies are K(tk) . I(dt) (DKD) and
+// I(ti) . K(dt) (KDK), each planet drifting about mu = G M_i, with no jump.
+template <int G, bool GR, int SCHEME, int EXCH, bool JAC = false>
 __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane) {
   Exch<G, EXCH> ex;
   ex.init(lane, L.m);
@@ -228,7 +336,25 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
   const double kg = GR ? p.kgr * L.m0 * L.m0 : 0.0;
   KepDiag dg{0.0, 1.0e300};
   double vkx, vky, vkz;
-  if (SCHEME == WH_DKD) {
+  if (JAC) {
+    const int pg = lane & (G - 1);
+    const JacConst jc = jac_const<G>(L.m0, L.m, pg);
+    if (SCHEME == WH_DKD) {
+      double tk = L.first ? h : dt;
+      for (int s = 0; s < p.n_steps; ++s) {
+        drift(L, jc.Mi, tk, dg);
+        tk = dt;
+        kick_jacobi<G, EXCH>(L, ex, jc, pg, dt, vkx, vky, vkz);
+      }
+    } else {
+      double ti = L.first ? h : dt;
+      for (int s = 0; s < p.n_steps; ++s) {
+        kick_jacobi<G, EXCH>(L, ex, jc, pg, ti, vkx, vky, vkz);
+        ti = dt;
+        drift(L, jc.Mi, dt, dg);
+      }
+    }
+  } else if (SCHEME == WH_DKD) {
     double tk = L.first ? h : dt;
     for (int s = 0; s < p.n_steps; ++s) {
       drift(L, L.m0, tk, dg);
@@ -260,26 +386,26 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
   }
 }
 
-template <int G, bool GR, int SCHEME, int EXCH>
+template <int G, bool GR, int SCHEME, int EXCH, bool JAC>
 __device__ void step_group(const StepParams& p, int slot, int lane) {
   Lane L = load_lane(p, slot);
-  step_lane<G, GR, SCHEME, EXCH>(p, L, lane);
+  step_lane<G, GR, SCHEME, EXCH, JAC>(p, L, lane);
   store_lane(p, slot, L);
 }
 
 // The compiler fits every variant in 128 VGPRs without spills, so four
 // wavefronts stay resident per SIMD; a launch holds one wave per 64 lanes of
 // the packed ensemble and each wave runs its whole chunk of steps.
-template <bool GR, int SCHEME, int EXCH>
+template <bool GR, int SCHEME, int EXCH, bool JAC = false>
 __global__ __launch_bounds__(256) void k_step(StepParams p) {
   const int lane = threadIdx.x & 63;
   const int wave = p.wave0 + (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (wave >= p.w8) return;
   const int slot = wave * 64 + lane;
-  if (wave < p.w1) step_group<1, GR, SCHEME, EXCH>(p, slot, lane);
-  else if (wave < p.w2) step_group<2, GR, SCHEME, EXCH>(p, slot, lane);
-  else if (wave < p.w4) step_group<4, GR, SCHEME, EXCH>(p, slot, lane);
-  else step_group<8, GR, SCHEME, EXCH>(p, slot, lane);
+  if (wave < p.w1) step_group<1, GR, SCHEME, EXCH, JAC>(p, slot, lane);
+  else if (wave < p.w2) step_group<2, GR, SCHEME, EXCH, JAC>(p, slot, lane);
+  else if (wave < p.w4) step_group<4, GR, SCHEME, EXCH, JAC>(p, slot, lane);
+  else step_group<8, GR, SCHEME, EXCH, JAC>(p, slot, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -295,21 +421,25 @@ struct SyncParams {
   double* e_out;
 };
 
-template <int G, bool GR, int SCHEME> __device__ void sync_lane(const StepParams& p, Lane& L, int lane) {
+template <int G, bool GR, int SCHEME, bool JAC = false>
+__device__ void sync_lane(const StepParams& p, Lane& L, int lane) {
+  const int pg = lane & (G - 1);
   if (!L.first) {   // uniform over the group: one system, one flag
     const double h = 0.5 * L.dt;
     if (SCHEME == WH_DKD) {
       KepDiag dg{0.0, 1.0e300};
-      drift(L, L.m0, h, dg);
+      drift(L, JAC ? jac_const<G>(L.m0, L.m, pg).Mi : L.m0, h, dg);
     } else {
       Exch<G, 0> ex;
       ex.init(lane, L.m);
       double vkx, vky, vkz;
-      kick_block<G, GR, 0>(L, ex, 1.0 / L.m0, GR ? p.kgr * L.m0 * L.m0 : 0.0, h, h, 0.0, vkx, vky, vkz);
+      if (JAC) kick_jacobi<G, 0>(L, ex, jac_const<G>(L.m0, L.m, pg), pg, h, vkx, vky, vkz);
+      else kick_block<G, GR, 0>(L, ex, 1.0 / L.m0, GR ? p.kgr * L.m0 * L.m0 : 0.0, h, h, 0.0, vkx, vky, vkz);
     }
   }
   L.qx += L.cqx; L.qy += L.cqy; L.qz += L.cqz;
   L.vx += L.cvx; L.vy += L.cvy; L.vz += L.cvz;
+  if (JAC) jacobi_to_dhc<G>(L, pg);
 }
 
 // Energy of the lane's system (every lane of the group gets it).
@@ -332,10 +462,10 @@ template <int G, bool GR> __device__ double group_energy(const StepParams& p, co
   return e + (sx * sx + sy * sy + sz * sz) / (2.0 * L.m0);
 }
 
-template <int G, bool GR, int SCHEME> __device__ void sync_group(const SyncParams& q, int slot, int lane) {
+template <int G, bool GR, int SCHEME, bool JAC> __device__ void sync_group(const SyncParams& q, int slot, int lane) {
   const StepParams& p = q.sp;
   Lane L = load_lane(p, slot);
-  sync_lane<G, GR, SCHEME>(p, L, lane);
+  sync_lane<G, GR, SCHEME, JAC>(p, L, lane);
   if (q.Q_out && L.sys >= 0 && L.pl >= 0) {
     size_t o = ((size_t)L.sys * 8 + L.pl) * 3;
     q.Q_out[o] = L.qx; q.Q_out[o + 1] = L.qy; q.Q_out[o + 2] = L.qz;
@@ -366,17 +496,35 @@ template <int G, bool GR, int SCHEME> __device__ void sync_group(const SyncParam
   }
 }
 
-template <bool GR, int SCHEME>
+template <bool GR, int SCHEME, bool JAC = false>
 __global__ __launch_bounds__(256) void k_sync(SyncParams q) {
   const StepParams& p = q.sp;
   const int lane = threadIdx.x & 63;
   const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (wave >= p.w8) return;
   const int slot = wave * 64 + lane;
-  if (wave < p.w1) sync_group<1, GR, SCHEME>(q, slot, lane);
-  else if (wave < p.w2) sync_group<2, GR, SCHEME>(q, slot, lane);
-  else if (wave < p.w4) sync_group<4, GR, SCHEME>(q, slot, lane);
-  else sync_group<8, GR, SCHEME>(q, slot, lane);
+  if (wave < p.w1) sync_group<1, GR, SCHEME, JAC>(q, slot, lane);
+  else if (wave < p.w2) sync_group<2, GR, SCHEME, JAC>(q, slot, lane);
+  else if (wave < p.w4) sync_group<4, GR, SCHEME, JAC>(q, slot, lane);
+  else sync_group<8, GR, SCHEME, JAC>(q, slot, lane);
+}
+
+// Initial state of a Jacobi context: the gathered DHC state (compensation
+// zero) converted in place.
+template <int G> __device__ void to_jacobi_group(const StepParams& p, int slot, int lane) {
+  Lane L = load_lane(p, slot);
+  dhc_to_jacobi<G>(L, lane & (G - 1));
+  store_lane(p, slot, L);
+}
+__global__ __launch_bounds__(256) void k_to_jacobi(StepParams p) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  const int slot = wave * 64 + lane;
+  if (wave < p.w1) to_jacobi_group<1>(p, slot, lane);
+  else if (wave < p.w2) to_jacobi_group<2>(p, slot, lane);
+  else if (wave < p.w4) to_jacobi_group<4>(p, slot, lane);
+  else to_jacobi_group<8>(p, slot, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -806,6 +954,10 @@ bool config_ok(const wh_config* c, std::string& why) {
   if (c->chunk_steps < 0) { why = "chunk_steps must be >= 0"; return false; }
   if (!(c->z_max >= 0.0)) { why = "z_max must be >= 0"; return false; }
   if (c->exchange < WH_EXCH_AUTO || c->exchange > WH_EXCH_DPP) { why = "unknown exchange"; return false; }
+  if (c->coords != WH_COORDS_DHC && c->coords != WH_COORDS_JACOBI) { why = "unknown coordinates"; return false; }
+  if (c->coords == WH_COORDS_JACOBI && c->gr_c > 0) {
+    why = "the GR kick is implemented in democratic heliocentric coordinates only"; return false;
+  }
   if (!(c->gr_c == c->gr_c)) { why = "gr_c is NaN"; return false; }
   return true;
 }
@@ -864,6 +1016,11 @@ StepParams step_params(const wh_ctx* c, int n_steps) {
 template <int EXCH>
 void launch_step_exch(const wh_ctx* c, const StepParams& p, dim3 grid, dim3 block, hipStream_t st) {
   const bool gr = c->cfg.gr_c > 0;
+  if (c->cfg.coords == WH_COORDS_JACOBI) {
+    if (c->cfg.scheme == WH_DKD) hipLaunchKernelGGL((k_step<false, WH_DKD, EXCH, true>), grid, block, 0, st, p);
+    else hipLaunchKernelGGL((k_step<false, WH_KDK, EXCH, true>), grid, block, 0, st, p);
+    return;
+  }
   if (c->cfg.scheme == WH_DKD) {
     if (gr) hipLaunchKernelGGL((k_step<true, WH_DKD, EXCH>), grid, block, 0, st, p);
     else hipLaunchKernelGGL((k_step<false, WH_DKD, EXCH>), grid, block, 0, st, p);
@@ -896,7 +1053,10 @@ wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st
   q.e_out = e;
   dim3 block(64), grid(c->P.nwaves);
   const bool gr = c->cfg.gr_c > 0;
-  if (c->cfg.scheme == WH_DKD) {
+  if (c->cfg.coords == WH_COORDS_JACOBI) {
+    if (c->cfg.scheme == WH_DKD) hipLaunchKernelGGL((k_sync<false, WH_DKD, true>), grid, block, 0, st, q);
+    else hipLaunchKernelGGL((k_sync<false, WH_KDK, true>), grid, block, 0, st, q);
+  } else if (c->cfg.scheme == WH_DKD) {
     if (gr) hipLaunchKernelGGL((k_sync<true, WH_DKD>), grid, block, 0, st, q);
     else hipLaunchKernelGGL((k_sync<false, WH_DKD>), grid, block, 0, st, q);
   } else {
@@ -960,6 +1120,7 @@ void wh_config_default(wh_config* cfg, int32_t n_systems) {
   cfg->graph_launches = 8;
   cfg->z_max = 1.0;
   cfg->exchange = WH_EXCH_AUTO;
+  cfg->coords = WH_COORDS_DHC;
 }
 
 size_t wh_workspace_bytes(const wh_config* cfg, const int32_t* n_planets) {
@@ -1043,6 +1204,8 @@ wh_status wh_init(wh_ctx** out, const wh_config* cfg, const int32_t* n_planets, 
                      c->slot_pl, m0, m, Q, V, dt);
   hipLaunchKernelGGL(k_fill_u32, dim3((S + 255) / 256), dim3(256), 0, stream, c->flags, 0u, S);
   hipLaunchKernelGGL(k_fill_u32, dim3((S + 255) / 256), dim3(256), 0, stream, (uint32_t*)c->synced, 1u, S);
+  if (cfg->coords == WH_COORDS_JACOBI)
+    hipLaunchKernelGGL(k_to_jacobi, dim3(c->P.nwaves), dim3(64), 0, stream, step_params(c, 0));
   if ((st = hip_check(hipGetLastError(), "init kernels"))) {
     delete c;
     return st;
@@ -1138,6 +1301,8 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
   if (n_steps < 0 || ckpt_every < 1 || ckpt_every > (1 << 30)) return fail(WH_EINVAL, "bad n_steps or ckpt_every");
   if (((uintptr_t)tape & 255) != 0) return fail(WH_EINVAL, "tape must be 256-byte aligned");
   if (c->cfg.scheme != WH_DKD) return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD");
+  if (c->cfg.coords != WH_COORDS_DHC)
+    return fail(WH_ESTATE, "reverse mode is implemented in democratic heliocentric coordinates");
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
   TapeLayout T = tape_layout(c->P.ns, n_steps, ckpt_every);
   if (tape_bytes < T.total) return fail(WH_EWORKSPACE, "tape too small: need " + std::to_string(T.total) + " bytes");

@@ -31,9 +31,9 @@ __device__ __forceinline__ double rsqrt_full(double x) {
 }
 
 // ---------------------------------------------------------------------------
-// Cross-lane moves of 64-bit values (two 32-bit moves each).
-// Every pattern used here reads a lane of the same row, so no lane ever
-// reads an invalid source and the "old" operand is never used.
+// Cross-lane moves of 64-bit values (two 32-bit moves each), with bound_ctrl
+// set: a lane whose source lies outside its 16-lane row reads 0 (only the row
+// shifts of the group scans below do that, and they mask such lanes out).
 template <int CTRL> __device__ __forceinline__ double dpp(double v) {
   int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
   int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
@@ -68,6 +68,41 @@ template <int G> __device__ __forceinline__ int group_or(int v) {
   if (G >= 4) v |= dpp_i<DPP_XOR2>(v);
   if (G >= 8) v |= dpp_i<DPP_HALF_MIRROR>(v);
   return v;
+}
+
+// Prefix and suffix sums inside an aligned G-lane group (p = lane index in
+// the group), Hillis-Steele over DPP row shifts: row_shr:n hands lane l the
+// value of lane l - n, row_shl:n that of lane l + n.  Groups never straddle a
+// 16-lane row, so every needed source is in the row; sources from the
+// neighbouring group are masked off.
+constexpr int DPP_ROW_SHL1 = 0x101, DPP_ROW_SHL2 = 0x102, DPP_ROW_SHL4 = 0x104;
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114;
+
+// sum over lanes p' <= p
+template <int G> __device__ __forceinline__ double group_scan_incl(double v, int p) {
+  if (G >= 2) { double t = dpp<DPP_ROW_SHR1>(v); v += (p >= 1) ? t : 0.0; }
+  if (G >= 4) { double t = dpp<DPP_ROW_SHR2>(v); v += (p >= 2) ? t : 0.0; }
+  if (G >= 8) { double t = dpp<DPP_ROW_SHR4>(v); v += (p >= 4) ? t : 0.0; }
+  return v;
+}
+// sum over lanes p' < p
+template <int G> __device__ __forceinline__ double group_scan_excl(double v, int p) {
+  if (G == 1) return 0.0;
+  double t = dpp<DPP_ROW_SHR1>(v);
+  return group_scan_incl<G>((p >= 1) ? t : 0.0, p);
+}
+// sum over lanes p' >= p
+template <int G> __device__ __forceinline__ double group_suffix_incl(double v, int p) {
+  if (G >= 2) { double t = dpp<DPP_ROW_SHL1>(v); v += (p + 1 < G) ? t : 0.0; }
+  if (G >= 4) { double t = dpp<DPP_ROW_SHL2>(v); v += (p + 2 < G) ? t : 0.0; }
+  if (G >= 8) { double t = dpp<DPP_ROW_SHL4>(v); v += (p + 4 < G) ? t : 0.0; }
+  return v;
+}
+// sum over lanes p' > p
+template <int G> __device__ __forceinline__ double group_suffix_excl(double v, int p) {
+  if (G == 1) return 0.0;
+  double t = dpp<DPP_ROW_SHL1>(v);
+  return group_suffix_incl<G>((p + 1 < G) ? t : 0.0, p);
 }
 
 // ---------------------------------------------------------------------------

@@ -16,6 +16,7 @@ from ._lib import check
 SCHEMES = {"dkd": _lib.WH_DKD, "kdk": _lib.WH_KDK}
 PACKINGS = {"auto": _lib.WH_PACK_AUTO, "pow2": _lib.WH_PACK_POW2, "g8": _lib.WH_PACK_G8}
 EXCHANGES = {"auto": _lib.WH_EXCH_AUTO, "lds": _lib.WH_EXCH_LDS, "dpp": _lib.WH_EXCH_DPP}
+COORDS = {"dhc": _lib.WH_COORDS_DHC, "jacobi": _lib.WH_COORDS_JACOBI}
 
 
 def _stream(device) -> int:
@@ -37,7 +38,7 @@ class Ensemble:
     """
 
     def __init__(self, n_planets, m0, m, Q, V, dt, *, gr_c=0.0, scheme="dkd", packing="auto", block_waves=1,
-                 chunk_steps=4096, graph_launches=8, z_max=1.0, exchange="auto", device="cuda"):
+                 chunk_steps=4096, graph_launches=8, z_max=1.0, exchange="auto", coords="dhc", device="cuda"):
         L = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("Ensemble needs a GPU (no CPU path exists)")
@@ -55,6 +56,7 @@ class Ensemble:
         cfg.graph_launches = int(graph_launches)
         cfg.z_max = float(z_max)
         cfg.exchange = EXCHANGES[exchange] if isinstance(exchange, str) else int(exchange)
+        cfg.coords = COORDS[coords] if isinstance(coords, str) else int(coords)
         self.cfg = cfg
         self.gr_c = float(gr_c)
         self.scheme = scheme
