@@ -57,6 +57,7 @@ def lib():
             "or_jacobi_kick_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld], None),
             "or_jacobi_kick_direct_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld], None),
             "or_count_ops_jacobi": ([i, i, i, i, i, _PL], None),
+            "or_saba_coeffs": ([i, _PLD, _PLD], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -78,7 +79,7 @@ def _i(a):
     return np.ascontiguousarray(a, dtype=np.int32)
 
 
-SCHEMES = {"dkd": 0, "kdk": 1}
+SCHEMES = {"dkd": 0, "kdk": 1, "saba2": 2, "saba3": 3, "saba4": 4}
 
 
 def kepler(Q, V, mu, tau, return_X=False):
@@ -285,3 +286,10 @@ def count_ops_jacobi(n_planets=8, n_halley=2, n_newton=2, terms_halley=4, terms_
     d = dict(add=int(c[0]), mul=int(c[1]), div=int(c[2]), sqrt=int(c[3]))
     d["flops"] = d["add"] + d["mul"] + d["div"] + d["sqrt"]
     return d
+
+
+def saba_coeffs(n):
+    """SABA_n coefficients (c_1..c_{n+1}, d_1..d_n) from Gauss-Legendre quadrature."""
+    c = np.zeros(n + 1, dtype=LD); d = np.zeros(n, dtype=LD)
+    lib().or_saba_coeffs(int(n), c, d)
+    return c, d

@@ -414,6 +414,73 @@ template <class T> void step(Sys<T>& s, const T& dt, int scheme, const T& gr_c, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// SABA_n splittings (Laskar & Robutel 2001) for H = A + B with A = the Kepler
+// part and B the perturbation:
+//   exp(c_1 dt A) exp(d_1 dt B) exp(c_2 dt A) ... exp(d_n dt B) exp(c_{n+1} dt A),
+// with d_k the weights of n-point Gauss-Legendre quadrature on [0, 1], c_1
+// its first node, c_k the gaps between consecutive nodes and c_{n+1} = 1 -
+// the last node.  n = 1 is the drift-kick-drift step.  The error is
+// O(eps dt^(2n) + eps^2 dt^2) for a perturbation of relative size eps.
+// Schemes 2, 3, 4 of the step functions below are SABA_2, SABA_3, SABA_4.
+struct Saba {
+  int n;
+  ld c[6], d[5];
+};
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton's method on the
+// Legendre polynomial P_n (three-term recurrence), mapped to [0, 1].
+Saba saba_coeffs(int n) {
+  Saba q;
+  q.n = n;
+  ld x[5], w[5];
+  for (int i = 0; i < n; ++i) {
+    ld z = std::cos(3.14159265358979323846264338327950288L * (i + 0.75L) / (n + 0.5L));
+    for (int it = 0; it < 100; ++it) {
+      ld p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        ld p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      ld pn = n == 1 ? z : p1, pm = n == 1 ? 1 : p0;    // P_n(z), P_{n-1}(z)
+      ld dp = n * (z * pn - pm) / (z * z - 1);
+      ld dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-19L) {
+        x[i] = z;
+        w[i] = 2 / ((1 - z * z) * dp * dp);
+        break;
+      }
+      x[i] = z;
+      w[i] = 2 / ((1 - z * z) * dp * dp);
+    }
+  }
+  // ascending nodes on [0, 1]
+  ld t[5], u[5];
+  for (int i = 0; i < n; ++i) {
+    t[i] = (1 - x[i]) / 2;   // x descending -> t ascending
+    u[i] = w[i] / 2;
+  }
+  q.c[0] = t[0];
+  for (int k = 1; k < n; ++k) q.c[k] = t[k] - t[k - 1];
+  q.c[n] = 1 - t[n - 1];
+  for (int k = 0; k < n; ++k) q.d[k] = u[k];
+  return q;
+}
+
+// DHC, no GR: B = H_I + H_J, whose flows commute (the interaction is
+// translation invariant), so exp(d dt B) = I(d dt) J(d dt) exactly.
+template <class T> void saba_step(Sys<T>& s, const T& dt, const Saba& q) {
+  typedef typename Real<T>::type R;
+  for (int k = 0; k < q.n; ++k) {
+    kepler_all(s, dt * T(R(q.c[k])));
+    interaction(s, dt * T(R(q.d[k])));
+    jump(s, dt * T(R(q.d[k])));
+  }
+  kepler_all(s, dt * T(R(q.c[q.n])));
+}
+
 // Energy (Sec. 3.1 Hamiltonian, H_0 = 0 in the barycentric frame):
 //   sum_i [m_i V_i^2/2 - m0 m_i/|Q_i|] - sum_{i<j} m_i m_j/|Q_ij|
 //   + |sum_i m_i V_i|^2 / (2 m0)  [ - sum_i 3 m0^2 m_i / (c^2 |Q_i|^2) ].
@@ -468,7 +535,12 @@ template <class T> void integrate_arrays(int S, int nmax, const int* np, const T
   for (int k = 0; k < S; ++k) {
     Sys<T> s;
     load(s, k, nmax, np, m0, m, Q, V);
-    for (long t = 0; t < n_steps; ++t) step(s, dt[k], scheme, gr_c, gr);
+    if (scheme >= 2) {
+      Saba q = saba_coeffs(scheme);
+      for (long t = 0; t < n_steps; ++t) saba_step(s, dt[k], q);
+    } else {
+      for (long t = 0; t < n_steps; ++t) step(s, dt[k], scheme, gr_c, gr);
+    }
     store(s, k, nmax, Q, V);
   }
 }
@@ -648,6 +720,15 @@ void jac_drift(JSys<ld>& s, ld tau) {
 
 // scheme 0: K(dt/2) I(dt) K(dt/2); scheme 1: I(dt/2) K(dt) I(dt/2).
 void jac_step(JSys<ld>& s, ld dt, int scheme) {
+  if (scheme >= 2) {     // SABA_n with B = H_I
+    Saba q = saba_coeffs(scheme);
+    for (int k = 0; k < q.n; ++k) {
+      jac_drift(s, dt * q.c[k]);
+      jac_kick(s, dt * q.d[k]);
+    }
+    jac_drift(s, dt * q.c[q.n]);
+    return;
+  }
   ld h = dt * 0.5L;
   if (scheme == 0) {
     jac_drift(s, h);
@@ -750,6 +831,13 @@ void or_integrate_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, 
 void or_integrate_d(int S, int nmax, const int* np, const double* m0, const double* m, double* Q, double* V,
                     const double* dt, long n_steps, int scheme, double gr_c, int nthreads) {
   integrate_arrays<double>(S, nmax, np, m0, m, Q, V, dt, n_steps, scheme, gr_c, nthreads);
+}
+
+// SABA_n coefficients: c[0..n], d[0..n-1].
+void or_saba_coeffs(int n, ld* c, ld* d) {
+  Saba q = saba_coeffs(n);
+  for (int k = 0; k <= n; ++k) c[k] = q.c[k];
+  for (int k = 0; k < n; ++k) d[k] = q.d[k];
 }
 
 // ---- Jacobi-coordinate map (Wisdom & Holman 1991) ----------------------
