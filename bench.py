@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--block-waves", type=int, default=1)
     ap.add_argument("--chunk", type=int, default=4096)
     ap.add_argument("--exchange", default="auto", choices=["auto", "dpp", "lds"])
+    ap.add_argument("--scheme", default=None, choices=["dkd", "kdk", "saba2", "saba3", "saba4"],
+                    help="step composition (default: the workload's, drift-kick-drift)")
     ap.add_argument("--coords", default="dhc", choices=["dhc", "jacobi"],
                     help="splitting coordinates: democratic heliocentric (the paper's) or Jacobi")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
@@ -91,21 +93,23 @@ def measured_traffic(workload: str, chunk: int, coords: str = "dhc"):
     return rec["bytes_per_launch"].get(workload)
 
 
-def flops_per_system_step(n_planets: np.ndarray, gr: bool, coords: str = "dhc") -> float:
+def flops_per_system_step(n_planets: np.ndarray, gr: bool, coords: str = "dhc", scheme: str = "dkd") -> float:
+    """A SABA_n step is n drifts and n kicks: n times the counted step."""
     from paper_2307_05683_amd.flops import ALGO_FLOPS, ALGO_FLOPS_GR, ALGO_FLOPS_JACOBI
     table = ALGO_FLOPS_JACOBI if coords == "jacobi" else (ALGO_FLOPS_GR if gr else ALGO_FLOPS)
-    return float(sum(table[int(n)] for n in n_planets))
+    stages = int(scheme[4:]) if scheme.startswith("saba") else 1
+    return float(stages * sum(table[int(n)] for n in n_planets))
 
 
-def cpu_baseline(systems, args, gr_c):
+def cpu_baseline(systems, args, gr_c, scheme="dkd"):
     import oracle
     sub = systems.subset(np.arange(min(args.cpu_systems, systems.S)))
     threads = oracle.max_threads()
     t0 = time.perf_counter()
     if args.coords == "jacobi":
-        oracle.jacobi_integrate(sub, args.cpu_steps, scheme="dkd", precision="d", nthreads=threads)
+        oracle.jacobi_integrate(sub, args.cpu_steps, scheme=scheme, precision="d", nthreads=threads)
     else:
-        oracle.integrate(sub, args.cpu_steps, scheme="dkd", gr_c=gr_c, precision="d", nthreads=threads)
+        oracle.integrate(sub, args.cpu_steps, scheme=scheme, gr_c=gr_c, precision="d", nthreads=threads)
     dt = time.perf_counter() - t0
     return {
         "value": sub.S * args.cpu_steps / dt,
@@ -164,7 +168,7 @@ def main():
     from paper_2307_05683_amd.ensemble import Ensemble
 
     gr_c = inputs.GR_C if args.workload == "large8gr" else 0.0
-    scheme = "kdk" if args.workload == "single8" else "dkd"
+    scheme = args.scheme or ("kdk" if args.workload == "single8" else "dkd")
     systems = inputs.workload(args.workload)
     dev = torch.device("cuda:0")
     if args.coords == "jacobi" and gr_c > 0:
@@ -206,7 +210,7 @@ def main():
     sys_steps = systems.S * args.steps
     value = sys_steps / gpu_s
     n_launch = -(-args.steps // opts["chunk_steps"])
-    flops_step = flops_per_system_step(systems.n_planets, gr_c > 0, args.coords)
+    flops_step = flops_per_system_step(systems.n_planets, gr_c > 0, args.coords, scheme)
     achieved = flops_step * args.steps / gpu_s / 1e12
     out = {
         "metric": "system-steps/s (8-planet FP64)" if "8" in args.workload else "system-steps/s (FP64)",
@@ -230,6 +234,7 @@ def main():
             "block_waves": opts["block_waves"],
             "exchange": opts["exchange"],
             "coords": args.coords,
+            "scheme": scheme,
             "flagged_systems": int((flags != 0).sum()),
         },
         "roofline": {
@@ -266,7 +271,7 @@ def main():
     ens.close()
     if not args.no_cpu:
         print("[bench] CPU baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(systems, args, gr_c)
+        out["cpu_baseline"] = cpu_baseline(systems, args, gr_c, scheme)
     print(json.dumps(out), flush=True)
 
 

@@ -61,8 +61,17 @@ enum {
 
 /* Step composition (Sec. 3.1). */
 enum {
-  WH_DKD = 0, /* K(dt/2) J(dt/2) I(dt) J(dt/2) K(dt/2): the paper's step */
-  WH_KDK = 1  /* I(dt/2) J(dt/2) K(dt) J(dt/2) I(dt/2)  (I includes GR) */
+  WH_DKD = 0,   /* K(dt/2) J(dt/2) I(dt) J(dt/2) K(dt/2): the paper's step */
+  WH_KDK = 1,   /* I(dt/2) J(dt/2) K(dt) J(dt/2) I(dt/2)  (I includes GR) */
+  /* Higher-order splittings (Sec. 3.1 mentions them; the paper uses none):
+   * SABA_n of Laskar & Robutel (2001), K(c_1 dt) B(d_1 dt) K(c_2 dt) ...
+   * B(d_n dt) K(c_{n+1} dt) with Gauss-Legendre coefficients and B the whole
+   * perturbation (I and J together in DHC, the Jacobi kick in Jacobi
+   * coordinates); error O(eps dt^(2n) + eps^2 dt^2), n drifts' and kicks'
+   * cost per step.  Not with GR, not in reverse mode. */
+  WH_SABA2 = 2,
+  WH_SABA3 = 3,
+  WH_SABA4 = 4
 };
 
 /* Lane packings of systems onto 64-lane wavefronts. */

@@ -49,7 +49,13 @@ struct StepParams {
   int n_steps;
   double kgr;            // 6 / c^2, or 0 without GR
   double zlim;           // WH_F_ZMAX threshold
+  int saba_n;            // SABA_n: number of kicks per step (0 otherwise)
+  double sc[5];          // SABA_n drift coefficients c_1 .. c_{n+1} (c_{n+1} = c_1)
+  double sd[4];          // SABA_n kick coefficients d_1 .. d_n
 };
+
+// Kernel scheme id of the SABA_n family (n read from StepParams).
+constexpr int SCHEME_SABA = 2;
 
 struct Lane {
   double qx, qy, qz, vx, vy, vz, m, m0, dt;
@@ -336,7 +342,31 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
   const double kg = GR ? p.kgr * L.m0 * L.m0 : 0.0;
   KepDiag dg{0.0, 1.0e300};
   double vkx, vky, vkz;
-  if (JAC) {
+  if (SCHEME == SCHEME_SABA) {
+    // SABA_n: K(c_1 dt) B(d_1 dt) K(c_2 dt) ... B(d_n dt) K(c_{n+1} dt), the
+    // closing drift merged with the next step's opening one (c_{n+1} = c_1).
+    // B is the whole perturbation: I and J together in DHC (their flows
+    // commute without GR), the Jacobi kick in Jacobi coordinates.
+    const int pg = lane & (G - 1);
+    JacConst jc{0.0, 0.0, 0.0, 0.0};
+    if (JAC) jc = jac_const<G>(L.m0, L.m, pg);
+    const double mu = JAC ? jc.Mi : L.m0;
+    const double c1dt = p.sc[0] * dt;
+    double tk = L.first ? c1dt : 2.0 * c1dt;
+    for (int s = 0; s < p.n_steps; ++s) {
+      drift(L, mu, tk, dg);
+      tk = 2.0 * c1dt;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (k < p.saba_n) {
+          const double tb = p.sd[k] * dt;
+          if (JAC) kick_jacobi<G, EXCH>(L, ex, jc, pg, tb, vkx, vky, vkz);
+          else kick_block<G, false, EXCH>(L, ex, inv_m0, 0.0, 0.5 * tb, tb, 0.5 * tb, vkx, vky, vkz);
+          if (k + 1 < p.saba_n) drift(L, mu, p.sc[k + 1] * dt, dg);
+        }
+      }
+    }
+  } else if (JAC) {
     const int pg = lane & (G - 1);
     const JacConst jc = jac_const<G>(L.m0, L.m, pg);
     if (SCHEME == WH_DKD) {
@@ -409,8 +439,9 @@ __global__ __launch_bounds__(256) void k_step(StepParams p) {
 }
 
 // ---------------------------------------------------------------------------
-// Synchronized copy: DKD applies the pending half drift K(h); KDK applies the
-// pending half kick J(h) [I + GR](h).  A synchronized state is left as is.
+// Synchronized copy: DKD applies the pending half drift K(h), SABA_n the
+// pending drift K(c_1 dt); KDK applies the pending half kick J(h) [I + GR](h).
+// A synchronized state is left as is.
 // The result is the compensated state plus the half step's increments.
 struct SyncParams {
   StepParams sp;
@@ -426,9 +457,10 @@ __device__ void sync_lane(const StepParams& p, Lane& L, int lane) {
   const int pg = lane & (G - 1);
   if (!L.first) {   // uniform over the group: one system, one flag
     const double h = 0.5 * L.dt;
-    if (SCHEME == WH_DKD) {
+    if (SCHEME == WH_DKD || SCHEME == SCHEME_SABA) {
       KepDiag dg{0.0, 1.0e300};
-      drift(L, JAC ? jac_const<G>(L.m0, L.m, pg).Mi : L.m0, h, dg);
+      const double tau = SCHEME == SCHEME_SABA ? p.sc[0] * L.dt : h;
+      drift(L, JAC ? jac_const<G>(L.m0, L.m, pg).Mi : L.m0, tau, dg);
     } else {
       Exch<G, 0> ex;
       ex.init(lane, L.m);
@@ -946,7 +978,13 @@ bool config_ok(const wh_config* c, std::string& why) {
   if (!c) { why = "null config"; return false; }
   if (c->n_systems < 1) { why = "n_systems must be >= 1"; return false; }
   if (c->G != 1.0) { why = "G must be 1 (units with G = 1)"; return false; }
-  if (c->scheme != WH_DKD && c->scheme != WH_KDK) { why = "scheme must be WH_DKD or WH_KDK"; return false; }
+  if (c->scheme != WH_DKD && c->scheme != WH_KDK && c->scheme != WH_SABA2 && c->scheme != WH_SABA3 &&
+      c->scheme != WH_SABA4) {
+    why = "scheme must be WH_DKD, WH_KDK or WH_SABA2..4"; return false;
+  }
+  if (c->scheme >= WH_SABA2 && c->gr_c > 0) {
+    why = "the SABA_n schemes need the perturbation's flow in one piece, which GR breaks"; return false;
+  }
   if (c->packing < WH_PACK_AUTO || c->packing > WH_PACK_G8) { why = "unknown packing"; return false; }
   if (c->block_waves != 0 && c->block_waves != 1 && c->block_waves != 2 && c->block_waves != 4) {
     why = "block_waves must be 0, 1, 2 or 4"; return false;
@@ -995,6 +1033,37 @@ struct wh_ctx {
 
 namespace {
 
+// SABA_n coefficients from n-point Gauss-Legendre quadrature on [0, 1]:
+// d_k the weights, c_1 the first node, c_k the gaps between nodes, c_{n+1}
+// = c_1 by symmetry.  Nodes by Newton's method on the Legendre polynomial.
+void saba_coefficients(int n, double* c, double* d) {
+  const double pi = 3.14159265358979323846;
+  std::vector<long double> t(n), w(n);
+  for (int i = 0; i < n; ++i) {
+    long double x = std::cos(pi * (n - i - 0.25) / (n + 0.5));   // ascending root guesses
+    long double dp = 1;
+    for (int it = 0; it < 60; ++it) {
+      long double pm = 1, pc = x;      // P_0, P_1
+      for (int k = 2; k <= n; ++k) {
+        long double pn = ((2 * k - 1) * x * pc - (k - 1) * pm) / k;
+        pm = pc;
+        pc = pn;
+      }
+      if (n == 1) pm = 1;
+      dp = n * (x * pc - pm) / (x * x - 1);
+      long double step = pc / dp;
+      x -= step;
+      if (std::fabs((double)step) < 1e-19) break;
+    }
+    t[i] = (x + 1) / 2;
+    w[i] = 1 / ((1 - x * x) * dp * dp);
+  }
+  c[0] = (double)t[0];
+  for (int k = 1; k < n; ++k) c[k] = (double)(t[k] - t[k - 1]);
+  c[n] = c[0];
+  for (int k = 0; k < n; ++k) d[k] = (double)w[k];
+}
+
 StepParams step_params(const wh_ctx* c, int n_steps) {
   StepParams p;
   p.st = c->st;
@@ -1010,13 +1079,26 @@ StepParams step_params(const wh_ctx* c, int n_steps) {
   p.n_steps = n_steps;
   p.kgr = c->cfg.gr_c > 0 ? 6.0 / (c->cfg.gr_c * c->cfg.gr_c) : 0.0;
   p.zlim = c->cfg.z_max > 0 ? c->cfg.z_max : 1.0;
+  p.saba_n = 0;
+  for (int k = 0; k < 5; ++k) p.sc[k] = 0.0;
+  for (int k = 0; k < 4; ++k) p.sd[k] = 0.0;
+  if (c->cfg.scheme >= WH_SABA2) {
+    p.saba_n = c->cfg.scheme;      // WH_SABA2..4 = 2..4
+    saba_coefficients(p.saba_n, p.sc, p.sd);
+  }
   return p;
 }
 
 template <int EXCH>
 void launch_step_exch(const wh_ctx* c, const StepParams& p, dim3 grid, dim3 block, hipStream_t st) {
   const bool gr = c->cfg.gr_c > 0;
-  if (c->cfg.coords == WH_COORDS_JACOBI) {
+  const bool jac = c->cfg.coords == WH_COORDS_JACOBI;
+  if (c->cfg.scheme >= WH_SABA2) {
+    if (jac) hipLaunchKernelGGL((k_step<false, SCHEME_SABA, EXCH, true>), grid, block, 0, st, p);
+    else hipLaunchKernelGGL((k_step<false, SCHEME_SABA, EXCH, false>), grid, block, 0, st, p);
+    return;
+  }
+  if (jac) {
     if (c->cfg.scheme == WH_DKD) hipLaunchKernelGGL((k_step<false, WH_DKD, EXCH, true>), grid, block, 0, st, p);
     else hipLaunchKernelGGL((k_step<false, WH_KDK, EXCH, true>), grid, block, 0, st, p);
     return;
@@ -1053,7 +1135,10 @@ wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st
   q.e_out = e;
   dim3 block(64), grid(c->P.nwaves);
   const bool gr = c->cfg.gr_c > 0;
-  if (c->cfg.coords == WH_COORDS_JACOBI) {
+  if (c->cfg.scheme >= WH_SABA2) {
+    if (c->cfg.coords == WH_COORDS_JACOBI) hipLaunchKernelGGL((k_sync<false, SCHEME_SABA, true>), grid, block, 0, st, q);
+    else hipLaunchKernelGGL((k_sync<false, SCHEME_SABA, false>), grid, block, 0, st, q);
+  } else if (c->cfg.coords == WH_COORDS_JACOBI) {
     if (c->cfg.scheme == WH_DKD) hipLaunchKernelGGL((k_sync<false, WH_DKD, true>), grid, block, 0, st, q);
     else hipLaunchKernelGGL((k_sync<false, WH_KDK, true>), grid, block, 0, st, q);
   } else if (c->cfg.scheme == WH_DKD) {
