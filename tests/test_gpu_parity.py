@@ -254,3 +254,62 @@ def test_energy_error_statistics_match_oracle():
     ratio = worst_g / worst_o
     assert np.mean((ratio > 0.5) & (ratio < 2.0)) >= 0.95
     assert abs(np.median(worst_g) / np.median(worst_o) - 1) < 0.1
+
+
+@pytest.mark.parametrize("opts", [{}, {"block_waves": 4, "chunk_steps": 1024}])
+def test_uneven_full_size_sampled(opts):
+    """The uneven batch at full size (16384 systems of 2..8 planets, per-system
+    dt), in the default and the autotuned launch configurations; sampled
+    systems checked one by one against the oracle."""
+    s = inputs.workload("uneven2to8")
+    e = Ensemble.from_systems(s, **opts)
+    e.step(1000)
+    Q, V = e.state()
+    Q = Q.cpu().numpy(); V = V.cpu().numpy()
+    e.close()
+    idx = np.random.default_rng(1).choice(s.S, 32, replace=False)
+    sub = s.subset(idx)
+    Qo, Vo = oracle.integrate(sub, 1000)
+    eq, ev = rel_err(sub, Q[idx], V[idx], Qo, Vo)
+    assert eq < TOL and ev < TOL, (eq, ev)
+
+
+def test_large_gr_full_size_sampled():
+    """65536 eight-planet systems with GR (c = 10065) at full size."""
+    s = inputs.workload("large8gr")
+    e = Ensemble.from_systems(s, gr_c=inputs.GR_C)
+    e.step(1000)
+    Q, V = e.state()
+    Q = Q.cpu().numpy(); V = V.cpu().numpy()
+    flags = e.flags().cpu().numpy()
+    e.close()
+    assert not flags.any()
+    idx = np.random.default_rng(2).choice(s.S, 24, replace=False)
+    sub = s.subset(idx)
+    Qo, Vo = oracle.integrate(sub, 1000, gr_c=inputs.GR_C)
+    eq, ev = rel_err(sub, Q[idx], V[idx], Qo, Vo)
+    assert eq < TOL and ev < TOL, (eq, ev)
+
+
+def test_million_systems_tiled():
+    """2^20 eight-planet systems (8.4 million lanes, 131072 wavefronts): the
+    4096 distinct systems of the uniform workload tiled 256 times.  Systems
+    are independent, so every copy must end bitwise equal to the first, and
+    sampled ones match the oracle."""
+    base = inputs.workload("uniform8")
+    reps = 256
+    t = inputs.Systems(np.tile(base.n_planets, reps), np.tile(base.m0, reps), np.tile(base.m, (reps, 1)),
+                       np.tile(base.Q, (reps, 1, 1)), np.tile(base.V, (reps, 1, 1)), np.tile(base.dt, reps))
+    assert t.S == 1 << 20
+    e = Ensemble.from_systems(t)
+    e.step(300)
+    Q, V = e.state()
+    e.close()
+    Q = Q.view(reps, base.S, 8, 3)
+    V = V.view(reps, base.S, 8, 3)
+    assert torch.equal(Q, Q[:1].expand_as(Q)) and torch.equal(V, V[:1].expand_as(V))
+    idx = np.random.default_rng(4).choice(base.S, 16, replace=False)
+    sub = base.subset(idx)
+    Qo, Vo = oracle.integrate(sub, 300)
+    eq, ev = rel_err(sub, Q[-1].cpu().numpy()[idx], V[-1].cpu().numpy()[idx], Qo, Vo)
+    assert eq < TOL and ev < TOL, (eq, ev)
