@@ -49,6 +49,11 @@ DEFAULT_STEPS = {"uniform8": 1_000_000, "uneven2to8": 1_000_000, "large8gr": 1_0
                  "adjoint8": 100_000}
 
 
+# Two planets per lane pays once the one-planet layout has more wavefronts
+# than the chip has SIMDs (fewer, heavier waves with more independent work).
+DEFAULT_PACKING = {"uneven2to8": "pair", "large8gr": "pair"}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,7 +61,9 @@ def parse():
                     help="timed Wisdom-Holman steps (default: 1e5 for adjoint8 and single8, 1e6 otherwise)")
     ap.add_argument("--warmup", type=int, default=4096, help="untimed steps before the timed region")
     ap.add_argument("--workload", default="uniform8", choices=sorted(WORKLOAD_TEXT))
-    ap.add_argument("--packing", default="auto")
+    ap.add_argument("--packing", default=None,
+                    help="auto|pow2|g8|pair|tuned (default: pair for uneven2to8 and large8gr, whose batches fill "
+                         "more wavefronts than the chip has SIMDs; auto otherwise)")
     ap.add_argument("--block-waves", type=int, default=1)
     ap.add_argument("--chunk", type=int, default=4096)
     ap.add_argument("--exchange", default="auto", choices=["auto", "dpp", "lds"])
@@ -74,7 +81,7 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(workload: str, chunk: int, coords: str = "dhc"):
+def measured_traffic(workload: str, chunk: int, coords: str = "dhc", packing: str = "auto"):
     """HBM bytes per launch from the committed counter summary, if the kernel
     sources are still the ones it was taken on (else None)."""
     import hashlib
@@ -90,7 +97,8 @@ def measured_traffic(workload: str, chunk: int, coords: str = "dhc"):
                 return None
     if chunk != rec["chunk_steps"] or coords != "dhc":
         return None
-    return rec["bytes_per_launch"].get(workload)
+    key = "%s/%s" % (workload, "pow2" if packing == "auto" else packing)
+    return rec["bytes_per_launch"].get(key)
 
 
 def flops_per_system_step(n_planets: np.ndarray, gr: bool, coords: str = "dhc", scheme: str = "dkd") -> float:
@@ -157,6 +165,8 @@ def adjoint_cost(systems, args, dev, stream, t_plain):
 
 def main():
     args = parse()
+    if args.packing is None:
+        args.packing = DEFAULT_PACKING.get(args.workload, "auto")
     if args.steps is None:
         args.steps = DEFAULT_STEPS.get(args.workload, 1_000_000)
     if args.gpus != 1:
@@ -243,9 +253,10 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": measured_traffic(args.workload, opts["chunk_steps"], args.coords),
+            "traffic": measured_traffic(args.workload, opts["chunk_steps"], args.coords, opts["packing"]),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
-            "kernel": "k_step (persistent step kernel)",
+            "kernel": "k_step_pair (persistent step kernel, two planets per lane)" if opts["packing"] == "pair"
+                      else "k_step (persistent step kernel)",
             "algorithmic_flops_per_step": flops_step,
             "avg_launch_ms": gpu_s * 1e3 / n_launch,
             "launches": n_launch,

@@ -1,6 +1,7 @@
 """Autotuner for the lane packing of an ensemble.
 
-Candidates: packing (1/2/4/8-lane groups or always 8 lanes), partner
+Candidates: packing (1/2/4/8-lane groups, always 8 lanes, or two planets
+per lane in 1/2/4-lane groups), partner
 exchange (DPP or LDS crossbar), wavefronts per workgroup and steps per
 launch (the splitting coordinates are the caller's choice, not a candidate:
 they change the results, not just the speed).  Each candidate integrates the real batch for a short run; the
@@ -21,10 +22,11 @@ import os
 import numpy as np
 import torch
 
+from . import _lib
 from .ensemble import Ensemble
 
 CANDIDATES = {
-    "packing": ["pow2", "g8"],
+    "packing": ["pow2", "g8", "pair"],
     "exchange": ["dpp", "lds"],
     "block_waves": [1, 4],
     "chunk_steps": [1024, 4096],
@@ -98,7 +100,10 @@ def autotune(systems, gr_c: float = 0.0, scheme: str = "dkd", steps: int = 1024,
         opts = dict(zip(names, values))
         # the steps of a probe must cover a few launches of the candidate's chunk
         n = max(steps, 2 * opts.get("chunk_steps", 0)) if "chunk_steps" in opts else steps
-        rate = time_candidate(systems, opts, gr_c, scheme, n, warmup, device, coords)
+        try:
+            rate = time_candidate(systems, opts, gr_c, scheme, n, warmup, device, coords)
+        except _lib.WHError:      # a combination the library does not run (e.g. pair packing with SABA_n)
+            continue
         table.append({"opts": opts, "system_steps_per_s": rate})
         if verbose:
             print("autotune %s: %.4g system-steps/s" % (opts, rate), flush=True)

@@ -22,6 +22,7 @@
 #include "wh.h"
 #include "wh_device.h"
 #include "wh_adjoint.h"
+#include "wh_pair.h"
 
 using namespace wh;
 
@@ -439,6 +440,113 @@ __global__ __launch_bounds__(256) void k_step(StepParams p) {
 }
 
 // ---------------------------------------------------------------------------
+// Two planets per lane (WH_PACK_PAIR, see wh_pair.h): wave w covers slots
+// [128 w, 128 w + 128); lane l holds slot 128 w + l ("a") and 128 w + 64 + l
+// ("b").  The step is the one-planet step applied to both slots, with the
+// interaction and momentum sums of the pair layout.
+
+template <int G, bool GR>
+__device__ __forceinline__ void kick_block_pair(Lane& A, Lane& B, const PairMass& pm, double inv_m0, double kg,
+                                                double ta, double ti, double tc) {
+  double sx, sy, sz;
+  double qax = A.qx, qay = A.qy, qaz = A.qz, qbx = B.qx, qby = B.qy, qbz = B.qz;
+  if (GR) {
+    pair_momentum<G>(A.m, A.vx, A.vy, A.vz, B.m, B.vx, B.vy, B.vz, sx, sy, sz);
+    const double k1 = ta * inv_m0;
+    const double dqx = k1 * sx, dqy = k1 * sy, dqz = k1 * sz;
+    A.cqx += dqx; A.cqy += dqy; A.cqz += dqz;
+    B.cqx += dqx; B.cqy += dqy; B.cqz += dqz;
+    qax += dqx; qay += dqy; qaz += dqz;
+    qbx += dqx; qby += dqy; qbz += dqz;
+  }
+  double aax, aay, aaz, abx, aby, abz;
+  accel_pair<G>(pm, A.m, B.m, qax, qay, qaz, qbx, qby, qbz, aax, aay, aaz, abx, aby, abz);
+  if (GR) {
+    double gx, gy, gz;
+    gr_accel(qax, qay, qaz, kg, gx, gy, gz);
+    aax += gx; aay += gy; aaz += gz;
+    gr_accel(qbx, qby, qbz, kg, gx, gy, gz);
+    abx += gx; aby += gy; abz += gz;
+  }
+  const double dvax = ti * aax, dvay = ti * aay, dvaz = ti * aaz;
+  const double dvbx = ti * abx, dvby = ti * aby, dvbz = ti * abz;
+  A.cvx += dvax; A.cvy += dvay; A.cvz += dvaz;
+  B.cvx += dvbx; B.cvy += dvby; B.cvz += dvbz;
+  pair_momentum<G>(A.m, A.vx + dvax, A.vy + dvay, A.vz + dvaz, B.m, B.vx + dvbx, B.vy + dvby, B.vz + dvbz, sx, sy,
+                   sz);
+  const double k2 = (GR ? tc : ta + tc) * inv_m0;
+  A.cqx += k2 * sx; A.cqy += k2 * sy; A.cqz += k2 * sz;
+  B.cqx += k2 * sx; B.cqy += k2 * sy; B.cqz += k2 * sz;
+  renorm_all(A);
+  renorm_all(B);
+}
+
+__device__ __forceinline__ int lane_flags(const Lane& L, const KepDiag& dg, double zlim) {
+  int f = 0;
+  if (L.pl >= 0) {
+    bool fin = __builtin_isfinite(L.qx) && __builtin_isfinite(L.qy) && __builtin_isfinite(L.qz) &&
+               __builtin_isfinite(L.vx) && __builtin_isfinite(L.vy) && __builtin_isfinite(L.vz);
+    if (!fin) f |= WH_F_NONFINITE;
+    if (!(dg.bmin > 0.0)) f |= WH_F_HYPERBOLIC;
+    if (!(dg.zmax <= zlim)) f |= WH_F_ZMAX;
+  }
+  return f;
+}
+
+template <int G, bool GR, int SCHEME>
+__device__ __forceinline__ void step_lane_pair(const StepParams& p, Lane& A, Lane& B, int lane) {
+  const PairMass pm = make_pair_mass<G>(A.m, B.m);
+  const double dt = A.dt;
+  const double h = 0.5 * dt;
+  const double inv_m0 = 1.0 / A.m0;
+  const double kg = GR ? p.kgr * A.m0 * A.m0 : 0.0;
+  KepDiag dga{0.0, 1.0e300}, dgb{0.0, 1.0e300};
+  if (SCHEME == WH_DKD) {
+    double tk = A.first ? h : dt;
+    for (int s = 0; s < p.n_steps; ++s) {
+      drift(A, A.m0, tk, dga);
+      drift(B, B.m0, tk, dgb);
+      tk = dt;
+      kick_block_pair<G, GR>(A, B, pm, inv_m0, kg, h, dt, h);
+    }
+  } else {
+    double ta = A.first ? 0.0 : h;
+    double ti = A.first ? h : dt;
+    for (int s = 0; s < p.n_steps; ++s) {
+      kick_block_pair<G, GR>(A, B, pm, inv_m0, kg, ta, ti, h);
+      ta = h;
+      ti = dt;
+      drift(A, A.m0, dt, dga);
+      drift(B, B.m0, dt, dgb);
+    }
+  }
+  int f = group_or<G>(lane_flags(A, dga, p.zlim) | lane_flags(B, dgb, p.zlim));
+  if ((lane & (G - 1)) == 0 && A.sys >= 0) {
+    p.flags[A.sys] |= (uint32_t)f;
+    p.synced[A.sys] = 0;
+  }
+}
+
+template <int G, bool GR, int SCHEME> __device__ void step_group_pair(const StepParams& p, int sa, int lane) {
+  Lane A = load_lane(p, sa);
+  Lane B = load_lane(p, sa + 64);
+  step_lane_pair<G, GR, SCHEME>(p, A, B, lane);
+  store_lane(p, sa, A);
+  store_lane(p, sa + 64, B);
+}
+
+template <bool GR, int SCHEME>
+__global__ __launch_bounds__(256) void k_step_pair(StepParams p) {
+  const int lane = threadIdx.x & 63;
+  const int wave = p.wave0 + (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  const int sa = wave * 128 + lane;
+  if (wave < p.w1) step_group_pair<1, GR, SCHEME>(p, sa, lane);
+  else if (wave < p.w2) step_group_pair<2, GR, SCHEME>(p, sa, lane);
+  else step_group_pair<4, GR, SCHEME>(p, sa, lane);
+}
+
+// ---------------------------------------------------------------------------
 // Synchronized copy: DKD applies the pending half drift K(h), SABA_n the
 // pending drift K(c_1 dt); KDK applies the pending half kick J(h) [I + GR](h).
 // A synchronized state is left as is.
@@ -539,6 +647,106 @@ __global__ __launch_bounds__(256) void k_sync(SyncParams q) {
   else if (wave < p.w2) sync_group<2, GR, SCHEME, JAC>(q, slot, lane);
   else if (wave < p.w4) sync_group<4, GR, SCHEME, JAC>(q, slot, lane);
   else sync_group<8, GR, SCHEME, JAC>(q, slot, lane);
+}
+
+// Synchronized copy of the pair layout: as sync_group for both slots.
+__device__ __forceinline__ void osculating(const Lane& L, double sx, double sy, double sz, double& a, double& e) {
+  const double ux = L.vx + sx / L.m0, uy = L.vy + sy / L.m0, uz = L.vz + sz / L.m0;
+  const double mu = L.m0 + L.m;
+  const double r = sqrt(L.qx * L.qx + L.qy * L.qy + L.qz * L.qz);
+  const double u2 = ux * ux + uy * uy + uz * uz;
+  a = 1.0 / (2.0 / r - u2 / mu);
+  const double hx = L.qy * uz - L.qz * uy, hy = L.qz * ux - L.qx * uz, hz = L.qx * uy - L.qy * ux;
+  const double ex = (uy * hz - uz * hy) / mu - L.qx / r;
+  const double ey = (uz * hx - ux * hz) / mu - L.qy / r;
+  const double ez = (ux * hy - uy * hx) / mu - L.qz / r;
+  e = sqrt(ex * ex + ey * ey + ez * ez);
+}
+
+__device__ __forceinline__ double planet_energy(const Lane& L, double kgr) {
+  const double r2 = L.qx * L.qx + L.qy * L.qy + L.qz * L.qz;
+  double e = 0.5 * L.m * (L.vx * L.vx + L.vy * L.vy + L.vz * L.vz) - L.m0 * L.m / sqrt(r2);
+  if (kgr > 0) e -= 0.5 * kgr * L.m0 * L.m0 * L.m / r2;
+  return e;
+}
+
+template <int G, bool GR> __device__ double group_energy_pair(const StepParams& p, const Lane& A, const Lane& B,
+                                                              int lane) {
+  double e = planet_energy(A, GR ? p.kgr : 0.0) + planet_energy(B, GR ? p.kgr : 0.0);
+  {
+    const double dx = A.qx - B.qx, dy = A.qy - B.qy, dz = A.qz - B.qz;
+    e -= A.m * B.m / sqrt(dx * dx + dy * dy + dz * dz);
+  }
+  double pair = 0.0;
+#pragma unroll
+  for (int k = 1; k < G; ++k) {
+    const int src = (lane ^ k) << 2;
+    const double pax = bperm(src, A.qx), pay = bperm(src, A.qy), paz = bperm(src, A.qz), pma = bperm(src, A.m);
+    const double pbx = bperm(src, B.qx), pby = bperm(src, B.qy), pbz = bperm(src, B.qz), pmb = bperm(src, B.m);
+    double dx, dy, dz;
+    dx = A.qx - pax; dy = A.qy - pay; dz = A.qz - paz; pair += A.m * pma / sqrt(dx * dx + dy * dy + dz * dz);
+    dx = A.qx - pbx; dy = A.qy - pby; dz = A.qz - pbz; pair += A.m * pmb / sqrt(dx * dx + dy * dy + dz * dz);
+    dx = B.qx - pax; dy = B.qy - pay; dz = B.qz - paz; pair += B.m * pma / sqrt(dx * dx + dy * dy + dz * dz);
+    dx = B.qx - pbx; dy = B.qy - pby; dz = B.qz - pbz; pair += B.m * pmb / sqrt(dx * dx + dy * dy + dz * dz);
+  }
+  e -= 0.5 * pair;
+  e = group_sum<G>(e);
+  double sx, sy, sz;
+  pair_momentum<G>(A.m, A.vx, A.vy, A.vz, B.m, B.vx, B.vy, B.vz, sx, sy, sz);
+  return e + (sx * sx + sy * sy + sz * sz) / (2.0 * A.m0);
+}
+
+__device__ __forceinline__ void write_state(const SyncParams& q, const Lane& L) {
+  if (q.Q_out && L.sys >= 0 && L.pl >= 0) {
+    size_t o = ((size_t)L.sys * 8 + L.pl) * 3;
+    q.Q_out[o] = L.qx; q.Q_out[o + 1] = L.qy; q.Q_out[o + 2] = L.qz;
+    q.V_out[o] = L.vx; q.V_out[o + 1] = L.vy; q.V_out[o + 2] = L.vz;
+  }
+}
+
+template <int G, bool GR, int SCHEME> __device__ void sync_group_pair(const SyncParams& q, int sa, int lane) {
+  const StepParams& p = q.sp;
+  Lane A = load_lane(p, sa);
+  Lane B = load_lane(p, sa + 64);
+  if (!A.first) {
+    const double h = 0.5 * A.dt;
+    if (SCHEME == WH_DKD) {
+      KepDiag dg{0.0, 1.0e300};
+      drift(A, A.m0, h, dg);
+      drift(B, B.m0, h, dg);
+    } else {
+      const PairMass pm = make_pair_mass<G>(A.m, B.m);
+      kick_block_pair<G, GR>(A, B, pm, 1.0 / A.m0, GR ? p.kgr * A.m0 * A.m0 : 0.0, h, h, 0.0);
+    }
+  }
+  A.qx += A.cqx; A.qy += A.cqy; A.qz += A.cqz; A.vx += A.cvx; A.vy += A.cvy; A.vz += A.cvz;
+  B.qx += B.cqx; B.qy += B.cqy; B.qz += B.cqz; B.vx += B.cvx; B.vy += B.cvy; B.vz += B.cvz;
+  write_state(q, A);
+  write_state(q, B);
+  if (q.E_out) {
+    const double E = group_energy_pair<G, GR>(p, A, B, lane);
+    if ((lane & (G - 1)) == 0 && A.sys >= 0) q.E_out[A.sys] = E;
+  }
+  if (q.a_out) {
+    double sx, sy, sz, a, e;
+    pair_momentum<G>(A.m, A.vx, A.vy, A.vz, B.m, B.vx, B.vy, B.vz, sx, sy, sz);
+    osculating(A, sx, sy, sz, a, e);
+    if (A.sys >= 0 && A.pl >= 0) { q.a_out[(size_t)A.sys * 8 + A.pl] = a; q.e_out[(size_t)A.sys * 8 + A.pl] = e; }
+    osculating(B, sx, sy, sz, a, e);
+    if (B.sys >= 0 && B.pl >= 0) { q.a_out[(size_t)B.sys * 8 + B.pl] = a; q.e_out[(size_t)B.sys * 8 + B.pl] = e; }
+  }
+}
+
+template <bool GR, int SCHEME>
+__global__ __launch_bounds__(256) void k_sync_pair(SyncParams q) {
+  const StepParams& p = q.sp;
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  const int sa = wave * 128 + lane;
+  if (wave < p.w1) sync_group_pair<1, GR, SCHEME>(q, sa, lane);
+  else if (wave < p.w2) sync_group_pair<2, GR, SCHEME>(q, sa, lane);
+  else sync_group_pair<4, GR, SCHEME>(q, sa, lane);
 }
 
 // Initial state of a Jacobi context: the gathered DHC state (compensation
@@ -791,7 +999,7 @@ __global__ void k_gather(double* st, int ns, double* m0s, double* dts, const int
     }
     st[6 * ns + slot] = m[(size_t)s * 8 + pl];
   } else {
-    int k = slot & 7;
+    int k = (slot & 7) | ((slot >> 3) & 8);   // distinct for the two slots of a lane in the pair layout
     double a = 1.0e4 * (1.0 + 0.25 * k);
     double ph = 0.3 + 0.7 * k;
     double vc = sqrt(M0 / a);
@@ -894,6 +1102,7 @@ wh_status hip_check(hipError_t e, const char* what) {
 }
 
 struct Packing {
+  bool pair = false;   // WH_PACK_PAIR: two slots (planets) per lane, 128 slots per wave
   int ns = 0, nwaves = 0;
   int w1 = 0, w2 = 0, w4 = 0, w8 = 0;
   int plain_begin[9] = {0}, plain_end[9] = {0};   // G8 packing: waves of each planet count
@@ -925,7 +1134,43 @@ bool make_packing(int S, const int32_t* np, int packing, Packing& P) {
       }
     P.nwaves += nw;
   };
-  if (packing == WH_PACK_G8) {
+  if (packing == WH_PACK_PAIR) {
+    // a system of N planets takes G = 1, 2 or 4 lanes (2G >= N); lane l of a
+    // group holds planet l in slot 128 w + (lane) and planet G + l in slot
+    // 128 w + 64 + (lane) of its wave w
+    int ends[3];
+    const int Gs[3] = {1, 2, 4};
+    for (int gi = 0; gi < 3; ++gi) {
+      const int G = Gs[gi];
+      std::vector<int> cls;
+      for (int s = 0; s < S; ++s)
+        if ((np[s] <= 2 ? 1 : np[s] <= 4 ? 2 : 4) == G) cls.push_back(s);
+      const int per_wave = 64 / G;
+      const int nw = ((int)cls.size() + per_wave - 1) / per_wave;
+      for (int w = 0; w < nw; ++w) {
+        int32_t a_sys[64], a_pl[64], b_sys[64], b_pl[64];
+        for (int j = 0; j < per_wave; ++j) {
+          const int idx = w * per_wave + j;
+          const int s = idx < (int)cls.size() ? cls[idx] : -1;
+          for (int l = 0; l < G; ++l) {
+            const int ln = j * G + l;
+            a_sys[ln] = s;
+            a_pl[ln] = s >= 0 && l < np[s] ? l : -1;
+            b_sys[ln] = s;
+            b_pl[ln] = s >= 0 && G + l < np[s] ? G + l : -1;
+          }
+        }
+        P.slot_sys.insert(P.slot_sys.end(), a_sys, a_sys + 64);
+        P.slot_pl.insert(P.slot_pl.end(), a_pl, a_pl + 64);
+        P.slot_sys.insert(P.slot_sys.end(), b_sys, b_sys + 64);
+        P.slot_pl.insert(P.slot_pl.end(), b_pl, b_pl + 64);
+      }
+      P.nwaves += nw;
+      ends[gi] = P.nwaves;
+    }
+    P.pair = true;
+    P.w1 = ends[0]; P.w2 = ends[1]; P.w4 = ends[2]; P.w8 = ends[2];
+  } else if (packing == WH_PACK_G8) {
     for (int n = 1; n <= 8; ++n) {
       std::vector<int> cls;
       for (int s = 0; s < S; ++s)
@@ -948,8 +1193,8 @@ bool make_packing(int S, const int32_t* np, int packing, Packing& P) {
     }
     P.w1 = ends[0]; P.w2 = ends[1]; P.w4 = ends[2]; P.w8 = ends[3];
   }
-  P.ns = P.nwaves * 64;
-  // every wave holds exactly 64 slots; the device tables are copied at ns
+  P.ns = P.nwaves * (P.pair ? 128 : 64);
+  // every wave holds exactly 64 (pair layout: 128) slots; the device tables are copied at ns
   if ((int)P.slot_sys.size() != P.ns || (int)P.slot_pl.size() != P.ns) return false;
   return true;
 }
@@ -985,7 +1230,7 @@ bool config_ok(const wh_config* c, std::string& why) {
   if (c->scheme >= WH_SABA2 && c->gr_c > 0) {
     why = "the SABA_n schemes need the perturbation's flow in one piece, which GR breaks"; return false;
   }
-  if (c->packing < WH_PACK_AUTO || c->packing > WH_PACK_G8) { why = "unknown packing"; return false; }
+  if (c->packing < WH_PACK_AUTO || c->packing > WH_PACK_PAIR) { why = "unknown packing"; return false; }
   if (c->block_waves != 0 && c->block_waves != 1 && c->block_waves != 2 && c->block_waves != 4) {
     why = "block_waves must be 0, 1, 2 or 4"; return false;
   }
@@ -993,6 +1238,10 @@ bool config_ok(const wh_config* c, std::string& why) {
   if (!(c->z_max >= 0.0)) { why = "z_max must be >= 0"; return false; }
   if (c->exchange < WH_EXCH_AUTO || c->exchange > WH_EXCH_DPP) { why = "unknown exchange"; return false; }
   if (c->coords != WH_COORDS_DHC && c->coords != WH_COORDS_JACOBI) { why = "unknown coordinates"; return false; }
+  if (c->packing == WH_PACK_PAIR && (c->coords != WH_COORDS_DHC || (c->scheme != WH_DKD && c->scheme != WH_KDK))) {
+    why = "the two-planets-per-lane packing runs the DHC drift-kick-drift and kick-drift-kick steps only";
+    return false;
+  }
   if (c->coords == WH_COORDS_JACOBI && c->gr_c > 0) {
     why = "the GR kick is implemented in democratic heliocentric coordinates only"; return false;
   }
@@ -1093,6 +1342,16 @@ template <int EXCH>
 void launch_step_exch(const wh_ctx* c, const StepParams& p, dim3 grid, dim3 block, hipStream_t st) {
   const bool gr = c->cfg.gr_c > 0;
   const bool jac = c->cfg.coords == WH_COORDS_JACOBI;
+  if (c->P.pair) {
+    if (c->cfg.scheme == WH_DKD) {
+      if (gr) hipLaunchKernelGGL((k_step_pair<true, WH_DKD>), grid, block, 0, st, p);
+      else hipLaunchKernelGGL((k_step_pair<false, WH_DKD>), grid, block, 0, st, p);
+    } else {
+      if (gr) hipLaunchKernelGGL((k_step_pair<true, WH_KDK>), grid, block, 0, st, p);
+      else hipLaunchKernelGGL((k_step_pair<false, WH_KDK>), grid, block, 0, st, p);
+    }
+    return;
+  }
   if (c->cfg.scheme >= WH_SABA2) {
     if (jac) hipLaunchKernelGGL((k_step<false, SCHEME_SABA, EXCH, true>), grid, block, 0, st, p);
     else hipLaunchKernelGGL((k_step<false, SCHEME_SABA, EXCH, false>), grid, block, 0, st, p);
@@ -1135,7 +1394,15 @@ wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st
   q.e_out = e;
   dim3 block(64), grid(c->P.nwaves);
   const bool gr = c->cfg.gr_c > 0;
-  if (c->cfg.scheme >= WH_SABA2) {
+  if (c->P.pair) {
+    if (c->cfg.scheme == WH_DKD) {
+      if (gr) hipLaunchKernelGGL((k_sync_pair<true, WH_DKD>), grid, block, 0, st, q);
+      else hipLaunchKernelGGL((k_sync_pair<false, WH_DKD>), grid, block, 0, st, q);
+    } else {
+      if (gr) hipLaunchKernelGGL((k_sync_pair<true, WH_KDK>), grid, block, 0, st, q);
+      else hipLaunchKernelGGL((k_sync_pair<false, WH_KDK>), grid, block, 0, st, q);
+    }
+  } else if (c->cfg.scheme >= WH_SABA2) {
     if (c->cfg.coords == WH_COORDS_JACOBI) hipLaunchKernelGGL((k_sync<false, SCHEME_SABA, true>), grid, block, 0, st, q);
     else hipLaunchKernelGGL((k_sync<false, SCHEME_SABA, false>), grid, block, 0, st, q);
   } else if (c->cfg.coords == WH_COORDS_JACOBI) {
@@ -1388,6 +1655,7 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
   if (c->cfg.scheme != WH_DKD) return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD");
   if (c->cfg.coords != WH_COORDS_DHC)
     return fail(WH_ESTATE, "reverse mode is implemented in democratic heliocentric coordinates");
+  if (c->P.pair) return fail(WH_ESTATE, "reverse mode is implemented for the one-planet-per-lane packings");
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
   TapeLayout T = tape_layout(c->P.ns, n_steps, ckpt_every);
   if (tape_bytes < T.total) return fail(WH_EWORKSPACE, "tape too small: need " + std::to_string(T.total) + " bytes");
