@@ -6,7 +6,10 @@ smoke check and the CPU-baseline leg of the benchmark may import this package.
 
 Arrays follow the input generator's layout: n_planets int32 [S], m0 [S],
 m [S, 8], Q [S, 8, 3], V [S, 8, 3], dt [S].  Long double is the parity
-precision; double is the timing precision.
+precision; double is the timing precision.  Besides the map itself:
+osculating elements (numpy, plain definitions), the Jacobi-coordinate map
+(jacobi_*), the SABA_n schemes ("saba2".."saba4"), the fixed-iteration
+Kepler solver of App. A (kepler_fixed) and the operation counts.
 """
 from __future__ import annotations
 

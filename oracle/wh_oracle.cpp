@@ -20,7 +20,14 @@
 //   * the tangent (variational) map, by running the same code on dual numbers;
 //   * a fixed-iteration Kepler solver (Sec. 3.2 and App. A) kept apart from
 //     the exact one, used only for the App. A experiment and the operation
-//     count.
+//     count (with either the direct or the Wronskian form of g');
+//   * the SABA_n splittings (Laskar & Robutel 2001; Sec. 3.1 mentions
+//     higher-order generalizations of the step) with Gauss-Legendre
+//     coefficients;
+//   * the Wisdom-Holman map in Jacobi coordinates (Wisdom & Holman 1991; the
+//     Sec. 3.5 footnote and Sec. 6 name it for two or four planets), its
+//     kick taken as the dual-number gradient of H_I, plus the closed-form
+//     Jacobi acceleration for the operation count.
 //
 // Scalar types: long double (parity reference), double (CPU timing baseline),
 // Dual<long double> (tangent map), Counted (operation count).
