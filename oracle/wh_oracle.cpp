@@ -440,7 +440,7 @@ struct Saba {
 Saba saba_coeffs(int n) {
   Saba q;
   q.n = n;
-  ld x[5], w[5];
+  ld x[5] = {0, 0, 0, 0, 0}, w[5] = {0, 0, 0, 0, 0};
   for (int i = 0; i < n; ++i) {
     ld z = std::cos(3.14159265358979323846264338327950288L * (i + 0.75L) / (n + 0.5L));
     for (int it = 0; it < 100; ++it) {
@@ -464,7 +464,7 @@ Saba saba_coeffs(int n) {
     }
   }
   // ascending nodes on [0, 1]
-  ld t[5], u[5];
+  ld t[5] = {0, 0, 0, 0, 0}, u[5] = {0, 0, 0, 0, 0};
   for (int i = 0; i < n; ++i) {
     t[i] = (1 - x[i]) / 2;   // x descending -> t ascending
     u[i] = w[i] / 2;
