@@ -52,14 +52,14 @@ def lib():
             "or_tangent_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, l, i, ld, _PLD, _PLD, _PLD, _PLD, i], None),
             "or_count_ops": ([i, i, i, i, i, i, _PL], None),
             "or_gbs_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld, l], ld),
-            "or_jacobi_integrate_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, l, i, i], None),
-            "or_jacobi_integrate_d": ([i, i, _PI, _PD, _PD, _PD, _PD, _PD, l, i, i], None),
+            "or_jacobi_integrate_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, l, i, ld, i], None),
+            "or_jacobi_integrate_d": ([i, i, _PI, _PD, _PD, _PD, _PD, _PD, l, i, d, i], None),
             "or_jacobi_from_dhc_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, _PLD], None),
             "or_jacobi_to_dhc_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, _PLD], None),
-            "or_jacobi_parts_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD], None),
-            "or_jacobi_kick_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld], None),
-            "or_jacobi_kick_direct_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld], None),
-            "or_count_ops_jacobi": ([i, i, i, i, i, _PL], None),
+            "or_jacobi_parts_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld, _PLD], None),
+            "or_jacobi_kick_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld, ld], None),
+            "or_jacobi_kick_direct_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld, ld], None),
+            "or_count_ops_jacobi": ([i, i, i, i, i, i, _PL], None),
             "or_saba_coeffs": ([i, _PLD, _PLD], None),
         }
         for name, (args, res) in sig.items():
@@ -230,18 +230,18 @@ def elements(sysm, Q=None, V=None):
 
 # ---- Wisdom-Holman map in Jacobi coordinates (Wisdom & Holman 1991) --------
 
-def jacobi_integrate(sysm, n_steps, scheme="dkd", precision="ld", nthreads=0, Q=None, V=None, dt=None):
+def jacobi_integrate(sysm, n_steps, scheme="dkd", precision="ld", nthreads=0, Q=None, V=None, dt=None, gr_c=0.0):
     """n_steps of the Jacobi-coordinate map; DHC (Q, V) in and out."""
     S = sysm.S
     dtv = sysm.dt if dt is None else dt
     if precision == "ld":
         Qa = _ld(sysm.Q if Q is None else Q).copy(); Va = _ld(sysm.V if V is None else V).copy()
         lib().or_jacobi_integrate_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), Qa, Va, _ld(dtv),
-                                     int(n_steps), SCHEMES[scheme], nthreads)
+                                     int(n_steps), SCHEMES[scheme], LD(gr_c), nthreads)
     else:
         Qa = _d(sysm.Q if Q is None else Q).copy(); Va = _d(sysm.V if V is None else V).copy()
         lib().or_jacobi_integrate_d(S, 8, _i(sysm.n_planets), _d(sysm.m0), _d(sysm.m), Qa, Va, _d(dtv),
-                                    int(n_steps), SCHEMES[scheme], nthreads)
+                                    int(n_steps), SCHEMES[scheme], float(gr_c), nthreads)
     return Qa, Va
 
 
@@ -260,32 +260,32 @@ def jacobi_to_dhc(sysm, xp, vp):
     return Q, V
 
 
-def jacobi_parts(sysm, Q=None, V=None):
+def jacobi_parts(sysm, Q=None, V=None, gr_c=0.0):
     """Per system (kinetic energy in Jacobi form, H_K, H_I)."""
     S = sysm.S
     out = np.zeros((S, 3), dtype=LD)
     lib().or_jacobi_parts_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), _ld(sysm.Q if Q is None else Q),
-                             _ld(sysm.V if V is None else V), out)
+                             _ld(sysm.V if V is None else V), LD(gr_c), out)
     return out[:, 0], out[:, 1], out[:, 2]
 
 
-def jacobi_kick(sysm, tau, Q=None, V=None, form="gradient"):
+def jacobi_kick(sysm, tau, Q=None, V=None, form="gradient", gr_c=0.0):
     """One kick of H_I: "gradient" = dual-number gradient of H_I, "direct" =
     the closed-form Jacobi acceleration."""
     S = sysm.S
     Qa = _ld(sysm.Q if Q is None else Q).copy(); Va = _ld(sysm.V if V is None else V).copy()
     f = lib().or_jacobi_kick_ld if form == "gradient" else lib().or_jacobi_kick_direct_ld
-    f(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), Qa, Va, LD(tau))
+    f(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), Qa, Va, LD(tau), LD(gr_c))
     return Qa, Va
 
 
-def count_ops_jacobi(n_planets=8, n_halley=2, n_newton=2, terms_halley=4, terms_newton=8):
+def count_ops_jacobi(n_planets=8, gr=False, n_halley=2, n_newton=2, terms_halley=4, terms_newton=8):
     """Operation count of one step of the Jacobi map."""
     c = np.zeros(4, dtype=np.int64)
     lib().or_set_series_recur(0)
     lib().or_set_guess(0)
     lib().or_set_gd_form(0)
-    lib().or_count_ops_jacobi(n_planets, n_halley, n_newton, terms_halley, terms_newton, c)
+    lib().or_count_ops_jacobi(n_planets, int(gr), n_halley, n_newton, terms_halley, terms_newton, c)
     d = dict(add=int(c[0]), mul=int(c[1]), div=int(c[2]), sqrt=int(c[3]))
     d["flops"] = d["add"] + d["mul"] + d["div"] + d["sqrt"]
     return d

@@ -575,6 +575,7 @@ template <class T> struct JSys {
   T M[9];        // M[i] = m_0 + ... + m_i over bodies 0..n (M[0] = m0)
   T x[8][3];     // Jacobi position of planet k (body k + 1)
   T v[8][3];     // Jacobi velocity
+  T gr_c;        // speed of light of the GR term, <= 0: no GR
 };
 
 template <class T> void jac_masses(JSys<T>& s) {
@@ -644,6 +645,9 @@ template <class T, class U> U jac_hint(const JSys<T>& s, const U xp[8][3]) {
     }
     U rp = sqrt(xp[i][0] * xp[i][0] + xp[i][1] * xp[i][1] + xp[i][2] * xp[i][2]);
     H += U(s.M[i + 1] * jac_reduced_mass(s, i)) / rp;
+    // the GR potential of Sec. 3.3 (reading of gr_kick), a function of the
+    // heliocentric positions and so part of the perturbation
+    if (val(s.gr_c) > 0) H -= U(T(3.0L) * s.m0 * s.m0 * s.m[i] / (s.gr_c * s.gr_c)) / (r * r);
   }
   return H;
 }
@@ -719,6 +723,21 @@ template <class T> void jac_kick_direct(JSys<T>& s, const T& tau) {
       s.v[i][a] += tau * (apl[i][a] - s.m0 * g[i][a] - A + kp * s.x[i][a]);
     }
   }
+  // GR: the force m_k gr_k on every planet and its reaction on the star give
+  // a'_i += gr_i + (sum_{k>=i} m_k gr_k) / M_{i-1}, gr_k = -6 m0^2 Q_k / (c^2 |Q_k|^4)
+  if (val(s.gr_c) > 0) {
+    T gr[8][3], gsuf[9][3];
+    for (int k = 0; k < s.n; ++k) {
+      T r2 = Q[k][0] * Q[k][0] + Q[k][1] * Q[k][1] + Q[k][2] * Q[k][2];
+      T w = T(R(6)) * s.m0 * s.m0 / (s.gr_c * s.gr_c * r2 * r2);
+      for (int a = 0; a < 3; ++a) gr[k][a] = -w * Q[k][a];
+    }
+    for (int a = 0; a < 3; ++a) gsuf[s.n][a] = T(R(0));
+    for (int k = s.n - 1; k >= 0; --k)
+      for (int a = 0; a < 3; ++a) gsuf[k][a] = gsuf[k + 1][a] + s.m[k] * gr[k][a];
+    for (int i = 0; i < s.n; ++i)
+      for (int a = 0; a < 3; ++a) s.v[i][a] += tau * (gr[i][a] + gsuf[i][a] / s.M[i]);
+  }
 }
 
 void jac_drift(JSys<ld>& s, ld tau) {
@@ -752,6 +771,7 @@ template <class A> void jac_load(JSys<ld>& s, int idx, int nmax, const int* np, 
                                  const A* V) {
   s.n = np[idx];
   s.m0 = m0[idx];
+  s.gr_c = 0;
   ld q[8][3], vv[8][3];
   for (int i = 0; i < s.n; ++i) {
     s.m[i] = m[idx * nmax + i];
@@ -773,12 +793,13 @@ template <class A> void jac_store(const JSys<ld>& s, int idx, int nmax, A* Q, A*
 }
 
 template <class A> void jac_integrate_arrays(int S, int nmax, const int* np, const A* m0, const A* m, A* Q, A* V,
-                                             const A* dt, long n_steps, int scheme, int nthreads) {
+                                             const A* dt, long n_steps, int scheme, ld gr_c, int nthreads) {
   if (nthreads <= 0) nthreads = omp_get_max_threads();
 #pragma omp parallel for schedule(static) num_threads(nthreads)
   for (int k = 0; k < S; ++k) {
     JSys<ld> s;
     jac_load(s, k, nmax, np, m0, m, Q, V);
+    s.gr_c = gr_c;
     for (long t = 0; t < n_steps; ++t) jac_step(s, (ld)dt[k], scheme);
     jac_store(s, k, nmax, Q, V);
   }
@@ -850,12 +871,12 @@ void or_saba_coeffs(int n, ld* c, ld* d) {
 // ---- Jacobi-coordinate map (Wisdom & Holman 1991) ----------------------
 // DHC in, DHC out; the state is carried in Jacobi coordinates in between.
 void or_jacobi_integrate_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, ld* Q, ld* V, const ld* dt,
-                            long n_steps, int scheme, int nthreads) {
-  jac_integrate_arrays(S, nmax, np, m0, m, Q, V, dt, n_steps, scheme, nthreads);
+                            long n_steps, int scheme, ld gr_c, int nthreads) {
+  jac_integrate_arrays(S, nmax, np, m0, m, Q, V, dt, n_steps, scheme, gr_c, nthreads);
 }
 void or_jacobi_integrate_d(int S, int nmax, const int* np, const double* m0, const double* m, double* Q, double* V,
-                           const double* dt, long n_steps, int scheme, int nthreads) {
-  jac_integrate_arrays(S, nmax, np, m0, m, Q, V, dt, n_steps, scheme, nthreads);
+                           const double* dt, long n_steps, int scheme, double gr_c, int nthreads) {
+  jac_integrate_arrays(S, nmax, np, m0, m, Q, V, dt, n_steps, scheme, (ld)gr_c, nthreads);
 }
 // Jacobi coordinates of DHC states (xp, vp: [S][nmax][3]).
 void or_jacobi_from_dhc_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, const ld* Q, const ld* V,
@@ -877,6 +898,7 @@ void or_jacobi_to_dhc_ld(int S, int nmax, const int* np, const ld* m0, const ld*
     JSys<ld> s;
     s.n = np[k];
     s.m0 = m0[k];
+    s.gr_c = 0;
     for (int i = 0; i < s.n; ++i) s.m[i] = m[k * nmax + i];
     jac_masses(s);
     for (int i = 0; i < s.n; ++i)
@@ -888,20 +910,23 @@ void or_jacobi_to_dhc_ld(int S, int nmax, const int* np, const ld* m0, const ld*
   }
 }
 // The closed-form kick (jac_kick_direct) on DHC states.
-void or_jacobi_kick_direct_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, ld* Q, ld* V, ld tau) {
+void or_jacobi_kick_direct_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, ld* Q, ld* V, ld tau,
+                              ld gr_c) {
   for (int k = 0; k < S; ++k) {
     JSys<ld> s;
     jac_load(s, k, nmax, np, m0, m, Q, V);
+    s.gr_c = gr_c;
     jac_kick_direct(s, tau);
     jac_store(s, k, nmax, Q, V);
   }
 }
 // Per system: [kinetic energy sum m'|v'|^2/2, H_K, H_I] of DHC states.
 void or_jacobi_parts_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, const ld* Q, const ld* V,
-                        ld* out) {
+                        ld gr_c, ld* out) {
   for (int k = 0; k < S; ++k) {
     JSys<ld> s;
     jac_load(s, k, nmax, np, m0, m, Q, V);
+    s.gr_c = gr_c;
     ld T = 0;
     for (int i = 0; i < s.n; ++i)
       T += 0.5L * jac_reduced_mass(s, i) * (s.v[i][0] * s.v[i][0] + s.v[i][1] * s.v[i][1] + s.v[i][2] * s.v[i][2]);
@@ -911,10 +936,11 @@ void or_jacobi_parts_ld(int S, int nmax, const int* np, const ld* m0, const ld* 
   }
 }
 // One kick of H_I over tau applied to DHC states (converted to Jacobi and back).
-void or_jacobi_kick_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, ld* Q, ld* V, ld tau) {
+void or_jacobi_kick_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, ld* Q, ld* V, ld tau, ld gr_c) {
   for (int k = 0; k < S; ++k) {
     JSys<ld> s;
     jac_load(s, k, nmax, np, m0, m, Q, V);
+    s.gr_c = gr_c;
     jac_kick(s, tau);
     jac_store(s, k, nmax, Q, V);
   }
@@ -1027,11 +1053,12 @@ void or_count_ops(int n, int gr, int nh, int nn, int th, int tn, long* counts) {
 // Operation count of one step of the Jacobi map: the fixed-iteration drift of
 // every planet about mu = G M_i and the closed-form kick (no jump).  The
 // interior masses are per-system constants and are not counted.
-void or_count_ops_jacobi(int n, int nh, int nn, int th, int tn, long* counts) {
+void or_count_ops_jacobi(int n, int gr, int nh, int nn, int th, int tn, long* counts) {
   typedef Counted C;
   JSys<C> s;
   s.n = n;
   s.m0 = C(1.0);
+  s.gr_c = C(gr ? 10065.0 : 0.0);
   for (int i = 0; i < n; ++i) {
     s.m[i] = C(1e-5);
     s.x[i][0] = C(1.0 + i); s.x[i][1] = C(0.01 * i); s.x[i][2] = C(0.0);

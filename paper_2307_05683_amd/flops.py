@@ -11,3 +11,4 @@ oracle/write_flops.py.
 ALGO_FLOPS = {1: 275, 2: 574, 3: 898, 4: 1247, 5: 1621, 6: 2020, 7: 2444, 8: 2893}
 ALGO_FLOPS_GR = {1: 310, 2: 637, 3: 989, 4: 1366, 5: 1768, 6: 2195, 7: 2647, 8: 3124}
 ALGO_FLOPS_JACOBI = {1: 329, 2: 683, 3: 1062, 4: 1466, 5: 1895, 6: 2349, 7: 2828, 8: 3332}
+ALGO_FLOPS_JACOBI_GR = {1: 361, 2: 747, 3: 1158, 4: 1594, 5: 2055, 6: 2541, 7: 3052, 8: 3588}

@@ -240,3 +240,71 @@ def test_operation_count_of_the_jacobi_step():
     assert all(e > 0 for e in extra)
     assert np.all(steps == steps[0])          # exactly linear in N
     assert oracle.count_ops_jacobi(2)["div"] > 0 and oracle.count_ops_jacobi(2)["sqrt"] > 0
+
+
+def test_gr_term_energy_identity_and_closed_form_kick():
+    """With the GR potential of Sec. 3.3 (as read for the DHC map) added to
+    H_I: H_K + H_I equals the DHC energy with GR, and the closed-form Jacobi
+    acceleration (GR part: gr_i + sum_{k>=i} m_k gr_k / M_{i-1}) equals the
+    dual-number gradient."""
+    s = inputs.make_systems(12, 49, n_planets=None, n_range=(1, 8))
+    c = 40.0
+    lm = live(s)
+    _, HK, HI = oracle.jacobi_parts(s, gr_c=c)
+    E = oracle.energy(s, gr_c=c)
+    assert np.abs((HK + HI - E) / E).max() < 1e-17
+    Qa, Va = oracle.jacobi_kick(s, 0.05, gr_c=c)
+    Qb, Vb = oracle.jacobi_kick(s, 0.05, form="direct", gr_c=c)
+    Qc, Vc = oracle.jacobi_kick(s, 0.05)
+    assert np.abs((Va - Vc)[lm].astype(float)).max() > 1e-4           # the GR part is not negligible
+    assert np.abs((Va - Vb)[lm].astype(float)).max() < 2e-18
+
+
+def test_gr_pericentre_precession_in_jacobi_coordinates():
+    """One light planet: the Jacobi map with GR precesses the pericentre by the
+    closed form of the -k/r^2 problem, 2 pi (1/sqrt(1 - 2k/h^2) - 1) per
+    radial period (k = 3 mu^2/c^2, h^2 = mu a (1 - e^2))."""
+    a, e, c = 1.0, 0.3, 20.0
+    pos, vel = inputs.elements_to_cartesian(1.0, np.array([a]), np.array([e]), np.zeros(1), np.zeros(1),
+                                            np.zeros(1), np.array([np.pi]))
+    s = inputs.Systems(np.array([1], np.int32), np.array([1.0]), np.zeros((1, 8)), np.zeros((1, 8, 3)),
+                       np.zeros((1, 8, 3)), np.array([0.0]))
+    s.m[0, 0] = 1e-14
+    s.Q[0, 0] = pos[0]
+    s.V[0, 0] = vel[0]
+    P = 2 * np.pi * a ** 1.5
+    dt = P / 2000
+    Q, V = s.Q.astype(LD), s.V.astype(LD)
+    angles = []
+    for _ in range(2 * 2000 + 200):
+        Qn, Vn = oracle.jacobi_integrate(s, 1, Q=Q, V=V, dt=np.array([dt]), gr_c=c)
+        eta0 = float((Q[0, 0] * V[0, 0]).sum()); eta1 = float((Qn[0, 0] * Vn[0, 0]).sum())
+        if eta0 < 0 <= eta1:
+            f = -eta0 / (eta1 - eta0)
+            th0 = np.arctan2(float(Q[0, 0, 1]), float(Q[0, 0, 0]))
+            th1 = np.arctan2(float(Qn[0, 0, 1]), float(Qn[0, 0, 0]))
+            angles.append(th0 + f * np.angle(np.exp(1j * (th1 - th0))))
+        Q, V = Qn, Vn
+    prec = np.diff(np.unwrap(np.array(angles)))
+    assert len(prec) >= 1
+    k = 3.0 / c ** 2
+    exact = 2 * np.pi * (1 / np.sqrt(1 - 2 * k / (a * (1 - e * e))) - 1)
+    assert np.all(np.abs(prec - exact) < 2e-3 * exact), (prec, exact)
+
+
+@pytest.mark.parametrize("scheme", ["dkd", "saba2"])
+def test_gr_energy_error_bounded_second_order(scheme):
+    s = heavy_system(n=2, seed=50)
+    c = 100.0
+    p_in = 2 * np.pi * np.sqrt(np.linalg.norm(s.Q[0, 0]) ** 3)
+    def err(dt, n):
+        E0 = oracle.energy(s, gr_c=c)[0]
+        Q, V = s.Q.astype(LD), s.V.astype(LD)
+        worst = 0.0
+        for _ in range(n // 10):
+            Q, V = oracle.jacobi_integrate(s, 10, scheme=scheme, Q=Q, V=V, dt=np.array([dt]), gr_c=c)
+            worst = max(worst, abs(float((oracle.energy(s, Q, V, gr_c=c)[0] - E0) / E0)))
+        return worst
+    e1, e2 = err(p_in / 20, 400), err(p_in / 40, 800)
+    lo, hi = (3.0, 5.0) if scheme == "dkd" else (3.0, 20.0)
+    assert e1 < 1e-5 and lo < e1 / e2 < hi, (e1, e2)
