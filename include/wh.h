@@ -68,7 +68,8 @@ enum {
    * B(d_n dt) K(c_{n+1} dt) with Gauss-Legendre coefficients and B the whole
    * perturbation (I and J together in DHC, the Jacobi kick in Jacobi
    * coordinates); error O(eps dt^(2n) + eps^2 dt^2), n drifts' and kicks'
-   * cost per step.  Not with GR, not in reverse mode. */
+   * cost per step.  GR only in Jacobi coordinates (in DHC its flow does not
+   * commute with the jump's); not in reverse mode. */
   WH_SABA2 = 2,
   WH_SABA3 = 3,
   WH_SABA4 = 4
@@ -97,7 +98,8 @@ enum {
                            two or four planets, Sec. 3.5 footnote and Sec. 6): planets in lane order, each
                            drifting about the centre of mass of the star and the planets inside it with
                            mu = G (m0 + m_1 + ... + m_i), and a kick of the remaining Hamiltonian; no jump.
-                           Inputs and outputs stay in the DHC layout; no GR, no reverse mode. */
+                           Inputs and outputs stay in the DHC layout; GR (the same potential) enters
+                           the kick; no reverse mode. */
 };
 
 /* Sticky per-system status bits. */

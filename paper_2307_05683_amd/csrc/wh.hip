@@ -263,9 +263,13 @@ __device__ __forceinline__ double diff_of_products(double a, double x, double b,
   return a * x - b * y;
 }
 
-template <int G, int EXCH>
+//
+// With GR (the potential of the DHC map, a function of the heliocentric
+// positions) the force m_k gr_k on each planet and its reaction on the star
+// add  gr_i + (sum_{k>=i} m_k gr_k) / M_{i-1}  to a'_i.
+template <int G, int EXCH, bool GR = false>
 __device__ __forceinline__ void kick_jacobi(Lane& L, const Exch<G, EXCH>& ex, const JacConst& jc, int p, double tau,
-                                            double& vkx, double& vky, double& vkz) {
+                                            double& vkx, double& vky, double& vkz, double kg = 0.0) {
   const double qx = jac_to_helio<G>(L.qx, jc.w, p);
   const double qy = jac_to_helio<G>(L.qy, jc.w, p);
   const double qz = jac_to_helio<G>(L.qz, jc.w, p);
@@ -280,9 +284,16 @@ __device__ __forceinline__ void kick_jacobi(Lane& L, const Exch<G, EXCH>& ex, co
   const double cx = fma(jc.ratio, group_suffix_excl<G>(wq * qx, p), group_scan_excl<G>(L.m * ax, p) * jc.inv_Mim1);
   const double cy = fma(jc.ratio, group_suffix_excl<G>(wq * qy, p), group_scan_excl<G>(L.m * ay, p) * jc.inv_Mim1);
   const double cz = fma(jc.ratio, group_suffix_excl<G>(wq * qz, p), group_scan_excl<G>(L.m * az, p) * jc.inv_Mim1);
-  const double dvx = tau * ((ax - cx) + diff_of_products(kp, L.qx, kq, qx));
-  const double dvy = tau * ((ay - cy) + diff_of_products(kp, L.qy, kq, qy));
-  const double dvz = tau * ((az - cz) + diff_of_products(kp, L.qz, kq, qz));
+  double dvx = tau * ((ax - cx) + diff_of_products(kp, L.qx, kq, qx));
+  double dvy = tau * ((ay - cy) + diff_of_products(kp, L.qy, kq, qy));
+  double dvz = tau * ((az - cz) + diff_of_products(kp, L.qz, kq, qz));
+  if (GR) {
+    double gx, gy, gz;
+    gr_accel(qx, qy, qz, kg, gx, gy, gz);
+    dvx = fma(tau, fma(group_suffix_incl<G>(L.m * gx, p), jc.inv_Mim1, gx), dvx);
+    dvy = fma(tau, fma(group_suffix_incl<G>(L.m * gy, p), jc.inv_Mim1, gy), dvy);
+    dvz = fma(tau, fma(group_suffix_incl<G>(L.m * gz, p), jc.inv_Mim1, gz), dvz);
+  }
   L.cvx += dvx; L.cvy += dvy; L.cvz += dvz;
   vkx = L.vx + dvx; vky = L.vy + dvy; vkz = L.vz + dvz;
   renorm_all(L);
@@ -361,7 +372,7 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
       for (int k = 0; k < 4; ++k) {
         if (k < p.saba_n) {
           const double tb = p.sd[k] * dt;
-          if (JAC) kick_jacobi<G, EXCH>(L, ex, jc, pg, tb, vkx, vky, vkz);
+          if (JAC) kick_jacobi<G, EXCH, GR>(L, ex, jc, pg, tb, vkx, vky, vkz, kg);
           else kick_block<G, false, EXCH>(L, ex, inv_m0, 0.0, 0.5 * tb, tb, 0.5 * tb, vkx, vky, vkz);
           if (k + 1 < p.saba_n) drift(L, mu, p.sc[k + 1] * dt, dg);
         }
@@ -375,12 +386,12 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
       for (int s = 0; s < p.n_steps; ++s) {
         drift(L, jc.Mi, tk, dg);
         tk = dt;
-        kick_jacobi<G, EXCH>(L, ex, jc, pg, dt, vkx, vky, vkz);
+        kick_jacobi<G, EXCH, GR>(L, ex, jc, pg, dt, vkx, vky, vkz, kg);
       }
     } else {
       double ti = L.first ? h : dt;
       for (int s = 0; s < p.n_steps; ++s) {
-        kick_jacobi<G, EXCH>(L, ex, jc, pg, ti, vkx, vky, vkz);
+        kick_jacobi<G, EXCH, GR>(L, ex, jc, pg, ti, vkx, vky, vkz, kg);
         ti = dt;
         drift(L, jc.Mi, dt, dg);
       }
@@ -573,7 +584,9 @@ __device__ void sync_lane(const StepParams& p, Lane& L, int lane) {
       Exch<G, 0> ex;
       ex.init(lane, L.m);
       double vkx, vky, vkz;
-      if (JAC) kick_jacobi<G, 0>(L, ex, jac_const<G>(L.m0, L.m, pg), pg, h, vkx, vky, vkz);
+      if (JAC)
+        kick_jacobi<G, 0, GR>(L, ex, jac_const<G>(L.m0, L.m, pg), pg, h, vkx, vky, vkz,
+                              GR ? p.kgr * L.m0 * L.m0 : 0.0);
       else kick_block<G, GR, 0>(L, ex, 1.0 / L.m0, GR ? p.kgr * L.m0 * L.m0 : 0.0, h, h, 0.0, vkx, vky, vkz);
     }
   }
@@ -1227,8 +1240,8 @@ bool config_ok(const wh_config* c, std::string& why) {
       c->scheme != WH_SABA4) {
     why = "scheme must be WH_DKD, WH_KDK or WH_SABA2..4"; return false;
   }
-  if (c->scheme >= WH_SABA2 && c->gr_c > 0) {
-    why = "the SABA_n schemes need the perturbation's flow in one piece, which GR breaks"; return false;
+  if (c->scheme >= WH_SABA2 && c->gr_c > 0 && c->coords != WH_COORDS_JACOBI) {
+    why = "SABA_n with GR needs Jacobi coordinates: in DHC the GR and jump flows do not commute"; return false;
   }
   if (c->packing < WH_PACK_AUTO || c->packing > WH_PACK_PAIR) { why = "unknown packing"; return false; }
   if (c->block_waves != 0 && c->block_waves != 1 && c->block_waves != 2 && c->block_waves != 4) {
@@ -1242,9 +1255,7 @@ bool config_ok(const wh_config* c, std::string& why) {
     why = "the two-planets-per-lane packing runs the DHC drift-kick-drift and kick-drift-kick steps only";
     return false;
   }
-  if (c->coords == WH_COORDS_JACOBI && c->gr_c > 0) {
-    why = "the GR kick is implemented in democratic heliocentric coordinates only"; return false;
-  }
+
   if (!(c->gr_c == c->gr_c)) { why = "gr_c is NaN"; return false; }
   return true;
 }
@@ -1353,13 +1364,19 @@ void launch_step_exch(const wh_ctx* c, const StepParams& p, dim3 grid, dim3 bloc
     return;
   }
   if (c->cfg.scheme >= WH_SABA2) {
-    if (jac) hipLaunchKernelGGL((k_step<false, SCHEME_SABA, EXCH, true>), grid, block, 0, st, p);
+    if (jac && gr) hipLaunchKernelGGL((k_step<true, SCHEME_SABA, EXCH, true>), grid, block, 0, st, p);
+    else if (jac) hipLaunchKernelGGL((k_step<false, SCHEME_SABA, EXCH, true>), grid, block, 0, st, p);
     else hipLaunchKernelGGL((k_step<false, SCHEME_SABA, EXCH, false>), grid, block, 0, st, p);
     return;
   }
   if (jac) {
-    if (c->cfg.scheme == WH_DKD) hipLaunchKernelGGL((k_step<false, WH_DKD, EXCH, true>), grid, block, 0, st, p);
-    else hipLaunchKernelGGL((k_step<false, WH_KDK, EXCH, true>), grid, block, 0, st, p);
+    if (c->cfg.scheme == WH_DKD) {
+      if (gr) hipLaunchKernelGGL((k_step<true, WH_DKD, EXCH, true>), grid, block, 0, st, p);
+      else hipLaunchKernelGGL((k_step<false, WH_DKD, EXCH, true>), grid, block, 0, st, p);
+    } else {
+      if (gr) hipLaunchKernelGGL((k_step<true, WH_KDK, EXCH, true>), grid, block, 0, st, p);
+      else hipLaunchKernelGGL((k_step<false, WH_KDK, EXCH, true>), grid, block, 0, st, p);
+    }
     return;
   }
   if (c->cfg.scheme == WH_DKD) {
@@ -1403,11 +1420,21 @@ wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st
       else hipLaunchKernelGGL((k_sync_pair<false, WH_KDK>), grid, block, 0, st, q);
     }
   } else if (c->cfg.scheme >= WH_SABA2) {
-    if (c->cfg.coords == WH_COORDS_JACOBI) hipLaunchKernelGGL((k_sync<false, SCHEME_SABA, true>), grid, block, 0, st, q);
-    else hipLaunchKernelGGL((k_sync<false, SCHEME_SABA, false>), grid, block, 0, st, q);
+    // (GR, allowed in Jacobi coordinates only, enters the energy of the copy)
+    if (c->cfg.coords == WH_COORDS_JACOBI) {
+      if (gr) hipLaunchKernelGGL((k_sync<true, SCHEME_SABA, true>), grid, block, 0, st, q);
+      else hipLaunchKernelGGL((k_sync<false, SCHEME_SABA, true>), grid, block, 0, st, q);
+    } else {
+      hipLaunchKernelGGL((k_sync<false, SCHEME_SABA, false>), grid, block, 0, st, q);
+    }
   } else if (c->cfg.coords == WH_COORDS_JACOBI) {
-    if (c->cfg.scheme == WH_DKD) hipLaunchKernelGGL((k_sync<false, WH_DKD, true>), grid, block, 0, st, q);
-    else hipLaunchKernelGGL((k_sync<false, WH_KDK, true>), grid, block, 0, st, q);
+    if (c->cfg.scheme == WH_DKD) {
+      if (gr) hipLaunchKernelGGL((k_sync<true, WH_DKD, true>), grid, block, 0, st, q);
+      else hipLaunchKernelGGL((k_sync<false, WH_DKD, true>), grid, block, 0, st, q);
+    } else {
+      if (gr) hipLaunchKernelGGL((k_sync<true, WH_KDK, true>), grid, block, 0, st, q);
+      else hipLaunchKernelGGL((k_sync<false, WH_KDK, true>), grid, block, 0, st, q);
+    }
   } else if (c->cfg.scheme == WH_DKD) {
     if (gr) hipLaunchKernelGGL((k_sync<true, WH_DKD>), grid, block, 0, st, q);
     else hipLaunchKernelGGL((k_sync<false, WH_DKD>), grid, block, 0, st, q);

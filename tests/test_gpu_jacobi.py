@@ -134,12 +134,29 @@ def test_plain_per_size_path_matches_fused_bitwise():
 
 def test_unsupported_combinations_rejected():
     s = inputs.make_systems(4, 63, n_planets=3)
-    with pytest.raises(_lib.WHError):
-        Ensemble.from_systems(s, coords="jacobi", gr_c=10065.0)
     e = Ensemble.from_systems(s, coords="jacobi")
     with pytest.raises(_lib.WHError):
         e.forward_ckpt(10, 5)
     e.close()
+
+
+@pytest.mark.parametrize("scheme,gr_c", [("dkd", 10065.0), ("kdk", 40.0), ("saba2", 40.0), ("dkd", 40.0)])
+def test_gr_1000_steps(scheme, gr_c):
+    """GR in Jacobi coordinates (the DHC potential, joined to the kick) and
+    SABA_2 with GR, which Jacobi coordinates allow (one position-only kick)."""
+    s = inputs.make_systems(40, 64, n_planets=None, n_range=(1, 8))
+    print("case: scheme=%s gr_c=%g" % (scheme, gr_c), flush=True)
+    e = Ensemble.from_systems(s, coords="jacobi", scheme=scheme, gr_c=gr_c)
+    e.step(1000)
+    Q, V = e.state()
+    E = e.energy().cpu().numpy()
+    e.close()
+    Qg, Vg = Q.cpu().numpy(), V.cpu().numpy()
+    Qo, Vo = oracle.jacobi_integrate(s, 1000, scheme=scheme, gr_c=gr_c)
+    eq, ev = rel_err(s, Qg, Vg, Qo, Vo)
+    assert eq < TOL and ev < TOL, (eq, ev)
+    Eo = oracle.energy(s, Qg, Vg, gr_c=gr_c).astype(float)
+    assert np.abs((E - Eo) / Eo).max() < 1e-14
 
 
 def test_uneven_workload_full_size_sampled():
