@@ -9,6 +9,10 @@
  * equation), the jump step (Sec. 3.4, jump equation) and an optional 1/r^2
  * GR kick (Sec. 3.3, final paragraphs), composed drift-kick-drift as in
  * Sec. 3.1 with combined drifts and "keep unsynchronized" output (Sec. 3.5).
+ * Options (wh_config): kick-drift-kick and SABA_n compositions, Jacobi
+ * coordinates, lane packings; besides the integration the library evaluates
+ * energies and osculating elements, runs reverse mode (wh_forward_ckpt,
+ * wh_adjoint_n) and the Kepler-solver envelope explorer.
  *
  * Conventions (Sec. 3.5 assumptions):
  *   - G = 1; masses constant; dt fixed per system and > 0 (integrate
@@ -113,7 +117,7 @@ typedef struct {
   int32_t n_systems;   /* S >= 1 */
   double G;            /* must be 1.0 (Sec. 3.5) */
   double gr_c;         /* speed of light for the GR kick; <= 0 turns GR off */
-  int32_t scheme;      /* WH_DKD or WH_KDK */
+  int32_t scheme;      /* WH_DKD, WH_KDK or WH_SABA2..4 */
   int32_t packing;     /* WH_PACK_* */
   int32_t block_waves; /* wavefronts per workgroup: 1, 2 or 4 (0 = 1) */
   int32_t chunk_steps; /* steps per kernel launch (0 = 4096) */
