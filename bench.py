@@ -81,9 +81,10 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(workload: str, chunk: int, coords: str = "dhc", packing: str = "auto"):
-    """HBM bytes per launch from the committed counter summary, if the kernel
-    sources are still the ones it was taken on (else None)."""
+def measured_counters(workload: str, chunk: int, coords: str = "dhc", packing: str = "auto"):
+    """HBM bytes and hardware FP64 flops per launch from the committed counter
+    summary, if the kernel sources are still the ones it was taken on (else
+    None)."""
     import hashlib
     import re
     try:
@@ -92,13 +93,18 @@ def measured_traffic(workload: str, chunk: int, coords: str = "dhc", packing: st
     except (OSError, AttributeError, ValueError):
         return None
     for name, digest in rec["sources"].items():
-        with open(os.path.join(ROOT, "paper_2307_05683_amd", "csrc", name), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != digest:
-                return None
+        try:
+            with open(os.path.join(ROOT, "paper_2307_05683_amd", "csrc", name), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
+        except OSError:
+            return None
     if chunk != rec["chunk_steps"] or coords != "dhc":
         return None
     key = "%s/%s" % (workload, "pow2" if packing == "auto" else packing)
-    return rec["bytes_per_launch"].get(key)
+    if key not in rec["bytes_per_launch"]:
+        return None
+    return {"traffic": rec["bytes_per_launch"][key], "hw_flops": rec.get("hw_flops_per_launch", {}).get(key)}
 
 
 def flops_per_system_step(n_planets: np.ndarray, gr: bool, coords: str = "dhc", scheme: str = "dkd") -> float:
@@ -275,7 +281,7 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": measured_traffic(args.workload, opts["chunk_steps"], args.coords, opts["packing"]),
+            "traffic": None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
             "kernel": "k_step_pair (persistent step kernel, two planets per lane)" if opts["packing"] == "pair"
                       else "k_step (persistent step kernel)",
@@ -284,6 +290,16 @@ def main():
             "launches": n_launch,
         },
     }
+    counters = measured_counters(args.workload, opts["chunk_steps"], args.coords, opts["packing"])
+    if counters and scheme == "dkd":
+        out["roofline"]["traffic"] = counters["traffic"]
+        if counters["hw_flops"]:
+            # FP64 flops the hardware executed (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes, FMA = 2, per step of a
+            # counted launch) over the timed steps: the kernel's own issue efficiency, beside the
+            # algorithmic fraction
+            hw = counters["hw_flops"] / opts["chunk_steps"] * args.steps / gpu_s / 1e12
+            out["roofline"]["achieved_hardware"] = hw
+            out["roofline"]["frac_hardware"] = hw / FP64_PEAK_TFLOPS
     if tune_table is not None:
         out["config"]["autotune"] = [dict(r["opts"], rate=r["system_steps_per_s"]) for r in tune_table]
     if args.workload == "adjoint8":
