@@ -50,8 +50,11 @@ DEFAULT_STEPS = {"uniform8": 1_000_000, "uneven2to8": 1_000_000, "large8gr": 1_0
 
 
 # Two planets per lane pays once the one-planet layout has more wavefronts
-# than the chip has SIMDs (fewer, heavier waves with more independent work).
-DEFAULT_PACKING = {"uneven2to8": "pair", "large8gr": "pair"}
+# than the chip has SIMDs (fewer, heavier waves with more independent work);
+# two lanes per planet pays when it has fewer (more, lighter waves).
+DEFAULT_PACKING = {"uneven2to8": "pair", "large8gr": "pair", "uniform8": "split", "single8": "split"}
+KERNEL_NAME = {"pair": "k_step_pair (persistent step kernel, two planets per lane)",
+               "split": "k_step_split (persistent step kernel, two lanes per planet)"}
 
 
 def parse():
@@ -62,9 +65,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=4096, help="untimed steps before the timed region")
     ap.add_argument("--workload", default="uniform8", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--packing", default=None,
-                    help="auto|pow2|g8|pair|tuned (default: pair for uneven2to8 and large8gr, whose batches fill "
-                         "more wavefronts than the chip has SIMDs; auto otherwise)")
-    ap.add_argument("--block-waves", type=int, default=1)
+                    help="auto|pow2|g8|pair|split|tuned (default: pair for uneven2to8 and large8gr, whose batches "
+                         "fill more wavefronts than the chip has SIMDs, split for uniform8 and single8, which fill "
+                         "fewer; auto otherwise)")
+    ap.add_argument("--block-waves", type=int, default=None,
+                    help="wavefronts per workgroup (default 4 for uniform8: one four-wave workgroup per CU puts "
+                         "exactly one of its 1024 wavefronts on each SIMD; 1 otherwise)")
     ap.add_argument("--chunk", type=int, default=4096)
     ap.add_argument("--exchange", default="auto", choices=["auto", "dpp", "lds"])
     ap.add_argument("--scheme", default=None, choices=["dkd", "kdk", "saba2", "saba3", "saba4"],
@@ -198,6 +204,8 @@ def main():
     args = parse()
     if args.packing is None:
         args.packing = DEFAULT_PACKING.get(args.workload, "auto")
+    if args.block_waves is None:
+        args.block_waves = 4 if args.workload == "uniform8" else 1
     if args.steps is None:
         args.steps = DEFAULT_STEPS.get(args.workload, 1_000_000)
     if args.gpus != 1:
@@ -283,8 +291,7 @@ def main():
             "frac": achieved / FP64_PEAK_TFLOPS,
             "traffic": None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
-            "kernel": "k_step_pair (persistent step kernel, two planets per lane)" if opts["packing"] == "pair"
-                      else "k_step (persistent step kernel)",
+            "kernel": KERNEL_NAME.get(opts["packing"], "k_step (persistent step kernel)"),
             "algorithmic_flops_per_step": flops_step,
             "avg_launch_ms": gpu_s * 1e3 / n_launch,
             "launches": n_launch,

@@ -23,6 +23,7 @@
 #include "wh_device.h"
 #include "wh_adjoint.h"
 #include "wh_pair.h"
+#include "wh_split.h"
 
 using namespace wh;
 
@@ -185,6 +186,18 @@ template <int G> struct Exch<G, 1> {
     interaction_accel_dpp<G>(t, qx, qy, qz, m, ax, ay, az);
   }
 };
+// The split layout (two lanes per planet, wh_split.h) has one schedule, all
+// DPP, whatever the exchange option.
+struct ExchSplit {
+  SplitMass t;
+  __device__ __forceinline__ void init(int lane, double m) { t = make_split_mass(lane, m); }
+  __device__ __forceinline__ void accel(double qx, double qy, double qz, double m, double& ax, double& ay,
+                                        double& az) const {
+    accel_split(t, qx, qy, qz, m, ax, ay, az);
+  }
+};
+template <> struct Exch<G_SPLIT, 0> : ExchSplit {};
+template <> struct Exch<G_SPLIT, 1> : ExchSplit {};
 
 // Kick block of the loop on the compensated state.  With GR:
 // J(ta) [I + GR](ti) J(tc); without GR the jumps commute with I and merge:
@@ -354,7 +367,7 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
   const double kg = GR ? p.kgr * L.m0 * L.m0 : 0.0;
   KepDiag dg{0.0, 1.0e300};
   double vkx, vky, vkz;
-  if (SCHEME == SCHEME_SABA) {
+  if constexpr (SCHEME == SCHEME_SABA) {
     // SABA_n: K(c_1 dt) B(d_1 dt) K(c_2 dt) ... B(d_n dt) K(c_{n+1} dt), the
     // closing drift merged with the next step's opening one (c_{n+1} = c_1).
     // B is the whole perturbation: I and J together in DHC (their flows
@@ -378,7 +391,7 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
         }
       }
     }
-  } else if (JAC) {
+  } else if constexpr (JAC) {
     const int pg = lane & (G - 1);
     const JacConst jc = jac_const<G>(L.m0, L.m, pg);
     if (SCHEME == WH_DKD) {
@@ -558,6 +571,19 @@ __global__ __launch_bounds__(256) void k_step_pair(StepParams p) {
 }
 
 // ---------------------------------------------------------------------------
+// Two lanes per planet (WH_PACK_SPLIT, see wh_split.h): every wave holds four
+// 16-lane groups, one system each, planet p in lanes 2p and 2p + 1.  The step
+// is the one-planet step with the split interaction and the planet sums of
+// that layout.
+template <bool GR, int SCHEME>
+__global__ __launch_bounds__(256) void k_step_split(StepParams p) {
+  const int lane = threadIdx.x & 63;
+  const int wave = p.wave0 + (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  step_group<G_SPLIT, GR, SCHEME, 1, false>(p, wave * 64 + lane, lane);
+}
+
+// ---------------------------------------------------------------------------
 // Synchronized copy: DKD applies the pending half drift K(h), SABA_n the
 // pending drift K(c_1 dt); KDK applies the pending half kick J(h) [I + GR](h).
 // A synchronized state is left as is.
@@ -579,12 +605,14 @@ __device__ void sync_lane(const StepParams& p, Lane& L, int lane) {
     if (SCHEME == WH_DKD || SCHEME == SCHEME_SABA) {
       KepDiag dg{0.0, 1.0e300};
       const double tau = SCHEME == SCHEME_SABA ? p.sc[0] * L.dt : h;
-      drift(L, JAC ? jac_const<G>(L.m0, L.m, pg).Mi : L.m0, tau, dg);
+      double mu = L.m0;
+      if constexpr (JAC) mu = jac_const<G>(L.m0, L.m, pg).Mi;
+      drift(L, mu, tau, dg);
     } else {
       Exch<G, 0> ex;
       ex.init(lane, L.m);
       double vkx, vky, vkz;
-      if (JAC)
+      if constexpr (JAC)
         kick_jacobi<G, 0, GR>(L, ex, jac_const<G>(L.m0, L.m, pg), pg, h, vkx, vky, vkz,
                               GR ? p.kgr * L.m0 * L.m0 : 0.0);
       else kick_block<G, GR, 0>(L, ex, 1.0 / L.m0, GR ? p.kgr * L.m0 * L.m0 : 0.0, h, h, 0.0, vkx, vky, vkz);
@@ -592,7 +620,7 @@ __device__ void sync_lane(const StepParams& p, Lane& L, int lane) {
   }
   L.qx += L.cqx; L.qy += L.cqy; L.qz += L.cqz;
   L.vx += L.cvx; L.vy += L.cvy; L.vz += L.cvz;
-  if (JAC) jacobi_to_dhc<G>(L, pg);
+  if constexpr (JAC) jacobi_to_dhc<G>(L, pg);
 }
 
 // Energy of the lane's system (every lane of the group gets it).
@@ -601,10 +629,14 @@ template <int G, bool GR> __device__ double group_energy(const StepParams& p, co
   const double r = sqrt(r2);
   double e = 0.5 * L.m * (L.vx * L.vx + L.vy * L.vy + L.vz * L.vz) - L.m0 * L.m / r;
   if (GR) e -= 0.5 * p.kgr * L.m0 * L.m0 * L.m / r2;   // 3 m0^2 m / (c^2 r^2)
+  // planets of the group and lanes per planet (2 in the split layout, where
+  // lane ^ 2k holds planet p ^ k)
+  constexpr int NP = G == G_SPLIT ? 8 : G;
+  constexpr int LS = G == G_SPLIT ? 2 : 1;
   double pair = 0.0;
 #pragma unroll
-  for (int k = 1; k < G; ++k) {
-    int src = (lane ^ k) << 2;
+  for (int k = 1; k < NP; ++k) {
+    int src = (lane ^ (k * LS)) << 2;
     double px = bperm(src, L.qx), py = bperm(src, L.qy), pz = bperm(src, L.qz), pm = bperm(src, L.m);
     double dx = L.qx - px, dy = L.qy - py, dz = L.qz - pz;
     pair += pm / sqrt(dx * dx + dy * dy + dz * dz);
@@ -619,7 +651,9 @@ template <int G, bool GR, int SCHEME, bool JAC> __device__ void sync_group(const
   const StepParams& p = q.sp;
   Lane L = load_lane(p, slot);
   sync_lane<G, GR, SCHEME, JAC>(p, L, lane);
-  if (q.Q_out && L.sys >= 0 && L.pl >= 0) {
+  // one writer per planet (the split layout holds two copies)
+  const bool writer = L.sys >= 0 && L.pl >= 0 && (G != G_SPLIT || (lane & 1) == 0);
+  if (q.Q_out && writer) {
     size_t o = ((size_t)L.sys * 8 + L.pl) * 3;
     q.Q_out[o] = L.qx; q.Q_out[o + 1] = L.qy; q.Q_out[o + 2] = L.qz;
     q.V_out[o] = L.vx; q.V_out[o + 1] = L.vy; q.V_out[o + 2] = L.vz;
@@ -641,7 +675,7 @@ template <int G, bool GR, int SCHEME, bool JAC> __device__ void sync_group(const
     double ex = (uy * hz - uz * hy) / mu - L.qx / r;
     double ey = (uz * hx - ux * hz) / mu - L.qy / r;
     double ez = (ux * hy - uy * hx) / mu - L.qz / r;
-    if (L.sys >= 0 && L.pl >= 0) {
+    if (writer) {
       size_t o = (size_t)L.sys * 8 + L.pl;
       q.a_out[o] = a;
       q.e_out[o] = sqrt(ex * ex + ey * ey + ez * ez);
@@ -660,6 +694,15 @@ __global__ __launch_bounds__(256) void k_sync(SyncParams q) {
   else if (wave < p.w2) sync_group<2, GR, SCHEME, JAC>(q, slot, lane);
   else if (wave < p.w4) sync_group<4, GR, SCHEME, JAC>(q, slot, lane);
   else sync_group<8, GR, SCHEME, JAC>(q, slot, lane);
+}
+
+template <bool GR, int SCHEME>
+__global__ __launch_bounds__(256) void k_sync_split(SyncParams q) {
+  const StepParams& p = q.sp;
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  sync_group<G_SPLIT, GR, SCHEME, false>(q, wave * 64 + lane, lane);
 }
 
 // Synchronized copy of the pair layout: as sync_group for both slots.
@@ -997,7 +1040,8 @@ __global__ __launch_bounds__(256) void k_adj_finish(AdjParams q) {
 // Kepler solves stay finite and their positions never coincide with another
 // lane's (their zero mass keeps them out of every other lane's sums).
 __global__ void k_gather(double* st, int ns, double* m0s, double* dts, const int* slot_sys, const int* slot_pl,
-                         const double* m0, const double* m, const double* Q, const double* V, const double* dt) {
+                         const double* m0, const double* m, const double* Q, const double* V, const double* dt,
+                         int split) {
   int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= ns) return;
   int s = slot_sys[slot], pl = slot_pl[slot];
@@ -1012,7 +1056,9 @@ __global__ void k_gather(double* st, int ns, double* m0s, double* dts, const int
     }
     st[6 * ns + slot] = m[(size_t)s * 8 + pl];
   } else {
-    int k = (slot & 7) | ((slot >> 3) & 8);   // distinct for the two slots of a lane in the pair layout
+    // distinct for the two slots of a lane in the pair layout; in the split
+    // layout the planet's index, the same for both of its copies
+    int k = split ? (slot >> 1) & 7 : (slot & 7) | ((slot >> 3) & 8);
     double a = 1.0e4 * (1.0 + 0.25 * k);
     double ph = 0.3 + 0.7 * k;
     double vc = sqrt(M0 / a);
@@ -1116,6 +1162,7 @@ wh_status hip_check(hipError_t e, const char* what) {
 
 struct Packing {
   bool pair = false;   // WH_PACK_PAIR: two slots (planets) per lane, 128 slots per wave
+  bool split = false;  // WH_PACK_SPLIT: two lanes (copies) per planet, 16 lanes per system
   int ns = 0, nwaves = 0;
   int w1 = 0, w2 = 0, w4 = 0, w8 = 0;
   int plain_begin[9] = {0}, plain_end[9] = {0};   // G8 packing: waves of each planet count
@@ -1183,6 +1230,22 @@ bool make_packing(int S, const int32_t* np, int packing, Packing& P) {
     }
     P.pair = true;
     P.w1 = ends[0]; P.w2 = ends[1]; P.w4 = ends[2]; P.w8 = ends[2];
+  } else if (packing == WH_PACK_SPLIT) {
+    // every system takes a 16-lane group, four per wave, in index order;
+    // planet p (padding beyond N) in lanes 2p and 2p + 1
+    const int nw = (S + 3) / 4;
+    for (int w = 0; w < nw; ++w)
+      for (int j = 0; j < 4; ++j) {
+        const int s = w * 4 + j < S ? w * 4 + j : -1;
+        for (int l = 0; l < 16; ++l) {
+          P.slot_sys.push_back(s);
+          P.slot_pl.push_back(s >= 0 && (l >> 1) < np[s] ? l >> 1 : -1);
+        }
+      }
+    P.nwaves = nw;
+    P.split = true;
+    P.w1 = P.w2 = P.w4 = 0;
+    P.w8 = nw;
   } else if (packing == WH_PACK_G8) {
     for (int n = 1; n <= 8; ++n) {
       std::vector<int> cls;
@@ -1243,7 +1306,7 @@ bool config_ok(const wh_config* c, std::string& why) {
   if (c->scheme >= WH_SABA2 && c->gr_c > 0 && c->coords != WH_COORDS_JACOBI) {
     why = "SABA_n with GR needs Jacobi coordinates: in DHC the GR and jump flows do not commute"; return false;
   }
-  if (c->packing < WH_PACK_AUTO || c->packing > WH_PACK_PAIR) { why = "unknown packing"; return false; }
+  if (c->packing < WH_PACK_AUTO || c->packing > WH_PACK_SPLIT) { why = "unknown packing"; return false; }
   if (c->block_waves != 0 && c->block_waves != 1 && c->block_waves != 2 && c->block_waves != 4) {
     why = "block_waves must be 0, 1, 2 or 4"; return false;
   }
@@ -1253,6 +1316,10 @@ bool config_ok(const wh_config* c, std::string& why) {
   if (c->coords != WH_COORDS_DHC && c->coords != WH_COORDS_JACOBI) { why = "unknown coordinates"; return false; }
   if (c->packing == WH_PACK_PAIR && (c->coords != WH_COORDS_DHC || (c->scheme != WH_DKD && c->scheme != WH_KDK))) {
     why = "the two-planets-per-lane packing runs the DHC drift-kick-drift and kick-drift-kick steps only";
+    return false;
+  }
+  if (c->packing == WH_PACK_SPLIT && (c->coords != WH_COORDS_DHC || (c->scheme != WH_DKD && c->scheme != WH_KDK))) {
+    why = "the two-lanes-per-planet packing runs the DHC drift-kick-drift and kick-drift-kick steps only";
     return false;
   }
 
@@ -1363,6 +1430,16 @@ void launch_step_exch(const wh_ctx* c, const StepParams& p, dim3 grid, dim3 bloc
     }
     return;
   }
+  if (c->P.split) {
+    if (c->cfg.scheme == WH_DKD) {
+      if (gr) hipLaunchKernelGGL((k_step_split<true, WH_DKD>), grid, block, 0, st, p);
+      else hipLaunchKernelGGL((k_step_split<false, WH_DKD>), grid, block, 0, st, p);
+    } else {
+      if (gr) hipLaunchKernelGGL((k_step_split<true, WH_KDK>), grid, block, 0, st, p);
+      else hipLaunchKernelGGL((k_step_split<false, WH_KDK>), grid, block, 0, st, p);
+    }
+    return;
+  }
   if (c->cfg.scheme >= WH_SABA2) {
     if (jac && gr) hipLaunchKernelGGL((k_step<true, SCHEME_SABA, EXCH, true>), grid, block, 0, st, p);
     else if (jac) hipLaunchKernelGGL((k_step<false, SCHEME_SABA, EXCH, true>), grid, block, 0, st, p);
@@ -1418,6 +1495,14 @@ wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st
     } else {
       if (gr) hipLaunchKernelGGL((k_sync_pair<true, WH_KDK>), grid, block, 0, st, q);
       else hipLaunchKernelGGL((k_sync_pair<false, WH_KDK>), grid, block, 0, st, q);
+    }
+  } else if (c->P.split) {
+    if (c->cfg.scheme == WH_DKD) {
+      if (gr) hipLaunchKernelGGL((k_sync_split<true, WH_DKD>), grid, block, 0, st, q);
+      else hipLaunchKernelGGL((k_sync_split<false, WH_DKD>), grid, block, 0, st, q);
+    } else {
+      if (gr) hipLaunchKernelGGL((k_sync_split<true, WH_KDK>), grid, block, 0, st, q);
+      else hipLaunchKernelGGL((k_sync_split<false, WH_KDK>), grid, block, 0, st, q);
     }
   } else if (c->cfg.scheme >= WH_SABA2) {
     // (GR, allowed in Jacobi coordinates only, enters the energy of the copy)
@@ -1580,7 +1665,7 @@ wh_status wh_init(wh_ctx** out, const wh_config* cfg, const int32_t* n_planets, 
     return st;
   }
   hipLaunchKernelGGL(k_gather, dim3((ns + 255) / 256), dim3(256), 0, stream, c->st, ns, c->m0s, c->dts, c->slot_sys,
-                     c->slot_pl, m0, m, Q, V, dt);
+                     c->slot_pl, m0, m, Q, V, dt, c->P.split ? 1 : 0);
   hipLaunchKernelGGL(k_fill_u32, dim3((S + 255) / 256), dim3(256), 0, stream, c->flags, 0u, S);
   hipLaunchKernelGGL(k_fill_u32, dim3((S + 255) / 256), dim3(256), 0, stream, (uint32_t*)c->synced, 1u, S);
   if (cfg->coords == WH_COORDS_JACOBI)
@@ -1682,7 +1767,8 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
   if (c->cfg.scheme != WH_DKD) return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD");
   if (c->cfg.coords != WH_COORDS_DHC)
     return fail(WH_ESTATE, "reverse mode is implemented in democratic heliocentric coordinates");
-  if (c->P.pair) return fail(WH_ESTATE, "reverse mode is implemented for the one-planet-per-lane packings");
+  if (c->P.pair || c->P.split)
+    return fail(WH_ESTATE, "reverse mode is implemented for the one-planet-per-lane packings");
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
   TapeLayout T = tape_layout(c->P.ns, n_steps, ckpt_every);
   if (tape_bytes < T.total) return fail(WH_EWORKSPACE, "tape too small: need " + std::to_string(T.total) + " bytes");

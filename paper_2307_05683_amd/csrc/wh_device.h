@@ -54,10 +54,26 @@ __device__ __forceinline__ double bperm(int src_byte_addr, double v) {
   return __hiloint2double(hi, lo);
 }
 
+// row_ror:n -- lane l of a 16-lane row reads lane (l - n) mod 16
+constexpr int DPP_ROR3 = 0x123, DPP_ROR7 = 0x127, DPP_ROR8 = 0x128, DPP_ROR9 = 0x129, DPP_ROR13 = 0x12D;
+
+// Group of 16 lanes = the split layout (wh_split.h): planet p in lanes 2p and
+// 2p + 1, which hold identical copies.
+constexpr int G_SPLIT = 16;
+
 // Sum over an aligned group of G lanes; every lane receives the same bits.
 // Butterfly: after stage s each lane holds the sum of its 2^s-lane block
-// (the GPU form of the three shuffle-and-add stages of Sec. 3.4).
+// (the GPU form of the three shuffle-and-add stages of Sec. 3.4).  In the
+// split layout the sum runs over planets, each counted once: lanes xor 2 are
+// planets p and p ^ 1 of one copy, after which every lane of a quad holds the
+// same bits, and the half-row mirror and the row rotation by 8 add the other
+// quad and the other half-row.
 template <int G> __device__ __forceinline__ double group_sum(double v) {
+  if (G == G_SPLIT) {
+    v += dpp<DPP_XOR2>(v);
+    v += dpp<DPP_HALF_MIRROR>(v);
+    return v + dpp<DPP_ROR8>(v);
+  }
   if (G >= 2) v += dpp<DPP_XOR1>(v);
   if (G >= 4) v += dpp<DPP_XOR2>(v);
   if (G >= 8) v += dpp<DPP_HALF_MIRROR>(v);
@@ -67,6 +83,7 @@ template <int G> __device__ __forceinline__ int group_or(int v) {
   if (G >= 2) v |= dpp_i<DPP_XOR1>(v);
   if (G >= 4) v |= dpp_i<DPP_XOR2>(v);
   if (G >= 8) v |= dpp_i<DPP_HALF_MIRROR>(v);
+  if (G >= 16) v |= dpp_i<DPP_ROR8>(v);
   return v;
 }
 

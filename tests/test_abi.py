@@ -37,6 +37,33 @@ def test_workspace_size_follows_packing():
     assert a < b
 
 
+def _layout_bytes(S, ns):
+    a = lambda x: (x + 255) // 256 * 256
+    return a(13 * 8 * ns) + 2 * a(8 * ns) + 2 * a(4 * ns) + 2 * a(4 * S)
+
+
+@pytest.mark.parametrize("S", [1, 4, 7, 64, 1001])
+def test_split_packing_takes_16_lanes_per_system(S):
+    cfg = _lib.default_config(S)
+    cfg.packing = _lib.WH_PACK_SPLIT
+    n = np.random.default_rng(S).integers(1, 9, S)
+    assert _ws(cfg, n) == _layout_bytes(S, 64 * ((S + 3) // 4))
+
+
+@pytest.mark.parametrize("packing", [_lib.WH_PACK_PAIR, _lib.WH_PACK_SPLIT])
+def test_pair_and_split_packings_need_dhc_wh(packing):
+    cfg = _lib.default_config(3)
+    cfg.packing = packing
+    assert _ws(cfg, [2, 5, 8]) > 0
+    cfg.scheme = _lib.WH_KDK
+    assert _ws(cfg, [2, 5, 8]) > 0
+    cfg.scheme = _lib.WH_SABA2
+    assert _ws(cfg, [2, 5, 8]) == 0
+    cfg.scheme = _lib.WH_DKD
+    cfg.coords = _lib.WH_COORDS_JACOBI
+    assert _ws(cfg, [2, 5, 8]) == 0
+
+
 @pytest.mark.parametrize("bad", [
     dict(G=2.0), dict(scheme=5), dict(packing=7), dict(block_waves=3), dict(chunk_steps=-1), dict(n_systems=0),
     dict(exchange=9),
