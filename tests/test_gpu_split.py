@@ -141,11 +141,16 @@ def test_flags_isolated():
     assert not flags[others].any()
 
 
-def test_full_size_sampled():
+@pytest.mark.parametrize("block_waves", [4, 1])
+def test_full_size_sampled(block_waves):
+    """The benchmark's workload (4096 eight-planet systems) in its launch
+    configuration (split packing, four-wave workgroups, 4096-step launches)
+    and with one-wave workgroups; sampled systems checked one by one
+    against the oracle."""
     s = inputs.workload("uniform8")
-    Qg, Vg, _, flags = run(s, 1000, packing="split", chunk_steps=4096, block_waves=1)
+    Qg, Vg, _, flags = run(s, 1000, packing="split", chunk_steps=4096, block_waves=block_waves)
     assert not flags.any()
-    idx = np.random.default_rng(6).choice(s.S, 24, replace=False)
+    idx = np.random.default_rng(6).choice(s.S, 48, replace=False)
     sub = s.subset(idx)
     Qo, Vo = oracle.integrate(sub, 1000)
     assert rel(sub, Qg[idx], Vg[idx], Qo, Vo) < TOL
