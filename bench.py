@@ -52,7 +52,9 @@ DEFAULT_STEPS = {"uniform8": 1_000_000, "uneven2to8": 1_000_000, "large8gr": 1_0
 # Two planets per lane pays once the one-planet layout has more wavefronts
 # than the chip has SIMDs (fewer, heavier waves with more independent work);
 # two lanes per planet pays when it has fewer (more, lighter waves).
-DEFAULT_PACKING = {"uneven2to8": "pair", "large8gr": "pair", "uniform8": "split", "single8": "split"}
+# The uneven batch is run as its workload states, with the autotuned packing
+# (which picks two planets per lane).
+DEFAULT_PACKING = {"uneven2to8": "tuned", "large8gr": "pair", "uniform8": "split", "single8": "split"}
 KERNEL_NAME = {"pair": "k_step_pair (persistent step kernel, two planets per lane)",
                "split": "k_step_split (persistent step kernel, two lanes per planet)"}
 
@@ -65,9 +67,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=4096, help="untimed steps before the timed region")
     ap.add_argument("--workload", default="uniform8", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--packing", default=None,
-                    help="auto|pow2|g8|pair|split|tuned (default: pair for uneven2to8 and large8gr, whose batches "
-                         "fill more wavefronts than the chip has SIMDs, split for uniform8 and single8, which fill "
-                         "fewer; auto otherwise)")
+                    help="auto|pow2|g8|pair|split|tuned (default: tuned for uneven2to8, pair for large8gr, whose "
+                         "batch fills more wavefronts than the chip has SIMDs, split for uniform8 and single8, which "
+                         "fill fewer; auto otherwise)")
     ap.add_argument("--block-waves", type=int, default=None,
                     help="wavefronts per workgroup (default 4 for uniform8: one four-wave workgroup per CU puts "
                          "exactly one of its 1024 wavefronts on each SIMD; 1 otherwise)")
