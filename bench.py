@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--cpu-systems", type=int, default=256)
     ap.add_argument("--plain-steps", type=int, default=2000, help="steps of the per-size reference path")
     ap.add_argument("--ckpt-every", type=int, default=1000, help="checkpoint interval of the adjoint workload")
+    ap.add_argument("--save-state", default=None,
+                    help="write the final synchronized states and per-system energy errors to this .npz file")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates memory counters)")
     return ap.parse_args()
@@ -232,6 +234,7 @@ def main():
         opts.update(best)
         print("[bench] chosen: %s" % best, file=sys.stderr, flush=True)
     ens = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, device=dev, **opts)
+    E0 = ens.energy()        # initial energy of every system (outside the timed region)
     print("[bench] %s: S=%d, warmup %d steps" % (args.workload, systems.S, args.warmup), file=sys.stderr, flush=True)
     if args.copy_probe_mb:
         x = torch.ones(args.copy_probe_mb << 17, dtype=torch.float64, device=dev)
@@ -255,6 +258,13 @@ def main():
     print("[bench] timed %d steps: %.3f s (events), %.3f s (wall)" % (args.steps, gpu_s, wall), file=sys.stderr,
           flush=True)
     flags = ens.flags().cpu().numpy()
+    E1 = ens.energy()
+    dE = ((E1 - E0) / E0).abs().cpu().numpy()
+    ok = flags == 0
+    if args.save_state:
+        Q, V = ens.state()
+        np.savez(args.save_state, Q=Q.cpu().numpy(), V=V.cpu().numpy(), rel_energy_error=dE, flags=flags,
+                 n_planets=systems.n_planets, steps=args.warmup + args.steps)
     sys_steps = systems.S * args.steps
     value = sys_steps / gpu_s
     n_launch = -(-args.steps // opts["chunk_steps"])
@@ -284,6 +294,15 @@ def main():
             "coords": args.coords,
             "scheme": scheme,
             "flagged_systems": int((flags != 0).sum()),
+        },
+        # relative energy error |E(T) - E(0)| / |E(0)| per system after the warmup and timed steps (unflagged)
+        "energy_error": {
+            "steps": args.warmup + args.steps,
+            "median": float(np.median(dE[ok])) if ok.any() else None,
+            "p90": float(np.percentile(dE[ok], 90)) if ok.any() else None,
+            "p99": float(np.percentile(dE[ok], 99)) if ok.any() else None,
+            "max": float(dE[ok].max()) if ok.any() else None,
+            "flagged_fraction": float(1.0 - ok.mean()),
         },
         "roofline": {
             "bound": "alu",
