@@ -117,7 +117,9 @@ enum {
 };
 
 typedef struct {
-  int32_t n_systems;   /* S >= 1 */
+  int32_t n_systems;   /* S >= 1; the packing may use at most 2^27 lane slots (16.7 million
+                          eight-planet systems with one planet per lane, 8.4 million with
+                          WH_PACK_SPLIT, 33.5 million with WH_PACK_PAIR) */
   double G;            /* must be 1.0 (Sec. 3.5) */
   double gr_c;         /* speed of light for the GR kick; <= 0 turns GR off */
   int32_t scheme;      /* WH_DKD, WH_KDK or WH_SABA2..4 */

@@ -1174,12 +1174,43 @@ int group_size(int n, int packing) {
   return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : 8;
 }
 
+// Device indexing is 32-bit: row r of a [rows][ns] array sits at r * ns, with
+// up to 13 rows (the state), so the lane-slot count is capped at 2^27
+// (14 GB of state; 16.7 million eight-planet systems with one planet per
+// lane).
+constexpr int64_t MAX_SLOTS = int64_t(1) << 27;
+
+// Lane slots a packing needs, counted before any table is built.
+int64_t slots_needed(int S, const int32_t* np, int packing) {
+  int64_t cnt[9] = {0};
+  for (int s = 0; s < S; ++s) cnt[np[s]]++;
+  auto waves = [](int64_t n, int per_wave) { return (n + per_wave - 1) / per_wave; };
+  if (packing == WH_PACK_SPLIT) return waves(S, 4) * 64;
+  if (packing == WH_PACK_PAIR)
+    return (waves(cnt[1] + cnt[2], 64) + waves(cnt[3] + cnt[4], 32) + waves(cnt[5] + cnt[6] + cnt[7] + cnt[8], 16)) *
+           128;
+  if (packing == WH_PACK_G8) {
+    int64_t w = 0;
+    for (int n = 1; n <= 8; ++n) w += waves(cnt[n], 8);
+    return w * 64;
+  }
+  return (waves(cnt[1], 64) + waves(cnt[2], 32) + waves(cnt[3] + cnt[4], 16) +
+          waves(cnt[5] + cnt[6] + cnt[7] + cnt[8], 8)) * 64;
+}
+
 // Lay systems out on lanes.  Systems of one group size fill whole waves; G8
 // packing also keeps each planet count on waves of its own (for the
 // per-size reference path).  Within a class systems keep their index order.
-bool make_packing(int S, const int32_t* np, int packing, Packing& P) {
+bool make_packing(int S, const int32_t* np, int packing, Packing& P, std::string* why = nullptr) {
   for (int s = 0; s < S; ++s)
-    if (np[s] < 1 || np[s] > 8) return false;
+    if (np[s] < 1 || np[s] > 8) {
+      if (why) *why = "planet counts must be in 1..8";
+      return false;
+    }
+  if (slots_needed(S, np, packing) > MAX_SLOTS) {
+    if (why) *why = "too many systems: the packing needs more than 2^27 lane slots";
+    return false;
+  }
   auto add_wave_block = [&](const std::vector<int>& systems, int G) {
     int per_wave = 64 / G;
     int nw = ((int)systems.size() + per_wave - 1) / per_wave;
@@ -1271,7 +1302,10 @@ bool make_packing(int S, const int32_t* np, int packing, Packing& P) {
   }
   P.ns = P.nwaves * (P.pair ? 128 : 64);
   // every wave holds exactly 64 (pair layout: 128) slots; the device tables are copied at ns
-  if ((int)P.slot_sys.size() != P.ns || (int)P.slot_pl.size() != P.ns) return false;
+  if ((int)P.slot_sys.size() != P.ns || (int)P.slot_pl.size() != P.ns || P.ns != slots_needed(S, np, packing)) {
+    if (why) *why = "internal error: inconsistent lane packing";
+    return false;
+  }
   return true;
 }
 
@@ -1609,9 +1643,9 @@ wh_status wh_init(wh_ctx** out, const wh_config* cfg, const int32_t* n_planets, 
   wh_ctx* c = new wh_ctx();
   c->cfg = *cfg;
   c->S = S;
-  if (!make_packing(S, n_planets, eff_packing(cfg), c->P)) {
+  if (!make_packing(S, n_planets, eff_packing(cfg), c->P, &why)) {
     delete c;
-    return fail(WH_EINVAL, "planet counts must be in 1..8");
+    return fail(WH_EINVAL, why);
   }
   c->lay = make_layout(S, c->P.ns);
   if (workspace_bytes < c->lay.total) {

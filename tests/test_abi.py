@@ -50,6 +50,18 @@ def test_split_packing_takes_16_lanes_per_system(S):
     assert _ws(cfg, n) == _layout_bytes(S, 64 * ((S + 3) // 4))
 
 
+@pytest.mark.parametrize("packing,max_systems", [(_lib.WH_PACK_POW2, 1 << 24), (_lib.WH_PACK_SPLIT, 1 << 23),
+                                                 (_lib.WH_PACK_PAIR, 1 << 25)])
+def test_lane_slot_cap(packing, max_systems):
+    # 32-bit device indexing: at most 2^27 lane slots; eight-planet systems
+    # take 8 (one planet per lane), 16 (split) or 4 (pair) slots each
+    cfg = _lib.default_config(max_systems + 1)
+    cfg.packing = packing
+    assert _ws(cfg, np.full(max_systems + 1, 8, dtype=np.int32)) == 0
+    cfg.n_systems = 1000
+    assert _ws(cfg, np.full(1000, 8, dtype=np.int32)) > 0
+
+
 @pytest.mark.parametrize("packing", [_lib.WH_PACK_PAIR, _lib.WH_PACK_SPLIT])
 def test_pair_and_split_packings_need_dhc_wh(packing):
     cfg = _lib.default_config(3)

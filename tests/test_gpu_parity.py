@@ -308,17 +308,19 @@ def test_large_gr_full_size_sampled():
     assert eq < TOL and ev < TOL, (eq, ev)
 
 
-def test_million_systems_tiled():
-    """2^20 eight-planet systems (8.4 million lanes, 131072 wavefronts): the
-    4096 distinct systems of the uniform workload tiled 256 times.  Systems
-    are independent, so every copy must end bitwise equal to the first, and
-    sampled ones match the oracle."""
+@pytest.mark.parametrize("packing", ["auto", "pair", "split"])
+def test_million_systems_tiled(packing):
+    """2^20 eight-planet systems (one planet per lane: 8.4 million lanes,
+    131072 wavefronts; pair: 65536; split: 262144): the 4096 distinct systems
+    of the uniform workload tiled 256 times.  Systems are independent, so
+    every copy must end bitwise equal to the first, and sampled ones match
+    the oracle."""
     base = inputs.workload("uniform8")
     reps = 256
     t = inputs.Systems(np.tile(base.n_planets, reps), np.tile(base.m0, reps), np.tile(base.m, (reps, 1)),
                        np.tile(base.Q, (reps, 1, 1)), np.tile(base.V, (reps, 1, 1)), np.tile(base.dt, reps))
     assert t.S == 1 << 20
-    e = Ensemble.from_systems(t)
+    e = Ensemble.from_systems(t, packing=packing)
     e.step(300)
     Q, V = e.state()
     e.close()
