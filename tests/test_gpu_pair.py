@@ -116,11 +116,15 @@ def test_flags_isolated():
     assert not flags[others].any()
 
 
-@pytest.mark.parametrize("workload,gr", [("uneven2to8", False), ("large8gr", True)])
-def test_full_size_sampled(workload, gr):
+@pytest.mark.parametrize("workload,gr,block_waves", [("uneven2to8", False, 1), ("uneven2to8", False, 4),
+                                                    ("large8gr", True, 1)])
+def test_full_size_sampled(workload, gr, block_waves):
+    """Full-size batches in the launch shapes the benchmark uses (the uneven
+    batch's autotuned pick is this layout with one- or four-wave
+    workgroups); sampled systems checked one by one against the oracle."""
     s = inputs.workload(workload)
     gr_c = inputs.GR_C if gr else 0.0
-    Qg, Vg, _, flags = run(s, 1000, packing="pair", gr_c=gr_c)
+    Qg, Vg, _, flags = run(s, 1000, packing="pair", gr_c=gr_c, block_waves=block_waves, chunk_steps=4096)
     assert not flags.any()
     idx = np.random.default_rng(5).choice(s.S, 24, replace=False)
     sub = s.subset(idx)
