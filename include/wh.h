@@ -191,7 +191,10 @@ int64_t wh_steps_done(const wh_ctx* ctx);
  * The adjoint re-runs each K-step segment from its checkpoint, records the
  * segment's per-step states and converged Kepler anomalies in the tape, and
  * sweeps it backwards with the hand-written transposed Jacobian of every
- * sub-step (the Kepler drift through the implicit function theorem). */
+ * sub-step (the Kepler drift through the implicit function theorem); the
+ * tape holds two segment buffers, so that segment k - 1 is recorded while
+ * segment k is swept.  wh_tape_bytes gives the size: 96 B per lane slot per
+ * checkpoint plus 2 x 80 B per lane slot and step of a segment. */
 size_t wh_tape_bytes(const wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every);
 wh_status wh_forward_ckpt(wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every, void* tape, size_t tape_bytes,
                           hipStream_t stream);

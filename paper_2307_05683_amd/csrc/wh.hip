@@ -825,16 +825,18 @@ __global__ __launch_bounds__(256) void k_to_jacobi(StepParams p) {
 
 // ---------------------------------------------------------------------------
 // Reverse mode (drift-kick-drift).  Checkpoints hold the double-double state
-// [12][ns] (Q, V, then their compensation); the segment tape holds, per step,
+// [12][ns] (Q, V, then their compensation); a segment tape holds, per step,
 // the rounded state entering the step, the step's Kepler anomaly and the
 // velocity after the step's kick, [step][TAPE_ROWS][ns]; the adjoint state is
-// [8][ns]: gQ, gV, gm, and the lane's share of gm0.
+// [8][ns]: gQ, gV, gm, and the lane's share of gm0.  Segments are swept from
+// the last to the first; while segment k is swept, the next launch's input,
+// segment k - 1, is recorded by other wavefronts of the same launch into the
+// second of two segment tapes.
 constexpr int TAPE_ROWS = 10;
 struct AdjParams {
   StepParams sp;
-  const double* ck;    // checkpoint the segment starts from
-  double* ck_out;      // checkpoint to write (forward pass)
-  double* tape;        // segment tape
+  const double* ck;    // k_adj_init: the final checkpoint
+  double* tape;        // tape of the segment being swept
   double* grad;        // adjoint state
   const double* gQ_T;  // caller layout [S*8*3]
   const double* gV_T;
@@ -842,8 +844,13 @@ struct AdjParams {
   double* gV_0;
   double* gm;          // [S*8]
   double* gm0;         // [S]
-  int n_seg;           // steps of the segment
-  int first_synced;    // the segment starts from the synchronized initial state
+  int n_seg;           // steps of the segment being swept
+  int first_synced;    // it starts from the synchronized initial state
+  int sweep_waves;     // wavefronts of the sweeping role (0: the launch only records)
+  const double* ck_rec;  // recording role: checkpoint of the segment to record,
+  double* tape_rec;      // the tape to fill,
+  int n_rec;             // its steps,
+  int rec_first_synced;  // and whether it starts from the synchronized initial state
 };
 
 __device__ __forceinline__ void load_ck(const double* ck, int ns, int slot, Lane& L) {
@@ -890,29 +897,26 @@ __device__ __forceinline__ void jump_vjp(Grad& a, double m, double vx, double vy
   if (leader) a.m0 -= kj / m0 * (sx * Gx + sy * Gy + sz * Gz);
 }
 
-// Forward recompute of a segment from its checkpoint, writing the tape, then
-// the reverse sweep.  Same arithmetic as the step kernel (DPP exchange).
+// Forward recompute of a segment from its checkpoint, writing its tape.  Same
+// arithmetic as the step kernel (DPP exchange).
 template <int G, bool GR>
-__device__ void adj_segment_lane(const AdjParams& q, int slot, int lane) {
+__device__ void adj_record_lane(const AdjParams& q, int slot, int lane) {
   const StepParams& p = q.sp;
   const int ns = p.ns;
   Lane L;
-  load_ck(q.ck, ns, slot, L);
+  load_ck(q.ck_rec, ns, slot, L);
   L.m = p.st[6 * ns + slot];
   L.m0 = p.m0s[slot];
   L.dt = p.dts[slot];
-  L.sys = p.slot_sys[slot];
-  L.pl = p.slot_pl[slot];
-  L.first = q.first_synced;
   Exch<G, 1> ex;
   ex.init(lane, L.m);
   const double dt = L.dt, h = 0.5 * dt;
   const double inv_m0 = 1.0 / L.m0;
   const double kg = GR ? p.kgr * L.m0 * L.m0 : 0.0;
   KepDiag dg{0.0, 1.0e300};
-  double tk = L.first ? h : dt;
-  for (int s = 0; s < q.n_seg; ++s) {
-    double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
+  double tk = q.rec_first_synced ? h : dt;
+  for (int s = 0; s < q.n_rec; ++s) {
+    double* row = q.tape_rec + (size_t)s * TAPE_ROWS * ns + slot;
     row[0] = L.qx; row[ns] = L.qy; row[2 * ns] = L.qz;
     row[3 * ns] = L.vx; row[4 * ns] = L.vy; row[5 * ns] = L.vz;
     row[6 * ns] = drift(L, L.m0, tk, dg);
@@ -921,11 +925,23 @@ __device__ void adj_segment_lane(const AdjParams& q, int slot, int lane) {
     kick_block<G, GR, 1>(L, ex, inv_m0, kg, h, dt, h, vkx, vky, vkz);
     row[7 * ns] = vkx; row[8 * ns] = vky; row[9 * ns] = vkz;   // V after the kick
   }
-  // reverse sweep
+}
+
+// Reverse sweep of a recorded segment: the adjoint state is carried back
+// through the transposed Jacobian of every sub-step.
+template <int G, bool GR>
+__device__ void adj_sweep_lane(const AdjParams& q, int slot, int lane) {
+  const StepParams& p = q.sp;
+  const int ns = p.ns;
+  const double m = p.st[6 * ns + slot], m0 = p.m0s[slot];
+  Exch<G, 1> ex;
+  ex.init(lane, m);
+  const double dt = p.dts[slot], h = 0.5 * dt;
+  const double inv_m0 = 1.0 / m0;
+  const double kg = GR ? p.kgr * m0 * m0 : 0.0;
   Grad a;
   load_grad(q.grad, ns, slot, a);
   const bool leader = (lane & (G - 1)) == 0;
-  const double m = L.m, m0 = L.m0;
   for (int s = q.n_seg - 1; s >= 0; --s) {
     const double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
     double q0x = row[0], q0y = row[ns], q0z = row[2 * ns];
@@ -965,16 +981,27 @@ __device__ void adj_segment_lane(const AdjParams& q, int slot, int lane) {
   store_grad(q.grad, ns, slot, a);
 }
 
+// Waves [0, sweep_waves) sweep one segment, the waves after them record the
+// previous segment; each role covers the packing's waves once.
 template <bool GR> __global__ __launch_bounds__(256) void k_adj_segment(AdjParams q) {
   const StepParams& p = q.sp;
   const int lane = threadIdx.x & 63;
-  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const bool sweep = wave < q.sweep_waves;
+  if (!sweep) wave -= q.sweep_waves;
   if (wave >= p.w8) return;
   const int slot = wave * 64 + lane;
-  if (wave < p.w1) adj_segment_lane<1, GR>(q, slot, lane);
-  else if (wave < p.w2) adj_segment_lane<2, GR>(q, slot, lane);
-  else if (wave < p.w4) adj_segment_lane<4, GR>(q, slot, lane);
-  else adj_segment_lane<8, GR>(q, slot, lane);
+  if (sweep) {
+    if (wave < p.w1) adj_sweep_lane<1, GR>(q, slot, lane);
+    else if (wave < p.w2) adj_sweep_lane<2, GR>(q, slot, lane);
+    else if (wave < p.w4) adj_sweep_lane<4, GR>(q, slot, lane);
+    else adj_sweep_lane<8, GR>(q, slot, lane);
+  } else {
+    if (wave < p.w1) adj_record_lane<1, GR>(q, slot, lane);
+    else if (wave < p.w2) adj_record_lane<2, GR>(q, slot, lane);
+    else if (wave < p.w4) adj_record_lane<4, GR>(q, slot, lane);
+    else adj_record_lane<8, GR>(q, slot, lane);
+  }
 }
 
 // Adjoint of the closing half drift K(h) of the synchronized output (or the
@@ -1582,7 +1609,7 @@ wh_status ensure_graph(wh_ctx* c) {
 struct TapeLayout {
   int64_t n_seg = 0;       // segments
   size_t ck = 0;           // checkpoints: (n_seg + 1) x [12][ns]
-  size_t seg = 0;          // segment tape: ckpt_every x [TAPE_ROWS][ns]
+  size_t seg[2] = {0, 0};  // two segment tapes: ckpt_every x [TAPE_ROWS][ns] each
   size_t grad = 0;         // adjoint state: [8][ns]
   size_t total = 0;
 };
@@ -1592,7 +1619,10 @@ TapeLayout tape_layout(int ns, int64_t n_steps, int64_t every) {
   T.n_seg = (n_steps + every - 1) / every;
   size_t o = 0;
   T.ck = o; o = align256(o + sizeof(double) * 12 * (size_t)ns * (size_t)(T.n_seg + 1));
-  T.seg = o; o = align256(o + sizeof(double) * TAPE_ROWS * (size_t)ns * (size_t)every);
+  for (int b = 0; b < 2; ++b) {
+    T.seg[b] = o;
+    o = align256(o + sizeof(double) * TAPE_ROWS * (size_t)ns * (size_t)every);
+  }
   T.grad = o; o = align256(o + sizeof(double) * 8 * (size_t)ns);
   T.total = o;
   return T;
@@ -1841,26 +1871,56 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
   const int ns = c->P.ns;
   TapeLayout T = tape_layout(ns, c->tape_steps, c->tape_every);
   double* ck = (double*)((char*)tape + T.ck);
+  double* seg[2] = {(double*)((char*)tape + T.seg[0]), (double*)((char*)tape + T.seg[1])};
   AdjParams q;
   q.sp = step_params(c, 0);
-  q.tape = (double*)((char*)tape + T.seg);
+  q.tape = seg[0];
   q.grad = (double*)((char*)tape + T.grad);
   q.gQ_T = gQ_T; q.gV_T = gV_T;
   q.gQ_0 = gQ_0; q.gV_0 = gV_0; q.gm = gm; q.gm0 = gm0;
-  q.ck_out = nullptr;
   q.ck = ck + (size_t)T.n_seg * 12 * ns;
   q.n_seg = 0;
   q.first_synced = 0;
+  q.sweep_waves = 0;
+  q.ck_rec = nullptr;
+  q.tape_rec = seg[1];
+  q.n_rec = 0;
+  q.rec_first_synced = 0;
   hipLaunchKernelGGL(k_adj_init, dim3((ns + 255) / 256), dim3(256), 0, stream, q, (int)(c->tape_steps == 0));
   const bool gr = c->cfg.gr_c > 0;
-  for (int64_t k = T.n_seg - 1; k >= 0; --k) {
-    q.ck = ck + (size_t)k * 12 * ns;
-    q.n_seg = (int)std::min<int64_t>(c->tape_every, c->tape_steps - k * c->tape_every);
-    q.first_synced = (k == 0);
-    if (gr) hipLaunchKernelGGL(k_adj_segment<true>, dim3(c->P.nwaves), dim3(64), 0, stream, q);
-    else hipLaunchKernelGGL(k_adj_segment<false>, dim3(c->P.nwaves), dim3(64), 0, stream, q);
+  const int nw = c->P.nwaves;
+  auto seg_steps = [&](int64_t k) {
+    return (int)std::min<int64_t>(c->tape_every, c->tape_steps - k * c->tape_every);
+  };
+  auto set_record = [&](int64_t k) {   // segment k into tape k mod 2
+    q.ck_rec = ck + (size_t)k * 12 * ns;
+    q.tape_rec = seg[k & 1];
+    q.n_rec = seg_steps(k);
+    q.rec_first_synced = (k == 0);
+  };
+  auto launch = [&](int sweep_waves, int record_waves) {
+    q.sweep_waves = sweep_waves;
+    const dim3 grid(sweep_waves + record_waves), block(64);
+    if (gr) hipLaunchKernelGGL(k_adj_segment<true>, grid, block, 0, stream, q);
+    else hipLaunchKernelGGL(k_adj_segment<false>, grid, block, 0, stream, q);
+  };
+  // record the last segment, then sweep segment k while recording k - 1
+  if (T.n_seg > 0) {
+    set_record(T.n_seg - 1);
+    launch(0, nw);
   }
-  hipLaunchKernelGGL(k_adj_finish, dim3(c->P.nwaves), dim3(64), 0, stream, q);
+  for (int64_t k = T.n_seg - 1; k >= 0; --k) {
+    q.tape = seg[k & 1];
+    q.n_seg = seg_steps(k);
+    q.first_synced = (k == 0);
+    if (k > 0) {
+      set_record(k - 1);
+      launch(nw, nw);
+    } else {
+      launch(nw, 0);
+    }
+  }
+  hipLaunchKernelGGL(k_adj_finish, dim3(nw), dim3(64), 0, stream, q);
   return hip_check(hipGetLastError(), "adjoint launch");
 }
 
