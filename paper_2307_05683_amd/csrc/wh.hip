@@ -2,8 +2,10 @@
 // declared in include/wh.h.
 //
 // Hot path: one persistent kernel advances every system by a chunk of steps
-// with the state held in VGPRs; each lane carries one planet, each aligned
-// group of G lanes one system, each 64-lane wavefront 64/G systems.  The
+// with the state held in VGPRs.  In the default layout each lane carries one
+// planet, each aligned group of G lanes one system, each 64-lane wavefront
+// 64/G systems; two further layouts put two planets on a lane (wh_pair.h) or
+// one planet on two lanes (wh_split.h).  The
 // step is the drift-kick-drift composition of the WHFast512 paper (Sec. 3.1)
 // with the drifts of consecutive steps merged and, without GR, the two half
 // jumps merged (they commute with the interaction kick then).  Output reads
@@ -1951,9 +1953,10 @@ const char* wh_last_error(void) { return g_err.c_str(); }
 
 void wh_destroy(wh_ctx* c) {
   if (!c) return;
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
-  if (c->graph) hipGraphDestroy(c->graph);
-  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  // teardown: nothing useful can be done with a failure here
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 
