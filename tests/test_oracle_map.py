@@ -86,6 +86,34 @@ def test_time_reversible(scheme, gr_c):
     assert dq < 1e-15 * np.abs(s.Q).max() and dv < 1e-15 * np.abs(s.V).max()
 
 
+@pytest.mark.parametrize("gr_c", [0.0, 30.0])
+def test_kdk_is_dkd_conjugated_by_a_half_step(gr_c):
+    """With U = I(h), J(h), K(h) (in the order they act; I includes GR), one
+    drift-kick-drift step is U^R U and one kick-drift-kick step U U^R (U^R the
+    same operators in reverse order), so n kick-drift-kick steps followed by
+    U equal U followed by n drift-kick-drift steps.  With GR the jump and the
+    kick do not commute, so a kick-drift-kick step that ordered them
+    differently would fail this."""
+    s = inputs.make_systems(5, 29, n_planets=None, n_range=(2, 8))
+    h = 0.5 * s.dt
+
+    def U(Q, V):
+        Q, V = oracle.substep("interaction", s, h, Q=Q, V=V)
+        if gr_c > 0:
+            Q, V = oracle.substep("gr", s, h, gr_c=gr_c, Q=Q, V=V)
+        Q, V = oracle.substep("jump", s, h, Q=Q, V=V)
+        return oracle.substep("kepler", s, h, Q=Q, V=V)
+
+    Qa, Va = oracle.integrate(s, 200, scheme="kdk", gr_c=gr_c)
+    Qa, Va = U(Qa, Va)
+    Qb, Vb = U(s.Q, s.V)
+    Qb, Vb = oracle.integrate(s, 200, scheme="dkd", gr_c=gr_c, Q=Qb, V=Vb)
+    lm = (np.arange(8)[None, :] < s.n_planets[:, None])
+    dq = np.abs((Qa - Qb).astype(float))[lm].max()
+    dv = np.abs((Va - Vb).astype(float))[lm].max()
+    assert dq < 1e-15 * np.abs(s.Q).max() and dv < 1e-15 * np.abs(s.V).max(), (dq, dv)
+
+
 @pytest.mark.parametrize("scheme,gr_c", [("dkd", 0.0), ("kdk", 30.0)])
 def test_symplectic(scheme, gr_c):
     """M^T Omega M = Omega for the Jacobian in canonical (Q, P = m V)."""
