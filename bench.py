@@ -345,6 +345,27 @@ def main():
         out["plain_per_size"] = {"value": systems.S * args.plain_steps / ps, "steps": args.plain_steps,
                                  "speedup_fused_over_plain": value / (systems.S * args.plain_steps / ps)}
         plain.close()
+        # the stronger variant: one persistent context per planet count (the
+        # same 8-lane groups, each size's steps in chunked launches), run one
+        # after the other -- separates the gain of packing from that of
+        # persistence
+        subs = [Ensemble.from_systems(systems.subset(np.flatnonzero(systems.n_planets == n)), gr_c=gr_c,
+                                      scheme=scheme, packing="g8", coords=args.coords, device=dev)
+                for n in range(1, 9) if (systems.n_planets == n).any()]
+        n_sub = 8 * args.plain_steps
+        for sub in subs:
+            sub.step(64)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for sub in subs:
+            sub.step(n_sub)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ts = ev0.elapsed_time(ev1) / 1e3
+        out["per_size_persistent"] = {"value": systems.S * n_sub / ts, "steps": n_sub,
+                                      "speedup_fused_over_it": value / (systems.S * n_sub / ts)}
+        for sub in subs:
+            sub.close()
     ens.close()
     if not args.no_cpu:
         print("[bench] CPU baseline (oracle) ...", file=sys.stderr, flush=True)
