@@ -88,7 +88,7 @@ enum {
                         4 per 5-8); DHC with WH_DKD or WH_KDK only, no reverse mode */
   WH_PACK_SPLIT = 3  /* two lanes per planet: a 16-lane group per system whatever N, the interaction kick
                         divided between the two copies of each planet (for ensembles with fewer
-                        wavefronts than the GPU has SIMDs); DHC with WH_DKD or WH_KDK only, no reverse mode */
+                        wavefronts than the GPU has SIMDs); DHC with WH_DKD or WH_KDK only */
 };
 
 /* Partner exchange of the interaction kick inside a lane group. */
@@ -194,7 +194,9 @@ int64_t wh_steps_done(const wh_ctx* ctx);
  * sub-step (the Kepler drift through the implicit function theorem); the
  * tape holds two segment buffers, so that segment k - 1 is recorded while
  * segment k is swept.  wh_tape_bytes gives the size: 96 B per lane slot per
- * checkpoint plus 2 x 80 B per lane slot and step of a segment. */
+ * checkpoint plus 2 x 80 B per lane slot and step of a segment.  Contexts in
+ * DHC with WH_DKD and the WH_PACK_POW2, WH_PACK_G8 or WH_PACK_SPLIT packing;
+ * other contexts get WH_ESTATE. */
 size_t wh_tape_bytes(const wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every);
 wh_status wh_forward_ckpt(wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every, void* tape, size_t tape_bytes,
                           hipStream_t stream);

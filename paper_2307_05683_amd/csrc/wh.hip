@@ -899,6 +899,15 @@ __device__ __forceinline__ void jump_vjp(Grad& a, double m, double vx, double vy
   if (leader) a.m0 -= kj / m0 * (sx * Gx + sy * Gy + sz * Gz);
 }
 
+// Adjoint of the interaction kick with the exchange the forward kick used.
+template <int G>
+__device__ __forceinline__ void interaction_vjp(const Exch<G, 1>& ex, double qx, double qy, double qz, double m,
+                                                double tau, double gvx, double gvy, double gvz, double& gqx,
+                                                double& gqy, double& gqz, double& gm) {
+  if constexpr (G == G_SPLIT) interaction_vjp_split(ex.t, qx, qy, qz, m, tau, gvx, gvy, gvz, gqx, gqy, gqz, gm);
+  else interaction_vjp_dpp<G>(ex.t, qx, qy, qz, m, tau, gvx, gvy, gvz, gqx, gqy, gqz, gm);
+}
+
 // Forward recompute of a segment from its checkpoint, writing its tape.  Same
 // arithmetic as the step kernel (DPP exchange).
 template <int G, bool GR>
@@ -943,7 +952,9 @@ __device__ void adj_sweep_lane(const AdjParams& q, int slot, int lane) {
   const double kg = GR ? p.kgr * m0 * m0 : 0.0;
   Grad a;
   load_grad(q.grad, ns, slot, a);
-  const bool leader = (lane & (G - 1)) == 0;
+  // the lane(s) of planet 0 add the star-mass terms of the jump (in the
+  // split layout both copies, so that the copies keep equal bits)
+  const bool leader = G == G_SPLIT ? (lane & 14) == 0 : (lane & (G - 1)) == 0;
   for (int s = q.n_seg - 1; s >= 0; --s) {
     const double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
     double q0x = row[0], q0y = row[ns], q0z = row[2 * ns];
@@ -965,7 +976,7 @@ __device__ void adj_sweep_lane(const AdjParams& q, int slot, int lane) {
       group_momentum<G>(m, v3x, v3y, v3z, s3x, s3y, s3z);
       jump_vjp<G>(a, m, v3x, v3y, v3z, kj, m0, s3x, s3y, s3z, leader);
       double gmu = 0.0;
-      interaction_vjp_dpp<G>(ex.t, q2x, q2y, q2z, m, dt, a.vx, a.vy, a.vz, a.qx, a.qy, a.qz, a.m);
+      interaction_vjp<G>(ex, q2x, q2y, q2z, m, dt, a.vx, a.vy, a.vz, a.qx, a.qy, a.qz, a.m);
       gr_vjp(q2x, q2y, q2z, kg, m0, dt, a.vx, a.vy, a.vz, a.qx, a.qy, a.qz, gmu);
       a.m0 += gmu;
       jump_vjp<G>(a, m, v1x, v1y, v1z, kj, m0, s1x, s1y, s1z, leader);
@@ -974,7 +985,7 @@ __device__ void adj_sweep_lane(const AdjParams& q, int slot, int lane) {
       double s2x, s2y, s2z;
       group_momentum<G>(m, v2x, v2y, v2z, s2x, s2y, s2z);
       jump_vjp<G>(a, m, v2x, v2y, v2z, dt * inv_m0, m0, s2x, s2y, s2z, leader);
-      interaction_vjp_dpp<G>(ex.t, q1x, q1y, q1z, m, dt, a.vx, a.vy, a.vz, a.qx, a.qy, a.qz, a.m);
+      interaction_vjp<G>(ex, q1x, q1y, q1z, m, dt, a.vx, a.vy, a.vz, a.qx, a.qy, a.qz, a.m);
     }
     double gmu = 0.0;
     kepler_vjp(k, q0x, q0y, q0z, v0x, v0y, v0z, m0, a.qx, a.qy, a.qz, a.vx, a.vy, a.vz, gmu);
@@ -985,7 +996,7 @@ __device__ void adj_sweep_lane(const AdjParams& q, int slot, int lane) {
 
 // Waves [0, sweep_waves) sweep one segment, the waves after them record the
 // previous segment; each role covers the packing's waves once.
-template <bool GR> __global__ __launch_bounds__(256) void k_adj_segment(AdjParams q) {
+template <bool GR, bool SPLIT> __global__ __launch_bounds__(256) void k_adj_segment(AdjParams q) {
   const StepParams& p = q.sp;
   const int lane = threadIdx.x & 63;
   int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -993,7 +1004,10 @@ template <bool GR> __global__ __launch_bounds__(256) void k_adj_segment(AdjParam
   if (!sweep) wave -= q.sweep_waves;
   if (wave >= p.w8) return;
   const int slot = wave * 64 + lane;
-  if (sweep) {
+  if (SPLIT) {
+    if (sweep) adj_sweep_lane<G_SPLIT, GR>(q, slot, lane);
+    else adj_record_lane<G_SPLIT, GR>(q, slot, lane);
+  } else if (sweep) {
     if (wave < p.w1) adj_sweep_lane<1, GR>(q, slot, lane);
     else if (wave < p.w2) adj_sweep_lane<2, GR>(q, slot, lane);
     else if (wave < p.w4) adj_sweep_lane<4, GR>(q, slot, lane);
@@ -1042,7 +1056,7 @@ template <int G> __device__ void adj_finish_lane(const AdjParams& q, int slot, i
   load_grad(q.grad, p.ns, slot, a);
   double g0 = group_sum<G>(a.m0);
   int sys = p.slot_sys[slot], pl = p.slot_pl[slot];
-  if (sys >= 0 && pl >= 0) {
+  if (sys >= 0 && pl >= 0 && (G != G_SPLIT || (lane & 1) == 0)) {
     size_t o = ((size_t)sys * 8 + pl) * 3;
     q.gQ_0[o] = a.qx; q.gQ_0[o + 1] = a.qy; q.gQ_0[o + 2] = a.qz;
     q.gV_0[o] = a.vx; q.gV_0[o + 1] = a.vy; q.gV_0[o + 2] = a.vz;
@@ -1051,13 +1065,14 @@ template <int G> __device__ void adj_finish_lane(const AdjParams& q, int slot, i
   if ((lane & (G - 1)) == 0 && sys >= 0) q.gm0[sys] = g0;
 }
 
-__global__ __launch_bounds__(256) void k_adj_finish(AdjParams q) {
+template <bool SPLIT> __global__ __launch_bounds__(256) void k_adj_finish(AdjParams q) {
   const StepParams& p = q.sp;
   const int lane = threadIdx.x & 63;
   const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (wave >= p.w8) return;
   const int slot = wave * 64 + lane;
-  if (wave < p.w1) adj_finish_lane<1>(q, slot, lane);
+  if (SPLIT) adj_finish_lane<G_SPLIT>(q, slot, lane);
+  else if (wave < p.w1) adj_finish_lane<1>(q, slot, lane);
   else if (wave < p.w2) adj_finish_lane<2>(q, slot, lane);
   else if (wave < p.w4) adj_finish_lane<4>(q, slot, lane);
   else adj_finish_lane<8>(q, slot, lane);
@@ -1833,8 +1848,7 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
   if (c->cfg.scheme != WH_DKD) return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD");
   if (c->cfg.coords != WH_COORDS_DHC)
     return fail(WH_ESTATE, "reverse mode is implemented in democratic heliocentric coordinates");
-  if (c->P.pair || c->P.split)
-    return fail(WH_ESTATE, "reverse mode is implemented for the one-planet-per-lane packings");
+  if (c->P.pair) return fail(WH_ESTATE, "reverse mode is not implemented for the two-planets-per-lane packing");
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
   TapeLayout T = tape_layout(c->P.ns, n_steps, ckpt_every);
   if (tape_bytes < T.total) return fail(WH_EWORKSPACE, "tape too small: need " + std::to_string(T.total) + " bytes");
@@ -1903,8 +1917,13 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
   auto launch = [&](int sweep_waves, int record_waves) {
     q.sweep_waves = sweep_waves;
     const dim3 grid(sweep_waves + record_waves), block(64);
-    if (gr) hipLaunchKernelGGL(k_adj_segment<true>, grid, block, 0, stream, q);
-    else hipLaunchKernelGGL(k_adj_segment<false>, grid, block, 0, stream, q);
+    if (c->P.split) {
+      if (gr) hipLaunchKernelGGL((k_adj_segment<true, true>), grid, block, 0, stream, q);
+      else hipLaunchKernelGGL((k_adj_segment<false, true>), grid, block, 0, stream, q);
+    } else {
+      if (gr) hipLaunchKernelGGL((k_adj_segment<true, false>), grid, block, 0, stream, q);
+      else hipLaunchKernelGGL((k_adj_segment<false, false>), grid, block, 0, stream, q);
+    }
   };
   // record the last segment, then sweep segment k while recording k - 1
   if (T.n_seg > 0) {
@@ -1922,7 +1941,8 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
       launch(nw, 0);
     }
   }
-  hipLaunchKernelGGL(k_adj_finish, dim3(nw), dim3(64), 0, stream, q);
+  if (c->P.split) hipLaunchKernelGGL(k_adj_finish<true>, dim3(nw), dim3(64), 0, stream, q);
+  else hipLaunchKernelGGL(k_adj_finish<false>, dim3(nw), dim3(64), 0, stream, q);
   return hip_check(hipGetLastError(), "adjoint launch");
 }
 

@@ -21,6 +21,7 @@
 // cover the 28 pairs of an 8-planet system; the copies then add their shares
 // (a0 + a1 and a1 + a0 are the same bits, so the copies stay identical).
 #pragma once
+#include "wh_adjoint.h"
 #include "wh_device.h"
 
 namespace wh {
@@ -28,6 +29,7 @@ namespace wh {
 struct SplitMass {
   double m1, m2;   // partner mass of rounds 1 and 2 (constant, Sec. 3.5)
   double w2;       // own mass for the round-2 reaction
+  double on2;      // 1, or 0 where round 2 repeats a pair
 };
 
 __device__ __forceinline__ SplitMass make_split_mass(int lane, double m) {
@@ -38,6 +40,7 @@ __device__ __forceinline__ SplitMass make_split_mass(int lane, double m) {
   const double m2 = dpp<DPP_ROR9>(m);
   t.m2 = dup ? 0.0 : m2;
   t.w2 = dup ? 0.0 : m;
+  t.on2 = dup ? 0.0 : 1.0;
   return t;
 }
 
@@ -62,6 +65,33 @@ __device__ __forceinline__ void accel_split(const SplitMass& t, double qx, doubl
   ax += dpp<DPP_XOR1>(ax);
   ay += dpp<DPP_XOR1>(ay);
   az += dpp<DPP_XOR1>(az);
+}
+
+// Adjoint of the split interaction kick V += tau a(Q) (pair_vjp per
+// evaluated pair, over the same two rounds): each lane accumulates its own
+// share and the share the inverse rotation returns for its planet, then the
+// copies add their shares as in the forward kick, so both keep the same bits.
+__device__ __forceinline__ void interaction_vjp_split(const SplitMass& t, double qx, double qy, double qz, double m,
+                                                      double tau, double gvx, double gvy, double gvz, double& gqx,
+                                                      double& gqy, double& gqz, double& gm) {
+  double cx, cy, cz, co, cp;
+  double sx, sy, sz, sm;
+  pair_vjp(qx, qy, qz, gvx, gvy, gvz, m, dpp<DPP_ROR13>(qx), dpp<DPP_ROR13>(qy), dpp<DPP_ROR13>(qz),
+           dpp<DPP_ROR13>(gvx), dpp<DPP_ROR13>(gvy), dpp<DPP_ROR13>(gvz), t.m1, tau, cx, cy, cz, co, cp);
+  sx = cx - dpp<DPP_ROR3>(cx);
+  sy = cy - dpp<DPP_ROR3>(cy);
+  sz = cz - dpp<DPP_ROR3>(cz);
+  sm = co + dpp<DPP_ROR3>(cp);
+  pair_vjp(qx, qy, qz, gvx, gvy, gvz, m, dpp<DPP_ROR9>(qx), dpp<DPP_ROR9>(qy), dpp<DPP_ROR9>(qz),
+           dpp<DPP_ROR9>(gvx), dpp<DPP_ROR9>(gvy), dpp<DPP_ROR9>(gvz), t.m2, tau * t.on2, cx, cy, cz, co, cp);
+  sx += cx - dpp<DPP_ROR7>(cx);
+  sy += cy - dpp<DPP_ROR7>(cy);
+  sz += cz - dpp<DPP_ROR7>(cz);
+  sm += co + dpp<DPP_ROR7>(cp);
+  gqx += sx + dpp<DPP_XOR1>(sx);
+  gqy += sy + dpp<DPP_XOR1>(sy);
+  gqz += sz + dpp<DPP_XOR1>(sz);
+  gm += sm + dpp<DPP_XOR1>(sm);
 }
 
 }  // namespace wh

@@ -23,8 +23,8 @@ def live(s):
     return np.arange(8)[None, :] < s.n_planets[:, None]
 
 
-def adjoint_run(s, n_steps, every, gQ_T, gV_T, gr_c=0.0):
-    e = Ensemble.from_systems(s, gr_c=gr_c)
+def adjoint_run(s, n_steps, every, gQ_T, gV_T, gr_c=0.0, packing="auto"):
+    e = Ensemble.from_systems(s, gr_c=gr_c, packing=packing)
     e.forward_ckpt(n_steps, every)
     QT, VT = e.state()
     g = e.adjoint(gQ_T, gV_T)
@@ -43,16 +43,19 @@ def random_dirs(s, seed):
     return dQ, dV, dm, dm0
 
 
-@pytest.mark.parametrize("n_steps,every,gr_c", [(200, 64, 0.0), (200, 64, 40.0), (150, 1000, 0.0), (64, 64, 0.0),
-                                                 (1, 1, 0.0), (97, 10, 10065.0)])
-def test_dot_product_vs_oracle_tangent(n_steps, every, gr_c):
+@pytest.mark.parametrize("n_steps,every,gr_c,packing", [(200, 64, 0.0, "auto"), (200, 64, 40.0, "auto"),
+                                                         (150, 1000, 0.0, "auto"), (64, 64, 0.0, "auto"),
+                                                         (1, 1, 0.0, "auto"), (97, 10, 10065.0, "auto"),
+                                                         (200, 64, 0.0, "split"), (200, 64, 40.0, "split"),
+                                                         (1, 1, 0.0, "split"), (97, 10, 10065.0, "split")])
+def test_dot_product_vs_oracle_tangent(n_steps, every, gr_c, packing):
     s = inputs.make_systems(16, 31, n_planets=None, n_range=(1, 8))
-    print("case: n_steps=%d every=%d gr_c=%g" % (n_steps, every, gr_c), flush=True)
+    print("case: n_steps=%d every=%d gr_c=%g packing=%s" % (n_steps, every, gr_c, packing), flush=True)
     rng = np.random.default_rng(5)
     lm = live(s)
     gQ_T = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None]
     gV_T = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None]
-    QT, VT, gQ0, gV0, gm, gm0 = adjoint_run(s, n_steps, every, gQ_T, gV_T, gr_c)
+    QT, VT, gQ0, gV0, gm, gm0 = adjoint_run(s, n_steps, every, gQ_T, gV_T, gr_c, packing)
     dQ, dV, dm, dm0 = random_dirs(s, 6)
     _, _, tQ, tV = oracle.tangent(s, n_steps, dQ, dV, dm, dm0, gr_c=gr_c)
     lhs = (gQ0 * dQ).sum((1, 2)) + (gV0 * dV).sum((1, 2)) + (gm * dm).sum(1) + gm0 * dm0
@@ -63,9 +66,10 @@ def test_dot_product_vs_oracle_tangent(n_steps, every, gr_c):
     assert rel.max() < 1e-9
 
 
+@pytest.mark.parametrize("packing", ["auto", "split"])
 @pytest.mark.parametrize("which", ["m", "m0"])
 @pytest.mark.parametrize("gr_c", [0.0, 40.0])
-def test_mass_gradients_vs_oracle_tangent(which, gr_c):
+def test_mass_gradients_vs_oracle_tangent(which, gr_c, packing):
     """Dot-product identity along mass directions only (the mass part of the
     gradient would be masked by the state part in a mixed direction)."""
     s = inputs.make_systems(16, 36, n_planets=None, n_range=(1, 8))
@@ -73,7 +77,7 @@ def test_mass_gradients_vs_oracle_tangent(which, gr_c):
     lm = live(s)
     gQ_T = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None]
     gV_T = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None]
-    _, _, gQ0, gV0, gm, gm0 = adjoint_run(s, 300, 64, gQ_T, gV_T, gr_c)
+    _, _, gQ0, gV0, gm, gm0 = adjoint_run(s, 300, 64, gQ_T, gV_T, gr_c, packing)
     z3 = np.zeros((s.S, 8, 3))
     dm = rng.normal(size=(s.S, 8)) * lm * s.m if which == "m" else np.zeros((s.S, 8))
     dm0 = rng.normal(size=s.S) * 0.01 if which == "m0" else np.zeros(s.S)
@@ -86,18 +90,20 @@ def test_mass_gradients_vs_oracle_tangent(which, gr_c):
     assert rel.max() < 1e-9
 
 
-def test_zero_steps_is_identity():
+@pytest.mark.parametrize("packing", ["auto", "split"])
+def test_zero_steps_is_identity(packing):
     s = inputs.make_systems(5, 32, n_planets=None, n_range=(1, 8))
     rng = np.random.default_rng(1)
     gQ_T = rng.normal(size=(s.S, 8, 3)) * live(s)[:, :, None]
     gV_T = rng.normal(size=(s.S, 8, 3)) * live(s)[:, :, None]
-    _, _, gQ0, gV0, gm, gm0 = adjoint_run(s, 0, 10, gQ_T, gV_T)
+    _, _, gQ0, gV0, gm, gm0 = adjoint_run(s, 0, 10, gQ_T, gV_T, packing=packing)
     assert np.array_equal(gQ0, gQ_T) and np.array_equal(gV0, gV_T)
     assert not gm.any() and not gm0.any()
 
 
+@pytest.mark.parametrize("packing", ["auto", "split"])
 @pytest.mark.parametrize("gr_c", [0.0, 10065.0])
-def test_checkpoint_interval_leaves_gradients_bitwise_equal(gr_c):
+def test_checkpoint_interval_leaves_gradients_bitwise_equal(gr_c, packing):
     """Restarting from a checkpoint reproduces the forward run bitwise, so the
     gradients may not depend on the interval (one segment, several with a
     partial last one, one step each) nor on how the recording of one
@@ -106,9 +112,9 @@ def test_checkpoint_interval_leaves_gradients_bitwise_equal(gr_c):
     rng = np.random.default_rng(2)
     gQ_T = rng.normal(size=(s.S, 8, 3)) * live(s)[:, :, None]
     gV_T = rng.normal(size=(s.S, 8, 3)) * live(s)[:, :, None]
-    ref = adjoint_run(s, 300, 300, gQ_T, gV_T, gr_c=gr_c)
+    ref = adjoint_run(s, 300, 300, gQ_T, gV_T, gr_c=gr_c, packing=packing)
     for every in (1, 7, 64, 1000):
-        out = adjoint_run(s, 300, every, gQ_T, gV_T, gr_c=gr_c)
+        out = adjoint_run(s, 300, every, gQ_T, gV_T, gr_c=gr_c, packing=packing)
         for a, b in zip(out, ref):
             assert np.array_equal(a, b), every
 
@@ -117,12 +123,13 @@ def loss_np(Q, s):
     return (Q ** 2 * live(s)[:, :, None]).sum((1, 2))
 
 
-def test_gradients_match_central_differences():
+@pytest.mark.parametrize("packing", ["auto", "split"])
+def test_gradients_match_central_differences(packing):
     """Loss L = sum_i |Q_i(T)|^2 per system; perturb one input coordinate in
     every system at once (systems are independent) with h = 1e-7 relative."""
     s = inputs.make_systems(32, 33, n_planets=8)
     n_steps, every = 400, 100
-    e = Ensemble.from_systems(s)
+    e = Ensemble.from_systems(s, packing=packing)
     e.forward_ckpt(n_steps, every)
     QT, VT = e.state()
     gQ0, gV0, gm, gm0 = [x.cpu().numpy() for x in e.adjoint(2 * QT, torch.zeros_like(VT))]
@@ -131,7 +138,7 @@ def test_gradients_match_central_differences():
     def run(mod):
         t = s.copy()
         mod(t)
-        f = Ensemble.from_systems(t)
+        f = Ensemble.from_systems(t, packing=packing)
         f.step(n_steps)
         Q, _ = f.state()
         f.close()
@@ -197,13 +204,15 @@ def test_tape_validation():
         e.adjoint(np.zeros((4, 8, 3)), np.zeros((4, 8, 3)))
     assert ei.value.code == _lib.WH_ESTATE
     e.close()
-    k = Ensemble.from_systems(s, scheme="kdk")
-    with pytest.raises(_lib.WHError):
-        k.forward_ckpt(10, 5)
-    k.close()
+    for kw in (dict(scheme="kdk"), dict(packing="pair"), dict(coords="jacobi")):
+        k = Ensemble.from_systems(s, **kw)
+        with pytest.raises(_lib.WHError):
+            k.forward_ckpt(10, 5)
+        k.close()
 
 
-def test_adjoint_workload_sampled():
+@pytest.mark.parametrize("packing", ["auto", "split"])
+def test_adjoint_workload_sampled(packing):
     """The adjoint workload shape (1024 eight-planet systems, checkpoints
     every 1000 steps), shortened to 3000 steps: sampled systems pass the
     dot-product test against the oracle tangent."""
@@ -212,7 +221,7 @@ def test_adjoint_workload_sampled():
     rng = np.random.default_rng(9)
     gQ_T = rng.normal(size=(s.S, 8, 3))
     gV_T = rng.normal(size=(s.S, 8, 3))
-    _, _, gQ0, gV0, gm, gm0 = adjoint_run(s, n_steps, every, gQ_T, gV_T)
+    _, _, gQ0, gV0, gm, gm0 = adjoint_run(s, n_steps, every, gQ_T, gV_T, packing=packing)
     idx = np.random.default_rng(2).choice(s.S, 6, replace=False)
     sub = s.subset(idx)
     dQ, dV, dm, dm0 = random_dirs(sub, 7)
