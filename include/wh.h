@@ -85,7 +85,7 @@ enum {
   WH_PACK_POW2 = 0,  /* one group of 1/2/4/8 lanes per system (next power of 2 >= N) */
   WH_PACK_G8 = 1,    /* one 8-lane group per system whatever N */
   WH_PACK_PAIR = 2,  /* two planets per lane: a group of 1/2/4 lanes per system (2 lanes per 3-4 planets,
-                        4 per 5-8); DHC with WH_DKD or WH_KDK only, no reverse mode */
+                        4 per 5-8); DHC with WH_DKD or WH_KDK only */
   WH_PACK_SPLIT = 3  /* two lanes per planet: a 16-lane group per system whatever N, the interaction kick
                         divided between the two copies of each planet (for ensembles with fewer
                         wavefronts than the GPU has SIMDs); DHC with WH_DKD or WH_KDK only */
@@ -195,8 +195,7 @@ int64_t wh_steps_done(const wh_ctx* ctx);
  * tape holds two segment buffers, so that segment k - 1 is recorded while
  * segment k is swept.  wh_tape_bytes gives the size: 96 B per lane slot per
  * checkpoint plus 2 x 80 B per lane slot and step of a segment.  Contexts in
- * DHC with WH_DKD and the WH_PACK_POW2, WH_PACK_G8 or WH_PACK_SPLIT packing;
- * other contexts get WH_ESTATE. */
+ * DHC with WH_DKD (any packing); other contexts get WH_ESTATE. */
 size_t wh_tape_bytes(const wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every);
 wh_status wh_forward_ckpt(wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every, void* tape, size_t tape_bytes,
                           hipStream_t stream);

@@ -471,9 +471,10 @@ __global__ __launch_bounds__(256) void k_step(StepParams p) {
 // ("b").  The step is the one-planet step applied to both slots, with the
 // interaction and momentum sums of the pair layout.
 
+// (vka, vkb) receive the velocities after the kick (kept by the adjoint).
 template <int G, bool GR>
 __device__ __forceinline__ void kick_block_pair(Lane& A, Lane& B, const PairMass& pm, double inv_m0, double kg,
-                                                double ta, double ti, double tc) {
+                                                double ta, double ti, double tc, double vka[3], double vkb[3]) {
   double sx, sy, sz;
   double qax = A.qx, qay = A.qy, qaz = A.qz, qbx = B.qx, qby = B.qy, qbz = B.qz;
   if (GR) {
@@ -498,8 +499,9 @@ __device__ __forceinline__ void kick_block_pair(Lane& A, Lane& B, const PairMass
   const double dvbx = ti * abx, dvby = ti * aby, dvbz = ti * abz;
   A.cvx += dvax; A.cvy += dvay; A.cvz += dvaz;
   B.cvx += dvbx; B.cvy += dvby; B.cvz += dvbz;
-  pair_momentum<G>(A.m, A.vx + dvax, A.vy + dvay, A.vz + dvaz, B.m, B.vx + dvbx, B.vy + dvby, B.vz + dvbz, sx, sy,
-                   sz);
+  vka[0] = A.vx + dvax; vka[1] = A.vy + dvay; vka[2] = A.vz + dvaz;
+  vkb[0] = B.vx + dvbx; vkb[1] = B.vy + dvby; vkb[2] = B.vz + dvbz;
+  pair_momentum<G>(A.m, vka[0], vka[1], vka[2], B.m, vkb[0], vkb[1], vkb[2], sx, sy, sz);
   const double k2 = (GR ? tc : ta + tc) * inv_m0;
   A.cqx += k2 * sx; A.cqy += k2 * sy; A.cqz += k2 * sz;
   B.cqx += k2 * sx; B.cqy += k2 * sy; B.cqz += k2 * sz;
@@ -527,19 +529,20 @@ __device__ __forceinline__ void step_lane_pair(const StepParams& p, Lane& A, Lan
   const double inv_m0 = 1.0 / A.m0;
   const double kg = GR ? p.kgr * A.m0 * A.m0 : 0.0;
   KepDiag dga{0.0, 1.0e300}, dgb{0.0, 1.0e300};
+  double vka[3], vkb[3];
   if (SCHEME == WH_DKD) {
     double tk = A.first ? h : dt;
     for (int s = 0; s < p.n_steps; ++s) {
       drift(A, A.m0, tk, dga);
       drift(B, B.m0, tk, dgb);
       tk = dt;
-      kick_block_pair<G, GR>(A, B, pm, inv_m0, kg, h, dt, h);
+      kick_block_pair<G, GR>(A, B, pm, inv_m0, kg, h, dt, h, vka, vkb);
     }
   } else {
     double ta = A.first ? 0.0 : h;
     double ti = A.first ? h : dt;
     for (int s = 0; s < p.n_steps; ++s) {
-      kick_block_pair<G, GR>(A, B, pm, inv_m0, kg, ta, ti, h);
+      kick_block_pair<G, GR>(A, B, pm, inv_m0, kg, ta, ti, h, vka, vkb);
       ta = h;
       ti = dt;
       drift(A, A.m0, dt, dga);
@@ -774,7 +777,8 @@ template <int G, bool GR, int SCHEME> __device__ void sync_group_pair(const Sync
       drift(B, B.m0, h, dg);
     } else {
       const PairMass pm = make_pair_mass<G>(A.m, B.m);
-      kick_block_pair<G, GR>(A, B, pm, 1.0 / A.m0, GR ? p.kgr * A.m0 * A.m0 : 0.0, h, h, 0.0);
+      double vka[3], vkb[3];
+      kick_block_pair<G, GR>(A, B, pm, 1.0 / A.m0, GR ? p.kgr * A.m0 * A.m0 : 0.0, h, h, 0.0, vka, vkb);
     }
   }
   A.qx += A.cqx; A.qy += A.cqy; A.qz += A.cqz; A.vx += A.cvx; A.vy += A.cvy; A.vz += A.cvz;
@@ -899,6 +903,20 @@ __device__ __forceinline__ void jump_vjp(Grad& a, double m, double vx, double vy
   if (leader) a.m0 -= kj / m0 * (sx * Gx + sy * Gy + sz * Gz);
 }
 
+// The jump adjoint in the pair layout: the sums run over both slots of the
+// group's lanes.
+template <int G>
+__device__ __forceinline__ void jump_vjp_pair(Grad& a, Grad& b, double ma, double mb, const double va[3],
+                                              const double vb[3], double kj, double m0, const double sm[3],
+                                              bool leader) {
+  const double Gx = group_sum<G>(a.qx + b.qx), Gy = group_sum<G>(a.qy + b.qy), Gz = group_sum<G>(a.qz + b.qz);
+  a.vx = fma(kj * ma, Gx, a.vx); a.vy = fma(kj * ma, Gy, a.vy); a.vz = fma(kj * ma, Gz, a.vz);
+  b.vx = fma(kj * mb, Gx, b.vx); b.vy = fma(kj * mb, Gy, b.vy); b.vz = fma(kj * mb, Gz, b.vz);
+  a.m += kj * (va[0] * Gx + va[1] * Gy + va[2] * Gz);
+  b.m += kj * (vb[0] * Gx + vb[1] * Gy + vb[2] * Gz);
+  if (leader) a.m0 -= kj / m0 * (sm[0] * Gx + sm[1] * Gy + sm[2] * Gz);
+}
+
 // Adjoint of the interaction kick with the exchange the forward kick used.
 template <int G>
 __device__ __forceinline__ void interaction_vjp(const Exch<G, 1>& ex, double qx, double qy, double qz, double m,
@@ -994,6 +1012,124 @@ __device__ void adj_sweep_lane(const AdjParams& q, int slot, int lane) {
   store_grad(q.grad, ns, slot, a);
 }
 
+// The same two roles in the pair layout: lane l of wave w holds slots
+// 128 w + l (a) and 128 w + 64 + l (b).
+template <int G, bool GR>
+__device__ void adj_record_pair(const AdjParams& q, int sa, int lane) {
+  const StepParams& p = q.sp;
+  const int ns = p.ns, sb = sa + 64;
+  Lane A, B;
+  load_ck(q.ck_rec, ns, sa, A);
+  load_ck(q.ck_rec, ns, sb, B);
+  A.m = p.st[6 * ns + sa]; B.m = p.st[6 * ns + sb];
+  A.m0 = p.m0s[sa]; B.m0 = p.m0s[sb];
+  const PairMass pm = make_pair_mass<G>(A.m, B.m);
+  const double dt = p.dts[sa], h = 0.5 * dt;
+  const double inv_m0 = 1.0 / A.m0;
+  const double kg = GR ? p.kgr * A.m0 * A.m0 : 0.0;
+  KepDiag dga{0.0, 1.0e300}, dgb{0.0, 1.0e300};
+  double tk = q.rec_first_synced ? h : dt;
+  for (int s = 0; s < q.n_rec; ++s) {
+    double* ra = q.tape_rec + (size_t)s * TAPE_ROWS * ns + sa;
+    double* rb = ra + 64;
+    ra[0] = A.qx; ra[ns] = A.qy; ra[2 * ns] = A.qz; ra[3 * ns] = A.vx; ra[4 * ns] = A.vy; ra[5 * ns] = A.vz;
+    rb[0] = B.qx; rb[ns] = B.qy; rb[2 * ns] = B.qz; rb[3 * ns] = B.vx; rb[4 * ns] = B.vy; rb[5 * ns] = B.vz;
+    ra[6 * ns] = drift(A, A.m0, tk, dga);
+    rb[6 * ns] = drift(B, B.m0, tk, dgb);
+    tk = dt;
+    double vka[3], vkb[3];
+    kick_block_pair<G, GR>(A, B, pm, inv_m0, kg, h, dt, h, vka, vkb);
+    ra[7 * ns] = vka[0]; ra[8 * ns] = vka[1]; ra[9 * ns] = vka[2];
+    rb[7 * ns] = vkb[0]; rb[8 * ns] = vkb[1]; rb[9 * ns] = vkb[2];
+  }
+}
+
+template <int G, bool GR>
+__device__ void adj_sweep_pair(const AdjParams& q, int sa, int lane) {
+  const StepParams& p = q.sp;
+  const int ns = p.ns, sb = sa + 64;
+  const double ma = p.st[6 * ns + sa], mb = p.st[6 * ns + sb], m0 = p.m0s[sa];
+  const PairMass pm = make_pair_mass<G>(ma, mb);
+  const double dt = p.dts[sa], h = 0.5 * dt;
+  const double inv_m0 = 1.0 / m0;
+  const double kg = GR ? p.kgr * m0 * m0 : 0.0;
+  Grad a, b;
+  load_grad(q.grad, ns, sa, a);
+  load_grad(q.grad, ns, sb, b);
+  const bool leader = (lane & (G - 1)) == 0;
+  for (int s = q.n_seg - 1; s >= 0; --s) {
+    const double* ra = q.tape + (size_t)s * TAPE_ROWS * ns + sa;
+    const double* rb = ra + 64;
+    const double q0a[3] = {ra[0], ra[ns], ra[2 * ns]}, v0a[3] = {ra[3 * ns], ra[4 * ns], ra[5 * ns]};
+    const double q0b[3] = {rb[0], rb[ns], rb[2 * ns]}, v0b[3] = {rb[3 * ns], rb[4 * ns], rb[5 * ns]};
+    const double vka[3] = {ra[7 * ns], ra[8 * ns], ra[9 * ns]}, vkb[3] = {rb[7 * ns], rb[8 * ns], rb[9 * ns]};
+    const double tau = (q.first_synced && s == 0) ? h : dt;
+    KepFwd ka, kb;
+    kepler_at_X(q0a[0], q0a[1], q0a[2], v0a[0], v0a[1], v0a[2], m0, tau, ra[6 * ns], ka);
+    kepler_at_X(q0b[0], q0b[1], q0b[2], v0b[0], v0b[1], v0b[2], m0, tau, rb[6 * ns], kb);
+    double q1a[3], v1a[3], q1b[3], v1b[3];
+    for (int k = 0; k < 3; ++k) {
+      q1a[k] = ka.f * q0a[k] + ka.g * v0a[k]; v1a[k] = ka.fd * q0a[k] + ka.gd * v0a[k];
+      q1b[k] = kb.f * q0b[k] + kb.g * v0b[k]; v1b[k] = kb.fd * q0b[k] + kb.gd * v0b[k];
+    }
+    double gqa[3] = {a.qx, a.qy, a.qz}, gqb[3] = {b.qx, b.qy, b.qz};
+    if (GR) {
+      double s1[3], s3[3];
+      pair_momentum<G>(ma, v1a[0], v1a[1], v1a[2], mb, v1b[0], v1b[1], v1b[2], s1[0], s1[1], s1[2]);
+      const double kj = h * inv_m0;
+      double q2a[3], q2b[3];
+      for (int k = 0; k < 3; ++k) { q2a[k] = q1a[k] + kj * s1[k]; q2b[k] = q1b[k] + kj * s1[k]; }
+      pair_momentum<G>(ma, vka[0], vka[1], vka[2], mb, vkb[0], vkb[1], vkb[2], s3[0], s3[1], s3[2]);
+      jump_vjp_pair<G>(a, b, ma, mb, vka, vkb, kj, m0, s3, leader);
+      const double gva[3] = {a.vx, a.vy, a.vz}, gvb[3] = {b.vx, b.vy, b.vz};
+      gqa[0] = a.qx; gqa[1] = a.qy; gqa[2] = a.qz; gqb[0] = b.qx; gqb[1] = b.qy; gqb[2] = b.qz;
+      interaction_vjp_pair<G>(pm, ma, mb, q2a, q2b, gva, gvb, dt, gqa, gqb, a.m, b.m);
+      double gmu_a = 0.0, gmu_b = 0.0;
+      gr_vjp(q2a[0], q2a[1], q2a[2], kg, m0, dt, gva[0], gva[1], gva[2], gqa[0], gqa[1], gqa[2], gmu_a);
+      gr_vjp(q2b[0], q2b[1], q2b[2], kg, m0, dt, gvb[0], gvb[1], gvb[2], gqb[0], gqb[1], gqb[2], gmu_b);
+      a.qx = gqa[0]; a.qy = gqa[1]; a.qz = gqa[2]; b.qx = gqb[0]; b.qy = gqb[1]; b.qz = gqb[2];
+      a.m0 += gmu_a;
+      b.m0 += gmu_b;
+      jump_vjp_pair<G>(a, b, ma, mb, v1a, v1b, kj, m0, s1, leader);
+    } else {
+      double s2[3];
+      pair_momentum<G>(ma, vka[0], vka[1], vka[2], mb, vkb[0], vkb[1], vkb[2], s2[0], s2[1], s2[2]);
+      jump_vjp_pair<G>(a, b, ma, mb, vka, vkb, dt * inv_m0, m0, s2, leader);
+      const double gva[3] = {a.vx, a.vy, a.vz}, gvb[3] = {b.vx, b.vy, b.vz};
+      gqa[0] = a.qx; gqa[1] = a.qy; gqa[2] = a.qz; gqb[0] = b.qx; gqb[1] = b.qy; gqb[2] = b.qz;
+      interaction_vjp_pair<G>(pm, ma, mb, q1a, q1b, gva, gvb, dt, gqa, gqb, a.m, b.m);
+      a.qx = gqa[0]; a.qy = gqa[1]; a.qz = gqa[2]; b.qx = gqb[0]; b.qy = gqb[1]; b.qz = gqb[2];
+    }
+    double gmu = 0.0;
+    kepler_vjp(ka, q0a[0], q0a[1], q0a[2], v0a[0], v0a[1], v0a[2], m0, a.qx, a.qy, a.qz, a.vx, a.vy, a.vz, gmu);
+    a.m0 += gmu;
+    gmu = 0.0;
+    kepler_vjp(kb, q0b[0], q0b[1], q0b[2], v0b[0], v0b[1], v0b[2], m0, b.qx, b.qy, b.qz, b.vx, b.vy, b.vz, gmu);
+    b.m0 += gmu;
+  }
+  store_grad(q.grad, ns, sa, a);
+  store_grad(q.grad, ns, sb, b);
+}
+
+template <bool GR> __global__ __launch_bounds__(256) void k_adj_segment_pair(AdjParams q) {
+  const StepParams& p = q.sp;
+  const int lane = threadIdx.x & 63;
+  int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const bool sweep = wave < q.sweep_waves;
+  if (!sweep) wave -= q.sweep_waves;
+  if (wave >= p.w8) return;
+  const int sa = wave * 128 + lane;
+  if (sweep) {
+    if (wave < p.w1) adj_sweep_pair<1, GR>(q, sa, lane);
+    else if (wave < p.w2) adj_sweep_pair<2, GR>(q, sa, lane);
+    else adj_sweep_pair<4, GR>(q, sa, lane);
+  } else {
+    if (wave < p.w1) adj_record_pair<1, GR>(q, sa, lane);
+    else if (wave < p.w2) adj_record_pair<2, GR>(q, sa, lane);
+    else adj_record_pair<4, GR>(q, sa, lane);
+  }
+}
+
 // Waves [0, sweep_waves) sweep one segment, the waves after them record the
 // previous segment; each role covers the packing's waves once.
 template <bool GR, bool SPLIT> __global__ __launch_bounds__(256) void k_adj_segment(AdjParams q) {
@@ -1063,6 +1199,37 @@ template <int G> __device__ void adj_finish_lane(const AdjParams& q, int slot, i
     q.gm[(size_t)sys * 8 + pl] = a.m;
   }
   if ((lane & (G - 1)) == 0 && sys >= 0) q.gm0[sys] = g0;
+}
+
+template <int G> __device__ void adj_finish_pair(const AdjParams& q, int sa, int lane) {
+  const StepParams& p = q.sp;
+  Grad g[2];
+  load_grad(q.grad, p.ns, sa, g[0]);
+  load_grad(q.grad, p.ns, sa + 64, g[1]);
+  const double g0 = group_sum<G>(g[0].m0 + g[1].m0);
+  for (int k = 0; k < 2; ++k) {
+    const int slot = sa + 64 * k;
+    const int sys = p.slot_sys[slot], pl = p.slot_pl[slot];
+    if (sys >= 0 && pl >= 0) {
+      size_t o = ((size_t)sys * 8 + pl) * 3;
+      q.gQ_0[o] = g[k].qx; q.gQ_0[o + 1] = g[k].qy; q.gQ_0[o + 2] = g[k].qz;
+      q.gV_0[o] = g[k].vx; q.gV_0[o + 1] = g[k].vy; q.gV_0[o + 2] = g[k].vz;
+      q.gm[(size_t)sys * 8 + pl] = g[k].m;
+    }
+  }
+  const int sys = p.slot_sys[sa];
+  if ((lane & (G - 1)) == 0 && sys >= 0) q.gm0[sys] = g0;
+}
+
+__global__ __launch_bounds__(256) void k_adj_finish_pair(AdjParams q) {
+  const StepParams& p = q.sp;
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  const int sa = wave * 128 + lane;
+  if (wave < p.w1) adj_finish_pair<1>(q, sa, lane);
+  else if (wave < p.w2) adj_finish_pair<2>(q, sa, lane);
+  else adj_finish_pair<4>(q, sa, lane);
 }
 
 template <bool SPLIT> __global__ __launch_bounds__(256) void k_adj_finish(AdjParams q) {
@@ -1848,7 +2015,6 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
   if (c->cfg.scheme != WH_DKD) return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD");
   if (c->cfg.coords != WH_COORDS_DHC)
     return fail(WH_ESTATE, "reverse mode is implemented in democratic heliocentric coordinates");
-  if (c->P.pair) return fail(WH_ESTATE, "reverse mode is not implemented for the two-planets-per-lane packing");
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
   TapeLayout T = tape_layout(c->P.ns, n_steps, ckpt_every);
   if (tape_bytes < T.total) return fail(WH_EWORKSPACE, "tape too small: need " + std::to_string(T.total) + " bytes");
@@ -1917,7 +2083,10 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
   auto launch = [&](int sweep_waves, int record_waves) {
     q.sweep_waves = sweep_waves;
     const dim3 grid(sweep_waves + record_waves), block(64);
-    if (c->P.split) {
+    if (c->P.pair) {
+      if (gr) hipLaunchKernelGGL(k_adj_segment_pair<true>, grid, block, 0, stream, q);
+      else hipLaunchKernelGGL(k_adj_segment_pair<false>, grid, block, 0, stream, q);
+    } else if (c->P.split) {
       if (gr) hipLaunchKernelGGL((k_adj_segment<true, true>), grid, block, 0, stream, q);
       else hipLaunchKernelGGL((k_adj_segment<false, true>), grid, block, 0, stream, q);
     } else {
@@ -1941,7 +2110,8 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
       launch(nw, 0);
     }
   }
-  if (c->P.split) hipLaunchKernelGGL(k_adj_finish<true>, dim3(nw), dim3(64), 0, stream, q);
+  if (c->P.pair) hipLaunchKernelGGL(k_adj_finish_pair, dim3(nw), dim3(64), 0, stream, q);
+  else if (c->P.split) hipLaunchKernelGGL(k_adj_finish<true>, dim3(nw), dim3(64), 0, stream, q);
   else hipLaunchKernelGGL(k_adj_finish<false>, dim3(nw), dim3(64), 0, stream, q);
   return hip_check(hipGetLastError(), "adjoint launch");
 }

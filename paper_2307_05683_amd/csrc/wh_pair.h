@@ -15,6 +15,7 @@
 // moves per lane instead of 27.  Everything else is the one-planet math of
 // wh_device.h applied to both slots.
 #pragma once
+#include "wh_adjoint.h"
 #include "wh_device.h"
 
 namespace wh {
@@ -117,6 +118,79 @@ __device__ __forceinline__ void pair_momentum(double ma, double vax, double vay,
   sx = group_sum<G>(fma(ma, vax, mb * vbx));
   sy = group_sum<G>(fma(ma, vay, mb * vby));
   sz = group_sum<G>(fma(ma, vaz, mb * vbz));
+}
+
+// ---------------------------------------------------------------------------
+// Reverse mode of the pair layout.  Vectors of the two slots are passed as
+// double[3] arrays (a: the lane's first planet, b: its second).
+
+// Adjoint of the interaction kick V += tau a(Q) for both slots: pair_vjp for
+// every pair accel_pair evaluates, over the same rounds.  A pair evaluated
+// once (the lane's own pair, the reaction round of G = 4) gives the partner
+// the negated share; in the symmetric rounds each side takes its own.
+template <int G>
+__device__ __forceinline__ void interaction_vjp_pair(const PairMass& pm, double ma, double mb, const double qa[3],
+                                                     const double qb[3], const double gva[3], const double gvb[3],
+                                                     double tau, double gqa[3], double gqb[3], double& gma,
+                                                     double& gmb) {
+  double c[3], co, cp;
+  auto vjp = [&](const double* q, const double* gv, double m, const double* p, const double* pg, double mj) {
+    pair_vjp(q[0], q[1], q[2], gv[0], gv[1], gv[2], m, p[0], p[1], p[2], pg[0], pg[1], pg[2], mj, tau, c[0], c[1],
+             c[2], co, cp);
+  };
+  vjp(qa, gva, ma, qb, gvb, mb);       // the lane's own pair
+  for (int k = 0; k < 3; ++k) { gqa[k] += c[k]; gqb[k] -= c[k]; }
+  gma += co; gmb += cp;
+  if (G == 2 || G == 4) {
+    // G = 4 round 1: the next lane of the quad, reactions returned
+    double pa[3], pb[3], pga[3], pgb[3], ra[3] = {0.0, 0.0, 0.0}, rb[3] = {0.0, 0.0, 0.0}, ram = 0.0, rbm = 0.0;
+    if (G == 4) {
+      for (int k = 0; k < 3; ++k) {
+        pa[k] = dpp<QP_NEXT>(qa[k]); pb[k] = dpp<QP_NEXT>(qb[k]);
+        pga[k] = dpp<QP_NEXT>(gva[k]); pgb[k] = dpp<QP_NEXT>(gvb[k]);
+      }
+      vjp(qa, gva, ma, pa, pga, pm.a1);
+      for (int k = 0; k < 3; ++k) { gqa[k] += c[k]; ra[k] -= c[k]; }
+      gma += co; ram += cp;
+      vjp(qa, gva, ma, pb, pgb, pm.b1);
+      for (int k = 0; k < 3; ++k) { gqa[k] += c[k]; rb[k] -= c[k]; }
+      gma += co; rbm += cp;
+      vjp(qb, gvb, mb, pa, pga, pm.a1);
+      for (int k = 0; k < 3; ++k) { gqb[k] += c[k]; ra[k] -= c[k]; }
+      gmb += co; ram += cp;
+      vjp(qb, gvb, mb, pb, pgb, pm.b1);
+      for (int k = 0; k < 3; ++k) { gqb[k] += c[k]; rb[k] -= c[k]; }
+      gmb += co; rbm += cp;
+      for (int k = 0; k < 3; ++k) { gqa[k] += dpp<QP_PREV>(ra[k]); gqb[k] += dpp<QP_PREV>(rb[k]); }
+      gma += dpp<QP_PREV>(ram);
+      gmb += dpp<QP_PREV>(rbm);
+    }
+    // symmetric round: G = 2 the partner lane (xor 1), G = 4 the opposite lane (xor 2)
+    double ma2, mb2;
+    for (int k = 0; k < 3; ++k) {
+      if (G == 2) {
+        pa[k] = dpp<DPP_XOR1>(qa[k]); pb[k] = dpp<DPP_XOR1>(qb[k]);
+        pga[k] = dpp<DPP_XOR1>(gva[k]); pgb[k] = dpp<DPP_XOR1>(gvb[k]);
+      } else {
+        pa[k] = dpp<DPP_XOR2>(qa[k]); pb[k] = dpp<DPP_XOR2>(qb[k]);
+        pga[k] = dpp<DPP_XOR2>(gva[k]); pgb[k] = dpp<DPP_XOR2>(gvb[k]);
+      }
+    }
+    ma2 = G == 2 ? pm.a1 : pm.a2;
+    mb2 = G == 2 ? pm.b1 : pm.b2;
+    vjp(qa, gva, ma, pa, pga, ma2);
+    for (int k = 0; k < 3; ++k) gqa[k] += c[k];
+    gma += co;
+    vjp(qa, gva, ma, pb, pgb, mb2);
+    for (int k = 0; k < 3; ++k) gqa[k] += c[k];
+    gma += co;
+    vjp(qb, gvb, mb, pa, pga, ma2);
+    for (int k = 0; k < 3; ++k) gqb[k] += c[k];
+    gmb += co;
+    vjp(qb, gvb, mb, pb, pgb, mb2);
+    for (int k = 0; k < 3; ++k) gqb[k] += c[k];
+    gmb += co;
+  }
 }
 
 }  // namespace wh
