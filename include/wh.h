@@ -85,10 +85,10 @@ enum {
   WH_PACK_POW2 = 0,  /* one group of 1/2/4/8 lanes per system (next power of 2 >= N) */
   WH_PACK_G8 = 1,    /* one 8-lane group per system whatever N */
   WH_PACK_PAIR = 2,  /* two planets per lane: a group of 1/2/4 lanes per system (2 lanes per 3-4 planets,
-                        4 per 5-8); DHC with WH_DKD or WH_KDK only */
+                        4 per 5-8); DHC only */
   WH_PACK_SPLIT = 3  /* two lanes per planet: a 16-lane group per system whatever N, the interaction kick
                         divided between the two copies of each planet (for ensembles with fewer
-                        wavefronts than the GPU has SIMDs); DHC with WH_DKD or WH_KDK only */
+                        wavefronts than the GPU has SIMDs); DHC only */
 };
 
 /* Partner exchange of the interaction kick inside a lane group. */

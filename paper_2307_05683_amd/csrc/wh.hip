@@ -376,7 +376,7 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
     // commute without GR), the Jacobi kick in Jacobi coordinates.
     const int pg = lane & (G - 1);
     JacConst jc{0.0, 0.0, 0.0, 0.0};
-    if (JAC) jc = jac_const<G>(L.m0, L.m, pg);
+    if constexpr (JAC) jc = jac_const<G>(L.m0, L.m, pg);
     const double mu = JAC ? jc.Mi : L.m0;
     const double c1dt = p.sc[0] * dt;
     double tk = L.first ? c1dt : 2.0 * c1dt;
@@ -387,7 +387,7 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
       for (int k = 0; k < 4; ++k) {
         if (k < p.saba_n) {
           const double tb = p.sd[k] * dt;
-          if (JAC) kick_jacobi<G, EXCH, GR>(L, ex, jc, pg, tb, vkx, vky, vkz, kg);
+          if constexpr (JAC) kick_jacobi<G, EXCH, GR>(L, ex, jc, pg, tb, vkx, vky, vkz, kg);
           else kick_block<G, false, EXCH>(L, ex, inv_m0, 0.0, 0.5 * tb, tb, 0.5 * tb, vkx, vky, vkz);
           if (k + 1 < p.saba_n) drift(L, mu, p.sc[k + 1] * dt, dg);
         }
@@ -530,7 +530,27 @@ __device__ __forceinline__ void step_lane_pair(const StepParams& p, Lane& A, Lan
   const double kg = GR ? p.kgr * A.m0 * A.m0 : 0.0;
   KepDiag dga{0.0, 1.0e300}, dgb{0.0, 1.0e300};
   double vka[3], vkb[3];
-  if (SCHEME == WH_DKD) {
+  if constexpr (SCHEME == SCHEME_SABA) {
+    // SABA_n as in step_lane, B = I and J together (DHC, no GR)
+    const double c1dt = p.sc[0] * dt;
+    double tk = A.first ? c1dt : 2.0 * c1dt;
+    for (int s = 0; s < p.n_steps; ++s) {
+      drift(A, A.m0, tk, dga);
+      drift(B, B.m0, tk, dgb);
+      tk = 2.0 * c1dt;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (k < p.saba_n) {
+          const double tb = p.sd[k] * dt;
+          kick_block_pair<G, false>(A, B, pm, inv_m0, 0.0, 0.5 * tb, tb, 0.5 * tb, vka, vkb);
+          if (k + 1 < p.saba_n) {
+            drift(A, A.m0, p.sc[k + 1] * dt, dga);
+            drift(B, B.m0, p.sc[k + 1] * dt, dgb);
+          }
+        }
+      }
+    }
+  } else if (SCHEME == WH_DKD) {
     double tk = A.first ? h : dt;
     for (int s = 0; s < p.n_steps; ++s) {
       drift(A, A.m0, tk, dga);
@@ -771,10 +791,11 @@ template <int G, bool GR, int SCHEME> __device__ void sync_group_pair(const Sync
   Lane B = load_lane(p, sa + 64);
   if (!A.first) {
     const double h = 0.5 * A.dt;
-    if (SCHEME == WH_DKD) {
+    if (SCHEME == WH_DKD || SCHEME == SCHEME_SABA) {
       KepDiag dg{0.0, 1.0e300};
-      drift(A, A.m0, h, dg);
-      drift(B, B.m0, h, dg);
+      const double tau = SCHEME == SCHEME_SABA ? p.sc[0] * A.dt : h;
+      drift(A, A.m0, tau, dg);
+      drift(B, B.m0, tau, dg);
     } else {
       const PairMass pm = make_pair_mass<G>(A.m, B.m);
       double vka[3], vkb[3];
@@ -1559,12 +1580,8 @@ bool config_ok(const wh_config* c, std::string& why) {
   if (!(c->z_max >= 0.0)) { why = "z_max must be >= 0"; return false; }
   if (c->exchange < WH_EXCH_AUTO || c->exchange > WH_EXCH_DPP) { why = "unknown exchange"; return false; }
   if (c->coords != WH_COORDS_DHC && c->coords != WH_COORDS_JACOBI) { why = "unknown coordinates"; return false; }
-  if (c->packing == WH_PACK_PAIR && (c->coords != WH_COORDS_DHC || (c->scheme != WH_DKD && c->scheme != WH_KDK))) {
-    why = "the two-planets-per-lane packing runs the DHC drift-kick-drift and kick-drift-kick steps only";
-    return false;
-  }
-  if (c->packing == WH_PACK_SPLIT && (c->coords != WH_COORDS_DHC || (c->scheme != WH_DKD && c->scheme != WH_KDK))) {
-    why = "the two-lanes-per-planet packing runs the DHC drift-kick-drift and kick-drift-kick steps only";
+  if ((c->packing == WH_PACK_PAIR || c->packing == WH_PACK_SPLIT) && c->coords != WH_COORDS_DHC) {
+    why = "the two-planets-per-lane and two-lanes-per-planet packings run in democratic heliocentric coordinates only";
     return false;
   }
 
@@ -1666,7 +1683,9 @@ void launch_step_exch(const wh_ctx* c, const StepParams& p, dim3 grid, dim3 bloc
   const bool gr = c->cfg.gr_c > 0;
   const bool jac = c->cfg.coords == WH_COORDS_JACOBI;
   if (c->P.pair) {
-    if (c->cfg.scheme == WH_DKD) {
+    if (c->cfg.scheme >= WH_SABA2) {
+      hipLaunchKernelGGL((k_step_pair<false, SCHEME_SABA>), grid, block, 0, st, p);
+    } else if (c->cfg.scheme == WH_DKD) {
       if (gr) hipLaunchKernelGGL((k_step_pair<true, WH_DKD>), grid, block, 0, st, p);
       else hipLaunchKernelGGL((k_step_pair<false, WH_DKD>), grid, block, 0, st, p);
     } else {
@@ -1676,7 +1695,9 @@ void launch_step_exch(const wh_ctx* c, const StepParams& p, dim3 grid, dim3 bloc
     return;
   }
   if (c->P.split) {
-    if (c->cfg.scheme == WH_DKD) {
+    if (c->cfg.scheme >= WH_SABA2) {
+      hipLaunchKernelGGL((k_step_split<false, SCHEME_SABA>), grid, block, 0, st, p);
+    } else if (c->cfg.scheme == WH_DKD) {
       if (gr) hipLaunchKernelGGL((k_step_split<true, WH_DKD>), grid, block, 0, st, p);
       else hipLaunchKernelGGL((k_step_split<false, WH_DKD>), grid, block, 0, st, p);
     } else {
@@ -1734,7 +1755,9 @@ wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st
   dim3 block(64), grid(c->P.nwaves);
   const bool gr = c->cfg.gr_c > 0;
   if (c->P.pair) {
-    if (c->cfg.scheme == WH_DKD) {
+    if (c->cfg.scheme >= WH_SABA2) {
+      hipLaunchKernelGGL((k_sync_pair<false, SCHEME_SABA>), grid, block, 0, st, q);
+    } else if (c->cfg.scheme == WH_DKD) {
       if (gr) hipLaunchKernelGGL((k_sync_pair<true, WH_DKD>), grid, block, 0, st, q);
       else hipLaunchKernelGGL((k_sync_pair<false, WH_DKD>), grid, block, 0, st, q);
     } else {
@@ -1742,7 +1765,9 @@ wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st
       else hipLaunchKernelGGL((k_sync_pair<false, WH_KDK>), grid, block, 0, st, q);
     }
   } else if (c->P.split) {
-    if (c->cfg.scheme == WH_DKD) {
+    if (c->cfg.scheme >= WH_SABA2) {
+      hipLaunchKernelGGL((k_sync_split<false, SCHEME_SABA>), grid, block, 0, st, q);
+    } else if (c->cfg.scheme == WH_DKD) {
       if (gr) hipLaunchKernelGGL((k_sync_split<true, WH_DKD>), grid, block, 0, st, q);
       else hipLaunchKernelGGL((k_sync_split<false, WH_DKD>), grid, block, 0, st, q);
     } else {

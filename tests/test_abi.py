@@ -63,14 +63,15 @@ def test_lane_slot_cap(packing, max_systems):
 
 
 @pytest.mark.parametrize("packing", [_lib.WH_PACK_PAIR, _lib.WH_PACK_SPLIT])
-def test_pair_and_split_packings_need_dhc_wh(packing):
+def test_pair_and_split_packings_need_dhc(packing):
     cfg = _lib.default_config(3)
     cfg.packing = packing
-    assert _ws(cfg, [2, 5, 8]) > 0
-    cfg.scheme = _lib.WH_KDK
-    assert _ws(cfg, [2, 5, 8]) > 0
-    cfg.scheme = _lib.WH_SABA2
+    for scheme in (_lib.WH_DKD, _lib.WH_KDK, _lib.WH_SABA2, _lib.WH_SABA4):
+        cfg.scheme = scheme
+        assert _ws(cfg, [2, 5, 8]) > 0
+    cfg.gr_c = 10065.0            # SABA_n with GR needs Jacobi coordinates
     assert _ws(cfg, [2, 5, 8]) == 0
+    cfg.gr_c = 0.0
     cfg.scheme = _lib.WH_DKD
     cfg.coords = _lib.WH_COORDS_JACOBI
     assert _ws(cfg, [2, 5, 8]) == 0

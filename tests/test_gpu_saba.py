@@ -49,6 +49,32 @@ def test_packings_and_exchanges(packing, exchange):
     check(s, 500, "saba2", "dhc", packing=packing, exchange=exchange)
 
 
+@pytest.mark.parametrize("scheme", ["saba2", "saba3", "saba4"])
+@pytest.mark.parametrize("packing", ["pair", "split"])
+def test_pair_and_split_layouts(packing, scheme):
+    s = inputs.make_systems(45, 97, n_planets=None, n_range=(1, 8), dt_mode="u15_30")
+    check(s, 1000, scheme, "dhc", packing=packing)
+
+
+@pytest.mark.parametrize("packing", ["pair", "split"])
+def test_pair_and_split_few_steps_and_outputs(packing):
+    s = inputs.make_systems(20, 98, n_planets=None, n_range=(1, 8))
+    for n in (1, 2, 5):
+        check(s, n, "saba3", "dhc", tol=1e-14, packing=packing)
+    # keep unsynchronized: outputs between chunks leave the run bitwise unchanged
+    a = Ensemble.from_systems(s, scheme="saba2", chunk_steps=32, packing=packing)
+    a.step(200)
+    Qa, Va = a.state()
+    b = Ensemble.from_systems(s, scheme="saba2", chunk_steps=32, packing=packing)
+    for _ in range(20):
+        b.step(10)
+        b.state()
+        b.energy()
+    Qb, Vb = b.state()
+    assert torch.equal(Qa, Qb) and torch.equal(Va, Vb)
+    a.close(); b.close()
+
+
 @pytest.mark.parametrize("n_steps", [1, 2, 5])
 @pytest.mark.parametrize("coords", ["dhc", "jacobi"])
 def test_few_steps(n_steps, coords):

@@ -122,7 +122,7 @@ def test_keep_unsynchronized_is_bitwise_reproducible():
 
 def test_unsupported_combinations_rejected():
     s = inputs.make_systems(4, 216, n_planets=3)
-    for kw in (dict(coords="jacobi"), dict(scheme="saba2")):
+    for kw in (dict(coords="jacobi"), dict(scheme="saba2", gr_c=10065.0)):
         with pytest.raises(_lib.WHError):
             Ensemble.from_systems(s, packing="split", **kw)
     e = Ensemble.from_systems(s, packing="split", scheme="kdk")
