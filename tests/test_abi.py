@@ -62,6 +62,28 @@ def test_lane_slot_cap(packing, max_systems):
     assert _ws(cfg, np.full(1000, 8, dtype=np.int32)) > 0
 
 
+@pytest.mark.parametrize("packing", [_lib.WH_PACK_POW2, _lib.WH_PACK_G8, _lib.WH_PACK_PAIR, _lib.WH_PACK_SPLIT])
+def test_slot_count_matches_the_layout_rules(packing):
+    # the library builds the slot tables and checks them against its own
+    # closed-form count; here the count is rebuilt from the layout rules
+    rng = np.random.default_rng(7)
+    for S in (1, 5, 64, 333):
+        n = rng.integers(1, 9, S)
+        cnt = np.bincount(n, minlength=9)
+        w = lambda k, per: -(-int(k) // per)
+        if packing == _lib.WH_PACK_POW2:
+            ns = 64 * (w(cnt[1], 64) + w(cnt[2], 32) + w(cnt[3] + cnt[4], 16) + w(cnt[5:].sum(), 8))
+        elif packing == _lib.WH_PACK_G8:
+            ns = 64 * sum(w(cnt[k], 8) for k in range(1, 9))
+        elif packing == _lib.WH_PACK_PAIR:
+            ns = 128 * (w(cnt[1] + cnt[2], 64) + w(cnt[3] + cnt[4], 32) + w(cnt[5:].sum(), 16))
+        else:
+            ns = 64 * w(S, 4)
+        cfg = _lib.default_config(S)
+        cfg.packing = packing
+        assert _ws(cfg, n) == _layout_bytes(S, ns), (S, packing)
+
+
 @pytest.mark.parametrize("packing", [_lib.WH_PACK_PAIR, _lib.WH_PACK_SPLIT])
 def test_pair_and_split_packings_need_dhc(packing):
     cfg = _lib.default_config(3)
