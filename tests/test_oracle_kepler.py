@@ -166,6 +166,18 @@ def test_fixed_solver_meets_paper_accuracy():
     assert np.abs(err).max() < 3 * g["rel_a_err_max"]
 
 
+def test_fixed_solver_six_final_terms_with_recurrence_arrangement():
+    """App. A: every passing combination needs 6 series terms in the last
+    iteration.  With the final series summed for c8, c9 and carried down to
+    c2, c3 by three steps of c_n = 1/n! - z c_{n+2} (reading R2 of the 6 vs 8
+    terms of Sec. 3.2), 6 terms meet the 1e-13 bound for all e <= 0.7 with 2
+    Halley (4 terms) + 2 Newton steps, and 5 do not."""
+    g = GOLD["kepler_accuracy"]
+    e = np.linspace(0, g["e_max"], 8)
+    assert np.abs(_mercury_test(e, 2, 2, 4, 6, recur=3)).max() < g["rel_a_err_max"]
+    assert np.abs(_mercury_test(e, 2, 2, 4, 5, recur=3)).max() > g["rel_a_err_max"]
+
+
 def test_fixed_solver_failing_combinations():
     """App. A: too few final series terms or too few iterations miss the bar."""
     g = GOLD["kepler_accuracy"]
