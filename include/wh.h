@@ -176,6 +176,14 @@ wh_status wh_energy(wh_ctx* ctx, double* E_out, hipStream_t stream);
  * a < 0 marks an unbound orbit. */
 wh_status wh_elements(wh_ctx* ctx, double* a_out, double* e_out, hipStream_t stream);
 
+/* Total angular momentum L = sum_i Q_i x m_i V_i of every system's
+ * synchronized copy (L_out: device [S*3]).  In democratic heliocentric
+ * coordinates with barycentric momenta this is the angular momentum of the
+ * whole system about its barycentre; the drift, the jump, the interaction
+ * kick and the GR kick of Sec. 3 each conserve it exactly, so its change
+ * measures rounding alone. */
+wh_status wh_angular_momentum(wh_ctx* ctx, double* L_out, hipStream_t stream);
+
 /* Copy the sticky WH_F_* bits (flags_out: device uint32 [S]). */
 wh_status wh_status_flags(wh_ctx* ctx, uint32_t* flags_out, hipStream_t stream);
 

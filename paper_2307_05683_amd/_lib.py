@@ -58,6 +58,7 @@ _SIGS = {
     "wh_energy": ([vp, vp, vp], i32),
     "wh_status_flags": ([vp, vp, vp], i32),
     "wh_elements": ([vp, vp, vp, vp], i32),
+    "wh_angular_momentum": ([vp, vp, vp], i32),
     "wh_steps_done": ([vp], i64),
     "wh_tape_bytes": ([vp, i64, i64], sz),
     "wh_forward_ckpt": ([vp, i64, i64, vp, sz, vp], i32),

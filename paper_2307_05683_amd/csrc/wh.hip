@@ -620,7 +620,15 @@ struct SyncParams {
   double* E_out;    // [S] or null
   double* a_out;    // [S*8] or null
   double* e_out;
+  double* L_out;    // [S*3] or null
 };
+
+// Angular momentum m (Q x V) of one planet.
+__device__ __forceinline__ void planet_angmom(const Lane& L, double& lx, double& ly, double& lz) {
+  lx = L.m * (L.qy * L.vz - L.qz * L.vy);
+  ly = L.m * (L.qz * L.vx - L.qx * L.vz);
+  lz = L.m * (L.qx * L.vy - L.qy * L.vx);
+}
 
 template <int G, bool GR, int SCHEME, bool JAC = false>
 __device__ void sync_lane(const StepParams& p, Lane& L, int lane) {
@@ -686,6 +694,14 @@ template <int G, bool GR, int SCHEME, bool JAC> __device__ void sync_group(const
   if (q.E_out) {
     double E = group_energy<G, GR>(p, L, lane);
     if ((lane & (G - 1)) == 0 && L.sys >= 0) q.E_out[L.sys] = E;
+  }
+  if (q.L_out) {
+    double lx, ly, lz;
+    planet_angmom(L, lx, ly, lz);
+    lx = group_sum<G>(lx); ly = group_sum<G>(ly); lz = group_sum<G>(lz);
+    if ((lane & (G - 1)) == 0 && L.sys >= 0) {
+      q.L_out[(size_t)L.sys * 3] = lx; q.L_out[(size_t)L.sys * 3 + 1] = ly; q.L_out[(size_t)L.sys * 3 + 2] = lz;
+    }
   }
   if (q.a_out) {
     // heliocentric velocity u = V + sum_j m_j V_j / m0, two-body elements
@@ -809,6 +825,15 @@ template <int G, bool GR, int SCHEME> __device__ void sync_group_pair(const Sync
   if (q.E_out) {
     const double E = group_energy_pair<G, GR>(p, A, B, lane);
     if ((lane & (G - 1)) == 0 && A.sys >= 0) q.E_out[A.sys] = E;
+  }
+  if (q.L_out) {
+    double ax, ay, az, bx, by, bz;
+    planet_angmom(A, ax, ay, az);
+    planet_angmom(B, bx, by, bz);
+    const double lx = group_sum<G>(ax + bx), ly = group_sum<G>(ay + by), lz = group_sum<G>(az + bz);
+    if ((lane & (G - 1)) == 0 && A.sys >= 0) {
+      q.L_out[(size_t)A.sys * 3] = lx; q.L_out[(size_t)A.sys * 3 + 1] = ly; q.L_out[(size_t)A.sys * 3 + 2] = lz;
+    }
   }
   if (q.a_out) {
     double sx, sy, sz, a, e;
@@ -1744,7 +1769,7 @@ void launch_step(const wh_ctx* c, int n_steps, hipStream_t st) {
 }
 
 wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st, double* a = nullptr,
-                      double* e = nullptr) {
+                      double* e = nullptr, double* L = nullptr) {
   SyncParams q;
   q.sp = step_params(c, 0);
   q.Q_out = Q;
@@ -1752,6 +1777,7 @@ wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st
   q.E_out = E;
   q.a_out = a;
   q.e_out = e;
+  q.L_out = L;
   dim3 block(64), grid(c->P.nwaves);
   const bool gr = c->cfg.gr_c > 0;
   if (c->P.pair) {
@@ -2015,6 +2041,12 @@ wh_status wh_elements(wh_ctx* c, double* a_out, double* e_out, hipStream_t strea
   if (!c) return fail(WH_EINVAL, "null context");
   if (!a_out || !e_out) return fail(WH_EINVAL, "null output pointer");
   return launch_sync(c, nullptr, nullptr, nullptr, stream, a_out, e_out);
+}
+
+wh_status wh_angular_momentum(wh_ctx* c, double* L_out, hipStream_t stream) {
+  if (!c) return fail(WH_EINVAL, "null context");
+  if (!L_out) return fail(WH_EINVAL, "null output pointer");
+  return launch_sync(c, nullptr, nullptr, nullptr, stream, nullptr, nullptr, L_out);
 }
 
 wh_status wh_status_flags(wh_ctx* c, uint32_t* flags_out, hipStream_t stream) {

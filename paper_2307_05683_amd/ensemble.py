@@ -118,6 +118,12 @@ class Ensemble:
         check(_lib.load().wh_elements(self._ctx, a.data_ptr(), e.data_ptr(), _stream(self.device)))
         return a, e
 
+    def angular_momentum(self):
+        """Total angular momentum sum_i Q_i x m_i V_i of every system: [S, 3]."""
+        L = torch.zeros((self.S, 3), dtype=torch.float64, device=self.device)
+        check(_lib.load().wh_angular_momentum(self._ctx, L.data_ptr(), _stream(self.device)))
+        return L
+
     def flags(self):
         f = torch.zeros(self.S, dtype=torch.int32, device=self.device)
         check(_lib.load().wh_status_flags(self._ctx, f.data_ptr(), _stream(self.device)))
