@@ -113,17 +113,37 @@ def test_keep_unsynchronized_is_bitwise_reproducible():
     a.close(); b.close()
 
 
-def test_graph_replay_matches_direct_launches_bitwise():
+@pytest.mark.parametrize("packing", ["auto", "pair", "split"])
+def test_graph_replay_matches_direct_launches_bitwise(packing):
+    """Replays of the captured chunk graph (with the program's own launches
+    and synchronizations between them) equal direct launches bit for bit."""
     s = inputs.make_systems(40, 10, n_planets=None, n_range=(2, 8))
-    a = Ensemble.from_systems(s, chunk_steps=16, graph_launches=4)
-    b = Ensemble.from_systems(s, chunk_steps=16, graph_launches=-1)
+    a = Ensemble.from_systems(s, chunk_steps=16, graph_launches=4, packing=packing)
+    b = Ensemble.from_systems(s, chunk_steps=16, graph_launches=-1, packing=packing)
     for e in (a, b):
         e.step(3 * 64 + 21)
+        e.energy()
+        torch.cuda.synchronize()
         e.step(64)
     Qa, Va = a.state()
     Qb, Vb = b.state()
     assert torch.equal(Qa, Qb) and torch.equal(Va, Vb)
     a.close(); b.close()
+
+
+@pytest.mark.parametrize("packing", ["auto", "pair", "split"])
+def test_chunk_length_does_not_change_results(packing):
+    """The state goes to memory and back between launches without loss, so
+    the steps per launch do not change a single bit."""
+    s = inputs.make_systems(40, 12, n_planets=None, n_range=(1, 8))
+    out = []
+    for chunk in (1, 7, 4096):
+        e = Ensemble.from_systems(s, chunk_steps=chunk, packing=packing)
+        e.step(150)
+        out.append(e.state())
+        e.close()
+    for Q, V in out[1:]:
+        assert torch.equal(Q, out[0][0]) and torch.equal(V, out[0][1])
 
 
 @pytest.mark.parametrize("scheme,gr_c", [("dkd", 0.0), ("kdk", 40.0)])
