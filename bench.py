@@ -56,7 +56,8 @@ DEFAULT_STEPS = {"uniform8": 1_000_000, "uneven2to8": 1_000_000, "large8gr": 1_0
 # (which picks two planets per lane).
 DEFAULT_PACKING = {"uneven2to8": "tuned", "large8gr": "pair", "uniform8": "split", "single8": "split"}
 KERNEL_NAME = {"pair": "k_step_pair (persistent step kernel, two planets per lane)",
-               "split": "k_step_split (persistent step kernel, two lanes per planet)"}
+               "split": "k_step_split (persistent step kernel, two lanes per planet)",
+               "serial": "k_step_serial (persistent step kernel, one lane per system)"}
 
 
 def parse():
@@ -67,7 +68,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=4096, help="untimed steps before the timed region")
     ap.add_argument("--workload", default="uniform8", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--packing", default=None,
-                    help="auto|pow2|g8|pair|split|tuned (default: tuned for uneven2to8, pair for large8gr, whose "
+                    help="auto|pow2|g8|pair|split|serial|tuned (default: tuned for uneven2to8, pair for large8gr, whose "
                          "batch fills more wavefronts than the chip has SIMDs, split for uniform8 and single8, which "
                          "fill fewer; auto otherwise)")
     ap.add_argument("--block-waves", type=int, default=None,

@@ -86,9 +86,12 @@ enum {
   WH_PACK_G8 = 1,    /* one 8-lane group per system whatever N */
   WH_PACK_PAIR = 2,  /* two planets per lane: a group of 1/2/4 lanes per system (2 lanes per 3-4 planets,
                         4 per 5-8); DHC only */
-  WH_PACK_SPLIT = 3  /* two lanes per planet: a 16-lane group per system whatever N, the interaction kick
+  WH_PACK_SPLIT = 3, /* two lanes per planet: a 16-lane group per system whatever N, the interaction kick
                         divided between the two copies of each planet (for ensembles with fewer
                         wavefronts than the GPU has SIMDs); DHC only */
+  WH_PACK_SERIAL = 4 /* one lane per system: the storage of WH_PACK_G8, but one thread runs all planets of
+                        a system (every pair visited once, no cross-lane traffic; 64 systems per wave, for
+                        very large ensembles); DHC only, no reverse mode */
 };
 
 /* Partner exchange of the interaction kick inside a lane group. */
@@ -118,8 +121,8 @@ enum {
 
 typedef struct {
   int32_t n_systems;   /* S >= 1; the packing may use at most 2^27 lane slots (16.7 million
-                          eight-planet systems with one planet per lane, 8.4 million with
-                          WH_PACK_SPLIT, 33.5 million with WH_PACK_PAIR) */
+                          eight-planet systems with one planet per lane or WH_PACK_SERIAL,
+                          8.4 million with WH_PACK_SPLIT, 33.5 million with WH_PACK_PAIR) */
   double G;            /* must be 1.0 (Sec. 3.5) */
   double gr_c;         /* speed of light for the GR kick; <= 0 turns GR off */
   int32_t scheme;      /* WH_DKD, WH_KDK or WH_SABA2..4 */
@@ -203,7 +206,7 @@ int64_t wh_steps_done(const wh_ctx* ctx);
  * tape holds two segment buffers, so that segment k - 1 is recorded while
  * segment k is swept.  wh_tape_bytes gives the size: 96 B per lane slot per
  * checkpoint plus 2 x 80 B per lane slot and step of a segment.  Contexts in
- * DHC with WH_DKD (any packing); other contexts get WH_ESTATE. */
+ * DHC with WH_DKD (any packing but WH_PACK_SERIAL); other contexts get WH_ESTATE. */
 size_t wh_tape_bytes(const wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every);
 wh_status wh_forward_ckpt(wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every, void* tape, size_t tape_bytes,
                           hipStream_t stream);

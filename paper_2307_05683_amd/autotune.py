@@ -1,9 +1,9 @@
 """Autotuner for the lane packing of an ensemble.
 
 Candidates: packing (1/2/4/8-lane groups, always 8 lanes, two planets per
-lane in 1/2/4-lane groups, or two lanes per planet in 16-lane groups),
-partner exchange (DPP or LDS crossbar; the two-per-lane and two-per-planet
-layouts have a single DPP schedule), wavefronts per workgroup and steps per
+lane in 1/2/4-lane groups, two lanes per planet in 16-lane groups, or one
+lane per system), partner exchange (DPP or LDS crossbar; the last three
+layouts have a single schedule), wavefronts per workgroup and steps per
 launch (the splitting coordinates are the caller's choice, not a candidate:
 they change the results, not just the speed).  Each candidate integrates the real batch for a short run; the
 fastest (system-steps per second, GPU event time) wins.  Results are cached
@@ -27,7 +27,7 @@ from . import _lib
 from .ensemble import Ensemble
 
 CANDIDATES = {
-    "packing": ["pow2", "g8", "pair", "split"],
+    "packing": ["pow2", "g8", "pair", "split", "serial"],
     "exchange": ["dpp", "lds"],
     "block_waves": [1, 4],
     "chunk_steps": [1024, 4096],
@@ -99,7 +99,7 @@ def autotune(systems, gr_c: float = 0.0, scheme: str = "dkd", steps: int = 1024,
     table = []
     for values in itertools.product(*(cands[n] for n in names)):
         opts = dict(zip(names, values))
-        if opts.get("packing") in ("pair", "split") and opts.get("exchange") == "lds":
+        if opts.get("packing") in ("pair", "split", "serial") and opts.get("exchange") == "lds":
             continue              # same kernel as the DPP candidate
         # the steps of a probe must cover a few launches of the candidate's chunk
         n = max(steps, 2 * opts.get("chunk_steps", 0)) if "chunk_steps" in opts else steps

@@ -609,6 +609,246 @@ __global__ __launch_bounds__(256) void k_step_split(StepParams p) {
 }
 
 // ---------------------------------------------------------------------------
+// One lane per system (WH_PACK_SERIAL): the storage is that of the G8 packing
+// (planet p of a system in slot p of its 8-slot group, each planet count on
+// waves of its own), but thread t runs the whole system of group t, as the
+// paper runs one system per core.  The interaction kick visits each of the
+// N(N-1)/2 pairs once and gives both planets their share (Sec. 3.3,
+// acceleration equation), and the jump sums the momenta in the thread
+// (Sec. 3.4): no cross-lane traffic, 64 systems per wave.  The body is
+// compiled for each planet count NP and a wave runs the one for the largest
+// count among its systems; slots beyond a system's own count are padding
+// planets (zero mass, far orbits), integrated like the G8 layout's padding
+// lanes.
+//
+// Registers hold the rounded state (Q, V, m) of every planet; the
+// compensation terms live in LDS (a thread-private [6][8] block of doubles,
+// lane-interleaved), since eight planets' full state would overflow the
+// thread's registers.  Each planet's terms are read once per step: its kick
+// increments, renormalization and next drift run back to back.
+constexpr int SERIAL_LDS_PER_WAVE = 6 * 8 * 64;   // doubles
+
+template <int NP> struct SerialState {
+  double qx[NP], qy[NP], qz[NP], vx[NP], vy[NP], vz[NP], m[NP];
+};
+
+// element (k, i) of the thread's compensation block: k = 0..5 (Q then V), planet i
+__device__ __forceinline__ double& comp_at(double* cl, int k, int i) { return cl[(k * 8 + i) * 64]; }
+
+template <int NP> __device__ __forceinline__ Lane serial_get(const SerialState<NP>& S, double* cl, int i) {
+  Lane L{};
+  L.qx = S.qx[i]; L.qy = S.qy[i]; L.qz = S.qz[i];
+  L.vx = S.vx[i]; L.vy = S.vy[i]; L.vz = S.vz[i];
+  L.m = S.m[i];
+  L.cqx = comp_at(cl, 0, i); L.cqy = comp_at(cl, 1, i); L.cqz = comp_at(cl, 2, i);
+  L.cvx = comp_at(cl, 3, i); L.cvy = comp_at(cl, 4, i); L.cvz = comp_at(cl, 5, i);
+  return L;
+}
+
+template <int NP> __device__ __forceinline__ void serial_put(SerialState<NP>& S, double* cl, int i, const Lane& L) {
+  S.qx[i] = L.qx; S.qy[i] = L.qy; S.qz[i] = L.qz;
+  S.vx[i] = L.vx; S.vy[i] = L.vy; S.vz[i] = L.vz;
+  comp_at(cl, 0, i) = L.cqx; comp_at(cl, 1, i) = L.cqy; comp_at(cl, 2, i) = L.cqz;
+  comp_at(cl, 3, i) = L.cvx; comp_at(cl, 4, i) = L.cvy; comp_at(cl, 5, i) = L.cvz;
+}
+
+// Kepler drift K(tau) of one planet; the diagnostics count the system's own
+// planets only.
+__device__ __forceinline__ void serial_drift(Lane& L, double mu, double tau, bool own, KepDiag& dg) {
+  KepDiag d{0.0, 1.0e300};
+  drift(L, mu, tau, d);
+  if (own) {
+    dg.zmax = fmax(dg.zmax, d.zmax);
+    dg.bmin = fmin(dg.bmin, d.bmin);
+  }
+}
+
+// J(ta) [I + GR](ti) J(tc) of one system (the operations of kick_block on
+// every planet), then, if do_drift, the next drift K(tau) of each planet
+// right after its renormalization.
+template <int NP, bool GR>
+__device__ __forceinline__ void serial_kick_drift(SerialState<NP>& S, double* cl, int n, double m0, double inv_m0,
+                                                  double kg, double ta, double ti, double tc, double tau,
+                                                  bool do_drift, KepDiag& dg) {
+  double qx[NP], qy[NP], qz[NP], ax[NP], ay[NP], az[NP];
+  double dqx = 0.0, dqy = 0.0, dqz = 0.0;
+  if (GR) {
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      sx = fma(S.m[i], S.vx[i], sx);
+      sy = fma(S.m[i], S.vy[i], sy);
+      sz = fma(S.m[i], S.vz[i], sz);
+    }
+    const double k1 = ta * inv_m0;
+    dqx = k1 * sx; dqy = k1 * sy; dqz = k1 * sz;
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    qx[i] = GR ? S.qx[i] + dqx : S.qx[i];
+    qy[i] = GR ? S.qy[i] + dqy : S.qy[i];
+    qz[i] = GR ? S.qz[i] + dqz : S.qz[i];
+    ax[i] = 0.0; ay[i] = 0.0; az[i] = 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i)
+#pragma unroll
+    for (int j = i + 1; j < NP; ++j) {
+      double dx, dy, dz;
+      const double ir3 = pair_accel(qx[i], qy[i], qz[i], qx[j], qy[j], qz[j], S.m[j], ax[i], ay[i], az[i], dx, dy,
+                                    dz);
+      const double w = S.m[i] * ir3;   // planet j's acceleration is +w d
+      ax[j] = fma(w, dx, ax[j]);
+      ay[j] = fma(w, dy, ay[j]);
+      az[j] = fma(w, dz, az[j]);
+    }
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    if (GR) {
+      double gx, gy, gz;
+      gr_accel(qx[i], qy[i], qz[i], kg, gx, gy, gz);
+      ax[i] += gx; ay[i] += gy; az[i] += gz;
+    }
+    ax[i] *= ti; ay[i] *= ti; az[i] *= ti;   // now the velocity increments
+    sx = fma(S.m[i], S.vx[i] + ax[i], sx);
+    sy = fma(S.m[i], S.vy[i] + ay[i], sy);
+    sz = fma(S.m[i], S.vz[i] + az[i], sz);
+  }
+  const double k2 = (GR ? tc : ta + tc) * inv_m0;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    Lane L = serial_get(S, cl, i);
+    if (GR) { L.cqx += dqx; L.cqy += dqy; L.cqz += dqz; }
+    L.cvx += ax[i]; L.cvy += ay[i]; L.cvz += az[i];
+    L.cqx += k2 * sx; L.cqy += k2 * sy; L.cqz += k2 * sz;
+    renorm_all(L);
+    if (do_drift) serial_drift(L, m0, tau, i < n, dg);
+    serial_put(S, cl, i, L);
+    // one planet at a time: hoisting the next planets' loads and solves
+    // would overflow the registers
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int NP, bool GR, int SCHEME>
+__device__ void step_serial(const StepParams& p, int base, int n, double* cl) {
+  const double* st = p.st;
+  const int ns = p.ns;
+  SerialState<NP> S;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    S.qx[i] = st[base + i];
+    S.qy[i] = st[ns + base + i];
+    S.qz[i] = st[2 * ns + base + i];
+    S.vx[i] = st[3 * ns + base + i];
+    S.vy[i] = st[4 * ns + base + i];
+    S.vz[i] = st[5 * ns + base + i];
+    S.m[i] = st[6 * ns + base + i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) comp_at(cl, k, i) = st[(7 + k) * ns + base + i];
+  }
+  const int sys = p.slot_sys[base];
+  const double dt = p.dts[base];
+  const double h = 0.5 * dt;
+  const double m0 = p.m0s[base];
+  const double inv_m0 = 1.0 / m0;
+  const double kg = GR ? p.kgr * m0 * m0 : 0.0;
+  const bool first = p.synced[sys] != 0;
+  KepDiag dg{0.0, 1.0e300};
+  auto drift_all = [&](double tau) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      Lane L = serial_get(S, cl, i);
+      serial_drift(L, m0, tau, i < n, dg);
+      serial_put(S, cl, i, L);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  const int ns_steps = p.n_steps;
+  if constexpr (SCHEME == SCHEME_SABA) {
+    // K(c_1 dt) B(d_1 dt) K(c_2 dt) ... B(d_n dt), the closing drift merged
+    // with the next step's opening one; each kick is followed by the drift
+    // after it, except the last kick of the last step
+    const double c1dt = p.sc[0] * dt;
+    if (ns_steps > 0) drift_all(first ? c1dt : 2.0 * c1dt);
+    for (int s = 0; s < ns_steps; ++s) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (k < p.saba_n) {
+          const double tb = p.sd[k] * dt;
+          const bool inner = k + 1 < p.saba_n;
+          const double tau = inner ? p.sc[k + 1] * dt : 2.0 * c1dt;
+          serial_kick_drift<NP, false>(S, cl, n, m0, inv_m0, 0.0, 0.5 * tb, tb, 0.5 * tb, tau,
+                                       inner || s + 1 < ns_steps, dg);
+        }
+      }
+    }
+  } else if (SCHEME == WH_DKD) {
+    if (ns_steps > 0) drift_all(first ? h : dt);
+    for (int s = 0; s < ns_steps; ++s)
+      serial_kick_drift<NP, GR>(S, cl, n, m0, inv_m0, kg, h, dt, h, dt, s + 1 < ns_steps, dg);
+  } else {
+    double ta = first ? 0.0 : h;
+    double ti = first ? h : dt;
+    for (int s = 0; s < ns_steps; ++s) {
+      serial_kick_drift<NP, GR>(S, cl, n, m0, inv_m0, kg, ta, ti, h, dt, true, dg);
+      ta = h;
+      ti = dt;
+    }
+  }
+  int f = 0;
+  double* so = p.st;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const bool fin = __builtin_isfinite(S.qx[i]) && __builtin_isfinite(S.qy[i]) && __builtin_isfinite(S.qz[i]) &&
+                     __builtin_isfinite(S.vx[i]) && __builtin_isfinite(S.vy[i]) && __builtin_isfinite(S.vz[i]);
+    if (i < n && !fin) f |= WH_F_NONFINITE;
+    so[base + i] = S.qx[i];
+    so[ns + base + i] = S.qy[i];
+    so[2 * ns + base + i] = S.qz[i];
+    so[3 * ns + base + i] = S.vx[i];
+    so[4 * ns + base + i] = S.vy[i];
+    so[5 * ns + base + i] = S.vz[i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) so[(7 + k) * ns + base + i] = comp_at(cl, k, i);
+  }
+  if (!(dg.bmin > 0.0)) f |= WH_F_HYPERBOLIC;
+  if (!(dg.zmax <= p.zlim)) f |= WH_F_ZMAX;
+  p.flags[sys] |= (uint32_t)f;
+  p.synced[sys] = 0;
+}
+
+// Dynamic LDS: SERIAL_LDS_PER_WAVE doubles per wave of the block.
+template <bool GR, int SCHEME>
+__global__ __launch_bounds__(256) void k_step_serial(StepParams p) {
+  extern __shared__ double serial_lds[];
+  const int g = p.wave0 * 8 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (g >= p.w8 * 8) return;
+  const int base = g * 8;
+  if (p.slot_sys[base] < 0) return;   // an empty group
+  double* cl = serial_lds + (threadIdx.x >> 6) * SERIAL_LDS_PER_WAVE + (threadIdx.x & 63);
+  int n = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) n += p.slot_pl[base + i] >= 0;
+  // the largest planet count among the wave's systems (wave-uniform)
+  int nw = 1;
+#pragma unroll
+  for (int k = 2; k <= 8; ++k)
+    if (__ballot(n >= k) != 0) nw = k;
+  switch (nw) {
+    case 1: step_serial<1, GR, SCHEME>(p, base, n, cl); break;
+    case 2: step_serial<2, GR, SCHEME>(p, base, n, cl); break;
+    case 3: step_serial<3, GR, SCHEME>(p, base, n, cl); break;
+    case 4: step_serial<4, GR, SCHEME>(p, base, n, cl); break;
+    case 5: step_serial<5, GR, SCHEME>(p, base, n, cl); break;
+    case 6: step_serial<6, GR, SCHEME>(p, base, n, cl); break;
+    case 7: step_serial<7, GR, SCHEME>(p, base, n, cl); break;
+    default: step_serial<8, GR, SCHEME>(p, base, n, cl); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Synchronized copy: DKD applies the pending half drift K(h), SABA_n the
 // pending drift K(c_1 dt); KDK applies the pending half kick J(h) [I + GR](h).
 // A synchronized state is left as is.
@@ -1420,6 +1660,7 @@ wh_status hip_check(hipError_t e, const char* what) {
 struct Packing {
   bool pair = false;   // WH_PACK_PAIR: two slots (planets) per lane, 128 slots per wave
   bool split = false;  // WH_PACK_SPLIT: two lanes (copies) per planet, 16 lanes per system
+  bool serial = false; // WH_PACK_SERIAL: the G8 storage, one thread per system in the step
   int ns = 0, nwaves = 0;
   int w1 = 0, w2 = 0, w4 = 0, w8 = 0;
   int plain_begin[9] = {0}, plain_end[9] = {0};   // G8 packing: waves of each planet count
@@ -1427,7 +1668,7 @@ struct Packing {
 };
 
 int group_size(int n, int packing) {
-  if (packing == WH_PACK_G8) return 8;
+  if (packing == WH_PACK_G8 || packing == WH_PACK_SERIAL) return 8;
   return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : 8;
 }
 
@@ -1446,7 +1687,7 @@ int64_t slots_needed(int S, const int32_t* np, int packing) {
   if (packing == WH_PACK_PAIR)
     return (waves(cnt[1] + cnt[2], 64) + waves(cnt[3] + cnt[4], 32) + waves(cnt[5] + cnt[6] + cnt[7] + cnt[8], 16)) *
            128;
-  if (packing == WH_PACK_G8) {
+  if (packing == WH_PACK_G8 || packing == WH_PACK_SERIAL) {
     int64_t w = 0;
     for (int n = 1; n <= 8; ++n) w += waves(cnt[n], 8);
     return w * 64;
@@ -1534,7 +1775,7 @@ bool make_packing(int S, const int32_t* np, int packing, Packing& P, std::string
     P.split = true;
     P.w1 = P.w2 = P.w4 = 0;
     P.w8 = nw;
-  } else if (packing == WH_PACK_G8) {
+  } else if (packing == WH_PACK_G8 || packing == WH_PACK_SERIAL) {
     for (int n = 1; n <= 8; ++n) {
       std::vector<int> cls;
       for (int s = 0; s < S; ++s)
@@ -1545,6 +1786,7 @@ bool make_packing(int S, const int32_t* np, int packing, Packing& P, std::string
     }
     P.w1 = P.w2 = P.w4 = 0;
     P.w8 = P.nwaves;
+    P.serial = packing == WH_PACK_SERIAL;
   } else {
     int ends[4];
     const int Gs[4] = {1, 2, 4, 8};
@@ -1597,7 +1839,7 @@ bool config_ok(const wh_config* c, std::string& why) {
   if (c->scheme >= WH_SABA2 && c->gr_c > 0 && c->coords != WH_COORDS_JACOBI) {
     why = "SABA_n with GR needs Jacobi coordinates: in DHC the GR and jump flows do not commute"; return false;
   }
-  if (c->packing < WH_PACK_AUTO || c->packing > WH_PACK_SPLIT) { why = "unknown packing"; return false; }
+  if (c->packing < WH_PACK_AUTO || c->packing > WH_PACK_SERIAL) { why = "unknown packing"; return false; }
   if (c->block_waves != 0 && c->block_waves != 1 && c->block_waves != 2 && c->block_waves != 4) {
     why = "block_waves must be 0, 1, 2 or 4"; return false;
   }
@@ -1605,8 +1847,10 @@ bool config_ok(const wh_config* c, std::string& why) {
   if (!(c->z_max >= 0.0)) { why = "z_max must be >= 0"; return false; }
   if (c->exchange < WH_EXCH_AUTO || c->exchange > WH_EXCH_DPP) { why = "unknown exchange"; return false; }
   if (c->coords != WH_COORDS_DHC && c->coords != WH_COORDS_JACOBI) { why = "unknown coordinates"; return false; }
-  if ((c->packing == WH_PACK_PAIR || c->packing == WH_PACK_SPLIT) && c->coords != WH_COORDS_DHC) {
-    why = "the two-planets-per-lane and two-lanes-per-planet packings run in democratic heliocentric coordinates only";
+  if ((c->packing == WH_PACK_PAIR || c->packing == WH_PACK_SPLIT || c->packing == WH_PACK_SERIAL) &&
+      c->coords != WH_COORDS_DHC) {
+    why = "the two-planets-per-lane, two-lanes-per-planet and one-lane-per-system packings run in democratic "
+          "heliocentric coordinates only";
     return false;
   }
 
@@ -1704,7 +1948,7 @@ StepParams step_params(const wh_ctx* c, int n_steps) {
 }
 
 template <int EXCH>
-void launch_step_exch(const wh_ctx* c, const StepParams& p, dim3 grid, dim3 block, hipStream_t st) {
+void launch_step_exch(const wh_ctx* c, const StepParams& p, dim3 grid, dim3 block, size_t smem, hipStream_t st) {
   const bool gr = c->cfg.gr_c > 0;
   const bool jac = c->cfg.coords == WH_COORDS_JACOBI;
   if (c->P.pair) {
@@ -1728,6 +1972,18 @@ void launch_step_exch(const wh_ctx* c, const StepParams& p, dim3 grid, dim3 bloc
     } else {
       if (gr) hipLaunchKernelGGL((k_step_split<true, WH_KDK>), grid, block, 0, st, p);
       else hipLaunchKernelGGL((k_step_split<false, WH_KDK>), grid, block, 0, st, p);
+    }
+    return;
+  }
+  if (c->P.serial) {
+    if (c->cfg.scheme >= WH_SABA2) {
+      hipLaunchKernelGGL((k_step_serial<false, SCHEME_SABA>), grid, block, smem, st, p);
+    } else if (c->cfg.scheme == WH_DKD) {
+      if (gr) hipLaunchKernelGGL((k_step_serial<true, WH_DKD>), grid, block, smem, st, p);
+      else hipLaunchKernelGGL((k_step_serial<false, WH_DKD>), grid, block, smem, st, p);
+    } else {
+      if (gr) hipLaunchKernelGGL((k_step_serial<true, WH_KDK>), grid, block, smem, st, p);
+      else hipLaunchKernelGGL((k_step_serial<false, WH_KDK>), grid, block, smem, st, p);
     }
     return;
   }
@@ -1757,10 +2013,20 @@ void launch_step_exch(const wh_ctx* c, const StepParams& p, dim3 grid, dim3 bloc
 }
 
 void launch_step_kernel(const wh_ctx* c, const StepParams& p, int n_waves, hipStream_t st) {
-  const int bw = c->block_waves;
-  dim3 block(64 * bw), grid((n_waves + bw - 1) / bw);
-  if (c->exchange == WH_EXCH_LDS) launch_step_exch<0>(c, p, grid, block, st);
-  else launch_step_exch<1>(c, p, grid, block, st);
+  int bw = c->block_waves;
+  int units = n_waves;
+  size_t smem = 0;
+  if (c->P.serial) {
+    // one thread per 8-slot group (8 per wave of slots), each with its
+    // compensation block in LDS; at most two waves per workgroup keep the
+    // dynamic LDS within 64 KiB
+    units = (n_waves * 8 + 63) / 64;
+    bw = bw > 2 ? 2 : bw;
+    smem = (size_t)bw * SERIAL_LDS_PER_WAVE * sizeof(double);
+  }
+  dim3 block(64 * bw), grid((units + bw - 1) / bw);
+  if (c->exchange == WH_EXCH_LDS) launch_step_exch<0>(c, p, grid, block, smem, st);
+  else launch_step_exch<1>(c, p, grid, block, smem, st);
 }
 
 void launch_step(const wh_ctx* c, int n_steps, hipStream_t st) {
@@ -2070,6 +2336,7 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
   if (n_steps < 0 || ckpt_every < 1 || ckpt_every > (1 << 30)) return fail(WH_EINVAL, "bad n_steps or ckpt_every");
   if (((uintptr_t)tape & 255) != 0) return fail(WH_EINVAL, "tape must be 256-byte aligned");
   if (c->cfg.scheme != WH_DKD) return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD");
+  if (c->P.serial) return fail(WH_ESTATE, "reverse mode is not implemented in the one-lane-per-system packing");
   if (c->cfg.coords != WH_COORDS_DHC)
     return fail(WH_ESTATE, "reverse mode is implemented in democratic heliocentric coordinates");
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");

@@ -51,7 +51,7 @@ def test_split_packing_takes_16_lanes_per_system(S):
 
 
 @pytest.mark.parametrize("packing,max_systems", [(_lib.WH_PACK_POW2, 1 << 24), (_lib.WH_PACK_SPLIT, 1 << 23),
-                                                 (_lib.WH_PACK_PAIR, 1 << 25)])
+                                                 (_lib.WH_PACK_PAIR, 1 << 25), (_lib.WH_PACK_SERIAL, 1 << 24)])
 def test_lane_slot_cap(packing, max_systems):
     # 32-bit device indexing: at most 2^27 lane slots; eight-planet systems
     # take 8 (one planet per lane), 16 (split) or 4 (pair) slots each
@@ -62,7 +62,8 @@ def test_lane_slot_cap(packing, max_systems):
     assert _ws(cfg, np.full(1000, 8, dtype=np.int32)) > 0
 
 
-@pytest.mark.parametrize("packing", [_lib.WH_PACK_POW2, _lib.WH_PACK_G8, _lib.WH_PACK_PAIR, _lib.WH_PACK_SPLIT])
+@pytest.mark.parametrize("packing", [_lib.WH_PACK_POW2, _lib.WH_PACK_G8, _lib.WH_PACK_PAIR, _lib.WH_PACK_SPLIT,
+                                     _lib.WH_PACK_SERIAL])
 def test_slot_count_matches_the_layout_rules(packing):
     # the library builds the slot tables and checks them against its own
     # closed-form count; here the count is rebuilt from the layout rules
@@ -73,7 +74,8 @@ def test_slot_count_matches_the_layout_rules(packing):
         w = lambda k, per: -(-int(k) // per)
         if packing == _lib.WH_PACK_POW2:
             ns = 64 * (w(cnt[1], 64) + w(cnt[2], 32) + w(cnt[3] + cnt[4], 16) + w(cnt[5:].sum(), 8))
-        elif packing == _lib.WH_PACK_G8:
+        elif packing in (_lib.WH_PACK_G8, _lib.WH_PACK_SERIAL):
+            # the one-lane-per-system packing keeps the G8 storage
             ns = 64 * sum(w(cnt[k], 8) for k in range(1, 9))
         elif packing == _lib.WH_PACK_PAIR:
             ns = 128 * (w(cnt[1] + cnt[2], 64) + w(cnt[3] + cnt[4], 32) + w(cnt[5:].sum(), 16))
@@ -84,8 +86,8 @@ def test_slot_count_matches_the_layout_rules(packing):
         assert _ws(cfg, n) == _layout_bytes(S, ns), (S, packing)
 
 
-@pytest.mark.parametrize("packing", [_lib.WH_PACK_PAIR, _lib.WH_PACK_SPLIT])
-def test_pair_and_split_packings_need_dhc(packing):
+@pytest.mark.parametrize("packing", [_lib.WH_PACK_PAIR, _lib.WH_PACK_SPLIT, _lib.WH_PACK_SERIAL])
+def test_pair_split_and_serial_packings_need_dhc(packing):
     cfg = _lib.default_config(3)
     cfg.packing = packing
     for scheme in (_lib.WH_DKD, _lib.WH_KDK, _lib.WH_SABA2, _lib.WH_SABA4):
@@ -100,7 +102,7 @@ def test_pair_and_split_packings_need_dhc(packing):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(G=2.0), dict(scheme=5), dict(packing=7), dict(block_waves=3), dict(chunk_steps=-1), dict(n_systems=0),
+    dict(G=2.0), dict(scheme=5), dict(packing=5), dict(packing=7), dict(block_waves=3), dict(chunk_steps=-1), dict(n_systems=0),
     dict(exchange=9),
 ])
 def test_invalid_configs_rejected(bad):

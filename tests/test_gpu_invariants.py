@@ -10,7 +10,8 @@ from paper_2307_05683_amd.ensemble import Ensemble
 
 pytestmark = pytest.mark.gpu
 
-LAYOUTS = [dict(packing="auto"), dict(packing="pair"), dict(packing="split"), dict(packing="auto", coords="jacobi")]
+LAYOUTS = [dict(packing="auto"), dict(packing="pair"), dict(packing="split"), dict(packing="serial"),
+           dict(packing="auto", coords="jacobi")]
 
 
 @pytest.mark.parametrize("opts", LAYOUTS)

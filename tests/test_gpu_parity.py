@@ -113,7 +113,7 @@ def test_keep_unsynchronized_is_bitwise_reproducible():
     a.close(); b.close()
 
 
-@pytest.mark.parametrize("packing", ["auto", "pair", "split"])
+@pytest.mark.parametrize("packing", ["auto", "pair", "split", "serial"])
 def test_graph_replay_matches_direct_launches_bitwise(packing):
     """Replays of the captured chunk graph (with the program's own launches
     and synchronizations between them) equal direct launches bit for bit."""
@@ -131,7 +131,7 @@ def test_graph_replay_matches_direct_launches_bitwise(packing):
     a.close(); b.close()
 
 
-@pytest.mark.parametrize("packing", ["auto", "pair", "split"])
+@pytest.mark.parametrize("packing", ["auto", "pair", "split", "serial"])
 def test_chunk_length_does_not_change_results(packing):
     """The state goes to memory and back between launches without loss, so
     the steps per launch do not change a single bit."""
@@ -276,7 +276,8 @@ def oracle_energy_worst(gr_c):
     return _ORACLE_WORST[gr_c]
 
 
-@pytest.mark.parametrize("packing,gr_c", [("auto", 0.0), ("pair", 0.0), ("split", 0.0), ("pair", 10065.0)])
+@pytest.mark.parametrize("packing,gr_c", [("auto", 0.0), ("pair", 0.0), ("split", 0.0), ("serial", 0.0),
+                                         ("pair", 10065.0), ("serial", 10065.0)])
 def test_energy_error_statistics_match_oracle(packing, gr_c):
     """Over a longer run the per-system maximum relative energy error of the
     GPU path matches the oracle's (ratio within [0.5, 2] for >= 95% of the
@@ -332,10 +333,11 @@ def test_large_gr_full_size_sampled():
     assert eq < TOL and ev < TOL, (eq, ev)
 
 
-@pytest.mark.parametrize("packing", ["auto", "pair", "split"])
+@pytest.mark.parametrize("packing", ["auto", "pair", "split", "serial"])
 def test_million_systems_tiled(packing):
     """2^20 eight-planet systems (one planet per lane: 8.4 million lanes,
-    131072 wavefronts; pair: 65536; split: 262144): the 4096 distinct systems
+    131072 wavefronts; pair: 65536; split: 262144; one lane per system: 16384):
+    the 4096 distinct systems
     of the uniform workload tiled 256 times.  Systems are independent, so
     every copy must end bitwise equal to the first, and sampled ones match
     the oracle."""

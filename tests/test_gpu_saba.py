@@ -50,14 +50,14 @@ def test_packings_and_exchanges(packing, exchange):
 
 
 @pytest.mark.parametrize("scheme", ["saba2", "saba3", "saba4"])
-@pytest.mark.parametrize("packing", ["pair", "split"])
-def test_pair_and_split_layouts(packing, scheme):
+@pytest.mark.parametrize("packing", ["pair", "split", "serial"])
+def test_pair_split_and_serial_layouts(packing, scheme):
     s = inputs.make_systems(45, 97, n_planets=None, n_range=(1, 8), dt_mode="u15_30")
     check(s, 1000, scheme, "dhc", packing=packing)
 
 
-@pytest.mark.parametrize("packing", ["pair", "split"])
-def test_pair_and_split_few_steps_and_outputs(packing):
+@pytest.mark.parametrize("packing", ["pair", "split", "serial"])
+def test_pair_split_and_serial_few_steps_and_outputs(packing):
     s = inputs.make_systems(20, 98, n_planets=None, n_range=(1, 8))
     for n in (1, 2, 5):
         check(s, n, "saba3", "dhc", tol=1e-14, packing=packing)
