@@ -91,7 +91,7 @@ enum {
                         wavefronts than the GPU has SIMDs); DHC only */
   WH_PACK_SERIAL = 4 /* one lane per system: the storage of WH_PACK_G8, but one thread runs all planets of
                         a system (every pair visited once, no cross-lane traffic; 64 systems per wave, for
-                        very large ensembles); DHC only, no reverse mode */
+                        very large ensembles); DHC only */
 };
 
 /* Partner exchange of the interaction kick inside a lane group. */
@@ -206,7 +206,7 @@ int64_t wh_steps_done(const wh_ctx* ctx);
  * tape holds two segment buffers, so that segment k - 1 is recorded while
  * segment k is swept.  wh_tape_bytes gives the size: 96 B per lane slot per
  * checkpoint plus 2 x 80 B per lane slot and step of a segment.  Contexts in
- * DHC with WH_DKD (any packing but WH_PACK_SERIAL); other contexts get WH_ESTATE. */
+ * DHC with WH_DKD (any packing); other contexts get WH_ESTATE. */
 size_t wh_tape_bytes(const wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every);
 wh_status wh_forward_ckpt(wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every, void* tape, size_t tape_bytes,
                           hipStream_t stream);

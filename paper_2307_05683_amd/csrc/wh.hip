@@ -653,23 +653,29 @@ template <int NP> __device__ __forceinline__ void serial_put(SerialState<NP>& S,
 }
 
 // Kepler drift K(tau) of one planet; the diagnostics count the system's own
-// planets only.
-__device__ __forceinline__ void serial_drift(Lane& L, double mu, double tau, bool own, KepDiag& dg) {
+// planets only.  Returns the anomaly X.
+__device__ __forceinline__ double serial_drift(Lane& L, double mu, double tau, bool own, KepDiag& dg) {
   KepDiag d{0.0, 1.0e300};
-  drift(L, mu, tau, d);
+  const double X = drift(L, mu, tau, d);
   if (own) {
     dg.zmax = fmax(dg.zmax, d.zmax);
     dg.bmin = fmin(dg.bmin, d.bmin);
   }
+  return X;
 }
 
 // J(ta) [I + GR](ti) J(tc) of one system (the operations of kick_block on
 // every planet), then, if do_drift, the next drift K(tau) of each planet
-// right after its renormalization.
-template <int NP, bool GR>
+// right after its renormalization.  REC: the velocities after the kick go to
+// vk[r * ns + i] (r = 0..2), as the adjoint's tape keeps them.  Contraction
+// is off here so that the recording instantiation (whose extra stores would
+// otherwise let the compiler fuse different products) rounds exactly as the
+// step kernel does.
+template <int NP, bool GR, bool REC = false>
 __device__ __forceinline__ void serial_kick_drift(SerialState<NP>& S, double* cl, int n, double m0, double inv_m0,
                                                   double kg, double ta, double ti, double tc, double tau,
-                                                  bool do_drift, KepDiag& dg) {
+                                                  bool do_drift, KepDiag& dg, double* vk = nullptr, int ns = 0) {
+#pragma clang fp contract(off)
   double qx[NP], qy[NP], qz[NP], ax[NP], ay[NP], az[NP];
   double dqx = 0.0, dqy = 0.0, dqz = 0.0;
   if (GR) {
@@ -711,6 +717,11 @@ __device__ __forceinline__ void serial_kick_drift(SerialState<NP>& S, double* cl
       ax[i] += gx; ay[i] += gy; az[i] += gz;
     }
     ax[i] *= ti; ay[i] *= ti; az[i] *= ti;   // now the velocity increments
+    if (REC) {
+      vk[i] = S.vx[i] + ax[i];
+      vk[ns + i] = S.vy[i] + ay[i];
+      vk[2 * ns + i] = S.vz[i] + az[i];
+    }
     sx = fma(S.m[i], S.vx[i] + ax[i], sx);
     sy = fma(S.m[i], S.vy[i] + ay[i], sy);
     sz = fma(S.m[i], S.vz[i] + az[i], sz);
@@ -1439,6 +1450,104 @@ template <bool GR, bool SPLIT> __global__ __launch_bounds__(256) void k_adj_segm
     else if (wave < p.w2) adj_record_lane<2, GR>(q, slot, lane);
     else if (wave < p.w4) adj_record_lane<4, GR>(q, slot, lane);
     else adj_record_lane<8, GR>(q, slot, lane);
+  }
+}
+
+// The one-lane-per-system packing keeps the G8 storage, so its reverse sweep
+// is the G8 layout's; the recording runs the serial forward step (the same
+// arithmetic as k_step_serial, so the recomputed segment equals the forward
+// run bit for bit) and writes the tape rows of every slot of the group.
+// Slots the wave's body does not integrate (beyond its largest planet count,
+// or an empty group) never change: their rows hold the stored state, X = 0
+// and the velocity, finite values that the zero masses keep out of every sum.
+__device__ __forceinline__ void record_static(const AdjParams& q, int base, int from) {
+  const int ns = q.sp.ns;
+  for (int i = from; i < 8; ++i) {
+    const int slot = base + i;
+    double v[6];
+    for (int r = 0; r < 6; ++r) v[r] = q.ck_rec[r * ns + slot];
+    for (int s = 0; s < q.n_rec; ++s) {
+      double* row = q.tape_rec + (size_t)s * TAPE_ROWS * ns + slot;
+      for (int r = 0; r < 6; ++r) row[r * ns] = v[r];
+      row[6 * ns] = 0.0;
+      for (int r = 0; r < 3; ++r) row[(7 + r) * ns] = v[3 + r];
+    }
+  }
+}
+
+template <int NP, bool GR>
+__device__ void adj_record_serial(const AdjParams& q, int base, int n, double* cl) {
+  const StepParams& p = q.sp;
+  const int ns = p.ns;
+  SerialState<NP> S;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const int slot = base + i;
+    S.qx[i] = q.ck_rec[slot]; S.qy[i] = q.ck_rec[ns + slot]; S.qz[i] = q.ck_rec[2 * ns + slot];
+    S.vx[i] = q.ck_rec[3 * ns + slot]; S.vy[i] = q.ck_rec[4 * ns + slot]; S.vz[i] = q.ck_rec[5 * ns + slot];
+    S.m[i] = p.st[6 * ns + slot];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) comp_at(cl, k, i) = q.ck_rec[(6 + k) * ns + slot];
+  }
+  const double dt = p.dts[base], h = 0.5 * dt;
+  const double m0 = p.m0s[base];
+  const double inv_m0 = 1.0 / m0;
+  const double kg = GR ? p.kgr * m0 * m0 : 0.0;
+  KepDiag dg{0.0, 1.0e300};
+  double tk = q.rec_first_synced ? h : dt;
+  for (int s = 0; s < q.n_rec; ++s) {
+    double* row = q.tape_rec + (size_t)s * TAPE_ROWS * ns + base;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      row[i] = S.qx[i]; row[ns + i] = S.qy[i]; row[2 * ns + i] = S.qz[i];
+      row[3 * ns + i] = S.vx[i]; row[4 * ns + i] = S.vy[i]; row[5 * ns + i] = S.vz[i];
+      Lane L = serial_get(S, cl, i);
+      row[6 * ns + i] = serial_drift(L, m0, tk, i < n, dg);
+      serial_put(S, cl, i, L);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    tk = dt;
+    serial_kick_drift<NP, GR, true>(S, cl, n, m0, inv_m0, kg, h, dt, h, 0.0, false, dg, row + 7 * ns, ns);
+  }
+  record_static(q, base, NP);
+}
+
+// Waves [0, sweep_waves) sweep (G8 waves, one planet per lane); the others
+// record, one thread per 8-slot group, with SERIAL_LDS_PER_WAVE doubles of
+// dynamic LDS per wave (one-wave workgroups).
+template <bool GR> __global__ __launch_bounds__(64) void k_adj_segment_serial(AdjParams q) {
+  extern __shared__ double serial_lds[];
+  const StepParams& p = q.sp;
+  const int lane = threadIdx.x;
+  const int wave = blockIdx.x;
+  if (wave < q.sweep_waves) {
+    if (wave < p.w8) adj_sweep_lane<8, GR>(q, wave * 64 + lane, lane);
+    return;
+  }
+  const int g = (wave - q.sweep_waves) * 64 + lane;
+  if (g >= p.w8 * 8) return;
+  const int base = g * 8;
+  if (p.slot_sys[base] < 0) {
+    record_static(q, base, 0);
+    return;
+  }
+  double* cl = serial_lds + lane;
+  int n = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) n += p.slot_pl[base + i] >= 0;
+  int nw = 1;
+#pragma unroll
+  for (int k = 2; k <= 8; ++k)
+    if (__ballot(n >= k) != 0) nw = k;
+  switch (nw) {
+    case 1: adj_record_serial<1, GR>(q, base, n, cl); break;
+    case 2: adj_record_serial<2, GR>(q, base, n, cl); break;
+    case 3: adj_record_serial<3, GR>(q, base, n, cl); break;
+    case 4: adj_record_serial<4, GR>(q, base, n, cl); break;
+    case 5: adj_record_serial<5, GR>(q, base, n, cl); break;
+    case 6: adj_record_serial<6, GR>(q, base, n, cl); break;
+    case 7: adj_record_serial<7, GR>(q, base, n, cl); break;
+    default: adj_record_serial<8, GR>(q, base, n, cl); break;
   }
 }
 
@@ -2336,7 +2445,6 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
   if (n_steps < 0 || ckpt_every < 1 || ckpt_every > (1 << 30)) return fail(WH_EINVAL, "bad n_steps or ckpt_every");
   if (((uintptr_t)tape & 255) != 0) return fail(WH_EINVAL, "tape must be 256-byte aligned");
   if (c->cfg.scheme != WH_DKD) return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD");
-  if (c->P.serial) return fail(WH_ESTATE, "reverse mode is not implemented in the one-lane-per-system packing");
   if (c->cfg.coords != WH_COORDS_DHC)
     return fail(WH_ESTATE, "reverse mode is implemented in democratic heliocentric coordinates");
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
@@ -2406,6 +2514,15 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
   };
   auto launch = [&](int sweep_waves, int record_waves) {
     q.sweep_waves = sweep_waves;
+    if (c->P.serial) {
+      // recording: one thread per 8-slot group, i.e. an eighth of the waves
+      const int rec = record_waves > 0 ? (record_waves * 8 + 63) / 64 : 0;
+      const dim3 grid(sweep_waves + rec), block(64);
+      const size_t smem = SERIAL_LDS_PER_WAVE * sizeof(double);
+      if (gr) hipLaunchKernelGGL(k_adj_segment_serial<true>, grid, block, smem, stream, q);
+      else hipLaunchKernelGGL(k_adj_segment_serial<false>, grid, block, smem, stream, q);
+      return;
+    }
     const dim3 grid(sweep_waves + record_waves), block(64);
     if (c->P.pair) {
       if (gr) hipLaunchKernelGGL(k_adj_segment_pair<true>, grid, block, 0, stream, q);

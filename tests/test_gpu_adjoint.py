@@ -49,7 +49,9 @@ def random_dirs(s, seed):
                                                          (200, 64, 0.0, "split"), (200, 64, 40.0, "split"),
                                                          (1, 1, 0.0, "split"), (97, 10, 10065.0, "split"),
                                                          (200, 64, 0.0, "pair"), (200, 64, 40.0, "pair"),
-                                                         (1, 1, 0.0, "pair"), (97, 10, 10065.0, "pair")])
+                                                         (1, 1, 0.0, "pair"), (97, 10, 10065.0, "pair"),
+                                                         (200, 64, 0.0, "serial"), (200, 64, 40.0, "serial"),
+                                                         (1, 1, 0.0, "serial"), (97, 10, 10065.0, "serial")])
 def test_dot_product_vs_oracle_tangent(n_steps, every, gr_c, packing):
     s = inputs.make_systems(16, 31, n_planets=None, n_range=(1, 8))
     print("case: n_steps=%d every=%d gr_c=%g packing=%s" % (n_steps, every, gr_c, packing), flush=True)
@@ -68,7 +70,7 @@ def test_dot_product_vs_oracle_tangent(n_steps, every, gr_c, packing):
     assert rel.max() < 1e-9
 
 
-@pytest.mark.parametrize("packing", ["auto", "split", "pair"])
+@pytest.mark.parametrize("packing", ["auto", "split", "pair", "serial"])
 @pytest.mark.parametrize("which", ["m", "m0"])
 @pytest.mark.parametrize("gr_c", [0.0, 40.0])
 def test_mass_gradients_vs_oracle_tangent(which, gr_c, packing):
@@ -92,7 +94,7 @@ def test_mass_gradients_vs_oracle_tangent(which, gr_c, packing):
     assert rel.max() < 1e-9
 
 
-@pytest.mark.parametrize("packing", ["auto", "split", "pair"])
+@pytest.mark.parametrize("packing", ["auto", "split", "pair", "serial"])
 def test_zero_steps_is_identity(packing):
     s = inputs.make_systems(5, 32, n_planets=None, n_range=(1, 8))
     rng = np.random.default_rng(1)
@@ -103,7 +105,7 @@ def test_zero_steps_is_identity(packing):
     assert not gm.any() and not gm0.any()
 
 
-@pytest.mark.parametrize("packing", ["auto", "split", "pair"])
+@pytest.mark.parametrize("packing", ["auto", "split", "pair", "serial"])
 @pytest.mark.parametrize("gr_c", [0.0, 10065.0])
 def test_checkpoint_interval_leaves_gradients_bitwise_equal(gr_c, packing):
     """Restarting from a checkpoint reproduces the forward run bitwise, so the
@@ -125,7 +127,7 @@ def loss_np(Q, s):
     return (Q ** 2 * live(s)[:, :, None]).sum((1, 2))
 
 
-@pytest.mark.parametrize("packing", ["auto", "split", "pair"])
+@pytest.mark.parametrize("packing", ["auto", "split", "pair", "serial"])
 def test_gradients_match_central_differences(packing):
     """Loss L = sum_i |Q_i(T)|^2 per system; perturb one input coordinate in
     every system at once (systems are independent) with h = 1e-7 relative."""
@@ -206,14 +208,15 @@ def test_tape_validation():
         e.adjoint(np.zeros((4, 8, 3)), np.zeros((4, 8, 3)))
     assert ei.value.code == _lib.WH_ESTATE
     e.close()
-    for kw in (dict(scheme="kdk"), dict(packing="pair", scheme="kdk"), dict(coords="jacobi")):
+    for kw in (dict(scheme="kdk"), dict(packing="pair", scheme="kdk"), dict(packing="serial", scheme="kdk"),
+               dict(coords="jacobi")):
         k = Ensemble.from_systems(s, **kw)
         with pytest.raises(_lib.WHError):
             k.forward_ckpt(10, 5)
         k.close()
 
 
-@pytest.mark.parametrize("packing", ["auto", "split", "pair"])
+@pytest.mark.parametrize("packing", ["auto", "split", "pair", "serial"])
 def test_adjoint_workload_sampled(packing):
     """The adjoint workload shape (1024 eight-planet systems, checkpoints
     every 1000 steps), shortened to 3000 steps: sampled systems pass the

@@ -148,9 +148,11 @@ def test_unsupported_combinations_rejected():
     for kw in (dict(coords="jacobi"), dict(scheme="saba2", gr_c=10065.0)):
         with pytest.raises(_lib.WHError):
             Ensemble.from_systems(s, packing="serial", **kw)
-    e = Ensemble.from_systems(s, packing="serial")
-    with pytest.raises(_lib.WHError):        # no reverse mode in this packing
+    e = Ensemble.from_systems(s, packing="serial", scheme="kdk")
+    with pytest.raises(_lib.WHError):        # reverse mode runs drift-kick-drift
         e.forward_ckpt(10, 5)
+    e.close()
+    e = Ensemble.from_systems(s, packing="serial")
     with pytest.raises(_lib.WHError):        # the per-size path is the G8 packing's
         e.step_plain(1)
     e.close()
@@ -177,3 +179,36 @@ def test_full_size_sampled():
     sub = s.subset(idx)
     Qo, Vo = oracle.integrate(sub, 1000, gr_c=inputs.GR_C)
     assert rel(sub, Qg[idx], Vg[idx], Qo, Vo) < TOL
+
+
+def test_reverse_mode_matches_one_planet_per_lane():
+    """The serial packing records its segments with its own step and sweeps
+    them with the G8 layout's adjoint: its gradients agree with those of the
+    one-planet-per-lane packing to rounding (the two forward runs differ only
+    in summation order)."""
+    s = inputs.make_systems(40, 319, n_planets=None, n_range=(1, 8))
+    rng = np.random.default_rng(3)
+    gQ_T = rng.normal(size=(s.S, 8, 3)) * live(s)[:, :, None]
+    gV_T = rng.normal(size=(s.S, 8, 3)) * live(s)[:, :, None]
+    out = {}
+    for packing in ("serial", "g8"):
+        e = Ensemble.from_systems(s, packing=packing, gr_c=inputs.GR_C)
+        e.forward_ckpt(300, 64)
+        out[packing] = [x.cpu().numpy() for x in e.adjoint(gQ_T, gV_T)]
+        e.close()
+    for a, b in zip(out["serial"], out["g8"]):
+        scale = np.abs(b).max()
+        assert np.abs(a - b).max() <= 1e-10 * scale
+
+
+def test_forward_ckpt_equals_step():
+    # the checkpointed forward run is the step kernel's run, bit for bit
+    s = inputs.make_systems(30, 320, n_planets=None, n_range=(1, 8))
+    a = Ensemble.from_systems(s, packing="serial")
+    a.forward_ckpt(250, 60)
+    b = Ensemble.from_systems(s, packing="serial")
+    b.step(250)
+    Qa, Va = a.state()
+    Qb, Vb = b.state()
+    assert torch.equal(Qa, Qb) and torch.equal(Va, Vb)
+    a.close(); b.close()
