@@ -206,7 +206,9 @@ int64_t wh_steps_done(const wh_ctx* ctx);
  * tape holds two segment buffers, so that segment k - 1 is recorded while
  * segment k is swept.  wh_tape_bytes gives the size: 96 B per lane slot per
  * checkpoint plus 2 x 80 B per lane slot and step of a segment.  Contexts in
- * DHC with WH_DKD (any packing); other contexts get WH_ESTATE. */
+ * DHC with WH_DKD or WH_KDK (any packing); other contexts get WH_ESTATE.  With WH_KDK a
+ * step of the tape is the kick block followed by the drift, and the synchronized
+ * output's pending half kick is differentiated too. */
 size_t wh_tape_bytes(const wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every);
 wh_status wh_forward_ckpt(wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every, void* tape, size_t tape_bytes,
                           hipStream_t stream);

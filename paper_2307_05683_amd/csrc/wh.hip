@@ -667,14 +667,16 @@ __device__ __forceinline__ double serial_drift(Lane& L, double mu, double tau, b
 // J(ta) [I + GR](ti) J(tc) of one system (the operations of kick_block on
 // every planet), then, if do_drift, the next drift K(tau) of each planet
 // right after its renormalization.  REC: the velocities after the kick go to
-// vk[r * ns + i] (r = 0..2), as the adjoint's tape keeps them.  Contraction
+// vk[r * ns + i] (r = 0..2), as the adjoint's tape keeps them, and, if xrec
+// is given, the drift's anomaly to xrec[i].  Contraction
 // is off here so that the recording instantiation (whose extra stores would
 // otherwise let the compiler fuse different products) rounds exactly as the
 // step kernel does.
 template <int NP, bool GR, bool REC = false>
 __device__ __forceinline__ void serial_kick_drift(SerialState<NP>& S, double* cl, int n, double m0, double inv_m0,
                                                   double kg, double ta, double ti, double tc, double tau,
-                                                  bool do_drift, KepDiag& dg, double* vk = nullptr, int ns = 0) {
+                                                  bool do_drift, KepDiag& dg, double* vk = nullptr, int ns = 0,
+                                                  double* xrec = nullptr) {
 #pragma clang fp contract(off)
   double qx[NP], qy[NP], qz[NP], ax[NP], ay[NP], az[NP];
   double dqx = 0.0, dqy = 0.0, dqz = 0.0;
@@ -734,7 +736,10 @@ __device__ __forceinline__ void serial_kick_drift(SerialState<NP>& S, double* cl
     L.cvx += ax[i]; L.cvy += ay[i]; L.cvz += az[i];
     L.cqx += k2 * sx; L.cqy += k2 * sy; L.cqz += k2 * sz;
     renorm_all(L);
-    if (do_drift) serial_drift(L, m0, tau, i < n, dg);
+    if (do_drift) {
+      const double X = serial_drift(L, m0, tau, i < n, dg);
+      if (REC && xrec) xrec[i] = X;
+    }
     serial_put(S, cl, i, L);
     // one planet at a time: hoisting the next planets' loads and solves
     // would overflow the registers
@@ -1223,9 +1228,40 @@ __device__ __forceinline__ void interaction_vjp(const Exch<G, 1>& ex, double qx,
   else interaction_vjp_dpp<G>(ex.t, qx, qy, qz, m, tau, gvx, gvy, gvz, gqx, gqy, gqz, gm);
 }
 
-// Forward recompute of a segment from its checkpoint, writing its tape.  Same
-// arithmetic as the step kernel (DPP exchange).
+// Adjoint of the kick block J(ta) [I + GR](ti) J(tc) (J(ta + tc) I(ti)
+// without GR) at the forward point (Q0, V0), with vk the velocity after the
+// kick: a holds dL/d(output) and receives dL/d(input).
 template <int G, bool GR>
+__device__ __forceinline__ void kick_block_vjp(Grad& a, const Exch<G, 1>& ex, double m, double m0, double inv_m0,
+                                               double kg, double q0x, double q0y, double q0z, double v0x, double v0y,
+                                               double v0z, double vkx, double vky, double vkz, double ta, double ti,
+                                               double tc, bool leader) {
+  if (GR) {
+    double s1x, s1y, s1z, s3x, s3y, s3z;
+    group_momentum<G>(m, v0x, v0y, v0z, s1x, s1y, s1z);
+    const double k1 = ta * inv_m0;
+    const double q2x = q0x + k1 * s1x, q2y = q0y + k1 * s1y, q2z = q0z + k1 * s1z;
+    group_momentum<G>(m, vkx, vky, vkz, s3x, s3y, s3z);
+    jump_vjp<G>(a, m, vkx, vky, vkz, tc * inv_m0, m0, s3x, s3y, s3z, leader);
+    double gmu = 0.0;
+    interaction_vjp<G>(ex, q2x, q2y, q2z, m, ti, a.vx, a.vy, a.vz, a.qx, a.qy, a.qz, a.m);
+    gr_vjp(q2x, q2y, q2z, kg, m0, ti, a.vx, a.vy, a.vz, a.qx, a.qy, a.qz, gmu);
+    a.m0 += gmu;
+    jump_vjp<G>(a, m, v0x, v0y, v0z, k1, m0, s1x, s1y, s1z, leader);
+  } else {
+    double s2x, s2y, s2z;
+    group_momentum<G>(m, vkx, vky, vkz, s2x, s2y, s2z);
+    jump_vjp<G>(a, m, vkx, vky, vkz, (ta + tc) * inv_m0, m0, s2x, s2y, s2z, leader);
+    interaction_vjp<G>(ex, q0x, q0y, q0z, m, ti, a.vx, a.vy, a.vz, a.qx, a.qy, a.qz, a.m);
+  }
+}
+
+// Forward recompute of a segment from its checkpoint, writing its tape.  Same
+// arithmetic as the step kernel (DPP exchange).  Per step the tape holds the
+// state at the start of the step, the anomaly X of its drift and the
+// velocity after its kick; with KDK the step is the kick block followed by
+// the drift.
+template <int G, bool GR, bool KDK = false>
 __device__ void adj_record_lane(const AdjParams& q, int slot, int lane) {
   const StepParams& p = q.sp;
   const int ns = p.ns;
@@ -1240,6 +1276,22 @@ __device__ void adj_record_lane(const AdjParams& q, int slot, int lane) {
   const double inv_m0 = 1.0 / L.m0;
   const double kg = GR ? p.kgr * L.m0 * L.m0 : 0.0;
   KepDiag dg{0.0, 1.0e300};
+  if constexpr (KDK) {
+    double ta = q.rec_first_synced ? 0.0 : h;
+    double ti = q.rec_first_synced ? h : dt;
+    for (int s = 0; s < q.n_rec; ++s) {
+      double* row = q.tape_rec + (size_t)s * TAPE_ROWS * ns + slot;
+      row[0] = L.qx; row[ns] = L.qy; row[2 * ns] = L.qz;
+      row[3 * ns] = L.vx; row[4 * ns] = L.vy; row[5 * ns] = L.vz;
+      double vkx, vky, vkz;
+      kick_block<G, GR, 1>(L, ex, inv_m0, kg, ta, ti, h, vkx, vky, vkz);
+      row[7 * ns] = vkx; row[8 * ns] = vky; row[9 * ns] = vkz;
+      ta = h;
+      ti = dt;
+      row[6 * ns] = drift(L, L.m0, dt, dg);
+    }
+    return;
+  }
   double tk = q.rec_first_synced ? h : dt;
   for (int s = 0; s < q.n_rec; ++s) {
     double* row = q.tape_rec + (size_t)s * TAPE_ROWS * ns + slot;
@@ -1255,7 +1307,7 @@ __device__ void adj_record_lane(const AdjParams& q, int slot, int lane) {
 
 // Reverse sweep of a recorded segment: the adjoint state is carried back
 // through the transposed Jacobian of every sub-step.
-template <int G, bool GR>
+template <int G, bool GR, bool KDK = false>
 __device__ void adj_sweep_lane(const AdjParams& q, int slot, int lane) {
   const StepParams& p = q.sp;
   const int ns = p.ns;
@@ -1270,6 +1322,41 @@ __device__ void adj_sweep_lane(const AdjParams& q, int slot, int lane) {
   // the lane(s) of planet 0 add the star-mass terms of the jump (in the
   // split layout both copies, so that the copies keep equal bits)
   const bool leader = G == G_SPLIT ? (lane & 14) == 0 : (lane & (G - 1)) == 0;
+  if constexpr (KDK) {
+    // step = kick block (ta, ti, h) then K(dt): the drift's adjoint first
+    for (int s = q.n_seg - 1; s >= 0; --s) {
+      const double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
+      const double q0x = row[0], q0y = row[ns], q0z = row[2 * ns];
+      const double v0x = row[3 * ns], v0y = row[4 * ns], v0z = row[5 * ns];
+      const double X = row[6 * ns];
+      const double vkx = row[7 * ns], vky = row[8 * ns], vkz = row[9 * ns];
+      const bool first = q.first_synced && s == 0;
+      const double ta = first ? 0.0 : h, ti = first ? h : dt;
+      // the drift's starting point: positions after both jumps
+      double s2x, s2y, s2z, q3x, q3y, q3z;
+      group_momentum<G>(m, vkx, vky, vkz, s2x, s2y, s2z);
+      if (GR) {
+        double s1x, s1y, s1z;
+        group_momentum<G>(m, v0x, v0y, v0z, s1x, s1y, s1z);
+        const double k1 = ta * inv_m0, k2 = h * inv_m0;
+        q3x = (q0x + k1 * s1x) + k2 * s2x;
+        q3y = (q0y + k1 * s1y) + k2 * s2y;
+        q3z = (q0z + k1 * s1z) + k2 * s2z;
+      } else {
+        const double k2 = (ta + h) * inv_m0;
+        q3x = q0x + k2 * s2x; q3y = q0y + k2 * s2y; q3z = q0z + k2 * s2z;
+      }
+      KepFwd k;
+      kepler_at_X(q3x, q3y, q3z, vkx, vky, vkz, m0, dt, X, k);
+      double gmu = 0.0;
+      kepler_vjp(k, q3x, q3y, q3z, vkx, vky, vkz, m0, a.qx, a.qy, a.qz, a.vx, a.vy, a.vz, gmu);
+      a.m0 += gmu;
+      kick_block_vjp<G, GR>(a, ex, m, m0, inv_m0, kg, q0x, q0y, q0z, v0x, v0y, v0z, vkx, vky, vkz, ta, ti, h,
+                            leader);
+    }
+    store_grad(q.grad, ns, slot, a);
+    return;
+  }
   for (int s = q.n_seg - 1; s >= 0; --s) {
     const double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
     double q0x = row[0], q0y = row[ns], q0z = row[2 * ns];
@@ -1309,9 +1396,46 @@ __device__ void adj_sweep_lane(const AdjParams& q, int slot, int lane) {
   store_grad(q.grad, ns, slot, a);
 }
 
+// Adjoint of the kick block in the pair layout (as kick_block_vjp, for both
+// slots of the lane).
+template <int G, bool GR>
+__device__ __forceinline__ void kick_block_vjp_pair(Grad& a, Grad& b, const PairMass& pm, double ma, double mb,
+                                                    double m0, double inv_m0, double kg, const double q0a[3],
+                                                    const double v0a[3], const double q0b[3], const double v0b[3],
+                                                    const double vka[3], const double vkb[3], double ta, double ti,
+                                                    double tc, bool leader) {
+  double gqa[3], gqb[3];
+  if (GR) {
+    double s1[3], s3[3], q2a[3], q2b[3];
+    pair_momentum<G>(ma, v0a[0], v0a[1], v0a[2], mb, v0b[0], v0b[1], v0b[2], s1[0], s1[1], s1[2]);
+    const double k1 = ta * inv_m0;
+    for (int k = 0; k < 3; ++k) { q2a[k] = q0a[k] + k1 * s1[k]; q2b[k] = q0b[k] + k1 * s1[k]; }
+    pair_momentum<G>(ma, vka[0], vka[1], vka[2], mb, vkb[0], vkb[1], vkb[2], s3[0], s3[1], s3[2]);
+    jump_vjp_pair<G>(a, b, ma, mb, vka, vkb, tc * inv_m0, m0, s3, leader);
+    const double gva[3] = {a.vx, a.vy, a.vz}, gvb[3] = {b.vx, b.vy, b.vz};
+    gqa[0] = a.qx; gqa[1] = a.qy; gqa[2] = a.qz; gqb[0] = b.qx; gqb[1] = b.qy; gqb[2] = b.qz;
+    interaction_vjp_pair<G>(pm, ma, mb, q2a, q2b, gva, gvb, ti, gqa, gqb, a.m, b.m);
+    double gmu_a = 0.0, gmu_b = 0.0;
+    gr_vjp(q2a[0], q2a[1], q2a[2], kg, m0, ti, gva[0], gva[1], gva[2], gqa[0], gqa[1], gqa[2], gmu_a);
+    gr_vjp(q2b[0], q2b[1], q2b[2], kg, m0, ti, gvb[0], gvb[1], gvb[2], gqb[0], gqb[1], gqb[2], gmu_b);
+    a.qx = gqa[0]; a.qy = gqa[1]; a.qz = gqa[2]; b.qx = gqb[0]; b.qy = gqb[1]; b.qz = gqb[2];
+    a.m0 += gmu_a;
+    b.m0 += gmu_b;
+    jump_vjp_pair<G>(a, b, ma, mb, v0a, v0b, k1, m0, s1, leader);
+  } else {
+    double s2[3];
+    pair_momentum<G>(ma, vka[0], vka[1], vka[2], mb, vkb[0], vkb[1], vkb[2], s2[0], s2[1], s2[2]);
+    jump_vjp_pair<G>(a, b, ma, mb, vka, vkb, (ta + tc) * inv_m0, m0, s2, leader);
+    const double gva[3] = {a.vx, a.vy, a.vz}, gvb[3] = {b.vx, b.vy, b.vz};
+    gqa[0] = a.qx; gqa[1] = a.qy; gqa[2] = a.qz; gqb[0] = b.qx; gqb[1] = b.qy; gqb[2] = b.qz;
+    interaction_vjp_pair<G>(pm, ma, mb, q0a, q0b, gva, gvb, ti, gqa, gqb, a.m, b.m);
+    a.qx = gqa[0]; a.qy = gqa[1]; a.qz = gqa[2]; b.qx = gqb[0]; b.qy = gqb[1]; b.qz = gqb[2];
+  }
+}
+
 // The same two roles in the pair layout: lane l of wave w holds slots
 // 128 w + l (a) and 128 w + 64 + l (b).
-template <int G, bool GR>
+template <int G, bool GR, bool KDK = false>
 __device__ void adj_record_pair(const AdjParams& q, int sa, int lane) {
   const StepParams& p = q.sp;
   const int ns = p.ns, sb = sa + 64;
@@ -1325,6 +1449,25 @@ __device__ void adj_record_pair(const AdjParams& q, int sa, int lane) {
   const double inv_m0 = 1.0 / A.m0;
   const double kg = GR ? p.kgr * A.m0 * A.m0 : 0.0;
   KepDiag dga{0.0, 1.0e300}, dgb{0.0, 1.0e300};
+  if constexpr (KDK) {
+    double ta = q.rec_first_synced ? 0.0 : h;
+    double ti = q.rec_first_synced ? h : dt;
+    for (int s = 0; s < q.n_rec; ++s) {
+      double* ra = q.tape_rec + (size_t)s * TAPE_ROWS * ns + sa;
+      double* rb = ra + 64;
+      ra[0] = A.qx; ra[ns] = A.qy; ra[2 * ns] = A.qz; ra[3 * ns] = A.vx; ra[4 * ns] = A.vy; ra[5 * ns] = A.vz;
+      rb[0] = B.qx; rb[ns] = B.qy; rb[2 * ns] = B.qz; rb[3 * ns] = B.vx; rb[4 * ns] = B.vy; rb[5 * ns] = B.vz;
+      double vka[3], vkb[3];
+      kick_block_pair<G, GR>(A, B, pm, inv_m0, kg, ta, ti, h, vka, vkb);
+      ra[7 * ns] = vka[0]; ra[8 * ns] = vka[1]; ra[9 * ns] = vka[2];
+      rb[7 * ns] = vkb[0]; rb[8 * ns] = vkb[1]; rb[9 * ns] = vkb[2];
+      ta = h;
+      ti = dt;
+      ra[6 * ns] = drift(A, A.m0, dt, dga);
+      rb[6 * ns] = drift(B, B.m0, dt, dgb);
+    }
+    return;
+  }
   double tk = q.rec_first_synced ? h : dt;
   for (int s = 0; s < q.n_rec; ++s) {
     double* ra = q.tape_rec + (size_t)s * TAPE_ROWS * ns + sa;
@@ -1341,7 +1484,7 @@ __device__ void adj_record_pair(const AdjParams& q, int sa, int lane) {
   }
 }
 
-template <int G, bool GR>
+template <int G, bool GR, bool KDK = false>
 __device__ void adj_sweep_pair(const AdjParams& q, int sa, int lane) {
   const StepParams& p = q.sp;
   const int ns = p.ns, sb = sa + 64;
@@ -1354,6 +1497,45 @@ __device__ void adj_sweep_pair(const AdjParams& q, int sa, int lane) {
   load_grad(q.grad, ns, sa, a);
   load_grad(q.grad, ns, sb, b);
   const bool leader = (lane & (G - 1)) == 0;
+  if constexpr (KDK) {
+    for (int s = q.n_seg - 1; s >= 0; --s) {
+      const double* ra = q.tape + (size_t)s * TAPE_ROWS * ns + sa;
+      const double* rb = ra + 64;
+      const double q0a[3] = {ra[0], ra[ns], ra[2 * ns]}, v0a[3] = {ra[3 * ns], ra[4 * ns], ra[5 * ns]};
+      const double q0b[3] = {rb[0], rb[ns], rb[2 * ns]}, v0b[3] = {rb[3 * ns], rb[4 * ns], rb[5 * ns]};
+      const double vka[3] = {ra[7 * ns], ra[8 * ns], ra[9 * ns]}, vkb[3] = {rb[7 * ns], rb[8 * ns], rb[9 * ns]};
+      const bool first = q.first_synced && s == 0;
+      const double ta = first ? 0.0 : h, ti = first ? h : dt;
+      double s2[3], q3a[3], q3b[3];
+      pair_momentum<G>(ma, vka[0], vka[1], vka[2], mb, vkb[0], vkb[1], vkb[2], s2[0], s2[1], s2[2]);
+      if (GR) {
+        double s1[3];
+        pair_momentum<G>(ma, v0a[0], v0a[1], v0a[2], mb, v0b[0], v0b[1], v0b[2], s1[0], s1[1], s1[2]);
+        const double k1 = ta * inv_m0, k2 = h * inv_m0;
+        for (int k = 0; k < 3; ++k) {
+          q3a[k] = (q0a[k] + k1 * s1[k]) + k2 * s2[k];
+          q3b[k] = (q0b[k] + k1 * s1[k]) + k2 * s2[k];
+        }
+      } else {
+        const double k2 = (ta + h) * inv_m0;
+        for (int k = 0; k < 3; ++k) { q3a[k] = q0a[k] + k2 * s2[k]; q3b[k] = q0b[k] + k2 * s2[k]; }
+      }
+      KepFwd ka, kb;
+      kepler_at_X(q3a[0], q3a[1], q3a[2], vka[0], vka[1], vka[2], m0, dt, ra[6 * ns], ka);
+      kepler_at_X(q3b[0], q3b[1], q3b[2], vkb[0], vkb[1], vkb[2], m0, dt, rb[6 * ns], kb);
+      double gmu = 0.0;
+      kepler_vjp(ka, q3a[0], q3a[1], q3a[2], vka[0], vka[1], vka[2], m0, a.qx, a.qy, a.qz, a.vx, a.vy, a.vz, gmu);
+      a.m0 += gmu;
+      gmu = 0.0;
+      kepler_vjp(kb, q3b[0], q3b[1], q3b[2], vkb[0], vkb[1], vkb[2], m0, b.qx, b.qy, b.qz, b.vx, b.vy, b.vz, gmu);
+      b.m0 += gmu;
+      kick_block_vjp_pair<G, GR>(a, b, pm, ma, mb, m0, inv_m0, kg, q0a, v0a, q0b, v0b, vka, vkb, ta, ti, h,
+                                 leader);
+    }
+    store_grad(q.grad, ns, sa, a);
+    store_grad(q.grad, ns, sb, b);
+    return;
+  }
   for (int s = q.n_seg - 1; s >= 0; --s) {
     const double* ra = q.tape + (size_t)s * TAPE_ROWS * ns + sa;
     const double* rb = ra + 64;
@@ -1408,7 +1590,7 @@ __device__ void adj_sweep_pair(const AdjParams& q, int sa, int lane) {
   store_grad(q.grad, ns, sb, b);
 }
 
-template <bool GR> __global__ __launch_bounds__(256) void k_adj_segment_pair(AdjParams q) {
+template <bool GR, bool KDK> __global__ __launch_bounds__(256) void k_adj_segment_pair(AdjParams q) {
   const StepParams& p = q.sp;
   const int lane = threadIdx.x & 63;
   int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -1417,19 +1599,19 @@ template <bool GR> __global__ __launch_bounds__(256) void k_adj_segment_pair(Adj
   if (wave >= p.w8) return;
   const int sa = wave * 128 + lane;
   if (sweep) {
-    if (wave < p.w1) adj_sweep_pair<1, GR>(q, sa, lane);
-    else if (wave < p.w2) adj_sweep_pair<2, GR>(q, sa, lane);
-    else adj_sweep_pair<4, GR>(q, sa, lane);
+    if (wave < p.w1) adj_sweep_pair<1, GR, KDK>(q, sa, lane);
+    else if (wave < p.w2) adj_sweep_pair<2, GR, KDK>(q, sa, lane);
+    else adj_sweep_pair<4, GR, KDK>(q, sa, lane);
   } else {
-    if (wave < p.w1) adj_record_pair<1, GR>(q, sa, lane);
-    else if (wave < p.w2) adj_record_pair<2, GR>(q, sa, lane);
-    else adj_record_pair<4, GR>(q, sa, lane);
+    if (wave < p.w1) adj_record_pair<1, GR, KDK>(q, sa, lane);
+    else if (wave < p.w2) adj_record_pair<2, GR, KDK>(q, sa, lane);
+    else adj_record_pair<4, GR, KDK>(q, sa, lane);
   }
 }
 
 // Waves [0, sweep_waves) sweep one segment, the waves after them record the
 // previous segment; each role covers the packing's waves once.
-template <bool GR, bool SPLIT> __global__ __launch_bounds__(256) void k_adj_segment(AdjParams q) {
+template <bool GR, bool SPLIT, bool KDK> __global__ __launch_bounds__(256) void k_adj_segment(AdjParams q) {
   const StepParams& p = q.sp;
   const int lane = threadIdx.x & 63;
   int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -1438,18 +1620,18 @@ template <bool GR, bool SPLIT> __global__ __launch_bounds__(256) void k_adj_segm
   if (wave >= p.w8) return;
   const int slot = wave * 64 + lane;
   if (SPLIT) {
-    if (sweep) adj_sweep_lane<G_SPLIT, GR>(q, slot, lane);
-    else adj_record_lane<G_SPLIT, GR>(q, slot, lane);
+    if (sweep) adj_sweep_lane<G_SPLIT, GR, KDK>(q, slot, lane);
+    else adj_record_lane<G_SPLIT, GR, KDK>(q, slot, lane);
   } else if (sweep) {
-    if (wave < p.w1) adj_sweep_lane<1, GR>(q, slot, lane);
-    else if (wave < p.w2) adj_sweep_lane<2, GR>(q, slot, lane);
-    else if (wave < p.w4) adj_sweep_lane<4, GR>(q, slot, lane);
-    else adj_sweep_lane<8, GR>(q, slot, lane);
+    if (wave < p.w1) adj_sweep_lane<1, GR, KDK>(q, slot, lane);
+    else if (wave < p.w2) adj_sweep_lane<2, GR, KDK>(q, slot, lane);
+    else if (wave < p.w4) adj_sweep_lane<4, GR, KDK>(q, slot, lane);
+    else adj_sweep_lane<8, GR, KDK>(q, slot, lane);
   } else {
-    if (wave < p.w1) adj_record_lane<1, GR>(q, slot, lane);
-    else if (wave < p.w2) adj_record_lane<2, GR>(q, slot, lane);
-    else if (wave < p.w4) adj_record_lane<4, GR>(q, slot, lane);
-    else adj_record_lane<8, GR>(q, slot, lane);
+    if (wave < p.w1) adj_record_lane<1, GR, KDK>(q, slot, lane);
+    else if (wave < p.w2) adj_record_lane<2, GR, KDK>(q, slot, lane);
+    else if (wave < p.w4) adj_record_lane<4, GR, KDK>(q, slot, lane);
+    else adj_record_lane<8, GR, KDK>(q, slot, lane);
   }
 }
 
@@ -1475,7 +1657,7 @@ __device__ __forceinline__ void record_static(const AdjParams& q, int base, int 
   }
 }
 
-template <int NP, bool GR>
+template <int NP, bool GR, bool KDK>
 __device__ void adj_record_serial(const AdjParams& q, int base, int n, double* cl) {
   const StepParams& p = q.sp;
   const int ns = p.ns;
@@ -1494,6 +1676,24 @@ __device__ void adj_record_serial(const AdjParams& q, int base, int n, double* c
   const double inv_m0 = 1.0 / m0;
   const double kg = GR ? p.kgr * m0 * m0 : 0.0;
   KepDiag dg{0.0, 1.0e300};
+  if constexpr (KDK) {
+    double ta = q.rec_first_synced ? 0.0 : h;
+    double ti = q.rec_first_synced ? h : dt;
+    for (int s = 0; s < q.n_rec; ++s) {
+      double* row = q.tape_rec + (size_t)s * TAPE_ROWS * ns + base;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        row[i] = S.qx[i]; row[ns + i] = S.qy[i]; row[2 * ns + i] = S.qz[i];
+        row[3 * ns + i] = S.vx[i]; row[4 * ns + i] = S.vy[i]; row[5 * ns + i] = S.vz[i];
+      }
+      serial_kick_drift<NP, GR, true>(S, cl, n, m0, inv_m0, kg, ta, ti, h, dt, true, dg, row + 7 * ns, ns,
+                                      row + 6 * ns);
+      ta = h;
+      ti = dt;
+    }
+    record_static(q, base, NP);
+    return;
+  }
   double tk = q.rec_first_synced ? h : dt;
   for (int s = 0; s < q.n_rec; ++s) {
     double* row = q.tape_rec + (size_t)s * TAPE_ROWS * ns + base;
@@ -1515,13 +1715,13 @@ __device__ void adj_record_serial(const AdjParams& q, int base, int n, double* c
 // Waves [0, sweep_waves) sweep (G8 waves, one planet per lane); the others
 // record, one thread per 8-slot group, with SERIAL_LDS_PER_WAVE doubles of
 // dynamic LDS per wave (one-wave workgroups).
-template <bool GR> __global__ __launch_bounds__(64) void k_adj_segment_serial(AdjParams q) {
+template <bool GR, bool KDK> __global__ __launch_bounds__(64) void k_adj_segment_serial(AdjParams q) {
   extern __shared__ double serial_lds[];
   const StepParams& p = q.sp;
   const int lane = threadIdx.x;
   const int wave = blockIdx.x;
   if (wave < q.sweep_waves) {
-    if (wave < p.w8) adj_sweep_lane<8, GR>(q, wave * 64 + lane, lane);
+    if (wave < p.w8) adj_sweep_lane<8, GR, KDK>(q, wave * 64 + lane, lane);
     return;
   }
   const int g = (wave - q.sweep_waves) * 64 + lane;
@@ -1540,14 +1740,14 @@ template <bool GR> __global__ __launch_bounds__(64) void k_adj_segment_serial(Ad
   for (int k = 2; k <= 8; ++k)
     if (__ballot(n >= k) != 0) nw = k;
   switch (nw) {
-    case 1: adj_record_serial<1, GR>(q, base, n, cl); break;
-    case 2: adj_record_serial<2, GR>(q, base, n, cl); break;
-    case 3: adj_record_serial<3, GR>(q, base, n, cl); break;
-    case 4: adj_record_serial<4, GR>(q, base, n, cl); break;
-    case 5: adj_record_serial<5, GR>(q, base, n, cl); break;
-    case 6: adj_record_serial<6, GR>(q, base, n, cl); break;
-    case 7: adj_record_serial<7, GR>(q, base, n, cl); break;
-    default: adj_record_serial<8, GR>(q, base, n, cl); break;
+    case 1: adj_record_serial<1, GR, KDK>(q, base, n, cl); break;
+    case 2: adj_record_serial<2, GR, KDK>(q, base, n, cl); break;
+    case 3: adj_record_serial<3, GR, KDK>(q, base, n, cl); break;
+    case 4: adj_record_serial<4, GR, KDK>(q, base, n, cl); break;
+    case 5: adj_record_serial<5, GR, KDK>(q, base, n, cl); break;
+    case 6: adj_record_serial<6, GR, KDK>(q, base, n, cl); break;
+    case 7: adj_record_serial<7, GR, KDK>(q, base, n, cl); break;
+    default: adj_record_serial<8, GR, KDK>(q, base, n, cl); break;
   }
 }
 
@@ -1579,6 +1779,89 @@ __global__ void k_adj_init(AdjParams q, int synced) {
     }
   }
   store_grad(q.grad, ns, slot, a);
+}
+
+// KDK: the synchronized output applies the pending half kick J(h) [I +
+// GR](h) to the stored state; its adjoint needs the group's sums, so it runs
+// per lane group.  The forward kick is re-evaluated at the stored state for
+// the velocity after it.
+__device__ __forceinline__ Grad gather_grad_T(const AdjParams& q, int slot) {
+  const StepParams& p = q.sp;
+  Grad a{0, 0, 0, 0, 0, 0, 0, 0};
+  const int sys = p.slot_sys[slot], pl = p.slot_pl[slot];
+  if (sys >= 0 && pl >= 0) {
+    const size_t o = ((size_t)sys * 8 + pl) * 3;
+    a.qx = q.gQ_T[o]; a.qy = q.gQ_T[o + 1]; a.qz = q.gQ_T[o + 2];
+    a.vx = q.gV_T[o]; a.vy = q.gV_T[o + 1]; a.vz = q.gV_T[o + 2];
+  }
+  return a;
+}
+
+template <int G, bool GR> __device__ void adj_init_kdk_lane(const AdjParams& q, int slot, int lane, int synced) {
+  const StepParams& p = q.sp;
+  const int ns = p.ns;
+  Grad a = gather_grad_T(q, slot);
+  if (!synced) {
+    Lane L;
+    load_ck(q.ck, ns, slot, L);
+    L.m = p.st[6 * ns + slot];
+    const double m0 = p.m0s[slot], h = 0.5 * p.dts[slot], inv_m0 = 1.0 / m0;
+    const double kg = GR ? p.kgr * m0 * m0 : 0.0;
+    Exch<G, 1> ex;
+    ex.init(lane, L.m);
+    const double q0x = L.qx, q0y = L.qy, q0z = L.qz, v0x = L.vx, v0y = L.vy, v0z = L.vz;
+    double vkx, vky, vkz;
+    kick_block<G, GR, 1>(L, ex, inv_m0, kg, h, h, 0.0, vkx, vky, vkz);
+    const bool leader = G == G_SPLIT ? (lane & 14) == 0 : (lane & (G - 1)) == 0;
+    kick_block_vjp<G, GR>(a, ex, L.m, m0, inv_m0, kg, q0x, q0y, q0z, v0x, v0y, v0z, vkx, vky, vkz, h, h, 0.0,
+                          leader);
+  }
+  store_grad(q.grad, ns, slot, a);
+}
+
+template <int G, bool GR> __device__ void adj_init_kdk_pair(const AdjParams& q, int sa, int lane, int synced) {
+  const StepParams& p = q.sp;
+  const int ns = p.ns, sb = sa + 64;
+  Grad a = gather_grad_T(q, sa), b = gather_grad_T(q, sb);
+  if (!synced) {
+    Lane A, B;
+    load_ck(q.ck, ns, sa, A);
+    load_ck(q.ck, ns, sb, B);
+    A.m = p.st[6 * ns + sa]; B.m = p.st[6 * ns + sb];
+    const double m0 = p.m0s[sa], h = 0.5 * p.dts[sa], inv_m0 = 1.0 / m0;
+    const double kg = GR ? p.kgr * m0 * m0 : 0.0;
+    const PairMass pm = make_pair_mass<G>(A.m, B.m);
+    const double q0a[3] = {A.qx, A.qy, A.qz}, v0a[3] = {A.vx, A.vy, A.vz};
+    const double q0b[3] = {B.qx, B.qy, B.qz}, v0b[3] = {B.vx, B.vy, B.vz};
+    double vka[3], vkb[3];
+    kick_block_pair<G, GR>(A, B, pm, inv_m0, kg, h, h, 0.0, vka, vkb);
+    kick_block_vjp_pair<G, GR>(a, b, pm, A.m, B.m, m0, inv_m0, kg, q0a, v0a, q0b, v0b, vka, vkb, h, h, 0.0,
+                               (lane & (G - 1)) == 0);
+  }
+  store_grad(q.grad, ns, sa, a);
+  store_grad(q.grad, ns, sb, b);
+}
+
+// LAYOUT: 0 one planet per lane (pow2, G8 and the serial packing's G8
+// storage), 1 split, 2 pair.
+template <bool GR, int LAYOUT> __global__ __launch_bounds__(256) void k_adj_init_kdk(AdjParams q, int synced) {
+  const StepParams& p = q.sp;
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  if (LAYOUT == 2) {
+    const int sa = wave * 128 + lane;
+    if (wave < p.w1) adj_init_kdk_pair<1, GR>(q, sa, lane, synced);
+    else if (wave < p.w2) adj_init_kdk_pair<2, GR>(q, sa, lane, synced);
+    else adj_init_kdk_pair<4, GR>(q, sa, lane, synced);
+    return;
+  }
+  const int slot = wave * 64 + lane;
+  if (LAYOUT == 1) adj_init_kdk_lane<G_SPLIT, GR>(q, slot, lane, synced);
+  else if (wave < p.w1) adj_init_kdk_lane<1, GR>(q, slot, lane, synced);
+  else if (wave < p.w2) adj_init_kdk_lane<2, GR>(q, slot, lane, synced);
+  else if (wave < p.w4) adj_init_kdk_lane<4, GR>(q, slot, lane, synced);
+  else adj_init_kdk_lane<8, GR>(q, slot, lane, synced);
 }
 
 template <int G> __device__ void adj_finish_lane(const AdjParams& q, int slot, int lane) {
@@ -2444,7 +2727,8 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
   if (!tape) return fail(WH_EINVAL, "null tape");
   if (n_steps < 0 || ckpt_every < 1 || ckpt_every > (1 << 30)) return fail(WH_EINVAL, "bad n_steps or ckpt_every");
   if (((uintptr_t)tape & 255) != 0) return fail(WH_EINVAL, "tape must be 256-byte aligned");
-  if (c->cfg.scheme != WH_DKD) return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD");
+  if (c->cfg.scheme != WH_DKD && c->cfg.scheme != WH_KDK)
+    return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD and WH_KDK");
   if (c->cfg.coords != WH_COORDS_DHC)
     return fail(WH_ESTATE, "reverse mode is implemented in democratic heliocentric coordinates");
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
@@ -2500,9 +2784,25 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
   q.tape_rec = seg[1];
   q.n_rec = 0;
   q.rec_first_synced = 0;
-  hipLaunchKernelGGL(k_adj_init, dim3((ns + 255) / 256), dim3(256), 0, stream, q, (int)(c->tape_steps == 0));
   const bool gr = c->cfg.gr_c > 0;
+  const bool kdk = c->cfg.scheme == WH_KDK;
   const int nw = c->P.nwaves;
+  const int synced_end = (int)(c->tape_steps == 0);
+  if (!kdk) {
+    hipLaunchKernelGGL(k_adj_init, dim3((ns + 255) / 256), dim3(256), 0, stream, q, synced_end);
+  } else {
+    const dim3 g(nw), b(64);
+    if (c->P.pair) {
+      if (gr) hipLaunchKernelGGL((k_adj_init_kdk<true, 2>), g, b, 0, stream, q, synced_end);
+      else hipLaunchKernelGGL((k_adj_init_kdk<false, 2>), g, b, 0, stream, q, synced_end);
+    } else if (c->P.split) {
+      if (gr) hipLaunchKernelGGL((k_adj_init_kdk<true, 1>), g, b, 0, stream, q, synced_end);
+      else hipLaunchKernelGGL((k_adj_init_kdk<false, 1>), g, b, 0, stream, q, synced_end);
+    } else {
+      if (gr) hipLaunchKernelGGL((k_adj_init_kdk<true, 0>), g, b, 0, stream, q, synced_end);
+      else hipLaunchKernelGGL((k_adj_init_kdk<false, 0>), g, b, 0, stream, q, synced_end);
+    }
+  }
   auto seg_steps = [&](int64_t k) {
     return (int)std::min<int64_t>(c->tape_every, c->tape_steps - k * c->tape_every);
   };
@@ -2519,20 +2819,40 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
       const int rec = record_waves > 0 ? (record_waves * 8 + 63) / 64 : 0;
       const dim3 grid(sweep_waves + rec), block(64);
       const size_t smem = SERIAL_LDS_PER_WAVE * sizeof(double);
-      if (gr) hipLaunchKernelGGL(k_adj_segment_serial<true>, grid, block, smem, stream, q);
-      else hipLaunchKernelGGL(k_adj_segment_serial<false>, grid, block, smem, stream, q);
+      if (kdk) {
+        if (gr) hipLaunchKernelGGL((k_adj_segment_serial<true, true>), grid, block, smem, stream, q);
+        else hipLaunchKernelGGL((k_adj_segment_serial<false, true>), grid, block, smem, stream, q);
+      } else {
+        if (gr) hipLaunchKernelGGL((k_adj_segment_serial<true, false>), grid, block, smem, stream, q);
+        else hipLaunchKernelGGL((k_adj_segment_serial<false, false>), grid, block, smem, stream, q);
+      }
       return;
     }
     const dim3 grid(sweep_waves + record_waves), block(64);
     if (c->P.pair) {
-      if (gr) hipLaunchKernelGGL(k_adj_segment_pair<true>, grid, block, 0, stream, q);
-      else hipLaunchKernelGGL(k_adj_segment_pair<false>, grid, block, 0, stream, q);
+      if (kdk) {
+        if (gr) hipLaunchKernelGGL((k_adj_segment_pair<true, true>), grid, block, 0, stream, q);
+        else hipLaunchKernelGGL((k_adj_segment_pair<false, true>), grid, block, 0, stream, q);
+      } else {
+        if (gr) hipLaunchKernelGGL((k_adj_segment_pair<true, false>), grid, block, 0, stream, q);
+        else hipLaunchKernelGGL((k_adj_segment_pair<false, false>), grid, block, 0, stream, q);
+      }
     } else if (c->P.split) {
-      if (gr) hipLaunchKernelGGL((k_adj_segment<true, true>), grid, block, 0, stream, q);
-      else hipLaunchKernelGGL((k_adj_segment<false, true>), grid, block, 0, stream, q);
+      if (kdk) {
+        if (gr) hipLaunchKernelGGL((k_adj_segment<true, true, true>), grid, block, 0, stream, q);
+        else hipLaunchKernelGGL((k_adj_segment<false, true, true>), grid, block, 0, stream, q);
+      } else {
+        if (gr) hipLaunchKernelGGL((k_adj_segment<true, true, false>), grid, block, 0, stream, q);
+        else hipLaunchKernelGGL((k_adj_segment<false, true, false>), grid, block, 0, stream, q);
+      }
     } else {
-      if (gr) hipLaunchKernelGGL((k_adj_segment<true, false>), grid, block, 0, stream, q);
-      else hipLaunchKernelGGL((k_adj_segment<false, false>), grid, block, 0, stream, q);
+      if (kdk) {
+        if (gr) hipLaunchKernelGGL((k_adj_segment<true, false, true>), grid, block, 0, stream, q);
+        else hipLaunchKernelGGL((k_adj_segment<false, false, true>), grid, block, 0, stream, q);
+      } else {
+        if (gr) hipLaunchKernelGGL((k_adj_segment<true, false, false>), grid, block, 0, stream, q);
+        else hipLaunchKernelGGL((k_adj_segment<false, false, false>), grid, block, 0, stream, q);
+      }
     }
   };
   // record the last segment, then sweep segment k while recording k - 1

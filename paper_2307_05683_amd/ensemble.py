@@ -197,7 +197,8 @@ class _Integrate(torch.autograd.Function):
 
 
 def integrate(Q0, V0, m, m0, dt, n_planets, n_steps, ckpt_every=1000, gr_c=0.0, **opts):
-    """Differentiable ensemble integration (drift-kick-drift).
+    """Differentiable ensemble integration (drift-kick-drift, or kick-drift-kick
+    with scheme="kdk" among the options).
 
     Q0, V0: [S, 8, 3], m: [S, 8], m0, dt: [S] float64 CUDA tensors;
     n_planets: host ints [S].  Returns the synchronized (Q_T, V_T).

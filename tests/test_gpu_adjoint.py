@@ -23,8 +23,8 @@ def live(s):
     return np.arange(8)[None, :] < s.n_planets[:, None]
 
 
-def adjoint_run(s, n_steps, every, gQ_T, gV_T, gr_c=0.0, packing="auto"):
-    e = Ensemble.from_systems(s, gr_c=gr_c, packing=packing)
+def adjoint_run(s, n_steps, every, gQ_T, gV_T, gr_c=0.0, packing="auto", scheme="dkd"):
+    e = Ensemble.from_systems(s, gr_c=gr_c, packing=packing, scheme=scheme)
     e.forward_ckpt(n_steps, every)
     QT, VT = e.state()
     g = e.adjoint(gQ_T, gV_T)
@@ -127,13 +127,14 @@ def loss_np(Q, s):
     return (Q ** 2 * live(s)[:, :, None]).sum((1, 2))
 
 
-@pytest.mark.parametrize("packing", ["auto", "split", "pair", "serial"])
-def test_gradients_match_central_differences(packing):
+@pytest.mark.parametrize("packing,scheme", [("auto", "dkd"), ("split", "dkd"), ("pair", "dkd"), ("serial", "dkd"),
+                                            ("auto", "kdk"), ("pair", "kdk")])
+def test_gradients_match_central_differences(packing, scheme):
     """Loss L = sum_i |Q_i(T)|^2 per system; perturb one input coordinate in
     every system at once (systems are independent) with h = 1e-7 relative."""
     s = inputs.make_systems(32, 33, n_planets=8)
     n_steps, every = 400, 100
-    e = Ensemble.from_systems(s, packing=packing)
+    e = Ensemble.from_systems(s, packing=packing, scheme=scheme)
     e.forward_ckpt(n_steps, every)
     QT, VT = e.state()
     gQ0, gV0, gm, gm0 = [x.cpu().numpy() for x in e.adjoint(2 * QT, torch.zeros_like(VT))]
@@ -142,7 +143,7 @@ def test_gradients_match_central_differences(packing):
     def run(mod):
         t = s.copy()
         mod(t)
-        f = Ensemble.from_systems(t, packing=packing)
+        f = Ensemble.from_systems(t, packing=packing, scheme=scheme)
         f.step(n_steps)
         Q, _ = f.state()
         f.close()
@@ -208,8 +209,8 @@ def test_tape_validation():
         e.adjoint(np.zeros((4, 8, 3)), np.zeros((4, 8, 3)))
     assert ei.value.code == _lib.WH_ESTATE
     e.close()
-    for kw in (dict(scheme="kdk"), dict(packing="pair", scheme="kdk"), dict(packing="serial", scheme="kdk"),
-               dict(coords="jacobi")):
+    for kw in (dict(scheme="saba2"), dict(packing="pair", scheme="saba3"), dict(packing="serial", scheme="saba2"),
+               dict(coords="jacobi"), dict(coords="jacobi", scheme="kdk")):
         k = Ensemble.from_systems(s, **kw)
         with pytest.raises(_lib.WHError):
             k.forward_ckpt(10, 5)
@@ -258,3 +259,52 @@ def test_adjoint_workload_full_length_sampled():
     rel = np.abs(lhs - rhs) / scale
     print("dot-product relative mismatch (1e5 steps): %s" % np.array2string(rel, precision=2), flush=True)
     assert rel.max() < 1e-6
+
+
+@pytest.mark.parametrize("packing", ["auto", "split", "pair", "serial"])
+@pytest.mark.parametrize("n_steps,every,gr_c", [(200, 64, 0.0), (200, 64, 40.0), (1, 1, 0.0), (97, 10, 10065.0),
+                                                (0, 5, 40.0)])
+def test_kick_drift_kick_dot_product_vs_oracle_tangent(n_steps, every, gr_c, packing):
+    """Reverse mode of the kick-drift-kick map (step = kick block, then the
+    drift; the synchronized output adds the pending half kick) against the
+    oracle's tangent of the same scheme."""
+    s = inputs.make_systems(16, 37, n_planets=None, n_range=(1, 8))
+    print("case: kdk n_steps=%d every=%d gr_c=%g packing=%s" % (n_steps, every, gr_c, packing), flush=True)
+    rng = np.random.default_rng(8)
+    lm = live(s)
+    gQ_T = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None]
+    gV_T = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None]
+    QT, VT, gQ0, gV0, gm, gm0 = adjoint_run(s, n_steps, every, gQ_T, gV_T, gr_c, packing, scheme="kdk")
+    Qo, Vo = oracle.integrate(s, n_steps, scheme="kdk", gr_c=gr_c)
+    assert np.abs(QT - Qo.astype(float))[lm].max() < 1e-12 * np.abs(Qo.astype(float))[lm].max()
+    for which in ("state", "m", "m0"):
+        dQ, dV, dm, dm0 = random_dirs(s, 9)
+        if which != "state":
+            dQ = np.zeros_like(dQ); dV = np.zeros_like(dV)
+            dm = dm if which == "m" else np.zeros_like(dm)
+            dm0 = dm0 if which == "m0" else np.zeros_like(dm0)
+        _, _, tQ, tV = oracle.tangent(s, n_steps, dQ, dV, dm, dm0, scheme="kdk", gr_c=gr_c)
+        lhs = (gQ0 * dQ).sum((1, 2)) + (gV0 * dV).sum((1, 2)) + (gm * dm).sum(1) + gm0 * dm0
+        if n_steps == 0 and which != "state":     # no step: the output does not depend on the masses
+            assert not gm.any() and not gm0.any()
+            continue
+        rhs = (gQ_T * tQ.astype(float)).sum((1, 2)) + (gV_T * tV.astype(float)).sum((1, 2))
+        scale = np.abs(gQ_T * tQ.astype(float)).sum((1, 2)) + np.abs(gV_T * tV.astype(float)).sum((1, 2))
+        rel = np.abs(lhs - rhs) / scale
+        print("kdk dot-product relative mismatch (%s): max %.2e" % (which, rel.max()), flush=True)
+        assert rel.max() < 1e-9
+
+
+@pytest.mark.parametrize("packing", ["auto", "split", "pair", "serial"])
+@pytest.mark.parametrize("gr_c", [0.0, 10065.0])
+def test_kick_drift_kick_checkpoint_interval_bitwise(gr_c, packing):
+    s = inputs.make_systems(19, 38, n_planets=None, n_range=(1, 8))
+    rng = np.random.default_rng(4)
+    gQ_T = rng.normal(size=(s.S, 8, 3)) * live(s)[:, :, None]
+    gV_T = rng.normal(size=(s.S, 8, 3)) * live(s)[:, :, None]
+    ref = adjoint_run(s, 300, 300, gQ_T, gV_T, gr_c=gr_c, packing=packing, scheme="kdk")
+    for every in (1, 7, 64):
+        out = adjoint_run(s, 300, every, gQ_T, gV_T, gr_c=gr_c, packing=packing, scheme="kdk")
+        for a, b in zip(out, ref):
+            assert np.array_equal(a, b), every
+
