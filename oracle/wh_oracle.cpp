@@ -995,7 +995,12 @@ void or_tangent_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, ld
     }
     D dtk(dt[k]);
     D c(gr_c);
-    for (long t = 0; t < n_steps; ++t) step(s, dtk, scheme, c, gr);
+    if (scheme >= 2) {
+      Saba q = saba_coeffs(scheme);
+      for (long t = 0; t < n_steps; ++t) saba_step(s, dtk, q);
+    } else {
+      for (long t = 0; t < n_steps; ++t) step(s, dtk, scheme, c, gr);
+    }
     for (int i = 0; i < s.n; ++i) {
       int p = k * nmax + i;
       for (int a = 0; a < 3; ++a) {

@@ -162,7 +162,10 @@ def test_converges_to_brute_force_at_second_order():
     assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
 
 
-def test_tangent_matches_central_differences():
+@pytest.mark.parametrize("scheme,gr_c", [("dkd", 0.0), ("kdk", 0.0), ("kdk", 40.0), ("saba2", 0.0), ("saba3", 0.0)])
+def test_tangent_matches_central_differences(scheme, gr_c):
+    """The dual-number tangent of each scheme's step, along state and mass
+    directions, against central differences of the same long-double map."""
     s = heavy_system(n=3, seed=26)
     rng = np.random.default_rng(7)
     dQ = np.zeros((1, 8, 3)); dV = np.zeros((1, 8, 3)); dm = np.zeros((1, 8))
@@ -171,7 +174,7 @@ def test_tangent_matches_central_differences():
     dm[0, :3] = rng.normal(size=3) * 1e-4
     dm0 = np.array([0.01])
     n_steps = 80
-    _, _, tQ, tV = oracle.tangent(s, n_steps, dQ, dV, dm, dm0)
+    _, _, tQ, tV = oracle.tangent(s, n_steps, dQ, dV, dm, dm0, scheme=scheme, gr_c=gr_c)
     h = LD(1e-7)
 
     def run(sign):
@@ -183,7 +186,7 @@ def test_tangent_matches_central_differences():
         S = t.S
         Qa, Va = Q.copy(), V.copy()
         oracle.lib().or_integrate_ld(S, 8, t.n_planets.astype(np.int32), m0, m, Qa, Va, s.dt.astype(LD),
-                                     n_steps, 0, LD(0), 1)
+                                     n_steps, oracle.SCHEMES[scheme], LD(gr_c), 1)
         return Qa, Va
 
     Qp, Vp = run(1)
