@@ -1261,7 +1261,7 @@ __device__ __forceinline__ void kick_block_vjp(Grad& a, const Exch<G, 1>& ex, do
 // state at the start of the step, the anomaly X of its drift and the
 // velocity after its kick; with KDK the step is the kick block followed by
 // the drift.
-template <int G, bool GR, bool KDK = false>
+template <int G, bool GR, int SCH = WH_DKD>
 __device__ void adj_record_lane(const AdjParams& q, int slot, int lane) {
   const StepParams& p = q.sp;
   const int ns = p.ns;
@@ -1276,7 +1276,26 @@ __device__ void adj_record_lane(const AdjParams& q, int slot, int lane) {
   const double inv_m0 = 1.0 / L.m0;
   const double kg = GR ? p.kgr * L.m0 * L.m0 : 0.0;
   KepDiag dg{0.0, 1.0e300};
-  if constexpr (KDK) {
+  if constexpr (SCH == SCHEME_SABA) {
+    // SABA_n: n units per step, unit k = K(tau_k) then the perturbation kick
+    // B(d_k dt); tau_0 = c_1 dt (2 c_1 dt after the first step), tau_k = c_{k+1} dt
+    const int nu = p.saba_n;
+    const double c1dt = p.sc[0] * dt;
+    for (int s = 0; s < q.n_rec; ++s)
+      for (int k = 0; k < nu; ++k) {
+        double* row = q.tape_rec + ((size_t)s * nu + k) * TAPE_ROWS * ns + slot;
+        const double tau = k > 0 ? p.sc[k] * dt : (q.rec_first_synced && s == 0 ? c1dt : 2.0 * c1dt);
+        const double tb = p.sd[k] * dt;
+        row[0] = L.qx; row[ns] = L.qy; row[2 * ns] = L.qz;
+        row[3 * ns] = L.vx; row[4 * ns] = L.vy; row[5 * ns] = L.vz;
+        row[6 * ns] = drift(L, L.m0, tau, dg);
+        double vkx, vky, vkz;
+        kick_block<G, false, 1>(L, ex, inv_m0, 0.0, 0.5 * tb, tb, 0.5 * tb, vkx, vky, vkz);
+        row[7 * ns] = vkx; row[8 * ns] = vky; row[9 * ns] = vkz;
+      }
+    return;
+  }
+  if constexpr (SCH == WH_KDK) {
     double ta = q.rec_first_synced ? 0.0 : h;
     double ti = q.rec_first_synced ? h : dt;
     for (int s = 0; s < q.n_rec; ++s) {
@@ -1307,7 +1326,7 @@ __device__ void adj_record_lane(const AdjParams& q, int slot, int lane) {
 
 // Reverse sweep of a recorded segment: the adjoint state is carried back
 // through the transposed Jacobian of every sub-step.
-template <int G, bool GR, bool KDK = false>
+template <int G, bool GR, int SCH = WH_DKD>
 __device__ void adj_sweep_lane(const AdjParams& q, int slot, int lane) {
   const StepParams& p = q.sp;
   const int ns = p.ns;
@@ -1322,7 +1341,31 @@ __device__ void adj_sweep_lane(const AdjParams& q, int slot, int lane) {
   // the lane(s) of planet 0 add the star-mass terms of the jump (in the
   // split layout both copies, so that the copies keep equal bits)
   const bool leader = G == G_SPLIT ? (lane & 14) == 0 : (lane & (G - 1)) == 0;
-  if constexpr (KDK) {
+  if constexpr (SCH == SCHEME_SABA) {
+    const int nu = p.saba_n;
+    const double c1dt = p.sc[0] * dt;
+    for (int u = q.n_seg * nu - 1; u >= 0; --u) {
+      const int s = u / nu, k = u - s * nu;
+      const double* row = q.tape + (size_t)u * TAPE_ROWS * ns + slot;
+      const double q0x = row[0], q0y = row[ns], q0z = row[2 * ns];
+      const double v0x = row[3 * ns], v0y = row[4 * ns], v0z = row[5 * ns];
+      const double vkx = row[7 * ns], vky = row[8 * ns], vkz = row[9 * ns];
+      const double tau = k > 0 ? p.sc[k] * dt : (q.first_synced && s == 0 ? c1dt : 2.0 * c1dt);
+      const double tb = p.sd[k] * dt;
+      KepFwd kf;
+      kepler_at_X(q0x, q0y, q0z, v0x, v0y, v0z, m0, tau, row[6 * ns], kf);
+      const double q1x = kf.f * q0x + kf.g * v0x, q1y = kf.f * q0y + kf.g * v0y, q1z = kf.f * q0z + kf.g * v0z;
+      const double v1x = kf.fd * q0x + kf.gd * v0x, v1y = kf.fd * q0y + kf.gd * v0y, v1z = kf.fd * q0z + kf.gd * v0z;
+      kick_block_vjp<G, false>(a, ex, m, m0, inv_m0, 0.0, q1x, q1y, q1z, v1x, v1y, v1z, vkx, vky, vkz, 0.5 * tb, tb,
+                               0.5 * tb, leader);
+      double gmu = 0.0;
+      kepler_vjp(kf, q0x, q0y, q0z, v0x, v0y, v0z, m0, a.qx, a.qy, a.qz, a.vx, a.vy, a.vz, gmu);
+      a.m0 += gmu;
+    }
+    store_grad(q.grad, ns, slot, a);
+    return;
+  }
+  if constexpr (SCH == WH_KDK) {
     // step = kick block (ta, ti, h) then K(dt): the drift's adjoint first
     for (int s = q.n_seg - 1; s >= 0; --s) {
       const double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
@@ -1435,7 +1478,7 @@ __device__ __forceinline__ void kick_block_vjp_pair(Grad& a, Grad& b, const Pair
 
 // The same two roles in the pair layout: lane l of wave w holds slots
 // 128 w + l (a) and 128 w + 64 + l (b).
-template <int G, bool GR, bool KDK = false>
+template <int G, bool GR, int SCH = WH_DKD>
 __device__ void adj_record_pair(const AdjParams& q, int sa, int lane) {
   const StepParams& p = q.sp;
   const int ns = p.ns, sb = sa + 64;
@@ -1449,7 +1492,27 @@ __device__ void adj_record_pair(const AdjParams& q, int sa, int lane) {
   const double inv_m0 = 1.0 / A.m0;
   const double kg = GR ? p.kgr * A.m0 * A.m0 : 0.0;
   KepDiag dga{0.0, 1.0e300}, dgb{0.0, 1.0e300};
-  if constexpr (KDK) {
+  if constexpr (SCH == SCHEME_SABA) {
+    const int nu = p.saba_n;
+    const double c1dt = p.sc[0] * dt;
+    for (int s = 0; s < q.n_rec; ++s)
+      for (int k = 0; k < nu; ++k) {
+        double* ra = q.tape_rec + ((size_t)s * nu + k) * TAPE_ROWS * ns + sa;
+        double* rb = ra + 64;
+        const double tau = k > 0 ? p.sc[k] * dt : (q.rec_first_synced && s == 0 ? c1dt : 2.0 * c1dt);
+        const double tb = p.sd[k] * dt;
+        ra[0] = A.qx; ra[ns] = A.qy; ra[2 * ns] = A.qz; ra[3 * ns] = A.vx; ra[4 * ns] = A.vy; ra[5 * ns] = A.vz;
+        rb[0] = B.qx; rb[ns] = B.qy; rb[2 * ns] = B.qz; rb[3 * ns] = B.vx; rb[4 * ns] = B.vy; rb[5 * ns] = B.vz;
+        ra[6 * ns] = drift(A, A.m0, tau, dga);
+        rb[6 * ns] = drift(B, B.m0, tau, dgb);
+        double vka[3], vkb[3];
+        kick_block_pair<G, false>(A, B, pm, inv_m0, 0.0, 0.5 * tb, tb, 0.5 * tb, vka, vkb);
+        ra[7 * ns] = vka[0]; ra[8 * ns] = vka[1]; ra[9 * ns] = vka[2];
+        rb[7 * ns] = vkb[0]; rb[8 * ns] = vkb[1]; rb[9 * ns] = vkb[2];
+      }
+    return;
+  }
+  if constexpr (SCH == WH_KDK) {
     double ta = q.rec_first_synced ? 0.0 : h;
     double ti = q.rec_first_synced ? h : dt;
     for (int s = 0; s < q.n_rec; ++s) {
@@ -1484,7 +1547,7 @@ __device__ void adj_record_pair(const AdjParams& q, int sa, int lane) {
   }
 }
 
-template <int G, bool GR, bool KDK = false>
+template <int G, bool GR, int SCH = WH_DKD>
 __device__ void adj_sweep_pair(const AdjParams& q, int sa, int lane) {
   const StepParams& p = q.sp;
   const int ns = p.ns, sb = sa + 64;
@@ -1497,7 +1560,40 @@ __device__ void adj_sweep_pair(const AdjParams& q, int sa, int lane) {
   load_grad(q.grad, ns, sa, a);
   load_grad(q.grad, ns, sb, b);
   const bool leader = (lane & (G - 1)) == 0;
-  if constexpr (KDK) {
+  if constexpr (SCH == SCHEME_SABA) {
+    const int nu = p.saba_n;
+    const double c1dt = p.sc[0] * dt;
+    for (int u = q.n_seg * nu - 1; u >= 0; --u) {
+      const int s = u / nu, k = u - s * nu;
+      const double* ra = q.tape + (size_t)u * TAPE_ROWS * ns + sa;
+      const double* rb = ra + 64;
+      const double q0a[3] = {ra[0], ra[ns], ra[2 * ns]}, v0a[3] = {ra[3 * ns], ra[4 * ns], ra[5 * ns]};
+      const double q0b[3] = {rb[0], rb[ns], rb[2 * ns]}, v0b[3] = {rb[3 * ns], rb[4 * ns], rb[5 * ns]};
+      const double vka[3] = {ra[7 * ns], ra[8 * ns], ra[9 * ns]}, vkb[3] = {rb[7 * ns], rb[8 * ns], rb[9 * ns]};
+      const double tau = k > 0 ? p.sc[k] * dt : (q.first_synced && s == 0 ? c1dt : 2.0 * c1dt);
+      const double tb = p.sd[k] * dt;
+      KepFwd ka, kb;
+      kepler_at_X(q0a[0], q0a[1], q0a[2], v0a[0], v0a[1], v0a[2], m0, tau, ra[6 * ns], ka);
+      kepler_at_X(q0b[0], q0b[1], q0b[2], v0b[0], v0b[1], v0b[2], m0, tau, rb[6 * ns], kb);
+      double q1a[3], v1a[3], q1b[3], v1b[3];
+      for (int c = 0; c < 3; ++c) {
+        q1a[c] = ka.f * q0a[c] + ka.g * v0a[c]; v1a[c] = ka.fd * q0a[c] + ka.gd * v0a[c];
+        q1b[c] = kb.f * q0b[c] + kb.g * v0b[c]; v1b[c] = kb.fd * q0b[c] + kb.gd * v0b[c];
+      }
+      kick_block_vjp_pair<G, false>(a, b, pm, ma, mb, m0, inv_m0, 0.0, q1a, v1a, q1b, v1b, vka, vkb, 0.5 * tb, tb,
+                                    0.5 * tb, leader);
+      double gmu = 0.0;
+      kepler_vjp(ka, q0a[0], q0a[1], q0a[2], v0a[0], v0a[1], v0a[2], m0, a.qx, a.qy, a.qz, a.vx, a.vy, a.vz, gmu);
+      a.m0 += gmu;
+      gmu = 0.0;
+      kepler_vjp(kb, q0b[0], q0b[1], q0b[2], v0b[0], v0b[1], v0b[2], m0, b.qx, b.qy, b.qz, b.vx, b.vy, b.vz, gmu);
+      b.m0 += gmu;
+    }
+    store_grad(q.grad, ns, sa, a);
+    store_grad(q.grad, ns, sb, b);
+    return;
+  }
+  if constexpr (SCH == WH_KDK) {
     for (int s = q.n_seg - 1; s >= 0; --s) {
       const double* ra = q.tape + (size_t)s * TAPE_ROWS * ns + sa;
       const double* rb = ra + 64;
@@ -1590,7 +1686,7 @@ __device__ void adj_sweep_pair(const AdjParams& q, int sa, int lane) {
   store_grad(q.grad, ns, sb, b);
 }
 
-template <bool GR, bool KDK> __global__ __launch_bounds__(256) void k_adj_segment_pair(AdjParams q) {
+template <bool GR, int SCH> __global__ __launch_bounds__(256) void k_adj_segment_pair(AdjParams q) {
   const StepParams& p = q.sp;
   const int lane = threadIdx.x & 63;
   int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -1599,19 +1695,19 @@ template <bool GR, bool KDK> __global__ __launch_bounds__(256) void k_adj_segmen
   if (wave >= p.w8) return;
   const int sa = wave * 128 + lane;
   if (sweep) {
-    if (wave < p.w1) adj_sweep_pair<1, GR, KDK>(q, sa, lane);
-    else if (wave < p.w2) adj_sweep_pair<2, GR, KDK>(q, sa, lane);
-    else adj_sweep_pair<4, GR, KDK>(q, sa, lane);
+    if (wave < p.w1) adj_sweep_pair<1, GR, SCH>(q, sa, lane);
+    else if (wave < p.w2) adj_sweep_pair<2, GR, SCH>(q, sa, lane);
+    else adj_sweep_pair<4, GR, SCH>(q, sa, lane);
   } else {
-    if (wave < p.w1) adj_record_pair<1, GR, KDK>(q, sa, lane);
-    else if (wave < p.w2) adj_record_pair<2, GR, KDK>(q, sa, lane);
-    else adj_record_pair<4, GR, KDK>(q, sa, lane);
+    if (wave < p.w1) adj_record_pair<1, GR, SCH>(q, sa, lane);
+    else if (wave < p.w2) adj_record_pair<2, GR, SCH>(q, sa, lane);
+    else adj_record_pair<4, GR, SCH>(q, sa, lane);
   }
 }
 
 // Waves [0, sweep_waves) sweep one segment, the waves after them record the
 // previous segment; each role covers the packing's waves once.
-template <bool GR, bool SPLIT, bool KDK> __global__ __launch_bounds__(256) void k_adj_segment(AdjParams q) {
+template <bool GR, bool SPLIT, int SCH> __global__ __launch_bounds__(256) void k_adj_segment(AdjParams q) {
   const StepParams& p = q.sp;
   const int lane = threadIdx.x & 63;
   int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -1620,18 +1716,18 @@ template <bool GR, bool SPLIT, bool KDK> __global__ __launch_bounds__(256) void 
   if (wave >= p.w8) return;
   const int slot = wave * 64 + lane;
   if (SPLIT) {
-    if (sweep) adj_sweep_lane<G_SPLIT, GR, KDK>(q, slot, lane);
-    else adj_record_lane<G_SPLIT, GR, KDK>(q, slot, lane);
+    if (sweep) adj_sweep_lane<G_SPLIT, GR, SCH>(q, slot, lane);
+    else adj_record_lane<G_SPLIT, GR, SCH>(q, slot, lane);
   } else if (sweep) {
-    if (wave < p.w1) adj_sweep_lane<1, GR, KDK>(q, slot, lane);
-    else if (wave < p.w2) adj_sweep_lane<2, GR, KDK>(q, slot, lane);
-    else if (wave < p.w4) adj_sweep_lane<4, GR, KDK>(q, slot, lane);
-    else adj_sweep_lane<8, GR, KDK>(q, slot, lane);
+    if (wave < p.w1) adj_sweep_lane<1, GR, SCH>(q, slot, lane);
+    else if (wave < p.w2) adj_sweep_lane<2, GR, SCH>(q, slot, lane);
+    else if (wave < p.w4) adj_sweep_lane<4, GR, SCH>(q, slot, lane);
+    else adj_sweep_lane<8, GR, SCH>(q, slot, lane);
   } else {
-    if (wave < p.w1) adj_record_lane<1, GR, KDK>(q, slot, lane);
-    else if (wave < p.w2) adj_record_lane<2, GR, KDK>(q, slot, lane);
-    else if (wave < p.w4) adj_record_lane<4, GR, KDK>(q, slot, lane);
-    else adj_record_lane<8, GR, KDK>(q, slot, lane);
+    if (wave < p.w1) adj_record_lane<1, GR, SCH>(q, slot, lane);
+    else if (wave < p.w2) adj_record_lane<2, GR, SCH>(q, slot, lane);
+    else if (wave < p.w4) adj_record_lane<4, GR, SCH>(q, slot, lane);
+    else adj_record_lane<8, GR, SCH>(q, slot, lane);
   }
 }
 
@@ -1644,11 +1740,12 @@ template <bool GR, bool SPLIT, bool KDK> __global__ __launch_bounds__(256) void 
 // and the velocity, finite values that the zero masses keep out of every sum.
 __device__ __forceinline__ void record_static(const AdjParams& q, int base, int from) {
   const int ns = q.sp.ns;
+  const int rows = q.n_rec * (q.sp.saba_n > 0 ? q.sp.saba_n : 1);   // SABA_n: n units per step
   for (int i = from; i < 8; ++i) {
     const int slot = base + i;
     double v[6];
     for (int r = 0; r < 6; ++r) v[r] = q.ck_rec[r * ns + slot];
-    for (int s = 0; s < q.n_rec; ++s) {
+    for (int s = 0; s < rows; ++s) {
       double* row = q.tape_rec + (size_t)s * TAPE_ROWS * ns + slot;
       for (int r = 0; r < 6; ++r) row[r * ns] = v[r];
       row[6 * ns] = 0.0;
@@ -1657,7 +1754,7 @@ __device__ __forceinline__ void record_static(const AdjParams& q, int base, int 
   }
 }
 
-template <int NP, bool GR, bool KDK>
+template <int NP, bool GR, int SCH>
 __device__ void adj_record_serial(const AdjParams& q, int base, int n, double* cl) {
   const StepParams& p = q.sp;
   const int ns = p.ns;
@@ -1676,7 +1773,30 @@ __device__ void adj_record_serial(const AdjParams& q, int base, int n, double* c
   const double inv_m0 = 1.0 / m0;
   const double kg = GR ? p.kgr * m0 * m0 : 0.0;
   KepDiag dg{0.0, 1.0e300};
-  if constexpr (KDK) {
+  if constexpr (SCH == SCHEME_SABA) {
+    const int nu = p.saba_n;
+    const double c1dt = p.sc[0] * dt;
+    for (int s = 0; s < q.n_rec; ++s)
+      for (int k = 0; k < nu; ++k) {
+        double* row = q.tape_rec + ((size_t)s * nu + k) * TAPE_ROWS * ns + base;
+        const double tau = k > 0 ? p.sc[k] * dt : (q.rec_first_synced && s == 0 ? c1dt : 2.0 * c1dt);
+        const double tb = p.sd[k] * dt;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          row[i] = S.qx[i]; row[ns + i] = S.qy[i]; row[2 * ns + i] = S.qz[i];
+          row[3 * ns + i] = S.vx[i]; row[4 * ns + i] = S.vy[i]; row[5 * ns + i] = S.vz[i];
+          Lane L = serial_get(S, cl, i);
+          row[6 * ns + i] = serial_drift(L, m0, tau, i < n, dg);
+          serial_put(S, cl, i, L);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        serial_kick_drift<NP, false, true>(S, cl, n, m0, inv_m0, 0.0, 0.5 * tb, tb, 0.5 * tb, 0.0, false, dg,
+                                           row + 7 * ns, ns);
+      }
+    record_static(q, base, NP);
+    return;
+  }
+  if constexpr (SCH == WH_KDK) {
     double ta = q.rec_first_synced ? 0.0 : h;
     double ti = q.rec_first_synced ? h : dt;
     for (int s = 0; s < q.n_rec; ++s) {
@@ -1715,13 +1835,13 @@ __device__ void adj_record_serial(const AdjParams& q, int base, int n, double* c
 // Waves [0, sweep_waves) sweep (G8 waves, one planet per lane); the others
 // record, one thread per 8-slot group, with SERIAL_LDS_PER_WAVE doubles of
 // dynamic LDS per wave (one-wave workgroups).
-template <bool GR, bool KDK> __global__ __launch_bounds__(64) void k_adj_segment_serial(AdjParams q) {
+template <bool GR, int SCH> __global__ __launch_bounds__(64) void k_adj_segment_serial(AdjParams q) {
   extern __shared__ double serial_lds[];
   const StepParams& p = q.sp;
   const int lane = threadIdx.x;
   const int wave = blockIdx.x;
   if (wave < q.sweep_waves) {
-    if (wave < p.w8) adj_sweep_lane<8, GR, KDK>(q, wave * 64 + lane, lane);
+    if (wave < p.w8) adj_sweep_lane<8, GR, SCH>(q, wave * 64 + lane, lane);
     return;
   }
   const int g = (wave - q.sweep_waves) * 64 + lane;
@@ -1740,19 +1860,20 @@ template <bool GR, bool KDK> __global__ __launch_bounds__(64) void k_adj_segment
   for (int k = 2; k <= 8; ++k)
     if (__ballot(n >= k) != 0) nw = k;
   switch (nw) {
-    case 1: adj_record_serial<1, GR, KDK>(q, base, n, cl); break;
-    case 2: adj_record_serial<2, GR, KDK>(q, base, n, cl); break;
-    case 3: adj_record_serial<3, GR, KDK>(q, base, n, cl); break;
-    case 4: adj_record_serial<4, GR, KDK>(q, base, n, cl); break;
-    case 5: adj_record_serial<5, GR, KDK>(q, base, n, cl); break;
-    case 6: adj_record_serial<6, GR, KDK>(q, base, n, cl); break;
-    case 7: adj_record_serial<7, GR, KDK>(q, base, n, cl); break;
-    default: adj_record_serial<8, GR, KDK>(q, base, n, cl); break;
+    case 1: adj_record_serial<1, GR, SCH>(q, base, n, cl); break;
+    case 2: adj_record_serial<2, GR, SCH>(q, base, n, cl); break;
+    case 3: adj_record_serial<3, GR, SCH>(q, base, n, cl); break;
+    case 4: adj_record_serial<4, GR, SCH>(q, base, n, cl); break;
+    case 5: adj_record_serial<5, GR, SCH>(q, base, n, cl); break;
+    case 6: adj_record_serial<6, GR, SCH>(q, base, n, cl); break;
+    case 7: adj_record_serial<7, GR, SCH>(q, base, n, cl); break;
+    default: adj_record_serial<8, GR, SCH>(q, base, n, cl); break;
   }
 }
 
-// Adjoint of the closing half drift K(h) of the synchronized output (or the
-// identity when no step was taken), from the caller's dL/dQ_T, dL/dV_T.
+// Adjoint of the closing drift of the synchronized output (K(h), or K(c_1 dt)
+// for SABA_n; the identity when no step was taken), from the caller's
+// dL/dQ_T, dL/dV_T.
 __global__ void k_adj_init(AdjParams q, int synced) {
   const StepParams& p = q.sp;
   const int ns = p.ns;
@@ -1767,7 +1888,8 @@ __global__ void k_adj_init(AdjParams q, int synced) {
     if (!synced) {
       double qx = q.ck[slot], qy = q.ck[ns + slot], qz = q.ck[2 * ns + slot];
       double vx = q.ck[3 * ns + slot], vy = q.ck[4 * ns + slot], vz = q.ck[5 * ns + slot];
-      double m0 = p.m0s[slot], h = 0.5 * p.dts[slot];
+      // the pending drift: K(dt/2), or K(c_1 dt) for SABA_n
+      double m0 = p.m0s[slot], h = p.saba_n > 0 ? p.sc[0] * p.dts[slot] : 0.5 * p.dts[slot];
       KepDiag dg{0.0, 1.0e300};
       KepCoef kc;
       double X = kepler_coeffs<KEP_NH, KEP_NN, KEP_KH, KEP_KN>(qx, qy, qz, vx, vy, vz, m0, h, dg, kc);
@@ -2507,18 +2629,40 @@ struct TapeLayout {
   size_t total = 0;
 };
 
-TapeLayout tape_layout(int ns, int64_t n_steps, int64_t every) {
+// units: tape row sets per step (SABA_n records each of its n drift-kick
+// units, the other schemes one)
+TapeLayout tape_layout(int ns, int64_t n_steps, int64_t every, int units) {
   TapeLayout T;
   T.n_seg = (n_steps + every - 1) / every;
   size_t o = 0;
   T.ck = o; o = align256(o + sizeof(double) * 12 * (size_t)ns * (size_t)(T.n_seg + 1));
   for (int b = 0; b < 2; ++b) {
     T.seg[b] = o;
-    o = align256(o + sizeof(double) * TAPE_ROWS * (size_t)ns * (size_t)every);
+    o = align256(o + sizeof(double) * TAPE_ROWS * (size_t)ns * (size_t)every * (size_t)units);
   }
   T.grad = o; o = align256(o + sizeof(double) * 8 * (size_t)ns);
   T.total = o;
   return T;
+}
+
+int tape_units(const wh_ctx* c) { return c->cfg.scheme >= WH_SABA2 ? c->cfg.scheme : 1; }
+
+// One launch of the reverse pass: sweep_waves wavefronts sweep a segment and
+// the following ones record the previous segment (record_waves wavefronts of
+// the packing; the serial packing records with one thread per 8-slot group).
+template <bool GR, int SCH>
+void launch_adj_segment(const wh_ctx* c, const AdjParams& q, int sweep_waves, int record_waves, hipStream_t st) {
+  if (c->P.serial) {
+    const int rec = record_waves > 0 ? (record_waves * 8 + 63) / 64 : 0;
+    const dim3 grid(sweep_waves + rec), block(64);
+    const size_t smem = SERIAL_LDS_PER_WAVE * sizeof(double);
+    hipLaunchKernelGGL((k_adj_segment_serial<GR, SCH>), grid, block, smem, st, q);
+    return;
+  }
+  const dim3 grid(sweep_waves + record_waves), block(64);
+  if (c->P.pair) hipLaunchKernelGGL((k_adj_segment_pair<GR, SCH>), grid, block, 0, st, q);
+  else if (c->P.split) hipLaunchKernelGGL((k_adj_segment<GR, true, SCH>), grid, block, 0, st, q);
+  else hipLaunchKernelGGL((k_adj_segment<GR, false, SCH>), grid, block, 0, st, q);
 }
 
 }  // namespace
@@ -2718,7 +2862,8 @@ int64_t wh_steps_done(const wh_ctx* c) { return c ? c->steps_done : -1; }
 
 size_t wh_tape_bytes(const wh_ctx* c, int64_t n_steps, int64_t ckpt_every) {
   if (!c || n_steps < 0 || ckpt_every < 1 || ckpt_every > (1 << 30)) return 0;
-  return tape_layout(c->P.ns, n_steps, ckpt_every).total;
+  if (ckpt_every * tape_units(c) > (1 << 30)) return 0;
+  return tape_layout(c->P.ns, n_steps, ckpt_every, tape_units(c)).total;
 }
 
 wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* tape, size_t tape_bytes,
@@ -2727,12 +2872,13 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
   if (!tape) return fail(WH_EINVAL, "null tape");
   if (n_steps < 0 || ckpt_every < 1 || ckpt_every > (1 << 30)) return fail(WH_EINVAL, "bad n_steps or ckpt_every");
   if (((uintptr_t)tape & 255) != 0) return fail(WH_EINVAL, "tape must be 256-byte aligned");
-  if (c->cfg.scheme != WH_DKD && c->cfg.scheme != WH_KDK)
-    return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD and WH_KDK");
+  if (c->cfg.scheme != WH_DKD && c->cfg.scheme != WH_KDK && c->cfg.scheme < WH_SABA2)
+    return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD, WH_KDK and WH_SABA2..4");
   if (c->cfg.coords != WH_COORDS_DHC)
     return fail(WH_ESTATE, "reverse mode is implemented in democratic heliocentric coordinates");
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
-  TapeLayout T = tape_layout(c->P.ns, n_steps, ckpt_every);
+  if (ckpt_every * tape_units(c) > (1 << 30)) return fail(WH_EINVAL, "ckpt_every too large for this scheme");
+  TapeLayout T = tape_layout(c->P.ns, n_steps, ckpt_every, tape_units(c));
   if (tape_bytes < T.total) return fail(WH_EWORKSPACE, "tape too small: need " + std::to_string(T.total) + " bytes");
   const int ns = c->P.ns;
   double* ck = (double*)((char*)tape + T.ck);
@@ -2767,7 +2913,7 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
   if (tape != c->tape || tape_bytes != c->tape_bytes || c->steps_done != c->tape_end)
     return fail(WH_ESTATE, "no matching wh_forward_ckpt for this tape (or steps taken since)");
   const int ns = c->P.ns;
-  TapeLayout T = tape_layout(ns, c->tape_steps, c->tape_every);
+  TapeLayout T = tape_layout(ns, c->tape_steps, c->tape_every, tape_units(c));
   double* ck = (double*)((char*)tape + T.ck);
   double* seg[2] = {(double*)((char*)tape + T.seg[0]), (double*)((char*)tape + T.seg[1])};
   AdjParams q;
@@ -2812,48 +2958,14 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
     q.n_rec = seg_steps(k);
     q.rec_first_synced = (k == 0);
   };
+  const bool saba = c->cfg.scheme >= WH_SABA2;
   auto launch = [&](int sweep_waves, int record_waves) {
     q.sweep_waves = sweep_waves;
-    if (c->P.serial) {
-      // recording: one thread per 8-slot group, i.e. an eighth of the waves
-      const int rec = record_waves > 0 ? (record_waves * 8 + 63) / 64 : 0;
-      const dim3 grid(sweep_waves + rec), block(64);
-      const size_t smem = SERIAL_LDS_PER_WAVE * sizeof(double);
-      if (kdk) {
-        if (gr) hipLaunchKernelGGL((k_adj_segment_serial<true, true>), grid, block, smem, stream, q);
-        else hipLaunchKernelGGL((k_adj_segment_serial<false, true>), grid, block, smem, stream, q);
-      } else {
-        if (gr) hipLaunchKernelGGL((k_adj_segment_serial<true, false>), grid, block, smem, stream, q);
-        else hipLaunchKernelGGL((k_adj_segment_serial<false, false>), grid, block, smem, stream, q);
-      }
-      return;
-    }
-    const dim3 grid(sweep_waves + record_waves), block(64);
-    if (c->P.pair) {
-      if (kdk) {
-        if (gr) hipLaunchKernelGGL((k_adj_segment_pair<true, true>), grid, block, 0, stream, q);
-        else hipLaunchKernelGGL((k_adj_segment_pair<false, true>), grid, block, 0, stream, q);
-      } else {
-        if (gr) hipLaunchKernelGGL((k_adj_segment_pair<true, false>), grid, block, 0, stream, q);
-        else hipLaunchKernelGGL((k_adj_segment_pair<false, false>), grid, block, 0, stream, q);
-      }
-    } else if (c->P.split) {
-      if (kdk) {
-        if (gr) hipLaunchKernelGGL((k_adj_segment<true, true, true>), grid, block, 0, stream, q);
-        else hipLaunchKernelGGL((k_adj_segment<false, true, true>), grid, block, 0, stream, q);
-      } else {
-        if (gr) hipLaunchKernelGGL((k_adj_segment<true, true, false>), grid, block, 0, stream, q);
-        else hipLaunchKernelGGL((k_adj_segment<false, true, false>), grid, block, 0, stream, q);
-      }
-    } else {
-      if (kdk) {
-        if (gr) hipLaunchKernelGGL((k_adj_segment<true, false, true>), grid, block, 0, stream, q);
-        else hipLaunchKernelGGL((k_adj_segment<false, false, true>), grid, block, 0, stream, q);
-      } else {
-        if (gr) hipLaunchKernelGGL((k_adj_segment<true, false, false>), grid, block, 0, stream, q);
-        else hipLaunchKernelGGL((k_adj_segment<false, false, false>), grid, block, 0, stream, q);
-      }
-    }
+    if (saba) launch_adj_segment<false, SCHEME_SABA>(c, q, sweep_waves, record_waves, stream);
+    else if (kdk && gr) launch_adj_segment<true, WH_KDK>(c, q, sweep_waves, record_waves, stream);
+    else if (kdk) launch_adj_segment<false, WH_KDK>(c, q, sweep_waves, record_waves, stream);
+    else if (gr) launch_adj_segment<true, WH_DKD>(c, q, sweep_waves, record_waves, stream);
+    else launch_adj_segment<false, WH_DKD>(c, q, sweep_waves, record_waves, stream);
   };
   // record the last segment, then sweep segment k while recording k - 1
   if (T.n_seg > 0) {

@@ -148,10 +148,6 @@ def test_unsupported_combinations_rejected():
     for kw in (dict(coords="jacobi"), dict(scheme="saba2", gr_c=10065.0)):
         with pytest.raises(_lib.WHError):
             Ensemble.from_systems(s, packing="serial", **kw)
-    e = Ensemble.from_systems(s, packing="serial", scheme="saba2")
-    with pytest.raises(_lib.WHError):        # reverse mode runs DKD and KDK, not SABA_n
-        e.forward_ckpt(10, 5)
-    e.close()
     e = Ensemble.from_systems(s, packing="serial")
     with pytest.raises(_lib.WHError):        # the per-size path is the G8 packing's
         e.step_plain(1)

@@ -125,10 +125,6 @@ def test_unsupported_combinations_rejected():
     for kw in (dict(coords="jacobi"), dict(scheme="saba2", gr_c=10065.0)):
         with pytest.raises(_lib.WHError):
             Ensemble.from_systems(s, packing="split", **kw)
-    e = Ensemble.from_systems(s, packing="split", scheme="saba2")
-    with pytest.raises(_lib.WHError):        # reverse mode runs DKD and KDK, not SABA_n
-        e.forward_ckpt(10, 5)
-    e.close()
 
 
 def test_flags_isolated():
