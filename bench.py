@@ -171,21 +171,22 @@ def cpu_baseline(systems, args, gr_c, scheme="dkd"):
     }
 
 
-def adjoint_cost(systems, args, dev, stream, t_plain):
+def adjoint_cost(systems, args, dev, stream, t_plain, gr_c, scheme, opts):
     """Forward with checkpoints + adjoint, against the plain forward of the
-    same steps (the cost ratio of reverse mode).  A short run first loads
-    every kernel involved; the loss seed dL/dQ_T = 2 Q_T is formed outside
-    the timed intervals."""
+    same steps (the cost ratio of reverse mode), with the scheme and packing
+    of the forward run.  A short run first loads every kernel involved; the
+    loss seed dL/dQ_T = 2 Q_T is formed outside the timed intervals."""
     import torch
     from paper_2307_05683_amd.ensemble import Ensemble
-    w = Ensemble.from_systems(systems.subset(np.arange(min(64, systems.S))), device=dev)
+    w = Ensemble.from_systems(systems.subset(np.arange(min(64, systems.S))), device=dev, gr_c=gr_c, scheme=scheme,
+                              **opts)
     w.forward_ckpt(4, 2)
     QT, VT = w.state()
     w.adjoint(2 * QT, torch.zeros_like(VT))
     torch.cuda.synchronize()
     w.close()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    e = Ensemble.from_systems(systems, device=dev)
+    e = Ensemble.from_systems(systems, device=dev, gr_c=gr_c, scheme=scheme, **opts)
     ev[0].record(stream)
     e.forward_ckpt(args.steps, args.ckpt_every)
     ev[1].record(stream)
@@ -332,7 +333,7 @@ def main():
     if tune_table is not None:
         out["config"]["autotune"] = [dict(r["opts"], rate=r["system_steps_per_s"]) for r in tune_table]
     if args.workload == "adjoint8":
-        out["adjoint"] = adjoint_cost(systems, args, dev, stream, gpu_s)
+        out["adjoint"] = adjoint_cost(systems, args, dev, stream, gpu_s, gr_c, scheme, opts)
     if args.workload == "uneven2to8" and args.plain_steps > 0:
         plain = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, packing="g8", coords=args.coords,
                                       device=dev)
