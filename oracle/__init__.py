@@ -50,6 +50,8 @@ def lib():
             "or_energy_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld, _PLD], None),
             "or_angmom_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD], None),
             "or_tangent_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, l, i, ld, _PLD, _PLD, _PLD, _PLD, i], None),
+            "or_jacobi_tangent_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, l, i, ld, _PLD, _PLD, _PLD, _PLD, i],
+                                     None),
             "or_count_ops": ([i, i, i, i, i, i, _PL], None),
             "or_gbs_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld, l], ld),
             "or_jacobi_integrate_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, l, i, ld, i], None),
@@ -167,16 +169,18 @@ def angmom(sysm, Q=None, V=None):
     return L
 
 
-def tangent(sysm, n_steps, dQ, dV, dm, dm0, scheme="dkd", gr_c=0.0, nthreads=0):
-    """Forward tangent map along one direction per system.
+def tangent(sysm, n_steps, dQ, dV, dm, dm0, scheme="dkd", gr_c=0.0, nthreads=0, coords="dhc"):
+    """Forward tangent map along one direction per system (coords "jacobi":
+    the Jacobi-coordinate map, DHC in and out).
 
     Returns (Q_T, V_T, dQ_T, dV_T) with dX_T = (d x_T / d x_0) . direction.
     """
     S = sysm.S
     Q = _ld(sysm.Q).copy(); V = _ld(sysm.V).copy()
     dQ = _ld(dQ).copy(); dV = _ld(dV).copy()
-    lib().or_tangent_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), Q, V, _ld(sysm.dt), int(n_steps),
-                        SCHEMES[scheme], LD(gr_c), _ld(dm0), _ld(dm), dQ, dV, nthreads)
+    f = lib().or_jacobi_tangent_ld if coords == "jacobi" else lib().or_tangent_ld
+    f(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), Q, V, _ld(sysm.dt), int(n_steps), SCHEMES[scheme],
+      LD(gr_c), _ld(dm0), _ld(dm), dQ, dV, nthreads)
     return Q, V, dQ, dV
 
 

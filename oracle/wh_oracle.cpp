@@ -767,6 +767,34 @@ void jac_step(JSys<ld>& s, ld dt, int scheme) {
   }
 }
 
+// The same map on any scalar type (dual numbers for the tangent map), with
+// the kick from its closed form (a test pins it to the gradient of H_I).
+template <class T> void jac_drift_t(JSys<T>& s, const T& tau) {
+  for (int i = 0; i < s.n; ++i) kepler_exact(s.x[i], s.v[i], s.M[i + 1], tau, (typename Real<T>::type*)0);
+}
+template <class T> void jac_step_t(JSys<T>& s, const T& dt, int scheme) {
+  typedef typename Real<T>::type R;
+  if (scheme >= 2) {
+    Saba q = saba_coeffs(scheme);
+    for (int k = 0; k < q.n; ++k) {
+      jac_drift_t(s, dt * T(R(q.c[k])));
+      jac_kick_direct(s, dt * T(R(q.d[k])));
+    }
+    jac_drift_t(s, dt * T(R(q.c[q.n])));
+    return;
+  }
+  T h = dt * T(R(0.5));
+  if (scheme == 0) {
+    jac_drift_t(s, h);
+    jac_kick_direct(s, dt);
+    jac_drift_t(s, h);
+  } else {
+    jac_kick_direct(s, h);
+    jac_drift_t(s, dt);
+    jac_kick_direct(s, h);
+  }
+}
+
 template <class A> void jac_load(JSys<ld>& s, int idx, int nmax, const int* np, const A* m0, const A* m, const A* Q,
                                  const A* V) {
   s.n = np[idx];
@@ -1075,6 +1103,45 @@ void or_count_ops_jacobi(int n, int gr, int nh, int nn, int th, int tn, long* co
   for (int i = 0; i < n; ++i) kepler_fixed<C>(s.x[i], s.v[i], s.M[i + 1], dt, nh, nn, th, tn);
   jac_kick_direct(s, dt);
   counts[0] = g_ops.add; counts[1] = g_ops.mul; counts[2] = g_ops.div; counts[3] = g_ops.sqrt;
+}
+
+// Tangent map of the Jacobi-coordinate map, with DHC inputs and outputs as
+// or_jacobi_integrate_ld: the transforms, drifts (mu = G M_i) and kicks on
+// dual numbers carrying the direction (dQ, dV, dm, dm0).
+void or_jacobi_tangent_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, ld* Q, ld* V, const ld* dt,
+                          long n_steps, int scheme, ld gr_c, const ld* dm0, const ld* dm, ld* dQ, ld* dV,
+                          int nthreads) {
+  typedef Dual<ld> D;
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+  for (int k = 0; k < S; ++k) {
+    JSys<D> s;
+    s.n = np[k];
+    s.m0 = D(m0[k], dm0[k]);
+    s.gr_c = D(gr_c);
+    D q[8][3], v[8][3];
+    for (int i = 0; i < s.n; ++i) {
+      int p = k * nmax + i;
+      s.m[i] = D(m[p], dm[p]);
+      for (int a = 0; a < 3; ++a) {
+        q[i][a] = D(Q[3 * p + a], dQ[3 * p + a]);
+        v[i][a] = D(V[3 * p + a], dV[3 * p + a]);
+      }
+    }
+    jac_from_dhc(s, q, v);
+    D dtk(dt[k]);
+    for (long t = 0; t < n_steps; ++t) jac_step_t(s, dtk, scheme);
+    jac_to_dhc(s, q, v);
+    for (int i = 0; i < s.n; ++i) {
+      int p = k * nmax + i;
+      for (int a = 0; a < 3; ++a) {
+        Q[3 * p + a] = q[i][a].v;
+        V[3 * p + a] = v[i][a].v;
+        dQ[3 * p + a] = q[i][a].d;
+        dV[3 * p + a] = v[i][a].d;
+      }
+    }
+  }
 }
 
 }  // extern "C"

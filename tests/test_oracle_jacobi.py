@@ -308,3 +308,38 @@ def test_gr_energy_error_bounded_second_order(scheme):
     e1, e2 = err(p_in / 20, 400), err(p_in / 40, 800)
     lo, hi = (3.0, 5.0) if scheme == "dkd" else (3.0, 20.0)
     assert e1 < 1e-5 and lo < e1 / e2 < hi, (e1, e2)
+
+
+@pytest.mark.parametrize("scheme,gr_c", [("dkd", 0.0), ("kdk", 0.0), ("dkd", 40.0), ("saba2", 0.0), ("saba3", 40.0)])
+def test_tangent_matches_central_differences(scheme, gr_c):
+    """The dual-number tangent of the Jacobi-coordinate map (DHC in and out,
+    masses included) against central differences of the same long-double map."""
+    s = inputs.make_systems(3, 61, n_planets=None, n_range=(2, 5))
+    rng = np.random.default_rng(3)
+    lm = np.arange(8)[None, :] < s.n_planets[:, None]
+    dQ = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None] * 0.1
+    dV = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None] * 0.01
+    dm = rng.normal(size=(s.S, 8)) * lm * s.m
+    dm0 = rng.normal(size=s.S) * 0.01
+    n_steps = 60
+    _, _, tQ, tV = oracle.tangent(s, n_steps, dQ, dV, dm, dm0, scheme=scheme, gr_c=gr_c, coords="jacobi")
+    h = LD(1e-7)
+
+    def run(sign):
+        t = s.copy()
+        t.m = (s.m.astype(LD) + sign * h * dm.astype(LD)).astype(float)
+        Q = s.Q.astype(LD) + sign * h * dQ.astype(LD)
+        V = s.V.astype(LD) + sign * h * dV.astype(LD)
+        m = s.m.astype(LD) + sign * h * dm.astype(LD)
+        m0 = s.m0.astype(LD) + sign * h * dm0.astype(LD)
+        Qa, Va = Q.copy(), V.copy()
+        oracle.lib().or_jacobi_integrate_ld(s.S, 8, s.n_planets.astype(np.int32), m0, m, Qa, Va, s.dt.astype(LD),
+                                            n_steps, oracle.SCHEMES[scheme], LD(gr_c), 1)
+        return Qa, Va
+
+    Qp, Vp = run(1)
+    Qm, Vm = run(-1)
+    fQ = ((Qp - Qm) / (2 * h)).astype(float)
+    fV = ((Vp - Vm) / (2 * h)).astype(float)
+    assert np.abs(fQ - tQ.astype(float)).max() < 1e-7 * np.abs(fQ).max()
+    assert np.abs(fV - tV.astype(float)).max() < 1e-7 * np.abs(fV).max()
