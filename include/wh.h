@@ -207,10 +207,11 @@ int64_t wh_steps_done(const wh_ctx* ctx);
  * segment k is swept.  wh_tape_bytes gives the size: 96 B per lane slot per
  * checkpoint plus 2 x 80 B per lane slot and step of a segment (2 x n x 80 B
  * for SABA_n, which records its n drift-kick units; ckpt_every x n must not
- * exceed 2^30).  Contexts in DHC with WH_DKD, WH_KDK or WH_SABA2..4 (any
- * packing); Jacobi contexts get WH_ESTATE.  With WH_KDK a step of the tape is
- * the kick block followed by the drift, and the synchronized output's pending
- * half kick is differentiated too; with SABA_n the pending drift K(c_1 dt). */
+ * exceed 2^30).  Every scheme, packing and coordinate system: with WH_KDK a
+ * step of the tape is the kick block followed by the drift, and the
+ * synchronized output's pending half kick is differentiated too; with SABA_n
+ * the pending drift K(c_1 dt); in Jacobi coordinates the gradients are those
+ * of the DHC inputs and outputs, through both coordinate transforms. */
 size_t wh_tape_bytes(const wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every);
 wh_status wh_forward_ckpt(wh_ctx* ctx, int64_t n_steps, int64_t ckpt_every, void* tape, size_t tape_bytes,
                           hipStream_t stream);

@@ -1871,6 +1871,406 @@ template <bool GR, int SCH> __global__ __launch_bounds__(64) void k_adj_segment_
   }
 }
 
+// ---------------------------------------------------------------------------
+// Reverse mode in Jacobi coordinates (one planet per lane).  The masses enter
+// through the interior masses: M_{i-1} = m0 + sum_{j<i} m_j, M_i, 1/M_{i-1},
+// w_i = m_i / M_i and ratio_i = m0 / M_{i-1}.  jac_mass_adj turns adjoints of
+// M_i, 1/M_{i-1}, w and ratio into those of m_i, m0 and M_{i-1}; the adjoint
+// of M_{i-1} is collected per lane and handed to m0 and the inner planets'
+// masses by jac_fold_mim1 (a suffix sum over the group).
+struct JacAdj {
+  double Mi, inv, w, ratio;
+};
+
+__device__ __forceinline__ void jac_mass_adj(const JacConst& jc, double m0, const JacAdj& g, Grad& a,
+                                             double& gMim1) {
+  const double gMi = g.Mi - jc.w * g.w / jc.Mi;
+  a.m += g.w / jc.Mi + gMi;
+  a.m0 += jc.inv_Mim1 * g.ratio;
+  const double ginv = g.inv + m0 * g.ratio;
+  gMim1 += gMi - jc.inv_Mim1 * jc.inv_Mim1 * ginv;
+}
+
+template <int G> __device__ __forceinline__ void jac_fold_mim1(Grad& a, double& gMim1, int p) {
+  a.m0 += gMim1;
+  a.m += group_suffix_excl<G>(gMim1, p);
+  gMim1 = 0.0;
+}
+
+// Adjoint of the Jacobi kick V' += tau a'(X', m) of kick_jacobi at Jacobi
+// positions (xx, xy, xz): a.v (unchanged by the kick's adjoint) gives
+// dL/dX' (added to a.q), dL/dm, dL/dm0 and the M_{i-1} adjoint.
+template <int G, bool GR>
+__device__ __forceinline__ void kick_jacobi_vjp(Grad& a, double& gMim1, const Exch<G, 1>& ex, const JacConst& jc,
+                                                int p, double m, double m0, double kg, double xx, double xy,
+                                                double xz, double tau) {
+  // forward values
+  const double qx = jac_to_helio<G>(xx, jc.w, p);
+  const double qy = jac_to_helio<G>(xy, jc.w, p);
+  const double qz = jac_to_helio<G>(xz, jc.w, p);
+  double ax, ay, az;
+  ex.accel(qx, qy, qz, m, ax, ay, az);
+  const double irq = rsqrt_full(fma(qx, qx, fma(qy, qy, qz * qz)));
+  const double irq2 = irq * irq, irq3 = irq2 * irq;
+  const double irp = rsqrt_full(fma(xx, xx, fma(xy, xy, xz * xz)));
+  const double irp2 = irp * irp, irp3 = irp2 * irp;
+  const double kp = jc.Mi * irp3, kq = (jc.Mi * jc.ratio) * irq3, wq = m * irq3;
+  const double sx = group_suffix_excl<G>(wq * qx, p), sy = group_suffix_excl<G>(wq * qy, p),
+               sz = group_suffix_excl<G>(wq * qz, p);
+  const double px = group_scan_excl<G>(m * ax, p), py = group_scan_excl<G>(m * ay, p),
+               pz = group_scan_excl<G>(m * az, p);
+  // adjoint of the acceleration a'
+  const double Gx = tau * a.vx, Gy = tau * a.vy, Gz = tau * a.vz;
+  JacAdj g{0.0, 0.0, 0.0, 0.0};
+  double gqx = -kq * Gx, gqy = -kq * Gy, gqz = -kq * Gz;
+  a.qx += kp * Gx; a.qy += kp * Gy; a.qz += kp * Gz;
+  const double gkp = Gx * xx + Gy * xy + Gz * xz;
+  const double gkq = -(Gx * qx + Gy * qy + Gz * qz);
+  // c = ratio * sum_{k>i} wq_k q_k + (sum_{j<i} m_j a_j) / M_{i-1}, entering as -c
+  g.ratio -= Gx * sx + Gy * sy + Gz * sz;
+  g.inv -= Gx * px + Gy * py + Gz * pz;
+  const double ux = group_scan_excl<G>(-jc.ratio * Gx, p), uy = group_scan_excl<G>(-jc.ratio * Gy, p),
+               uz = group_scan_excl<G>(-jc.ratio * Gz, p);
+  const double gwq = ux * qx + uy * qy + uz * qz;
+  gqx += wq * ux; gqy += wq * uy; gqz += wq * uz;
+  const double hx = group_suffix_excl<G>(-jc.inv_Mim1 * Gx, p), hy = group_suffix_excl<G>(-jc.inv_Mim1 * Gy, p),
+               hz = group_suffix_excl<G>(-jc.inv_Mim1 * Gz, p);
+  const double gax = Gx + m * hx, gay = Gy + m * hy, gaz = Gz + m * hz;
+  a.m += hx * ax + hy * ay + hz * az;
+  if (GR) {
+    // + gr_i + (sum_{k>=i} m_k gr_k) / M_{i-1}
+    double grx, gry, grz;
+    gr_accel(qx, qy, qz, kg, grx, gry, grz);
+    const double SGx = group_suffix_incl<G>(m * grx, p), SGy = group_suffix_incl<G>(m * gry, p),
+                 SGz = group_suffix_incl<G>(m * grz, p);
+    g.inv += Gx * SGx + Gy * SGy + Gz * SGz;
+    const double vx = group_scan_incl<G>(jc.inv_Mim1 * Gx, p), vy = group_scan_incl<G>(jc.inv_Mim1 * Gy, p),
+                 vz = group_scan_incl<G>(jc.inv_Mim1 * Gz, p);
+    a.m += vx * grx + vy * gry + vz * grz;
+    double gmu = 0.0;
+    gr_vjp(qx, qy, qz, kg, m0, 1.0, Gx + m * vx, Gy + m * vy, Gz + m * vz, gqx, gqy, gqz, gmu);
+    a.m0 += gmu;
+  }
+  // wq = m |q|^-3, kq = M_i ratio |q|^-3, kp = M_i |x'|^-3
+  a.m += irq3 * gwq;
+  const double girq3 = m * gwq + (jc.Mi * jc.ratio) * gkq;
+  g.Mi += jc.ratio * irq3 * gkq + irp3 * gkp;
+  g.ratio += jc.Mi * irq3 * gkq;
+  const double cq = -3.0 * girq3 * irq3 * irq2;
+  gqx += cq * qx; gqy += cq * qy; gqz += cq * qz;
+  const double cp = -3.0 * (jc.Mi * gkp) * irp3 * irp2;
+  a.qx += cp * xx; a.qy += cp * xy; a.qz += cp * xz;
+  // the planet-planet accelerations at the heliocentric positions
+  interaction_vjp<G>(ex, qx, qy, qz, m, 1.0, gax, gay, gaz, gqx, gqy, gqz, a.m);
+  // q = x' + sum_{j<i} w_j x'_j
+  const double tx = group_suffix_excl<G>(gqx, p), ty = group_suffix_excl<G>(gqy, p),
+               tz = group_suffix_excl<G>(gqz, p);
+  a.qx += gqx + jc.w * tx; a.qy += gqy + jc.w * ty; a.qz += gqz + jc.w * tz;
+  g.w += tx * xx + ty * xy + tz * xz;
+  jac_mass_adj(jc, m0, g, a, gMim1);
+}
+
+// Adjoint of the Jacobi drift K(tau) about mu = G M_i at (x0, v0) with the
+// recorded anomaly X: a goes from the drift's output to its input.
+__device__ __forceinline__ void jac_drift_vjp(Grad& a, double& gMim1, double mi, double x0x, double x0y, double x0z,
+                                              double v0x, double v0y, double v0z, double tau, double X, KepFwd& k) {
+  kepler_at_X(x0x, x0y, x0z, v0x, v0y, v0z, mi, tau, X, k);
+  double gmu = 0.0;
+  kepler_vjp(k, x0x, x0y, x0z, v0x, v0y, v0z, mi, a.qx, a.qy, a.qz, a.vx, a.vy, a.vz, gmu);
+  a.m += gmu;      // M_i = M_{i-1} + m_i
+  gMim1 += gmu;
+}
+
+// Adjoint of the output transform Jacobi -> DHC (jacobi_to_dhc) at the
+// Jacobi state (x', v'): a.q, a.v hold dL/dQ, dL/dV and receive dL/dx',
+// dL/dv'.
+template <int G>
+__device__ __forceinline__ void jac_to_dhc_vjp(Grad& a, double& gMim1, const JacConst& jc, int p, double m,
+                                               double m0, double xx, double xy, double xz, double vx, double vy,
+                                               double vz) {
+  const double Mn = m0 + group_sum<G>(m);
+  const double ux = jac_to_helio<G>(vx, jc.w, p), uy = jac_to_helio<G>(vy, jc.w, p),
+               uz = jac_to_helio<G>(vz, jc.w, p);
+  double Px, Py, Pz;
+  group_momentum<G>(m, ux, uy, uz, Px, Py, Pz);
+  const double Sx = group_sum<G>(a.vx), Sy = group_sum<G>(a.vy), Sz = group_sum<G>(a.vz);
+  const double iMn = 1.0 / Mn;
+  const double gux = a.vx - m * Sx * iMn, guy = a.vy - m * Sy * iMn, guz = a.vz - m * Sz * iMn;
+  a.m -= (ux * Sx + uy * Sy + uz * Sz) * iMn;
+  const double gMn = (Px * Sx + Py * Sy + Pz * Sz) * iMn * iMn;   // Mn = m0 + sum_j m_j
+  a.m += gMn;
+  if (p == 0) a.m0 += gMn;
+  JacAdj g{0.0, 0.0, 0.0, 0.0};
+  const double tux = group_suffix_excl<G>(gux, p), tuy = group_suffix_excl<G>(guy, p),
+               tuz = group_suffix_excl<G>(guz, p);
+  a.vx = gux + jc.w * tux; a.vy = guy + jc.w * tuy; a.vz = guz + jc.w * tuz;
+  const double tqx = group_suffix_excl<G>(a.qx, p), tqy = group_suffix_excl<G>(a.qy, p),
+               tqz = group_suffix_excl<G>(a.qz, p);
+  g.w = tux * vx + tuy * vy + tuz * vz + tqx * xx + tqy * xy + tqz * xz;
+  a.qx += jc.w * tqx; a.qy += jc.w * tqy; a.qz += jc.w * tqz;
+  jac_mass_adj(jc, m0, g, a, gMim1);
+}
+
+// Adjoint of the input transform DHC -> Jacobi (dhc_to_jacobi) at the DHC
+// state (Q, V): a.q, a.v hold dL/dx', dL/dv' and receive dL/dQ, dL/dV.
+template <int G>
+__device__ __forceinline__ void dhc_to_jac_vjp(Grad& a, double& gMim1, const JacConst& jc, int p, double m,
+                                               double m0, double Qx, double Qy, double Qz, double Vx, double Vy,
+                                               double Vz) {
+  double Px, Py, Pz;
+  group_momentum<G>(m, Vx, Vy, Vz, Px, Py, Pz);
+  const double ux = Vx + Px / m0, uy = Vy + Py / m0, uz = Vz + Pz / m0;
+  JacAdj g{0.0, 0.0, 0.0, 0.0};
+  // x' = Q - (sum_{j<i} m_j Q_j) / M_{i-1}
+  const double bx = group_suffix_excl<G>(jc.inv_Mim1 * a.qx, p), by = group_suffix_excl<G>(jc.inv_Mim1 * a.qy, p),
+               bz = group_suffix_excl<G>(jc.inv_Mim1 * a.qz, p);
+  g.inv -= a.qx * group_scan_excl<G>(m * Qx, p) + a.qy * group_scan_excl<G>(m * Qy, p) +
+           a.qz * group_scan_excl<G>(m * Qz, p);
+  a.m -= Qx * bx + Qy * by + Qz * bz;
+  a.qx -= m * bx; a.qy -= m * by; a.qz -= m * bz;
+  // v' = u - (sum_{j<i} m_j u_j) / M_{i-1}
+  const double cx = group_suffix_excl<G>(jc.inv_Mim1 * a.vx, p), cy = group_suffix_excl<G>(jc.inv_Mim1 * a.vy, p),
+               cz = group_suffix_excl<G>(jc.inv_Mim1 * a.vz, p);
+  g.inv -= a.vx * group_scan_excl<G>(m * ux, p) + a.vy * group_scan_excl<G>(m * uy, p) +
+           a.vz * group_scan_excl<G>(m * uz, p);
+  a.m -= ux * cx + uy * cy + uz * cz;
+  const double gux = a.vx - m * cx, guy = a.vy - m * cy, guz = a.vz - m * cz;
+  // u = V + (sum_j m_j V_j) / m0
+  const double Sx = group_sum<G>(gux), Sy = group_sum<G>(guy), Sz = group_sum<G>(guz);
+  a.vx = gux + m * Sx / m0; a.vy = guy + m * Sy / m0; a.vz = guz + m * Sz / m0;
+  a.m += (Vx * Sx + Vy * Sy + Vz * Sz) / m0;
+  if (p == 0) a.m0 -= (Px * Sx + Py * Sy + Pz * Sz) / (m0 * m0);
+  jac_mass_adj(jc, m0, g, a, gMim1);
+}
+
+// Recording and sweeping of a Jacobi context (per lane; tape rows as in DHC:
+// the state at the start of the step or unit, the drift's X, V' after the
+// kick).
+template <int G, bool GR, int SCH>
+__device__ void adj_record_jac(const AdjParams& q, int slot, int lane) {
+  const StepParams& p = q.sp;
+  const int ns = p.ns;
+  const int pg = lane & (G - 1);
+  Lane L;
+  load_ck(q.ck_rec, ns, slot, L);
+  L.m = p.st[6 * ns + slot];
+  L.m0 = p.m0s[slot];
+  Exch<G, 1> ex;
+  ex.init(lane, L.m);
+  const JacConst jc = jac_const<G>(L.m0, L.m, pg);
+  const double dt = p.dts[slot], h = 0.5 * dt;
+  const double kg = GR ? p.kgr * L.m0 * L.m0 : 0.0;
+  KepDiag dg{0.0, 1.0e300};
+  auto put_state = [&](double* row) {
+    row[0] = L.qx; row[ns] = L.qy; row[2 * ns] = L.qz;
+    row[3 * ns] = L.vx; row[4 * ns] = L.vy; row[5 * ns] = L.vz;
+  };
+  double vkx, vky, vkz;
+  if constexpr (SCH == SCHEME_SABA) {
+    const int nu = p.saba_n;
+    const double c1dt = p.sc[0] * dt;
+    for (int s = 0; s < q.n_rec; ++s)
+      for (int k = 0; k < nu; ++k) {
+        double* row = q.tape_rec + ((size_t)s * nu + k) * TAPE_ROWS * ns + slot;
+        const double tau = k > 0 ? p.sc[k] * dt : (q.rec_first_synced && s == 0 ? c1dt : 2.0 * c1dt);
+        put_state(row);
+        row[6 * ns] = drift(L, jc.Mi, tau, dg);
+        kick_jacobi<G, 1, GR>(L, ex, jc, pg, p.sd[k] * dt, vkx, vky, vkz, kg);
+        row[7 * ns] = vkx; row[8 * ns] = vky; row[9 * ns] = vkz;
+      }
+  } else if constexpr (SCH == WH_KDK) {
+    double ti = q.rec_first_synced ? h : dt;
+    for (int s = 0; s < q.n_rec; ++s) {
+      double* row = q.tape_rec + (size_t)s * TAPE_ROWS * ns + slot;
+      put_state(row);
+      kick_jacobi<G, 1, GR>(L, ex, jc, pg, ti, vkx, vky, vkz, kg);
+      row[7 * ns] = vkx; row[8 * ns] = vky; row[9 * ns] = vkz;
+      ti = dt;
+      row[6 * ns] = drift(L, jc.Mi, dt, dg);
+    }
+  } else {
+    double tk = q.rec_first_synced ? h : dt;
+    for (int s = 0; s < q.n_rec; ++s) {
+      double* row = q.tape_rec + (size_t)s * TAPE_ROWS * ns + slot;
+      put_state(row);
+      row[6 * ns] = drift(L, jc.Mi, tk, dg);
+      tk = dt;
+      kick_jacobi<G, 1, GR>(L, ex, jc, pg, dt, vkx, vky, vkz, kg);
+      row[7 * ns] = vkx; row[8 * ns] = vky; row[9 * ns] = vkz;
+    }
+  }
+}
+
+template <int G, bool GR, int SCH>
+__device__ void adj_sweep_jac(const AdjParams& q, int slot, int lane) {
+  const StepParams& p = q.sp;
+  const int ns = p.ns;
+  const int pg = lane & (G - 1);
+  const double m = p.st[6 * ns + slot], m0 = p.m0s[slot];
+  Exch<G, 1> ex;
+  ex.init(lane, m);
+  const JacConst jc = jac_const<G>(m0, m, pg);
+  const double dt = p.dts[slot], h = 0.5 * dt;
+  const double kg = GR ? p.kgr * m0 * m0 : 0.0;
+  Grad a;
+  load_grad(q.grad, ns, slot, a);
+  double gMim1 = 0.0;
+  KepFwd k;
+  if constexpr (SCH == SCHEME_SABA) {
+    const int nu = p.saba_n;
+    const double c1dt = p.sc[0] * dt;
+    for (int u = q.n_seg * nu - 1; u >= 0; --u) {
+      const int s = u / nu, kk = u - s * nu;
+      const double* row = q.tape + (size_t)u * TAPE_ROWS * ns + slot;
+      const double tau = kk > 0 ? p.sc[kk] * dt : (q.first_synced && s == 0 ? c1dt : 2.0 * c1dt);
+      const double x0x = row[0], x0y = row[ns], x0z = row[2 * ns];
+      const double v0x = row[3 * ns], v0y = row[4 * ns], v0z = row[5 * ns];
+      kepler_at_X(x0x, x0y, x0z, v0x, v0y, v0z, jc.Mi, tau, row[6 * ns], k);
+      const double x1x = k.f * x0x + k.g * v0x, x1y = k.f * x0y + k.g * v0y, x1z = k.f * x0z + k.g * v0z;
+      kick_jacobi_vjp<G, GR>(a, gMim1, ex, jc, pg, m, m0, kg, x1x, x1y, x1z, p.sd[kk] * dt);
+      jac_drift_vjp(a, gMim1, jc.Mi, x0x, x0y, x0z, v0x, v0y, v0z, tau, row[6 * ns], k);
+      jac_fold_mim1<G>(a, gMim1, pg);
+    }
+  } else if constexpr (SCH == WH_KDK) {
+    for (int s = q.n_seg - 1; s >= 0; --s) {
+      const double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
+      const double x0x = row[0], x0y = row[ns], x0z = row[2 * ns];
+      const double ti = (q.first_synced && s == 0) ? h : dt;
+      // K(dt) from (x0, V' after the kick), then the kick at x0
+      jac_drift_vjp(a, gMim1, jc.Mi, x0x, x0y, x0z, row[7 * ns], row[8 * ns], row[9 * ns], dt, row[6 * ns], k);
+      kick_jacobi_vjp<G, GR>(a, gMim1, ex, jc, pg, m, m0, kg, x0x, x0y, x0z, ti);
+      jac_fold_mim1<G>(a, gMim1, pg);
+    }
+  } else {
+    for (int s = q.n_seg - 1; s >= 0; --s) {
+      const double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
+      const double tau = (q.first_synced && s == 0) ? h : dt;
+      const double x0x = row[0], x0y = row[ns], x0z = row[2 * ns];
+      const double v0x = row[3 * ns], v0y = row[4 * ns], v0z = row[5 * ns];
+      kepler_at_X(x0x, x0y, x0z, v0x, v0y, v0z, jc.Mi, tau, row[6 * ns], k);
+      const double x1x = k.f * x0x + k.g * v0x, x1y = k.f * x0y + k.g * v0y, x1z = k.f * x0z + k.g * v0z;
+      kick_jacobi_vjp<G, GR>(a, gMim1, ex, jc, pg, m, m0, kg, x1x, x1y, x1z, dt);
+      jac_drift_vjp(a, gMim1, jc.Mi, x0x, x0y, x0z, v0x, v0y, v0z, tau, row[6 * ns], k);
+      jac_fold_mim1<G>(a, gMim1, pg);   // per step, so the sums do not depend on the segments
+    }
+  }
+  store_grad(q.grad, ns, slot, a);
+}
+
+template <bool GR, int SCH> __global__ __launch_bounds__(256) void k_adj_segment_jac(AdjParams q) {
+  const StepParams& p = q.sp;
+  const int lane = threadIdx.x & 63;
+  int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const bool sweep = wave < q.sweep_waves;
+  if (!sweep) wave -= q.sweep_waves;
+  if (wave >= p.w8) return;
+  const int slot = wave * 64 + lane;
+  if (sweep) {
+    if (wave < p.w1) adj_sweep_jac<1, GR, SCH>(q, slot, lane);
+    else if (wave < p.w2) adj_sweep_jac<2, GR, SCH>(q, slot, lane);
+    else if (wave < p.w4) adj_sweep_jac<4, GR, SCH>(q, slot, lane);
+    else adj_sweep_jac<8, GR, SCH>(q, slot, lane);
+  } else {
+    if (wave < p.w1) adj_record_jac<1, GR, SCH>(q, slot, lane);
+    else if (wave < p.w2) adj_record_jac<2, GR, SCH>(q, slot, lane);
+    else if (wave < p.w4) adj_record_jac<4, GR, SCH>(q, slot, lane);
+    else adj_record_jac<8, GR, SCH>(q, slot, lane);
+  }
+}
+
+// The synchronized output of a Jacobi context: the pending operation (K(h),
+// K(c_1 dt) or the half kick) on the stored state, then the transform to
+// DHC.  The grad rows hold the caller's dL/dQ_T, dL/dV_T on entry and
+// dL/d(stored state) on return.
+template <int G, bool GR, int SCH> __device__ void adj_init_jac_lane(const AdjParams& q, int slot, int lane,
+                                                                   int synced) {
+  const StepParams& p = q.sp;
+  const int ns = p.ns;
+  const int pg = lane & (G - 1);
+  Grad a;
+  load_grad(q.grad, ns, slot, a);
+  Lane L;
+  load_ck(q.ck, ns, slot, L);
+  L.m = p.st[6 * ns + slot];
+  const double m0 = p.m0s[slot], dt = p.dts[slot];
+  const double kg = GR ? p.kgr * m0 * m0 : 0.0;
+  const JacConst jc = jac_const<G>(m0, L.m, pg);
+  Exch<G, 1> ex;
+  ex.init(lane, L.m);
+  double gMim1 = 0.0;
+  const double x0x = L.qx, x0y = L.qy, x0z = L.qz, v0x = L.vx, v0y = L.vy, v0z = L.vz;
+  double tau = 0.0, X = 0.0;
+  if (!synced) {
+    KepDiag dg{0.0, 1.0e300};
+    if (SCH == WH_KDK) {
+      double vkx, vky, vkz;
+      kick_jacobi<G, 1, GR>(L, ex, jc, pg, 0.5 * dt, vkx, vky, vkz, kg);
+    } else {
+      tau = SCH == SCHEME_SABA ? p.sc[0] * dt : 0.5 * dt;
+      X = drift(L, jc.Mi, tau, dg);
+    }
+  }
+  jac_to_dhc_vjp<G>(a, gMim1, jc, pg, L.m, m0, L.qx + L.cqx, L.qy + L.cqy, L.qz + L.cqz, L.vx + L.cvx,
+                    L.vy + L.cvy, L.vz + L.cvz);
+  if (!synced) {
+    if (SCH == WH_KDK) {
+      kick_jacobi_vjp<G, GR>(a, gMim1, ex, jc, pg, L.m, m0, kg, x0x, x0y, x0z, 0.5 * dt);
+    } else {
+      KepFwd k;
+      jac_drift_vjp(a, gMim1, jc.Mi, x0x, x0y, x0z, v0x, v0y, v0z, tau, X, k);
+    }
+  }
+  jac_fold_mim1<G>(a, gMim1, pg);
+  store_grad(q.grad, ns, slot, a);
+}
+
+template <bool GR, int SCH> __global__ __launch_bounds__(256) void k_adj_init_jac(AdjParams q, int synced) {
+  const StepParams& p = q.sp;
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  const int slot = wave * 64 + lane;
+  if (wave < p.w1) adj_init_jac_lane<1, GR, SCH>(q, slot, lane, synced);
+  else if (wave < p.w2) adj_init_jac_lane<2, GR, SCH>(q, slot, lane, synced);
+  else if (wave < p.w4) adj_init_jac_lane<4, GR, SCH>(q, slot, lane, synced);
+  else adj_init_jac_lane<8, GR, SCH>(q, slot, lane, synced);
+}
+
+// Before the outputs: the grad rows hold dL/d(initial Jacobi state); the
+// input transform's adjoint at the initial DHC state (rebuilt from the first
+// checkpoint) turns them into dL/d(Q0, V0) and adds the mass terms.
+template <int G> __device__ void adj_in_jac_lane(const AdjParams& q, int slot, int lane) {
+  const StepParams& p = q.sp;
+  const int ns = p.ns;
+  const int pg = lane & (G - 1);
+  Grad a;
+  load_grad(q.grad, ns, slot, a);
+  Lane L;
+  load_ck(q.ck, ns, slot, L);
+  L.m = p.st[6 * ns + slot];
+  L.m0 = p.m0s[slot];
+  L.qx += L.cqx; L.qy += L.cqy; L.qz += L.cqz;
+  L.vx += L.cvx; L.vy += L.cvy; L.vz += L.cvz;
+  const JacConst jc = jac_const<G>(L.m0, L.m, pg);
+  jacobi_to_dhc<G>(L, pg);
+  double gMim1 = 0.0;
+  dhc_to_jac_vjp<G>(a, gMim1, jc, pg, L.m, L.m0, L.qx, L.qy, L.qz, L.vx, L.vy, L.vz);
+  jac_fold_mim1<G>(a, gMim1, pg);
+  store_grad(q.grad, ns, slot, a);
+}
+
+__global__ __launch_bounds__(256) void k_adj_in_jac(AdjParams q) {
+  const StepParams& p = q.sp;
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  const int slot = wave * 64 + lane;
+  if (wave < p.w1) adj_in_jac_lane<1>(q, slot, lane);
+  else if (wave < p.w2) adj_in_jac_lane<2>(q, slot, lane);
+  else if (wave < p.w4) adj_in_jac_lane<4>(q, slot, lane);
+  else adj_in_jac_lane<8>(q, slot, lane);
+}
+
 // Adjoint of the closing drift of the synchronized output (K(h), or K(c_1 dt)
 // for SABA_n; the identity when no step was taken), from the caller's
 // dL/dQ_T, dL/dV_T.
@@ -2874,8 +3274,6 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
   if (((uintptr_t)tape & 255) != 0) return fail(WH_EINVAL, "tape must be 256-byte aligned");
   if (c->cfg.scheme != WH_DKD && c->cfg.scheme != WH_KDK && c->cfg.scheme < WH_SABA2)
     return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD, WH_KDK and WH_SABA2..4");
-  if (c->cfg.coords != WH_COORDS_DHC)
-    return fail(WH_ESTATE, "reverse mode is implemented in democratic heliocentric coordinates");
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
   if (ckpt_every * tape_units(c) > (1 << 30)) return fail(WH_EINVAL, "ckpt_every too large for this scheme");
   TapeLayout T = tape_layout(c->P.ns, n_steps, ckpt_every, tape_units(c));
@@ -2932,9 +3330,24 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
   q.rec_first_synced = 0;
   const bool gr = c->cfg.gr_c > 0;
   const bool kdk = c->cfg.scheme == WH_KDK;
+  const bool jac = c->cfg.coords == WH_COORDS_JACOBI;
   const int nw = c->P.nwaves;
   const int synced_end = (int)(c->tape_steps == 0);
-  if (!kdk) {
+  if (jac) {
+    // gather dL/dQ_T, dL/dV_T, then the output transform and pending operation per lane group
+    hipLaunchKernelGGL(k_adj_init, dim3((ns + 255) / 256), dim3(256), 0, stream, q, 1);
+    const dim3 g(nw), b(64);
+    if (c->cfg.scheme >= WH_SABA2) {
+      if (gr) hipLaunchKernelGGL((k_adj_init_jac<true, SCHEME_SABA>), g, b, 0, stream, q, synced_end);
+      else hipLaunchKernelGGL((k_adj_init_jac<false, SCHEME_SABA>), g, b, 0, stream, q, synced_end);
+    } else if (kdk) {
+      if (gr) hipLaunchKernelGGL((k_adj_init_jac<true, WH_KDK>), g, b, 0, stream, q, synced_end);
+      else hipLaunchKernelGGL((k_adj_init_jac<false, WH_KDK>), g, b, 0, stream, q, synced_end);
+    } else {
+      if (gr) hipLaunchKernelGGL((k_adj_init_jac<true, WH_DKD>), g, b, 0, stream, q, synced_end);
+      else hipLaunchKernelGGL((k_adj_init_jac<false, WH_DKD>), g, b, 0, stream, q, synced_end);
+    }
+  } else if (!kdk) {
     hipLaunchKernelGGL(k_adj_init, dim3((ns + 255) / 256), dim3(256), 0, stream, q, synced_end);
   } else {
     const dim3 g(nw), b(64);
@@ -2961,6 +3374,16 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
   const bool saba = c->cfg.scheme >= WH_SABA2;
   auto launch = [&](int sweep_waves, int record_waves) {
     q.sweep_waves = sweep_waves;
+    if (jac) {
+      const dim3 grid(sweep_waves + record_waves), block(64);
+      if (saba && gr) hipLaunchKernelGGL((k_adj_segment_jac<true, SCHEME_SABA>), grid, block, 0, stream, q);
+      else if (saba) hipLaunchKernelGGL((k_adj_segment_jac<false, SCHEME_SABA>), grid, block, 0, stream, q);
+      else if (kdk && gr) hipLaunchKernelGGL((k_adj_segment_jac<true, WH_KDK>), grid, block, 0, stream, q);
+      else if (kdk) hipLaunchKernelGGL((k_adj_segment_jac<false, WH_KDK>), grid, block, 0, stream, q);
+      else if (gr) hipLaunchKernelGGL((k_adj_segment_jac<true, WH_DKD>), grid, block, 0, stream, q);
+      else hipLaunchKernelGGL((k_adj_segment_jac<false, WH_DKD>), grid, block, 0, stream, q);
+      return;
+    }
     if (saba) launch_adj_segment<false, SCHEME_SABA>(c, q, sweep_waves, record_waves, stream);
     else if (kdk && gr) launch_adj_segment<true, WH_KDK>(c, q, sweep_waves, record_waves, stream);
     else if (kdk) launch_adj_segment<false, WH_KDK>(c, q, sweep_waves, record_waves, stream);
@@ -2982,6 +3405,10 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
     } else {
       launch(nw, 0);
     }
+  }
+  if (jac) {
+    q.ck = ck;   // the first checkpoint: the initial state the input transform is differentiated at
+    hipLaunchKernelGGL(k_adj_in_jac, dim3(nw), dim3(64), 0, stream, q);
   }
   if (c->P.pair) hipLaunchKernelGGL(k_adj_finish_pair, dim3(nw), dim3(64), 0, stream, q);
   else if (c->P.split) hipLaunchKernelGGL(k_adj_finish<true>, dim3(nw), dim3(64), 0, stream, q);

@@ -209,11 +209,12 @@ def test_tape_validation():
         e.adjoint(np.zeros((4, 8, 3)), np.zeros((4, 8, 3)))
     assert ei.value.code == _lib.WH_ESTATE
     e.close()
-    for kw in (dict(coords="jacobi"), dict(coords="jacobi", scheme="kdk"), dict(coords="jacobi", scheme="saba2")):
-        k = Ensemble.from_systems(s, **kw)
-        with pytest.raises(_lib.WHError):
-            k.forward_ckpt(10, 5)
-        k.close()
+    k = Ensemble.from_systems(s)
+    with pytest.raises(_lib.WHError):          # the tape of another run
+        k.forward_ckpt(10, 5)
+        k.step(1)
+        k.adjoint(np.zeros((4, 8, 3)), np.zeros((4, 8, 3)))
+    k.close()
 
 
 @pytest.mark.parametrize("packing", ["auto", "split", "pair", "serial"])
@@ -352,4 +353,64 @@ def test_saba_checkpoint_interval_bitwise(packing):
     for every in (1, 7, 64):
         out = adjoint_run(s, 120, every, gQ_T, gV_T, packing=packing, scheme="saba3")
         for a, b in zip(out, ref):
+            assert np.array_equal(a, b), every
+
+
+@pytest.mark.parametrize("scheme,gr_c,n_steps,every", [("dkd", 0.0, 150, 40), ("dkd", 10065.0, 97, 10),
+                                                       ("kdk", 40.0, 150, 1000), ("kdk", 0.0, 1, 1),
+                                                       ("saba2", 0.0, 60, 7), ("saba3", 40.0, 60, 25),
+                                                       ("dkd", 40.0, 0, 5)])
+@pytest.mark.parametrize("packing", ["auto", "g8"])
+def test_jacobi_dot_product_vs_oracle_tangent(scheme, gr_c, n_steps, every, packing):
+    """Reverse mode of Jacobi contexts: DHC gradients through the input and
+    output transforms, the drifts about M_i and the Jacobi kick, against the
+    oracle's tangent of the Jacobi map."""
+    s = inputs.make_systems(16, 42, n_planets=None, n_range=(1, 8))
+    print("case: jacobi %s gr_c=%g n_steps=%d every=%d %s" % (scheme, gr_c, n_steps, every, packing), flush=True)
+    rng = np.random.default_rng(12)
+    lm = live(s)
+    gQ_T = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None]
+    gV_T = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None]
+    e = Ensemble.from_systems(s, gr_c=gr_c, scheme=scheme, coords="jacobi", packing=packing)
+    e.forward_ckpt(n_steps, every)
+    QT, VT = e.state()
+    gQ0, gV0, gm, gm0 = [x.cpu().numpy() for x in e.adjoint(gQ_T, gV_T)]
+    e.close()
+    for which in ("state", "m", "m0"):
+        dQ, dV, dm, dm0 = random_dirs(s, 13)
+        if which != "state":
+            dQ = np.zeros_like(dQ); dV = np.zeros_like(dV)
+            dm = dm if which == "m" else np.zeros_like(dm)
+            dm0 = dm0 if which == "m0" else np.zeros_like(dm0)
+        lhs = (gQ0 * dQ).sum((1, 2)) + (gV0 * dV).sum((1, 2)) + (gm * dm).sum(1) + gm0 * dm0
+        if n_steps == 0 and which != "state":
+            # no step: the round trip DHC -> Jacobi -> DHC does not depend on the
+            # masses; their gradient is rounding noise of the two transforms
+            ref = (np.abs(gQ_T * s.Q) + np.abs(gV_T * s.V)).sum((1, 2))
+            assert np.all(np.abs(lhs) < 1e-13 * ref)
+            continue
+        _, _, tQ, tV = oracle.tangent(s, n_steps, dQ, dV, dm, dm0, scheme=scheme, gr_c=gr_c, coords="jacobi")
+        rhs = (gQ_T * tQ.astype(float)).sum((1, 2)) + (gV_T * tV.astype(float)).sum((1, 2))
+        scale = np.abs(gQ_T * tQ.astype(float)).sum((1, 2)) + np.abs(gV_T * tV.astype(float)).sum((1, 2))
+        rel = np.abs(lhs - rhs) / scale
+        print("jacobi %s dot-product relative mismatch (%s): max %.2e" % (scheme, which, rel.max()), flush=True)
+        assert rel.max() < 1e-9
+
+
+@pytest.mark.parametrize("scheme,gr_c", [("dkd", 0.0), ("kdk", 10065.0), ("saba2", 0.0)])
+def test_jacobi_checkpoint_interval_bitwise(scheme, gr_c):
+    s = inputs.make_systems(19, 43, n_planets=None, n_range=(1, 8))
+    rng = np.random.default_rng(6)
+    gQ_T = rng.normal(size=(s.S, 8, 3)) * live(s)[:, :, None]
+    gV_T = rng.normal(size=(s.S, 8, 3)) * live(s)[:, :, None]
+
+    def run(every):
+        e = Ensemble.from_systems(s, gr_c=gr_c, scheme=scheme, coords="jacobi")
+        e.forward_ckpt(120, every)
+        out = [x.cpu().numpy() for x in e.state() + e.adjoint(gQ_T, gV_T)]
+        e.close()
+        return out
+    ref = run(120)
+    for every in (1, 7, 64):
+        for a, b in zip(run(every), ref):
             assert np.array_equal(a, b), every

@@ -135,10 +135,9 @@ def test_plain_per_size_path_matches_fused_bitwise():
 
 def test_unsupported_combinations_rejected():
     s = inputs.make_systems(4, 63, n_planets=3)
-    e = Ensemble.from_systems(s, coords="jacobi")
-    with pytest.raises(_lib.WHError):
-        e.forward_ckpt(10, 5)
-    e.close()
+    for packing in ("pair", "split", "serial"):       # Jacobi runs one planet per lane
+        with pytest.raises(_lib.WHError):
+            Ensemble.from_systems(s, coords="jacobi", packing=packing)
 
 
 @pytest.mark.parametrize("scheme,gr_c", [("dkd", 10065.0), ("kdk", 40.0), ("saba2", 40.0), ("dkd", 40.0)])

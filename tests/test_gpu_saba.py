@@ -96,14 +96,10 @@ def test_keep_unsynchronized_is_bitwise_reproducible():
     a.close(); b.close()
 
 
-def test_gr_in_dhc_and_jacobi_reverse_mode_rejected():
+def test_gr_in_dhc_rejected():
     s = inputs.make_systems(4, 95, n_planets=3)
     with pytest.raises(_lib.WHError):
         Ensemble.from_systems(s, scheme="saba2", gr_c=10065.0)
-    e = Ensemble.from_systems(s, scheme="saba2", coords="jacobi")
-    with pytest.raises(_lib.WHError):        # reverse mode runs in DHC
-        e.forward_ckpt(10, 5)
-    e.close()
 
 
 @pytest.mark.parametrize("coords", ["dhc", "jacobi"])
