@@ -197,8 +197,9 @@ class _Integrate(torch.autograd.Function):
 
 
 def integrate(Q0, V0, m, m0, dt, n_planets, n_steps, ckpt_every=1000, gr_c=0.0, **opts):
-    """Differentiable ensemble integration (drift-kick-drift, or kick-drift-kick
-    with scheme="kdk" among the options).
+    """Differentiable ensemble integration.  The options go to Ensemble
+    (scheme "dkd", "kdk", "saba2".."saba4"; any packing; coords "dhc" or
+    "jacobi").
 
     Q0, V0: [S, 8, 3], m: [S, 8], m0, dt: [S] float64 CUDA tensors;
     n_planets: host ints [S].  Returns the synchronized (Q_T, V_T).

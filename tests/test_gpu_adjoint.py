@@ -180,14 +180,16 @@ def test_gradients_match_central_differences(packing, scheme):
     assert rel.max() < 1e-6
 
 
-def test_autograd_function_and_gradcheck():
+@pytest.mark.parametrize("opts", [{}, {"scheme": "kdk", "packing": "pair", "gr_c": 40.0},
+                                  {"scheme": "saba2", "coords": "jacobi", "gr_c": 40.0}])
+def test_autograd_function_and_gradcheck(opts):
     s = inputs.make_systems(2, 34, n_planets=None, n_range=(2, 3))
     t = lambda a: torch.tensor(a, dtype=torch.float64, device=DEV, requires_grad=True)
     Q0, V0, m, m0 = t(s.Q), t(s.V), t(s.m), t(s.m0)
     dt = torch.tensor(s.dt, dtype=torch.float64, device=DEV)
 
     def f(Q0, V0, m, m0):
-        QT, VT = integrate(Q0, V0, m, m0, dt, s.n_planets, 6, ckpt_every=4)
+        QT, VT = integrate(Q0, V0, m, m0, dt, s.n_planets, 6, ckpt_every=4, **opts)
         return QT, VT
 
     assert torch.autograd.gradcheck(f, (Q0, V0, m, m0), eps=1e-7, atol=1e-6, rtol=1e-5)
