@@ -358,3 +358,55 @@ def test_million_systems_tiled(packing):
     Qo, Vo = oracle.integrate(sub, 300)
     eq, ev = rel_err(sub, Q[-1].cpu().numpy()[idx], V[-1].cpu().numpy()[idx], Qo, Vo)
     assert eq < TOL and ev < TOL, (eq, ev)
+
+
+@pytest.mark.parametrize("packing,scheme,gr_c", [("auto", "dkd", 0.0), ("auto", "kdk", 10065.0), ("pair", "dkd", 40.0),
+                                                 ("split", "saba3", 0.0), ("serial", "dkd", 10065.0)])
+def test_massless_planets(packing, scheme, gr_c):
+    """Test particles (m = 0, which the method allows) inside real systems:
+    they feel the planets and the star but act on nothing.  Parity with the
+    oracle after 1e3 steps, and the energy of a synchronized copy equals the
+    oracle's on the same state (a test particle's terms vanish; a system of
+    test particles only has E = 0)."""
+    s = inputs.make_systems(40, 71, n_planets=None, n_range=(2, 8))
+    rng = np.random.default_rng(4)
+    lm = live(s)
+    zero = lm & (rng.random(lm.shape) < 0.3)
+    s.m[zero] = 0.0
+    check(s, 1000, scheme=scheme, gr_c=gr_c, packing=packing)
+    # the energy is that of the massive bodies alone: a test particle's terms vanish
+    e = Ensemble.from_systems(s, scheme=scheme, gr_c=gr_c, packing=packing)
+    e.step(100)
+    Q, V = e.state()
+    E = e.energy().cpu().numpy()
+    e.close()
+    Eo = oracle.energy(s, Q.cpu().numpy(), V.cpu().numpy(), gr_c=gr_c).astype(float)
+    # (a system whose planets are all test particles has E = 0 exactly)
+    assert np.all(np.abs(E - Eo) <= 1e-14 * np.abs(Eo))
+
+
+@pytest.mark.parametrize("packing", ["auto", "pair"])
+def test_massless_planets_reverse_mode(packing):
+    """The gradient with respect to a test particle's (zero) mass is the
+    derivative of the map there, which the oracle's tangent gives."""
+    s = inputs.make_systems(16, 72, n_planets=None, n_range=(2, 8))
+    rng = np.random.default_rng(5)
+    lm = live(s)
+    zero = lm & (rng.random(lm.shape) < 0.3)
+    s.m[zero] = 0.0
+    gQ_T = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None]
+    gV_T = rng.normal(size=(s.S, 8, 3)) * lm[:, :, None]
+    e = Ensemble.from_systems(s, packing=packing)
+    e.forward_ckpt(200, 64)
+    gQ0, gV0, gm, gm0 = [x.cpu().numpy() for x in e.adjoint(gQ_T, gV_T)]
+    e.close()
+    dm = np.where(zero, 1e-6, 0.0)
+    z3 = np.zeros((s.S, 8, 3))
+    _, _, tQ, tV = oracle.tangent(s, 200, z3, z3, dm, np.zeros(s.S))
+    lhs = (gm * dm).sum(1)
+    rhs = (gQ_T * tQ.astype(float)).sum((1, 2)) + (gV_T * tV.astype(float)).sum((1, 2))
+    scale = np.abs(gQ_T * tQ.astype(float)).sum((1, 2)) + np.abs(gV_T * tV.astype(float)).sum((1, 2))
+    has = zero.any(axis=1)
+    rel = np.abs(lhs - rhs)[has] / scale[has]
+    print("test-particle mass direction: max mismatch %.2e" % rel.max(), flush=True)
+    assert rel.max() < 1e-9
