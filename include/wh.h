@@ -109,7 +109,7 @@ enum {
                            drifting about the centre of mass of the star and the planets inside it with
                            mu = G (m0 + m_1 + ... + m_i), and a kick of the remaining Hamiltonian; no jump.
                            Inputs and outputs stay in the DHC layout; GR (the same potential) enters
-                           the kick; no reverse mode. */
+                           the kick; one planet per lane (WH_PACK_POW2 or WH_PACK_G8). */
 };
 
 /* Sticky per-system status bits. */

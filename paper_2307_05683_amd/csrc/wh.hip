@@ -4,8 +4,9 @@
 // Hot path: one persistent kernel advances every system by a chunk of steps
 // with the state held in VGPRs.  In the default layout each lane carries one
 // planet, each aligned group of G lanes one system, each 64-lane wavefront
-// 64/G systems; two further layouts put two planets on a lane (wh_pair.h) or
-// one planet on two lanes (wh_split.h).  The
+// 64/G systems; further layouts put two planets on a lane (wh_pair.h), one
+// planet on two lanes (wh_split.h) or a whole system on one lane (the serial
+// step below).  The
 // step is the drift-kick-drift composition of the WHFast512 paper (Sec. 3.1)
 // with the drifts of consecutive steps merged and, without GR, the two half
 // jumps merged (they commute with the interaction kick then).  Output reads
