@@ -1480,7 +1480,7 @@ __device__ __forceinline__ void kick_block_vjp_pair(Grad& a, Grad& b, const Pair
 // The same two roles in the pair layout: lane l of wave w holds slots
 // 128 w + l (a) and 128 w + 64 + l (b).
 template <int G, bool GR, int SCH = WH_DKD>
-__device__ void adj_record_pair(const AdjParams& q, int sa, int lane) {
+__device__ void adj_record_pair(const AdjParams& q, int sa) {
   const StepParams& p = q.sp;
   const int ns = p.ns, sb = sa + 64;
   Lane A, B;
@@ -1700,9 +1700,9 @@ template <bool GR, int SCH> __global__ __launch_bounds__(256) void k_adj_segment
     else if (wave < p.w2) adj_sweep_pair<2, GR, SCH>(q, sa, lane);
     else adj_sweep_pair<4, GR, SCH>(q, sa, lane);
   } else {
-    if (wave < p.w1) adj_record_pair<1, GR, SCH>(q, sa, lane);
-    else if (wave < p.w2) adj_record_pair<2, GR, SCH>(q, sa, lane);
-    else adj_record_pair<4, GR, SCH>(q, sa, lane);
+    if (wave < p.w1) adj_record_pair<1, GR, SCH>(q, sa);
+    else if (wave < p.w2) adj_record_pair<2, GR, SCH>(q, sa);
+    else adj_record_pair<4, GR, SCH>(q, sa);
   }
 }
 
