@@ -27,3 +27,21 @@ def test_autotune_choice_cache_and_results(tmp_path, monkeypatch):
     live = torch.tensor(np.arange(8)[None, :] < s.n_planets[:, None], device=Qa.device)
     d = (Qa - Qb).abs()[live].max().item()
     assert d < 1e-13 * Qb.abs().max().item()
+
+
+def test_autotune_times_every_packing(tmp_path, monkeypatch):
+    """Every lane packing is a candidate (the exchange only varies where a
+    layout has two schedules), and each candidate's run agrees with the
+    default packing to rounding."""
+    monkeypatch.setenv("WH_TUNE_CACHE", str(tmp_path / "tune.json"))
+    s = inputs.make_systems(200, 42, n_planets=None, n_range=(1, 8))
+    cands = {"packing": ["pow2", "g8", "pair", "split", "serial"], "exchange": ["dpp", "lds"], "block_waves": [1],
+             "chunk_steps": [256]}
+    best, table = autotune(s, steps=256, warmup=16, candidates=cands, use_cache=False)
+    packings = sorted(r["opts"]["packing"] for r in table)
+    assert packings == ["g8", "g8", "pair", "pow2", "pow2", "serial", "split"], packings
+    b = Ensemble.from_systems(s); b.step(200); Qb, _ = b.state(); b.close()
+    live = torch.tensor(np.arange(8)[None, :] < s.n_planets[:, None], device=Qb.device)
+    for r in table:
+        a = Ensemble.from_systems(s, **r["opts"]); a.step(200); Qa, _ = a.state(); a.close()
+        assert (Qa - Qb).abs()[live].max().item() < 1e-13 * Qb.abs().max().item(), r["opts"]
