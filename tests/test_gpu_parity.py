@@ -196,23 +196,27 @@ def test_energy_matches_oracle(scheme, gr_c):
     e.close()
 
 
-def test_flags_isolated_and_healthy_systems_unaffected():
+@pytest.mark.parametrize("packing", ["auto", "pair", "split", "serial"])
+def test_flags_isolated_and_healthy_systems_unaffected(packing):
     s = inputs.make_systems(24, 14, n_planets=None, n_range=(2, 8))
     bad = s.copy()
-    # system 3: one planet on an unbound orbit; system 7: a NaN velocity
+    # system 3: one planet on an unbound orbit; system 7: a NaN velocity;
+    # system 11: two planets starting at the same place (the first half drift
+    # separates them; whatever follows stays inside that system)
     bad.V[3, 0] *= 3.0
     bad.V[7, 1, 0] = np.nan
-    e = Ensemble.from_systems(bad)
+    bad.Q[11, 1] = bad.Q[11, 0]
+    e = Ensemble.from_systems(bad, packing=packing)
     e.step(50)
     f = e.flags().cpu().numpy()
     Qb, Vb = e.state()
     e.close()
     assert f[3] & _lib.WH_F_HYPERBOLIC
     assert f[7] & _lib.WH_F_NONFINITE
-    others = [k for k in range(s.S) if k not in (3, 7)]
+    others = [k for k in range(s.S) if k not in (3, 7, 11)]
     assert np.all(f[others] == 0)
     good = s.subset(others)
-    g = Ensemble.from_systems(good)
+    g = Ensemble.from_systems(good, packing=packing)
     g.step(50)
     Qg, Vg = g.state()
     g.close()
