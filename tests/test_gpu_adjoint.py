@@ -416,3 +416,23 @@ def test_jacobi_checkpoint_interval_bitwise(scheme, gr_c):
     for every in (1, 7, 64):
         for a, b in zip(run(every), ref):
             assert np.array_equal(a, b), every
+
+
+def test_tape_size_follows_the_scheme():
+    """The tape holds 96 B per slot per checkpoint plus two segment buffers of
+    80 B per slot and recorded unit (one unit per step, n for SABA_n).  From
+    a checkpoint interval of 100 to one of 200 (1000 steps), each segment
+    buffer grows by 100 x 80 x units B per slot and 5 checkpoints go."""
+    s = inputs.make_systems(40, 44, n_planets=None, n_range=(1, 8))
+    L = _lib.load()
+    grow = {}
+    for scheme in ("dkd", "kdk", "saba3"):
+        e = Ensemble.from_systems(s, scheme=scheme)
+        grow[scheme] = int(L.wh_tape_bytes(e._ctx, 1000, 200)) - int(L.wh_tape_bytes(e._ctx, 1000, 100))
+        assert int(L.wh_tape_bytes(e._ctx, 10, 0)) == 0                  # ckpt_every < 1
+        assert int(L.wh_tape_bytes(e._ctx, 10, (1 << 30) + 1)) == 0      # beyond the cap
+        e.close()
+    ns = grow["dkd"] // (2 * 100 * 80 - 5 * 96)
+    assert ns % 64 == 0 and grow["dkd"] == ns * (2 * 100 * 80 - 5 * 96)
+    assert grow["kdk"] == grow["dkd"]
+    assert grow["saba3"] == ns * (2 * 100 * 80 * 3 - 5 * 96)
