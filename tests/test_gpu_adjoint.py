@@ -436,3 +436,27 @@ def test_tape_size_follows_the_scheme():
     assert ns % 64 == 0 and grow["dkd"] == ns * (2 * 100 * 80 - 5 * 96)
     assert grow["kdk"] == grow["dkd"]
     assert grow["saba3"] == ns * (2 * 100 * 80 * 3 - 5 * 96)
+
+
+@pytest.mark.parametrize("packing", ["pair", "serial"])
+def test_reverse_mode_on_the_gr_workload_sampled(packing):
+    """Reverse mode at the size of the GR workload (65536 eight-planet
+    systems with GR; 4096 pair wavefronts, or 1024 one-lane-per-system ones),
+    a short run with three segments: sampled systems pass the dot-product
+    test against the oracle tangent."""
+    s = inputs.workload("large8gr")
+    n_steps, every = 60, 25
+    rng = np.random.default_rng(14)
+    gQ_T = rng.normal(size=(s.S, 8, 3))
+    gV_T = rng.normal(size=(s.S, 8, 3))
+    _, _, gQ0, gV0, gm, gm0 = adjoint_run(s, n_steps, every, gQ_T, gV_T, gr_c=inputs.GR_C, packing=packing)
+    idx = np.random.default_rng(3).choice(s.S, 8, replace=False)
+    sub = s.subset(idx)
+    dQ, dV, dm, dm0 = random_dirs(sub, 15)
+    _, _, tQ, tV = oracle.tangent(sub, n_steps, dQ, dV, dm, dm0, gr_c=inputs.GR_C)
+    lhs = (gQ0[idx] * dQ).sum((1, 2)) + (gV0[idx] * dV).sum((1, 2)) + (gm[idx] * dm).sum(1) + gm0[idx] * dm0
+    rhs = (gQ_T[idx] * tQ.astype(float)).sum((1, 2)) + (gV_T[idx] * tV.astype(float)).sum((1, 2))
+    scale = np.abs(gQ_T[idx] * tQ.astype(float)).sum((1, 2)) + np.abs(gV_T[idx] * tV.astype(float)).sum((1, 2))
+    rel = np.abs(lhs - rhs) / scale
+    print("dot-product relative mismatch (GR workload, %s): max %.2e" % (packing, rel.max()), flush=True)
+    assert rel.max() < 1e-9
