@@ -3009,16 +3009,27 @@ wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st
 
 wh_status ensure_graph(wh_ctx* c) {
   if (c->gexec) return WH_OK;
-  wh_status s;
-  if ((s = hip_check(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate"))) return s;
-  if ((s = hip_check(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture")))
+  // a failed attempt releases what it made, so a later call starts afresh
+  auto release = [c](wh_status s) {
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->graph = nullptr;
+    c->cap_stream = nullptr;
+    c->gexec = nullptr;
     return s;
+  };
+  wh_status s;
+  if ((s = hip_check(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate")))
+    return release(s);
+  if ((s = hip_check(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture")))
+    return release(s);
   for (int i = 0; i < c->graph_launches; ++i) launch_step(c, c->chunk, c->cap_stream);
   hipError_t le = hipGetLastError();
   hipError_t ee = hipStreamEndCapture(c->cap_stream, &c->graph);
-  if ((s = hip_check(le, "launch during capture"))) return s;
-  if ((s = hip_check(ee, "end capture"))) return s;
-  if ((s = hip_check(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0), "graph instantiate"))) return s;
+  if ((s = hip_check(le, "launch during capture"))) return release(s);
+  if ((s = hip_check(ee, "end capture"))) return release(s);
+  if ((s = hip_check(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0), "graph instantiate")))
+    return release(s);
   return WH_OK;
 }
 
@@ -3128,6 +3139,7 @@ wh_status wh_init(wh_ctx** out, const wh_config* cfg, const int32_t* n_planets, 
       (st = hip_check(hipMemcpyAsync(h_dt.data(), dt, sizeof(double) * S, hipMemcpyDeviceToHost, stream), "copy dt")) ||
       (st = hip_check(hipMemcpyAsync(h_m.data(), m, sizeof(double) * 8 * S, hipMemcpyDeviceToHost, stream), "copy m")) ||
       (st = hip_check(hipStreamSynchronize(stream), "synchronize"))) {
+    (void)hipStreamSynchronize(stream);   // copies already queued write into the host vectors
     delete c;
     return st;
   }
@@ -3159,23 +3171,25 @@ wh_status wh_init(wh_ctx** out, const wh_config* cfg, const int32_t* n_planets, 
   c->chunk = cfg->chunk_steps > 0 ? cfg->chunk_steps : 4096;
   c->graph_launches = cfg->graph_launches == 0 ? 8 : cfg->graph_launches;
   const int ns = c->P.ns;
+  // from here on the stream may hold copies that read the context's slot
+  // tables: drain it before freeing the context on a failure
+  auto abandon = [&](wh_status s) {
+    (void)hipStreamSynchronize(stream);
+    delete c;
+    return s;
+  };
   if ((st = hip_check(hipMemcpyAsync(c->slot_sys, c->P.slot_sys.data(), sizeof(int) * ns, hipMemcpyHostToDevice,
                                      stream), "upload slot table")) ||
       (st = hip_check(hipMemcpyAsync(c->slot_pl, c->P.slot_pl.data(), sizeof(int) * ns, hipMemcpyHostToDevice,
-                                     stream), "upload slot table"))) {
-    delete c;
-    return st;
-  }
+                                     stream), "upload slot table")))
+    return abandon(st);
   hipLaunchKernelGGL(k_gather, dim3((ns + 255) / 256), dim3(256), 0, stream, c->st, ns, c->m0s, c->dts, c->slot_sys,
                      c->slot_pl, m0, m, Q, V, dt, c->P.split ? 1 : 0);
   hipLaunchKernelGGL(k_fill_u32, dim3((S + 255) / 256), dim3(256), 0, stream, c->flags, 0u, S);
   hipLaunchKernelGGL(k_fill_u32, dim3((S + 255) / 256), dim3(256), 0, stream, (uint32_t*)c->synced, 1u, S);
   if (cfg->coords == WH_COORDS_JACOBI)
     hipLaunchKernelGGL(k_to_jacobi, dim3(c->P.nwaves), dim3(64), 0, stream, step_params(c, 0));
-  if ((st = hip_check(hipGetLastError(), "init kernels"))) {
-    delete c;
-    return st;
-  }
+  if ((st = hip_check(hipGetLastError(), "init kernels"))) return abandon(st);
   // the slot tables live in the context and must outlive the async copies;
   // synchronize so the caller may free the input arrays right away
   if ((st = hip_check(hipStreamSynchronize(stream), "synchronize"))) {
