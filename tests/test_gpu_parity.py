@@ -234,13 +234,24 @@ def test_zmax_flag_on_large_step():
     assert np.all(f[[0, 1, 3, 4, 5, 6, 7]] == 0)
 
 
-@pytest.mark.parametrize("field,value", [("dt", 0.0), ("dt", -1.0), ("m0", 0.0), ("m", -1e-5)])
+@pytest.mark.parametrize("field,value", [("dt", 0.0), ("dt", -1.0), ("dt", float("nan")), ("m0", 0.0),
+                                         ("m0", float("inf")), ("m", -1e-5), ("m", float("nan"))])
 def test_invalid_inputs_rejected(field, value):
     s = inputs.make_systems(4, 16, n_planets=3)
+    good = inputs.make_systems(4, 16, n_planets=3)
     getattr(s, field)[1] = value
     with pytest.raises(_lib.WHError) as ei:
         Ensemble.from_systems(s)
     assert ei.value.code == _lib.WH_EINVAL
+    # a rejected call leaves nothing behind: the same systems, valid, still integrate
+    e = Ensemble.from_systems(good)
+    e.step(10)
+    Q, V = e.state()
+    assert e.steps_done == 10
+    e.close()
+    Qo, Vo = oracle.integrate(good, 10)
+    eq, ev = rel_err(good, Q.cpu().numpy(), V.cpu().numpy(), Qo, Vo)
+    assert eq < TOL and ev < TOL, (eq, ev)
 
 
 def test_uniform_full_size_sampled():
