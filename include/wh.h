@@ -240,6 +240,33 @@ wh_status wh_kepler_envelope(int64_t n, const double* Q, const double* V, const 
                              int32_t terms_newton, double* Q_out, double* V_out, double* a_err, double* zmax_out,
                              hipStream_t stream);
 
+/* ---- integration without device allocation -----------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one call
+ * that does what wh_init + wh_step_n(n_steps) + wh_get_state + wh_destroy do,
+ * with the context's workspace in a fixed device array inside the library
+ * instead of a caller buffer, and direct launches instead of a replayed HIP
+ * graph (cfg->graph_launches is ignored); results are bitwise those of that
+ * sequence with the same configuration.  It calls no hipMalloc, hipFree or
+ * other allocating routine.
+ *   cfg, n_planets (host [S]): as for wh_init; m0, m, Q, V, dt: device
+ *   inputs in the layout above (read during the call's kernels, so they must
+ *   stay valid until the stream has passed it); Q_out, V_out: device
+ *   [S*8*3], the synchronized state after n_steps >= 0 steps.
+ * The array holds WH_NOALLOC_MAX_BYTES per GPU (allocated when the library's
+ * code object is loaded on that GPU, kept until the process ends); a batch
+ * whose wh_workspace_bytes() exceeds it is rejected with WH_EWORKSPACE before
+ * anything is enqueued (16 MiB: about 16000 eight-planet systems with one
+ * planet per lane, 8000 with WH_PACK_SPLIT).  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (different streams or
+ * threads without ordering between them) race; calls on one stream are
+ * ordered and safe.  Like wh_init it reads the masses and steps back to the
+ * host to validate them (a stream synchronization). */
+#define WH_NOALLOC_MAX_BYTES (16u << 20)
+wh_status wh_integrate_noalloc(const wh_config* cfg, const int32_t* n_planets, const double* m0, const double* m,
+                               const double* Q, const double* V, const double* dt, int64_t n_steps, double* Q_out,
+                               double* V_out, hipStream_t stream);
+
 /* Message of the calling thread's last failed call ("" if none). */
 const char* wh_last_error(void);
 

@@ -21,6 +21,7 @@ WH_PACK_AUTO, WH_PACK_POW2, WH_PACK_G8, WH_PACK_PAIR, WH_PACK_SPLIT, WH_PACK_SER
 WH_F_NONFINITE, WH_F_HYPERBOLIC, WH_F_ZMAX = 1, 2, 4
 WH_EXCH_AUTO, WH_EXCH_LDS, WH_EXCH_DPP = 0, 1, 2
 WH_COORDS_DHC, WH_COORDS_JACOBI = 0, 1
+WH_NOALLOC_MAX_BYTES = 16 << 20
 ERRORS = {WH_EINVAL: "WH_EINVAL", WH_EWORKSPACE: "WH_EWORKSPACE", WH_EHIP: "WH_EHIP", WH_ESTATE: "WH_ESTATE"}
 
 
@@ -64,6 +65,7 @@ _SIGS = {
     "wh_forward_ckpt": ([vp, i64, i64, vp, sz, vp], i32),
     "wh_adjoint_n": ([vp, vp, sz, vp, vp, vp, vp, vp, vp, vp], i32),
     "wh_kepler_envelope": ([i64, vp, vp, vp, vp, i64, i32, i32, i32, i32, vp, vp, vp, vp, vp], i32),
+    "wh_integrate_noalloc": ([C.POINTER(Config), C.POINTER(i32), vp, vp, vp, vp, vp, i64, vp, vp, vp], i32),
     "wh_last_error": ([], C.c_char_p),
     "wh_destroy": ([vp], None),
 }

@@ -19,6 +19,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -3082,6 +3083,36 @@ void launch_adj_segment(const wh_ctx* c, const AdjParams& q, int sweep_waves, in
 // ===========================================================================
 // C ABI
 // ===========================================================================
+// Scratch array of wh_integrate_noalloc: that entry point's workspace, for
+// callers that cannot allocate device memory.  Every GPU the library runs on
+// holds its own copy (WH_NOALLOC_MAX_BYTES) until the process ends.  In host
+// code the name is a stand-in, not a device address: the device address comes
+// from hipGetSymbolAddress, once per device, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[WH_NOALLOC_MAX_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // device address of scratch, per device id
+
+// Address of the current device's scratch array (looked up on the first call
+// on each device, with that device current).
+wh_status scratch_address(void** out) {
+  int dev = -1;
+  wh_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (st) return st;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if ((st = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"))) return st;
+    if (!p || ((uintptr_t)p & 255) != 0) return fail(WH_EHIP, "scratch array address is null or misaligned");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return WH_OK;
+}
+}  // namespace
+
 extern "C" {
 
 void wh_config_default(wh_config* cfg, int32_t n_systems) {
@@ -3452,6 +3483,36 @@ wh_status wh_kepler_envelope(int64_t n, const double* Q, const double* V, const 
   int64_t blocks = std::min<int64_t>((n + 255) / 256, 1 << 20);
   hipLaunchKernelGGL(k_envelope, dim3((unsigned)blocks), dim3(256), 0, stream, p);
   return hip_check(hipGetLastError(), "envelope launch");
+}
+
+wh_status wh_integrate_noalloc(const wh_config* cfg, const int32_t* n_planets, const double* m0, const double* m,
+                               const double* Q, const double* V, const double* dt, int64_t n_steps, double* Q_out,
+                               double* V_out, hipStream_t stream) {
+  std::string why;
+  if (!config_ok(cfg, why)) return fail(WH_EINVAL, why);
+  if (!n_planets) return fail(WH_EINVAL, "null planet-count array");
+  if (n_steps < 0) return fail(WH_EINVAL, "n_steps must be >= 0");
+  if (!Q_out || !V_out) return fail(WH_EINVAL, "null output pointer");
+  // no graph: its instantiation may allocate device memory
+  wh_config c2 = *cfg;
+  c2.graph_launches = -1;
+  const size_t need = wh_workspace_bytes(&c2, n_planets);
+  if (need == 0) return fail(WH_EINVAL, "invalid planet counts or packing");
+  if (need > (size_t)WH_NOALLOC_MAX_BYTES)
+    return fail(WH_EWORKSPACE, "wh_integrate_noalloc: this batch needs " + std::to_string(need) +
+                                   " bytes of workspace, more than the fixed scratch array of " +
+                                   std::to_string((size_t)WH_NOALLOC_MAX_BYTES) + " bytes");
+  void* ws = nullptr;
+  wh_status st = scratch_address(&ws);
+  if (st) return st;
+  wh_ctx* c = nullptr;
+  if ((st = wh_init(&c, &c2, n_planets, m0, m, Q, V, dt, ws, (size_t)WH_NOALLOC_MAX_BYTES, stream))) return st;
+  st = wh_step_n(c, n_steps, stream);
+  if (!st) st = wh_get_state(c, Q_out, V_out, stream);
+  // the kernels hold everything they need by value: the host context may go
+  // while they are still in flight
+  wh_destroy(c);
+  return st;
 }
 
 const char* wh_last_error(void) { return g_err.c_str(); }

@@ -122,3 +122,22 @@ def test_defaults():
     cfg = _lib.default_config(4)
     assert cfg.G == 1.0 and cfg.scheme == _lib.WH_DKD and cfg.gr_c == 0.0
     assert cfg.chunk_steps > 0 and cfg.z_max > 0
+
+
+def test_noalloc_entry_point_rejects_oversized_batches_before_any_device_call():
+    """wh_integrate_noalloc checks the batch against its fixed scratch array
+    before touching the device (so this runs without a GPU): 200000
+    eight-planet systems need ~200 MB of workspace against 16 MiB."""
+    import ctypes as C
+    import numpy as np
+    L = _lib.load()
+    n = 200000
+    cfg = _lib.default_config(n)
+    npl = np.full(n, 8, dtype=np.int32)
+    p = npl.ctypes.data_as(C.POINTER(C.c_int32))
+    assert L.wh_workspace_bytes(C.byref(cfg), p) > _lib.WH_NOALLOC_MAX_BYTES
+    rc = L.wh_integrate_noalloc(C.byref(cfg), p, None, None, None, None, None, 10, 8, 8, None)
+    assert rc == _lib.WH_EWORKSPACE
+    assert b"scratch" in L.wh_last_error()
+    rc = L.wh_integrate_noalloc(C.byref(cfg), p, None, None, None, None, None, -1, 8, 8, None)
+    assert rc == _lib.WH_EINVAL
