@@ -133,6 +133,15 @@ typedef struct {
   double z_max;        /* WH_F_ZMAX threshold on the Stumpff argument (0 = 1.0) */
   int32_t exchange;    /* WH_EXCH_* */
   int32_t coords;      /* WH_COORDS_* */
+  int32_t balance;     /* 1: balanced launch windows.  When the packing has more wavefronts than the GPU
+                          can hold at its occupancy, one launch per chunk leaves some SIMDs a wave more
+                          than others; instead each chunk of chunk_steps steps runs as a sequence of
+                          launches ("windows") of at most (resident waves per SIMD) x (SIMDs)
+                          wavefronts, each wave given a share of the chunk's steps in inverse proportion
+                          to its per-step cost (group size), so that every SIMD carries about the same
+                          work in every window.  Results are bitwise those of balance = 0 (a launch
+                          boundary only stores and reloads the state).  WH_PACK_SERIAL ignores it.
+                          0: one launch per chunk. */
 } wh_config;
 
 /* Fills *cfg with the defaults above (DKD, no GR, auto packing, DHC). */
@@ -192,6 +201,29 @@ wh_status wh_status_flags(wh_ctx* ctx, uint32_t* flags_out, hipStream_t stream);
 
 /* Steps taken so far by every system (identical for all systems). */
 int64_t wh_steps_done(const wh_ctx* ctx);
+
+/* ---- bitwise snapshots of the unsynchronized state ----------------------
+ * wh_save_state copies the context's internal state -- the unsynchronized,
+ * compensated state of every lane slot (Sec. 3.5: integration continues from
+ * it, outputs only synchronize copies), the sticky flags, the per-system
+ * synchronized markers and the step count -- into a caller-owned, 256-byte
+ * aligned device buffer of wh_state_bytes() bytes.  wh_restore_state loads
+ * such a snapshot into a context created for the same batch (same planet
+ * counts and order), packing, scheme, coordinates and GR setting (WH_ESTATE
+ * otherwise, WH_EINVAL for a buffer that is not a snapshot): stepping on
+ * from it gives bitwise the results the saved context would have given.  The
+ * buffer may be copied to the host and back in between (checkpoint files).
+ * Restore reads the snapshot's header back to the host (a stream
+ * synchronization) and drops any recorded reverse-mode tape. */
+size_t wh_state_bytes(const wh_ctx* ctx);
+wh_status wh_save_state(wh_ctx* ctx, void* dst, size_t bytes, hipStream_t stream);
+wh_status wh_restore_state(wh_ctx* ctx, const void* src, size_t bytes, hipStream_t stream);
+
+/* Launches per chunk of wh_step_n: 1 without balanced windows (or when the
+ * packing fits the GPU's resident wavefronts), else the number of windows;
+ * *slots (may be null) receives the wavefronts per window the plan assumed
+ * resident (0 without a plan).  -1 for a null context.  Host-only query. */
+int32_t wh_launch_windows(const wh_ctx* ctx, int32_t* slots);
 
 /* ---- reverse mode ------------------------------------------------------
  * Gradients of a loss of the synchronized final state with respect to the

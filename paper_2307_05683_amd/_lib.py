@@ -44,6 +44,7 @@ class Config(C.Structure):
         ("z_max", C.c_double),
         ("exchange", C.c_int32),
         ("coords", C.c_int32),
+        ("balance", C.c_int32),
     ]
 
 
@@ -61,6 +62,10 @@ _SIGS = {
     "wh_elements": ([vp, vp, vp, vp], i32),
     "wh_angular_momentum": ([vp, vp, vp], i32),
     "wh_steps_done": ([vp], i64),
+    "wh_launch_windows": ([vp, C.POINTER(i32)], i32),
+    "wh_state_bytes": ([vp], sz),
+    "wh_save_state": ([vp, vp, sz, vp], i32),
+    "wh_restore_state": ([vp, vp, sz, vp], i32),
     "wh_tape_bytes": ([vp, i64, i64], sz),
     "wh_forward_ckpt": ([vp, i64, i64, vp, sz, vp], i32),
     "wh_adjoint_n": ([vp, vp, sz, vp, vp, vp, vp, vp, vp, vp], i32),

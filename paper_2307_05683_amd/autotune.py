@@ -3,8 +3,8 @@
 Candidates: packing (1/2/4/8-lane groups, always 8 lanes, two planets per
 lane in 1/2/4-lane groups, two lanes per planet in 16-lane groups, or one
 lane per system), partner exchange (DPP or LDS crossbar; the last three
-layouts have a single schedule), wavefronts per workgroup and steps per
-launch (the splitting coordinates are the caller's choice, not a candidate:
+layouts have a single schedule), wavefronts per workgroup, steps per
+launch and balanced launch windows (on or off) (the splitting coordinates are the caller's choice, not a candidate:
 they change the results, not just the speed).  Each candidate integrates the real batch for a short run; the
 fastest (system-steps per second, GPU event time) wins.  Results are cached
 in a JSON file keyed by GPU architecture, coordinates, scheme, GR on/off, the batch size
@@ -31,6 +31,7 @@ CANDIDATES = {
     "exchange": ["dpp", "lds"],
     "block_waves": [1, 4],
     "chunk_steps": [1024, 4096],
+    "balance": [0, 1],
 }
 
 
@@ -101,6 +102,8 @@ def autotune(systems, gr_c: float = 0.0, scheme: str = "dkd", steps: int = 1024,
         opts = dict(zip(names, values))
         if opts.get("packing") in ("pair", "split", "serial") and opts.get("exchange") == "lds":
             continue              # same kernel as the DPP candidate
+        if opts.get("packing") == "serial" and opts.get("balance"):
+            continue              # the serial layout ignores the launch plan
         # the steps of a probe must cover a few launches of the candidate's chunk
         n = max(steps, 2 * opts.get("chunk_steps", 0)) if "chunk_steps" in opts else steps
         try:

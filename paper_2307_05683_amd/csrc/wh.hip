@@ -28,8 +28,10 @@
 #include "wh_adjoint.h"
 #include "wh_pair.h"
 #include "wh_split.h"
+#include "wh_host.h"
 
 using namespace wh;
+using namespace wh_host;
 
 // ===========================================================================
 // Device side
@@ -39,7 +41,7 @@ namespace {
 // State arrays, structure of arrays over lane slots: rows 0-2 Q, 3-5 V,
 // 6 m, 7-9 and 10-12 the compensation terms of Q and V (the low-order parts
 // that rounding dropped from earlier increments).
-constexpr int ROWS = 13;
+constexpr int ROWS = WH_STATE_ROWS;
 
 struct StepParams {
   double* st;            // [ROWS][ns]
@@ -58,7 +60,30 @@ struct StepParams {
   int saba_n;            // SABA_n: number of kicks per step (0 otherwise)
   double sc[5];          // SABA_n drift coefficients c_1 .. c_{n+1} (c_{n+1} = c_1)
   double sd[4];          // SABA_n kick coefficients d_1 .. d_n
+  // Balanced launch window (null: the launch covers waves wave0.. with
+  // n_steps each): wavefront k of the launch runs wave plan_wave[k] of the
+  // packing for plan_steps[k] steps, k < plan_n.
+  const int* plan_wave;
+  const int* plan_steps;
+  int plan_n;
 };
+
+// Wave of the packing and step count of launch wavefront k (k uniform over
+// the wavefront); false if the launch has no such wavefront.  (Declaring the
+// values wave-uniform with readfirstlane turned the group-size dispatch into
+// scalar branches and cost the pair kernel ~60 VGPRs, so they stay vector
+// values.)
+__device__ __forceinline__ bool launch_wave(const StepParams& p, int k, int& wave, int& n_steps) {
+  if (p.plan_wave) {
+    if (k >= p.plan_n) return false;
+    wave = p.plan_wave[k];
+    n_steps = p.plan_steps[k];
+    return true;
+  }
+  wave = p.wave0 + k;
+  n_steps = p.n_steps;
+  return wave < p.w8;
+}
 
 // Kernel scheme id of the SABA_n family (n read from StepParams).
 constexpr int SCHEME_SABA = 2;
@@ -458,8 +483,10 @@ __device__ void step_group(const StepParams& p, int slot, int lane) {
 template <bool GR, int SCHEME, int EXCH, bool JAC = false>
 __global__ __launch_bounds__(256) void k_step(StepParams p) {
   const int lane = threadIdx.x & 63;
-  const int wave = p.wave0 + (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  if (wave >= p.w8) return;
+  int wave;
+  if (!launch_wave(p, (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), wave,
+                   p.n_steps))
+    return;
   const int slot = wave * 64 + lane;
   if (wave < p.w1) step_group<1, GR, SCHEME, EXCH, JAC>(p, slot, lane);
   else if (wave < p.w2) step_group<2, GR, SCHEME, EXCH, JAC>(p, slot, lane);
@@ -589,8 +616,10 @@ template <int G, bool GR, int SCHEME> __device__ void step_group_pair(const Step
 template <bool GR, int SCHEME>
 __global__ __launch_bounds__(256) void k_step_pair(StepParams p) {
   const int lane = threadIdx.x & 63;
-  const int wave = p.wave0 + (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  if (wave >= p.w8) return;
+  int wave;
+  if (!launch_wave(p, (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), wave,
+                   p.n_steps))
+    return;
   const int sa = wave * 128 + lane;
   if (wave < p.w1) step_group_pair<1, GR, SCHEME>(p, sa, lane);
   else if (wave < p.w2) step_group_pair<2, GR, SCHEME>(p, sa, lane);
@@ -605,8 +634,10 @@ __global__ __launch_bounds__(256) void k_step_pair(StepParams p) {
 template <bool GR, int SCHEME>
 __global__ __launch_bounds__(256) void k_step_split(StepParams p) {
   const int lane = threadIdx.x & 63;
-  const int wave = p.wave0 + (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  if (wave >= p.w8) return;
+  int wave;
+  if (!launch_wave(p, (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), wave,
+                   p.n_steps))
+    return;
   step_group<G_SPLIT, GR, SCHEME, 1, false>(p, wave * 64 + lane, lane);
 }
 
@@ -1142,7 +1173,7 @@ __global__ __launch_bounds__(256) void k_to_jacobi(StepParams p) {
 // the last to the first; while segment k is swept, the next launch's input,
 // segment k - 1, is recorded by other wavefronts of the same launch into the
 // second of two segment tapes.
-constexpr int TAPE_ROWS = 10;
+constexpr int TAPE_ROWS = WH_TAPE_ROWS;
 struct AdjParams {
   StepParams sp;
   const double* ck;    // k_adj_init: the final checkpoint
@@ -2491,6 +2522,19 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int n) {
   if (i < n) p[i] = v;
 }
 
+// Header of a state snapshot (wh_save_state): what a restoring context must
+// match, and the step count of the saved state.
+struct StateHeader {
+  uint64_t magic;
+  int32_t version, S, ns, packing, coords, scheme, gr, rows;
+  int64_t steps_done;
+};
+constexpr uint64_t STATE_MAGIC = 0x5748535441544531ull;   // "WHSTATE1"
+
+__global__ void k_write_header(StateHeader h, StateHeader* dst) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *dst = h;
+}
+
 __global__ void k_copy_u32(uint32_t* dst, const uint32_t* src, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
@@ -2573,209 +2617,6 @@ wh_status hip_check(hipError_t e, const char* what) {
   return WH_OK;
 }
 
-struct Packing {
-  bool pair = false;   // WH_PACK_PAIR: two slots (planets) per lane, 128 slots per wave
-  bool split = false;  // WH_PACK_SPLIT: two lanes (copies) per planet, 16 lanes per system
-  bool serial = false; // WH_PACK_SERIAL: the G8 storage, one thread per system in the step
-  int ns = 0, nwaves = 0;
-  int w1 = 0, w2 = 0, w4 = 0, w8 = 0;
-  int plain_begin[9] = {0}, plain_end[9] = {0};   // G8 packing: waves of each planet count
-  std::vector<int32_t> slot_sys, slot_pl;
-};
-
-int group_size(int n, int packing) {
-  if (packing == WH_PACK_G8 || packing == WH_PACK_SERIAL) return 8;
-  return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : 8;
-}
-
-// Device indexing is 32-bit: row r of a [rows][ns] array sits at r * ns, with
-// up to 13 rows (the state), so the lane-slot count is capped at 2^27
-// (14 GB of state; 16.7 million eight-planet systems with one planet per
-// lane).
-constexpr int64_t MAX_SLOTS = int64_t(1) << 27;
-
-// Lane slots a packing needs, counted before any table is built.
-int64_t slots_needed(int S, const int32_t* np, int packing) {
-  int64_t cnt[9] = {0};
-  for (int s = 0; s < S; ++s) cnt[np[s]]++;
-  auto waves = [](int64_t n, int per_wave) { return (n + per_wave - 1) / per_wave; };
-  if (packing == WH_PACK_SPLIT) return waves(S, 4) * 64;
-  if (packing == WH_PACK_PAIR)
-    return (waves(cnt[1] + cnt[2], 64) + waves(cnt[3] + cnt[4], 32) + waves(cnt[5] + cnt[6] + cnt[7] + cnt[8], 16)) *
-           128;
-  if (packing == WH_PACK_G8 || packing == WH_PACK_SERIAL) {
-    int64_t w = 0;
-    for (int n = 1; n <= 8; ++n) w += waves(cnt[n], 8);
-    return w * 64;
-  }
-  return (waves(cnt[1], 64) + waves(cnt[2], 32) + waves(cnt[3] + cnt[4], 16) +
-          waves(cnt[5] + cnt[6] + cnt[7] + cnt[8], 8)) * 64;
-}
-
-// Lay systems out on lanes.  Systems of one group size fill whole waves; G8
-// packing also keeps each planet count on waves of its own (for the
-// per-size reference path).  Within a class systems keep their index order.
-bool make_packing(int S, const int32_t* np, int packing, Packing& P, std::string* why = nullptr) {
-  for (int s = 0; s < S; ++s)
-    if (np[s] < 1 || np[s] > 8) {
-      if (why) *why = "planet counts must be in 1..8";
-      return false;
-    }
-  if (slots_needed(S, np, packing) > MAX_SLOTS) {
-    if (why) *why = "too many systems: the packing needs more than 2^27 lane slots";
-    return false;
-  }
-  auto add_wave_block = [&](const std::vector<int>& systems, int G) {
-    int per_wave = 64 / G;
-    int nw = ((int)systems.size() + per_wave - 1) / per_wave;
-    for (int w = 0; w < nw; ++w)
-      for (int j = 0; j < per_wave; ++j) {
-        int idx = w * per_wave + j;
-        int s = idx < (int)systems.size() ? systems[idx] : -1;
-        for (int l = 0; l < G; ++l) {
-          P.slot_sys.push_back(s);
-          P.slot_pl.push_back(s >= 0 && l < np[s] ? l : -1);
-        }
-      }
-    P.nwaves += nw;
-  };
-  if (packing == WH_PACK_PAIR) {
-    // a system of N planets takes G = 1, 2 or 4 lanes (2G >= N); lane l of a
-    // group holds planet l in slot 128 w + (lane) and planet G + l in slot
-    // 128 w + 64 + (lane) of its wave w
-    int ends[3];
-    const int Gs[3] = {1, 2, 4};
-    for (int gi = 0; gi < 3; ++gi) {
-      const int G = Gs[gi];
-      std::vector<int> cls;
-      for (int s = 0; s < S; ++s)
-        if ((np[s] <= 2 ? 1 : np[s] <= 4 ? 2 : 4) == G) cls.push_back(s);
-      const int per_wave = 64 / G;
-      const int nw = ((int)cls.size() + per_wave - 1) / per_wave;
-      for (int w = 0; w < nw; ++w) {
-        int32_t a_sys[64], a_pl[64], b_sys[64], b_pl[64];
-        for (int j = 0; j < per_wave; ++j) {
-          const int idx = w * per_wave + j;
-          const int s = idx < (int)cls.size() ? cls[idx] : -1;
-          for (int l = 0; l < G; ++l) {
-            const int ln = j * G + l;
-            a_sys[ln] = s;
-            a_pl[ln] = s >= 0 && l < np[s] ? l : -1;
-            b_sys[ln] = s;
-            b_pl[ln] = s >= 0 && G + l < np[s] ? G + l : -1;
-          }
-        }
-        P.slot_sys.insert(P.slot_sys.end(), a_sys, a_sys + 64);
-        P.slot_pl.insert(P.slot_pl.end(), a_pl, a_pl + 64);
-        P.slot_sys.insert(P.slot_sys.end(), b_sys, b_sys + 64);
-        P.slot_pl.insert(P.slot_pl.end(), b_pl, b_pl + 64);
-      }
-      P.nwaves += nw;
-      ends[gi] = P.nwaves;
-    }
-    P.pair = true;
-    P.w1 = ends[0]; P.w2 = ends[1]; P.w4 = ends[2]; P.w8 = ends[2];
-  } else if (packing == WH_PACK_SPLIT) {
-    // every system takes a 16-lane group, four per wave, in index order;
-    // planet p (padding beyond N) in lanes 2p and 2p + 1
-    const int nw = (S + 3) / 4;
-    for (int w = 0; w < nw; ++w)
-      for (int j = 0; j < 4; ++j) {
-        const int s = w * 4 + j < S ? w * 4 + j : -1;
-        for (int l = 0; l < 16; ++l) {
-          P.slot_sys.push_back(s);
-          P.slot_pl.push_back(s >= 0 && (l >> 1) < np[s] ? l >> 1 : -1);
-        }
-      }
-    P.nwaves = nw;
-    P.split = true;
-    P.w1 = P.w2 = P.w4 = 0;
-    P.w8 = nw;
-  } else if (packing == WH_PACK_G8 || packing == WH_PACK_SERIAL) {
-    for (int n = 1; n <= 8; ++n) {
-      std::vector<int> cls;
-      for (int s = 0; s < S; ++s)
-        if (np[s] == n) cls.push_back(s);
-      P.plain_begin[n] = P.nwaves;
-      add_wave_block(cls, 8);
-      P.plain_end[n] = P.nwaves;
-    }
-    P.w1 = P.w2 = P.w4 = 0;
-    P.w8 = P.nwaves;
-    P.serial = packing == WH_PACK_SERIAL;
-  } else {
-    int ends[4];
-    const int Gs[4] = {1, 2, 4, 8};
-    for (int gi = 0; gi < 4; ++gi) {
-      std::vector<int> cls;
-      for (int s = 0; s < S; ++s)
-        if (group_size(np[s], packing) == Gs[gi]) cls.push_back(s);
-      add_wave_block(cls, Gs[gi]);
-      ends[gi] = P.nwaves;
-    }
-    P.w1 = ends[0]; P.w2 = ends[1]; P.w4 = ends[2]; P.w8 = ends[3];
-  }
-  P.ns = P.nwaves * (P.pair ? 128 : 64);
-  // every wave holds exactly 64 (pair layout: 128) slots; the device tables are copied at ns
-  if ((int)P.slot_sys.size() != P.ns || (int)P.slot_pl.size() != P.ns || P.ns != slots_needed(S, np, packing)) {
-    if (why) *why = "internal error: inconsistent lane packing";
-    return false;
-  }
-  return true;
-}
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-struct Layout {
-  size_t st, m0s, dts, slot_sys, slot_pl, flags, synced, total;
-};
-
-Layout make_layout(int S, int ns) {
-  Layout L;
-  size_t o = 0;
-  L.st = o; o = align256(o + sizeof(double) * ROWS * (size_t)ns);
-  L.m0s = o; o = align256(o + sizeof(double) * (size_t)ns);
-  L.dts = o; o = align256(o + sizeof(double) * (size_t)ns);
-  L.slot_sys = o; o = align256(o + sizeof(int) * (size_t)ns);
-  L.slot_pl = o; o = align256(o + sizeof(int) * (size_t)ns);
-  L.flags = o; o = align256(o + sizeof(uint32_t) * (size_t)S);
-  L.synced = o; o = align256(o + sizeof(int) * (size_t)S);
-  L.total = o;
-  return L;
-}
-
-bool config_ok(const wh_config* c, std::string& why) {
-  if (!c) { why = "null config"; return false; }
-  if (c->n_systems < 1) { why = "n_systems must be >= 1"; return false; }
-  if (c->G != 1.0) { why = "G must be 1 (units with G = 1)"; return false; }
-  if (c->scheme != WH_DKD && c->scheme != WH_KDK && c->scheme != WH_SABA2 && c->scheme != WH_SABA3 &&
-      c->scheme != WH_SABA4) {
-    why = "scheme must be WH_DKD, WH_KDK or WH_SABA2..4"; return false;
-  }
-  if (c->scheme >= WH_SABA2 && c->gr_c > 0 && c->coords != WH_COORDS_JACOBI) {
-    why = "SABA_n with GR needs Jacobi coordinates: in DHC the GR and jump flows do not commute"; return false;
-  }
-  if (c->packing < WH_PACK_AUTO || c->packing > WH_PACK_SERIAL) { why = "unknown packing"; return false; }
-  if (c->block_waves != 0 && c->block_waves != 1 && c->block_waves != 2 && c->block_waves != 4) {
-    why = "block_waves must be 0, 1, 2 or 4"; return false;
-  }
-  if (c->chunk_steps < 0) { why = "chunk_steps must be >= 0"; return false; }
-  if (!(c->z_max >= 0.0)) { why = "z_max must be >= 0"; return false; }
-  if (c->exchange < WH_EXCH_AUTO || c->exchange > WH_EXCH_DPP) { why = "unknown exchange"; return false; }
-  if (c->coords != WH_COORDS_DHC && c->coords != WH_COORDS_JACOBI) { why = "unknown coordinates"; return false; }
-  if ((c->packing == WH_PACK_PAIR || c->packing == WH_PACK_SPLIT || c->packing == WH_PACK_SERIAL) &&
-      c->coords != WH_COORDS_DHC) {
-    why = "the two-planets-per-lane, two-lanes-per-planet and one-lane-per-system packings run in democratic "
-          "heliocentric coordinates only";
-    return false;
-  }
-
-  if (!(c->gr_c == c->gr_c)) { why = "gr_c is NaN"; return false; }
-  return true;
-}
-
-int eff_packing(const wh_config* c) { return c->packing == WH_PACK_AUTO ? WH_PACK_POW2 : c->packing; }
-
 }  // namespace
 
 struct wh_ctx {
@@ -2803,40 +2644,16 @@ struct wh_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // balanced launch windows of one chunk (empty: one launch per chunk):
+  // window k covers entries [plan_off[k], plan_off[k + 1]) of the device
+  // tables plan_wave / plan_steps
+  std::vector<int> plan_off;
+  int* plan_wave = nullptr;
+  int* plan_steps = nullptr;
+  int plan_slots = 0;   // wavefronts the GPU holds at the kernel's occupancy
 };
 
 namespace {
-
-// SABA_n coefficients from n-point Gauss-Legendre quadrature on [0, 1]:
-// d_k the weights, c_1 the first node, c_k the gaps between nodes, c_{n+1}
-// = c_1 by symmetry.  Nodes by Newton's method on the Legendre polynomial.
-void saba_coefficients(int n, double* c, double* d) {
-  const double pi = 3.14159265358979323846;
-  std::vector<long double> t(n), w(n);
-  for (int i = 0; i < n; ++i) {
-    long double x = std::cos(pi * (n - i - 0.25) / (n + 0.5));   // ascending root guesses
-    long double dp = 1;
-    for (int it = 0; it < 60; ++it) {
-      long double pm = 1, pc = x;      // P_0, P_1
-      for (int k = 2; k <= n; ++k) {
-        long double pn = ((2 * k - 1) * x * pc - (k - 1) * pm) / k;
-        pm = pc;
-        pc = pn;
-      }
-      if (n == 1) pm = 1;
-      dp = n * (x * pc - pm) / (x * x - 1);
-      long double step = pc / dp;
-      x -= step;
-      if (std::fabs((double)step) < 1e-19) break;
-    }
-    t[i] = (x + 1) / 2;
-    w[i] = 1 / ((1 - x * x) * dp * dp);
-  }
-  c[0] = (double)t[0];
-  for (int k = 1; k < n; ++k) c[k] = (double)(t[k] - t[k - 1]);
-  c[n] = c[0];
-  for (int k = 0; k < n; ++k) d[k] = (double)w[k];
-}
 
 StepParams step_params(const wh_ctx* c, int n_steps) {
   StepParams p;
@@ -2854,6 +2671,9 @@ StepParams step_params(const wh_ctx* c, int n_steps) {
   p.kgr = c->cfg.gr_c > 0 ? 6.0 / (c->cfg.gr_c * c->cfg.gr_c) : 0.0;
   p.zlim = c->cfg.z_max > 0 ? c->cfg.z_max : 1.0;
   p.saba_n = 0;
+  p.plan_wave = nullptr;
+  p.plan_steps = nullptr;
+  p.plan_n = 0;
   for (int k = 0; k < 5; ++k) p.sc[k] = 0.0;
   for (int k = 0; k < 4; ++k) p.sd[k] = 0.0;
   if (c->cfg.scheme >= WH_SABA2) {
@@ -2863,91 +2683,128 @@ StepParams step_params(const wh_ctx* c, int n_steps) {
   return p;
 }
 
-template <int EXCH>
-void launch_step_exch(const wh_ctx* c, const StepParams& p, dim3 grid, dim3 block, size_t smem, hipStream_t st) {
+// The step kernel of a context's configuration (host stub address, for
+// hipLaunchKernel and the occupancy query).
+template <int EXCH> const void* step_kernel_exch(const wh_ctx* c) {
   const bool gr = c->cfg.gr_c > 0;
   const bool jac = c->cfg.coords == WH_COORDS_JACOBI;
+  const bool saba = c->cfg.scheme >= WH_SABA2, dkd = c->cfg.scheme == WH_DKD;
   if (c->P.pair) {
-    if (c->cfg.scheme >= WH_SABA2) {
-      hipLaunchKernelGGL((k_step_pair<false, SCHEME_SABA>), grid, block, 0, st, p);
-    } else if (c->cfg.scheme == WH_DKD) {
-      if (gr) hipLaunchKernelGGL((k_step_pair<true, WH_DKD>), grid, block, 0, st, p);
-      else hipLaunchKernelGGL((k_step_pair<false, WH_DKD>), grid, block, 0, st, p);
-    } else {
-      if (gr) hipLaunchKernelGGL((k_step_pair<true, WH_KDK>), grid, block, 0, st, p);
-      else hipLaunchKernelGGL((k_step_pair<false, WH_KDK>), grid, block, 0, st, p);
-    }
-    return;
+    if (saba) return (const void*)k_step_pair<false, SCHEME_SABA>;
+    if (dkd) return gr ? (const void*)k_step_pair<true, WH_DKD> : (const void*)k_step_pair<false, WH_DKD>;
+    return gr ? (const void*)k_step_pair<true, WH_KDK> : (const void*)k_step_pair<false, WH_KDK>;
   }
   if (c->P.split) {
-    if (c->cfg.scheme >= WH_SABA2) {
-      hipLaunchKernelGGL((k_step_split<false, SCHEME_SABA>), grid, block, 0, st, p);
-    } else if (c->cfg.scheme == WH_DKD) {
-      if (gr) hipLaunchKernelGGL((k_step_split<true, WH_DKD>), grid, block, 0, st, p);
-      else hipLaunchKernelGGL((k_step_split<false, WH_DKD>), grid, block, 0, st, p);
-    } else {
-      if (gr) hipLaunchKernelGGL((k_step_split<true, WH_KDK>), grid, block, 0, st, p);
-      else hipLaunchKernelGGL((k_step_split<false, WH_KDK>), grid, block, 0, st, p);
-    }
-    return;
+    if (saba) return (const void*)k_step_split<false, SCHEME_SABA>;
+    if (dkd) return gr ? (const void*)k_step_split<true, WH_DKD> : (const void*)k_step_split<false, WH_DKD>;
+    return gr ? (const void*)k_step_split<true, WH_KDK> : (const void*)k_step_split<false, WH_KDK>;
   }
   if (c->P.serial) {
-    if (c->cfg.scheme >= WH_SABA2) {
-      hipLaunchKernelGGL((k_step_serial<false, SCHEME_SABA>), grid, block, smem, st, p);
-    } else if (c->cfg.scheme == WH_DKD) {
-      if (gr) hipLaunchKernelGGL((k_step_serial<true, WH_DKD>), grid, block, smem, st, p);
-      else hipLaunchKernelGGL((k_step_serial<false, WH_DKD>), grid, block, smem, st, p);
-    } else {
-      if (gr) hipLaunchKernelGGL((k_step_serial<true, WH_KDK>), grid, block, smem, st, p);
-      else hipLaunchKernelGGL((k_step_serial<false, WH_KDK>), grid, block, smem, st, p);
-    }
-    return;
+    if (saba) return (const void*)k_step_serial<false, SCHEME_SABA>;
+    if (dkd) return gr ? (const void*)k_step_serial<true, WH_DKD> : (const void*)k_step_serial<false, WH_DKD>;
+    return gr ? (const void*)k_step_serial<true, WH_KDK> : (const void*)k_step_serial<false, WH_KDK>;
   }
-  if (c->cfg.scheme >= WH_SABA2) {
-    if (jac && gr) hipLaunchKernelGGL((k_step<true, SCHEME_SABA, EXCH, true>), grid, block, 0, st, p);
-    else if (jac) hipLaunchKernelGGL((k_step<false, SCHEME_SABA, EXCH, true>), grid, block, 0, st, p);
-    else hipLaunchKernelGGL((k_step<false, SCHEME_SABA, EXCH, false>), grid, block, 0, st, p);
-    return;
+  if (saba) {
+    // (GR is allowed with SABA_n in Jacobi coordinates only)
+    if (jac) return gr ? (const void*)k_step<true, SCHEME_SABA, EXCH, true>
+                       : (const void*)k_step<false, SCHEME_SABA, EXCH, true>;
+    return (const void*)k_step<false, SCHEME_SABA, EXCH, false>;
   }
   if (jac) {
-    if (c->cfg.scheme == WH_DKD) {
-      if (gr) hipLaunchKernelGGL((k_step<true, WH_DKD, EXCH, true>), grid, block, 0, st, p);
-      else hipLaunchKernelGGL((k_step<false, WH_DKD, EXCH, true>), grid, block, 0, st, p);
-    } else {
-      if (gr) hipLaunchKernelGGL((k_step<true, WH_KDK, EXCH, true>), grid, block, 0, st, p);
-      else hipLaunchKernelGGL((k_step<false, WH_KDK, EXCH, true>), grid, block, 0, st, p);
-    }
-    return;
+    if (dkd) return gr ? (const void*)k_step<true, WH_DKD, EXCH, true> : (const void*)k_step<false, WH_DKD, EXCH, true>;
+    return gr ? (const void*)k_step<true, WH_KDK, EXCH, true> : (const void*)k_step<false, WH_KDK, EXCH, true>;
   }
-  if (c->cfg.scheme == WH_DKD) {
-    if (gr) hipLaunchKernelGGL((k_step<true, WH_DKD, EXCH>), grid, block, 0, st, p);
-    else hipLaunchKernelGGL((k_step<false, WH_DKD, EXCH>), grid, block, 0, st, p);
-  } else {
-    if (gr) hipLaunchKernelGGL((k_step<true, WH_KDK, EXCH>), grid, block, 0, st, p);
-    else hipLaunchKernelGGL((k_step<false, WH_KDK, EXCH>), grid, block, 0, st, p);
-  }
+  if (dkd) return gr ? (const void*)k_step<true, WH_DKD, EXCH> : (const void*)k_step<false, WH_DKD, EXCH>;
+  return gr ? (const void*)k_step<true, WH_KDK, EXCH> : (const void*)k_step<false, WH_KDK, EXCH>;
 }
 
-void launch_step_kernel(const wh_ctx* c, const StepParams& p, int n_waves, hipStream_t st) {
-  int bw = c->block_waves;
-  int units = n_waves;
-  size_t smem = 0;
+const void* step_kernel(const wh_ctx* c) {
+  return c->exchange == WH_EXCH_LDS ? step_kernel_exch<0>(c) : step_kernel_exch<1>(c);
+}
+
+// Workgroup shape of the step kernel: bw wavefronts per workgroup and the
+// dynamic LDS per workgroup (the serial layout keeps its compensation terms
+// there: one thread per 8-slot group, at most two waves per workgroup so the
+// LDS stays within 64 KiB).
+void step_block_shape(const wh_ctx* c, int& bw, size_t& smem) {
+  bw = c->block_waves;
+  smem = 0;
   if (c->P.serial) {
-    // one thread per 8-slot group (8 per wave of slots), each with its
-    // compensation block in LDS; at most two waves per workgroup keep the
-    // dynamic LDS within 64 KiB
-    units = (n_waves * 8 + 63) / 64;
     bw = bw > 2 ? 2 : bw;
     smem = (size_t)bw * SERIAL_LDS_PER_WAVE * sizeof(double);
   }
+}
+
+// Launch the step kernel over n_waves wavefronts of the packing (units of the
+// launch: waves, or for the serial layout one thread per 8-slot group).
+void launch_step_kernel(const wh_ctx* c, const StepParams& p, int n_waves, hipStream_t st) {
+  int bw;
+  size_t smem;
+  step_block_shape(c, bw, smem);
+  const int units = c->P.serial ? (n_waves * 8 + 63) / 64 : n_waves;
   dim3 block(64 * bw), grid((units + bw - 1) / bw);
-  if (c->exchange == WH_EXCH_LDS) launch_step_exch<0>(c, p, grid, block, smem, st);
-  else launch_step_exch<1>(c, p, grid, block, smem, st);
+  StepParams q = p;
+  void* args[] = {(void*)&q};
+  (void)hipLaunchKernel(step_kernel(c), grid, block, args, smem, st);
 }
 
 void launch_step(const wh_ctx* c, int n_steps, hipStream_t st) {
   StepParams p = step_params(c, n_steps);
   launch_step_kernel(c, p, c->P.nwaves, st);
+}
+
+// Balanced launch windows for one chunk (wh_config.balance): slots =
+// (resident waves per SIMD at the step kernel's occupancy) x (SIMDs), using at
+// most as many waves per SIMD as the packing has waves for; plan_windows
+// (wh_host.h) cuts the chunk.  No plan (one launch per chunk) when the
+// packing has no more waves than slots, or more than 16 per slot (the single
+// launch's imbalance is then small), or for the serial layout.
+wh_status build_plan(wh_ctx* c, std::vector<int>& hw, std::vector<int>& hs) {
+  c->plan_off.clear();
+  c->plan_slots = 0;
+  hw.clear();
+  hs.clear();
+  if (c->cfg.balance != 1 || c->P.serial) return WH_OK;
+  int dev = 0, ncu = 0, nb = 0;
+  wh_status st;
+  if ((st = hip_check(hipGetDevice(&dev), "hipGetDevice")) ||
+      (st = hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "CU count")))
+    return st;
+  int bw;
+  size_t smem;
+  step_block_shape(c, bw, smem);
+  if ((st = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel(c), 64 * bw, smem),
+                      "occupancy query")))
+    return st;
+  const int simds = 4 * ncu;                 // CDNA: four SIMDs per compute unit
+  const int per_simd = nb * bw / 4;          // resident wavefronts per SIMD
+  const int W = c->P.nwaves;
+  const int k = std::min(per_simd, W / std::max(simds, 1));
+  if (k < 1) return WH_OK;
+  const int slots = k * simds;
+  if (W <= slots || W > 16 * slots) return WH_OK;
+  std::vector<double> cost(W);
+  for (int w = 0; w < W; ++w) cost[w] = wave_step_cost(c->P, c->cfg.gr_c > 0, w);
+  plan_windows(cost, c->chunk, slots, PLAN_Q, hw, hs, c->plan_off);
+  if (hw.size() > plan_capacity(&c->cfg, c->P)) return fail(WH_EHIP, "internal error: launch plan too large");
+  c->plan_slots = slots;
+  return WH_OK;
+}
+
+// One chunk of c->chunk steps for every wave: the balanced windows, or one
+// launch.
+void launch_chunk(const wh_ctx* c, hipStream_t st) {
+  if (c->plan_off.size() < 2) {
+    launch_step(c, c->chunk, st);
+    return;
+  }
+  for (size_t k = 0; k + 1 < c->plan_off.size(); ++k) {
+    StepParams p = step_params(c, 0);
+    p.plan_wave = c->plan_wave + c->plan_off[k];
+    p.plan_steps = c->plan_steps + c->plan_off[k];
+    p.plan_n = c->plan_off[k + 1] - c->plan_off[k];
+    launch_step_kernel(c, p, p.plan_n, st);
+  }
 }
 
 wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st, double* a = nullptr,
@@ -3024,7 +2881,7 @@ wh_status ensure_graph(wh_ctx* c) {
     return release(s);
   if ((s = hip_check(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture")))
     return release(s);
-  for (int i = 0; i < c->graph_launches; ++i) launch_step(c, c->chunk, c->cap_stream);
+  for (int i = 0; i < c->graph_launches; ++i) launch_chunk(c, c->cap_stream);
   hipError_t le = hipGetLastError();
   hipError_t ee = hipStreamEndCapture(c->cap_stream, &c->graph);
   if ((s = hip_check(le, "launch during capture"))) return release(s);
@@ -3032,30 +2889,6 @@ wh_status ensure_graph(wh_ctx* c) {
   if ((s = hip_check(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0), "graph instantiate")))
     return release(s);
   return WH_OK;
-}
-
-struct TapeLayout {
-  int64_t n_seg = 0;       // segments
-  size_t ck = 0;           // checkpoints: (n_seg + 1) x [12][ns]
-  size_t seg[2] = {0, 0};  // two segment tapes: ckpt_every x [TAPE_ROWS][ns] each
-  size_t grad = 0;         // adjoint state: [8][ns]
-  size_t total = 0;
-};
-
-// units: tape row sets per step (SABA_n records each of its n drift-kick
-// units, the other schemes one)
-TapeLayout tape_layout(int ns, int64_t n_steps, int64_t every, int units) {
-  TapeLayout T;
-  T.n_seg = (n_steps + every - 1) / every;
-  size_t o = 0;
-  T.ck = o; o = align256(o + sizeof(double) * 12 * (size_t)ns * (size_t)(T.n_seg + 1));
-  for (int b = 0; b < 2; ++b) {
-    T.seg[b] = o;
-    o = align256(o + sizeof(double) * TAPE_ROWS * (size_t)ns * (size_t)every * (size_t)units);
-  }
-  T.grad = o; o = align256(o + sizeof(double) * 8 * (size_t)ns);
-  T.total = o;
-  return T;
 }
 
 int tape_units(const wh_ctx* c) { return c->cfg.scheme >= WH_SABA2 ? c->cfg.scheme : 1; }
@@ -3115,28 +2948,14 @@ wh_status scratch_address(void** out) {
 
 extern "C" {
 
-void wh_config_default(wh_config* cfg, int32_t n_systems) {
-  if (!cfg) return;
-  memset(cfg, 0, sizeof(*cfg));
-  cfg->n_systems = n_systems;
-  cfg->G = 1.0;
-  cfg->gr_c = 0.0;
-  cfg->scheme = WH_DKD;
-  cfg->packing = WH_PACK_AUTO;
-  cfg->block_waves = 1;
-  cfg->chunk_steps = 4096;
-  cfg->graph_launches = 8;
-  cfg->z_max = 1.0;
-  cfg->exchange = WH_EXCH_AUTO;
-  cfg->coords = WH_COORDS_DHC;
-}
+void wh_config_default(wh_config* cfg, int32_t n_systems) { config_defaults(cfg, n_systems); }
 
 size_t wh_workspace_bytes(const wh_config* cfg, const int32_t* n_planets) {
   std::string why;
   if (!config_ok(cfg, why) || !n_planets) return 0;
   Packing P;
   if (!make_packing(cfg->n_systems, n_planets, eff_packing(cfg), P)) return 0;
-  return make_layout(cfg->n_systems, P.ns).total;
+  return make_layout(cfg->n_systems, P.ns, plan_capacity(cfg, P)).total;
 }
 
 wh_status wh_init(wh_ctx** out, const wh_config* cfg, const int32_t* n_planets, const double* m0, const double* m,
@@ -3157,7 +2976,7 @@ wh_status wh_init(wh_ctx** out, const wh_config* cfg, const int32_t* n_planets, 
     delete c;
     return fail(WH_EINVAL, why);
   }
-  c->lay = make_layout(S, c->P.ns);
+  c->lay = make_layout(S, c->P.ns, plan_capacity(cfg, c->P));
   if (workspace_bytes < c->lay.total) {
     delete c;
     return fail(WH_EWORKSPACE, "workspace too small: need " + std::to_string(c->lay.total) + " bytes");
@@ -3197,6 +3016,8 @@ wh_status wh_init(wh_ctx** out, const wh_config* cfg, const int32_t* n_planets, 
   c->slot_pl = (int*)(c->ws + c->lay.slot_pl);
   c->flags = (uint32_t*)(c->ws + c->lay.flags);
   c->synced = (int*)(c->ws + c->lay.synced);
+  c->plan_wave = (int*)(c->ws + c->lay.plan_wave);
+  c->plan_steps = (int*)(c->ws + c->lay.plan_steps);
   c->block_waves = cfg->block_waves > 0 ? cfg->block_waves : 1;
   c->exchange = cfg->exchange == WH_EXCH_LDS ? WH_EXCH_LDS : WH_EXCH_DPP;
   c->chunk = cfg->chunk_steps > 0 ? cfg->chunk_steps : 4096;
@@ -3209,6 +3030,14 @@ wh_status wh_init(wh_ctx** out, const wh_config* cfg, const int32_t* n_planets, 
     delete c;
     return s;
   };
+  std::vector<int> plan_w, plan_s;   // outlive the copies: the stream is synchronized below
+  if ((st = build_plan(c, plan_w, plan_s))) return abandon(st);
+  if (!plan_w.empty() &&
+      ((st = hip_check(hipMemcpyAsync(c->plan_wave, plan_w.data(), sizeof(int) * plan_w.size(),
+                                      hipMemcpyHostToDevice, stream), "upload launch plan")) ||
+       (st = hip_check(hipMemcpyAsync(c->plan_steps, plan_s.data(), sizeof(int) * plan_s.size(),
+                                      hipMemcpyHostToDevice, stream), "upload launch plan"))))
+    return abandon(st);
   if ((st = hip_check(hipMemcpyAsync(c->slot_sys, c->P.slot_sys.data(), sizeof(int) * ns, hipMemcpyHostToDevice,
                                      stream), "upload slot table")) ||
       (st = hip_check(hipMemcpyAsync(c->slot_pl, c->P.slot_pl.data(), sizeof(int) * ns, hipMemcpyHostToDevice,
@@ -3245,7 +3074,7 @@ wh_status wh_step_n(wh_ctx* c, int64_t n_steps, hipStream_t stream) {
       if ((st = hip_check(hipGraphLaunch(c->gexec, stream), "graph launch"))) return st;
     full -= reps * c->graph_launches;
   }
-  for (int64_t i = 0; i < full; ++i) launch_step(c, c->chunk, stream);
+  for (int64_t i = 0; i < full; ++i) launch_chunk(c, stream);
   if (rem) launch_step(c, rem, stream);
   if ((st = hip_check(hipGetLastError(), "step kernel launch"))) return st;
   c->steps_done += n_steps;
@@ -3306,6 +3135,99 @@ wh_status wh_status_flags(wh_ctx* c, uint32_t* flags_out, hipStream_t stream) {
 
 int64_t wh_steps_done(const wh_ctx* c) { return c ? c->steps_done : -1; }
 
+}  // extern "C"
+
+namespace {
+struct SnapLayout {
+  size_t st, flags, synced, total;
+};
+SnapLayout snap_layout(const wh_ctx* c) {
+  SnapLayout L;
+  size_t o = align256(sizeof(StateHeader));
+  L.st = o; o = align256(o + sizeof(double) * ROWS * (size_t)c->P.ns);
+  L.flags = o; o = align256(o + sizeof(uint32_t) * (size_t)c->S);
+  L.synced = o; o = align256(o + sizeof(int) * (size_t)c->S);
+  L.total = o;
+  return L;
+}
+StateHeader snap_header(const wh_ctx* c) {
+  StateHeader h;
+  h.magic = STATE_MAGIC;
+  h.version = 1;
+  h.S = c->S;
+  h.ns = c->P.ns;
+  h.packing = eff_packing(&c->cfg);
+  h.coords = c->cfg.coords;
+  h.scheme = c->cfg.scheme;
+  h.gr = c->cfg.gr_c > 0 ? 1 : 0;
+  h.rows = ROWS;
+  h.steps_done = c->steps_done;
+  return h;
+}
+}  // namespace
+
+extern "C" {
+
+size_t wh_state_bytes(const wh_ctx* c) { return c ? snap_layout(c).total : 0; }
+
+wh_status wh_save_state(wh_ctx* c, void* dst, size_t bytes, hipStream_t stream) {
+  if (!c) return fail(WH_EINVAL, "null context");
+  if (!dst) return fail(WH_EINVAL, "null snapshot buffer");
+  if (((uintptr_t)dst & 255) != 0) return fail(WH_EINVAL, "snapshot buffer must be 256-byte aligned");
+  const SnapLayout L = snap_layout(c);
+  if (bytes < L.total) return fail(WH_EWORKSPACE, "snapshot buffer too small: need " + std::to_string(L.total));
+  char* d = (char*)dst;
+  hipLaunchKernelGGL(k_write_header, dim3(1), dim3(64), 0, stream, snap_header(c), (StateHeader*)d);
+  wh_status st;
+  if ((st = hip_check(hipGetLastError(), "snapshot header")) ||
+      (st = hip_check(hipMemcpyAsync(d + L.st, c->st, sizeof(double) * ROWS * (size_t)c->P.ns,
+                                     hipMemcpyDeviceToDevice, stream), "snapshot state")) ||
+      (st = hip_check(hipMemcpyAsync(d + L.flags, c->flags, sizeof(uint32_t) * (size_t)c->S,
+                                     hipMemcpyDeviceToDevice, stream), "snapshot flags")) ||
+      (st = hip_check(hipMemcpyAsync(d + L.synced, c->synced, sizeof(int) * (size_t)c->S, hipMemcpyDeviceToDevice,
+                                     stream), "snapshot synced")))
+    return st;
+  return WH_OK;
+}
+
+wh_status wh_restore_state(wh_ctx* c, const void* src, size_t bytes, hipStream_t stream) {
+  if (!c) return fail(WH_EINVAL, "null context");
+  if (!src) return fail(WH_EINVAL, "null snapshot buffer");
+  if (((uintptr_t)src & 255) != 0) return fail(WH_EINVAL, "snapshot buffer must be 256-byte aligned");
+  const SnapLayout L = snap_layout(c);
+  if (bytes < sizeof(StateHeader)) return fail(WH_EINVAL, "not a wh_save_state snapshot (too short)");
+  StateHeader h;
+  wh_status st;
+  if ((st = hip_check(hipMemcpyAsync(&h, src, sizeof(h), hipMemcpyDeviceToHost, stream), "read snapshot header")) ||
+      (st = hip_check(hipStreamSynchronize(stream), "synchronize")))
+    return st;
+  const StateHeader mine = snap_header(c);
+  if (h.magic != STATE_MAGIC || h.version != 1) return fail(WH_EINVAL, "not a wh_save_state snapshot");
+  if (h.S != mine.S || h.ns != mine.ns || h.packing != mine.packing || h.coords != mine.coords ||
+      h.scheme != mine.scheme || h.gr != mine.gr || h.rows != mine.rows)
+    return fail(WH_ESTATE, "snapshot of a context with another batch, packing, scheme, coordinates or GR setting");
+  if (h.steps_done < 0) return fail(WH_EINVAL, "corrupt snapshot header");
+  if (bytes < L.total) return fail(WH_EWORKSPACE, "snapshot buffer smaller than this context's state");
+  const char* s = (const char*)src;
+  if ((st = hip_check(hipMemcpyAsync(c->st, s + L.st, sizeof(double) * ROWS * (size_t)c->P.ns,
+                                     hipMemcpyDeviceToDevice, stream), "restore state")) ||
+      (st = hip_check(hipMemcpyAsync(c->flags, s + L.flags, sizeof(uint32_t) * (size_t)c->S,
+                                     hipMemcpyDeviceToDevice, stream), "restore flags")) ||
+      (st = hip_check(hipMemcpyAsync(c->synced, s + L.synced, sizeof(int) * (size_t)c->S, hipMemcpyDeviceToDevice,
+                                     stream), "restore synced")))
+    return st;
+  c->steps_done = h.steps_done;
+  c->tape = nullptr;      // a recorded tape belongs to the state it was recorded from
+  c->tape_end = -1;
+  return WH_OK;
+}
+
+int32_t wh_launch_windows(const wh_ctx* c, int32_t* slots) {
+  if (!c) return -1;
+  if (slots) *slots = c->plan_slots;
+  return c->plan_off.size() < 2 ? 1 : (int32_t)c->plan_off.size() - 1;
+}
+
 size_t wh_tape_bytes(const wh_ctx* c, int64_t n_steps, int64_t ckpt_every) {
   if (!c || n_steps < 0 || ckpt_every < 1 || ckpt_every > (1 << 30)) return 0;
   if (ckpt_every * tape_units(c) > (1 << 30)) return 0;
@@ -3323,6 +3245,7 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
   if (ckpt_every * tape_units(c) > (1 << 30)) return fail(WH_EINVAL, "ckpt_every too large for this scheme");
   TapeLayout T = tape_layout(c->P.ns, n_steps, ckpt_every, tape_units(c));
+  if (T.total == 0) return fail(WH_EINVAL, "tape size overflows size_t for these n_steps and ckpt_every");
   if (tape_bytes < T.total) return fail(WH_EWORKSPACE, "tape too small: need " + std::to_string(T.total) + " bytes");
   const int ns = c->P.ns;
   double* ck = (double*)((char*)tape + T.ck);

@@ -431,6 +431,12 @@ def test_tape_size_follows_the_scheme():
         grow[scheme] = int(L.wh_tape_bytes(e._ctx, 1000, 200)) - int(L.wh_tape_bytes(e._ctx, 1000, 100))
         assert int(L.wh_tape_bytes(e._ctx, 10, 0)) == 0                  # ckpt_every < 1
         assert int(L.wh_tape_bytes(e._ctx, 10, (1 << 30) + 1)) == 0      # beyond the cap
+        # sizes that do not fit in size_t: 96 B per slot for each of ~2^62 checkpoints
+        assert int(L.wh_tape_bytes(e._ctx, (1 << 62) + 3, 1)) == 0
+        assert int(L.wh_tape_bytes(e._ctx, (1 << 63) - 1, 2)) == 0
+        rc = L.wh_forward_ckpt(e._ctx, (1 << 62) + 3, 1, e.workspace.data_ptr() + 256 - e.workspace.data_ptr() % 256,
+                               1 << 20, 0)
+        assert rc == _lib.WH_EINVAL                     # rejected before any launch
         e.close()
     ns = grow["dkd"] // (2 * 100 * 80 - 5 * 96)
     assert ns % 64 == 0 and grow["dkd"] == ns * (2 * 100 * 80 - 5 * 96)
@@ -460,3 +466,30 @@ def test_reverse_mode_on_the_gr_workload_sampled(packing):
     rel = np.abs(lhs - rhs) / scale
     print("dot-product relative mismatch (GR workload, %s): max %.2e" % (packing, rel.max()), flush=True)
     assert rel.max() < 1e-9
+
+
+def test_backward_releases_the_tape():
+    """The autograd function saves its workspace and tape for backward: they
+    stay while the graph is retained (a second backward works), and torch
+    frees them after a backward without retain_graph (a further backward
+    raises instead of reading freed memory)."""
+    s = inputs.make_systems(64, 45, n_planets=8)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device=DEV, requires_grad=True)
+    Q0, V0, m, m0 = t(s.Q), t(s.V), t(s.m), t(s.m0)
+    dt = torch.tensor(s.dt, dtype=torch.float64, device=DEV)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    QT, VT = integrate(Q0, V0, m, m0, dt, s.n_planets, 2000, ckpt_every=1000)
+    L = (QT ** 2).sum()
+    held = torch.cuda.memory_allocated() - base          # workspace + tape (2 x 1000 steps x 80 B x 512 slots)
+    assert held > 80e6
+    L.backward(retain_graph=True)
+    g1 = Q0.grad.clone()
+    Q0.grad = None
+    L.backward()                                         # the retained graph still has its tape
+    assert torch.equal(Q0.grad, g1)
+    torch.cuda.synchronize()
+    after = torch.cuda.memory_allocated() - base
+    assert after < 0.1 * held, (after, held)             # freed with the graph's saved tensors
+    with pytest.raises(RuntimeError):
+        L.backward()
