@@ -1,28 +1,39 @@
 """Benchmark: Wisdom-Holman ensemble throughput on one MI355X.
 
-Default workload: 4096 independent systems of 8 planets (star mass 1,
-planet masses log-uniform in [1e-7, 1e-3], semi-major axes log-uniform in
-[0.4, 30] with >= 10 mutual Hill radii spacing, e and i uniform in
-[0, 0.05], dt = P_inner/20, drift-kick-drift, no GR), seeded and synthetic.
-A "step" is one Wisdom-Holman timestep of every system of the batch (the
-Kepler drift, interaction kick and jump of every planet); the metric is
-system-steps per second.  The state is resident in device memory before
-the timed region starts.
+Headline workload (the largest single-GPU configuration): 65536 independent
+systems of 8 planets with the GR potential (c = 10065), star mass 1, planet
+masses log-uniform in [1e-7, 1e-3], semi-major axes log-uniform in [0.4, 30]
+with >= 10 mutual Hill radii spacing, e and i uniform in [0, 0.05],
+dt = P_inner/20, drift-kick-drift; seeded and synthetic.
 
-Printed: one JSON line with the metric, a roofline object for the step
-kernel (algorithmic FP64 flops per launch / average launch time, against
-the 78.6 TFLOP/s FP64 vector peak) and a CPU baseline (the oracle timed on
-the host's cores on a bounded sample of the same workload).
+A bench "step" is one launch of the persistent step kernel: every system of
+the batch advances by --chunk (4096) Wisdom-Holman timesteps (Kepler drift,
+interaction kick, jumps and GR kick of every planet, 4096 times) with the
+state held in registers.  --steps K times K such launches back to back on
+the stream the kernel runs on; the metric counts Wisdom-Holman
+system-steps per second.  The state is resident in device memory before the
+timed region starts.
 
-Other workloads: --workload uneven2to8 (16384 systems, 2..8 planets,
-per-system dt) also times the per-size reference path; --workload large8gr
-(65536 systems with GR).
+Printed: one JSON line with the metric, a roofline object for the dominant
+kernel (algorithmic FP64 flops per launch / average launch duration, against
+the 78.6 TFLOP/s FP64 vector peak), a CPU baseline (the oracle timed on the
+host's cores on bounded samples) and, measured in the same run, the other
+parts of the metric:
+  legs.uniform8   -- 4096 x 8 planets, no GR: system-steps/s and frac;
+  legs.uneven2to8 -- 16384 systems of 2..8 planets with per-system dt: the
+                     fused persistent kernel against the plain per-size-launch
+                     kernel (ratio) and its frac;
+  legs.adjoint8   -- 1024 x 8 planets, 2e4 steps, checkpoints every 1000:
+                     reverse-mode cost over the plain forward of the same run;
+  legs.single8    -- the one-system configuration (1 x 8 planets, 1e5 steps,
+                     kick-drift-kick): steps/s on one 16-lane group.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -34,27 +45,28 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 
 WORKLOAD_TEXT = {
+    "large8gr": "65536 systems x 8 planets, GR (c = 10065), dt = P_inner/20, drift-kick-drift",
     "uniform8": "4096 systems x 8 planets, dt = P_inner/20, drift-kick-drift, no GR",
     "uneven2to8": "16384 systems x 2..8 planets (uniform), dt uniform in [P_inner/30, P_inner/15], drift-kick-drift",
-    "large8gr": "65536 systems x 8 planets, GR (c = 10065), dt = P_inner/20, drift-kick-drift",
     "single8": "1 system x 8 planets, dt = P_inner/20, kick-drift-kick",
     "adjoint8": "1024 systems x 8 planets, dt = P_inner/20, drift-kick-drift; reverse mode with checkpoints "
                 "every 1000 steps, loss sum |Q(T)|^2",
 }
 
-
-# Steps of each workload's run; large8gr's 1e7-step run is timed over 1e6
-# steps to keep the GPU held for seconds, not a minute.
-DEFAULT_STEPS = {"uniform8": 1_000_000, "uneven2to8": 1_000_000, "large8gr": 1_000_000, "single8": 100_000,
-                 "adjoint8": 100_000}
-
-
-# Two planets per lane pays once the one-planet layout has more wavefronts
-# than the chip has SIMDs (fewer, heavier waves with more independent work);
-# two lanes per planet pays when it has fewer (more, lighter waves).
-# The uneven batch is run as its workload states, with the autotuned packing
-# (which picks two planets per lane).
-DEFAULT_PACKING = {"uneven2to8": "tuned", "large8gr": "pair", "uniform8": "split", "single8": "split"}
+# Lane packing per workload.  Two planets per lane pays once the one-planet
+# layout has more wavefronts than the chip has SIMDs (fewer, heavier waves
+# with more independent work); two lanes per planet pays when it has fewer.
+DEFAULT_PACKING = {"large8gr": "pair", "uneven2to8": "pow2", "uniform8": "split", "single8": "split",
+                   "adjoint8": "split"}
+# Wavefronts per workgroup: four-wave workgroups put one wave of each
+# workgroup on each SIMD of a CU.
+DEFAULT_BLOCK_WAVES = {"large8gr": 1, "uneven2to8": 4, "uniform8": 4, "single8": 1, "adjoint8": 4}
+# Balanced launch windows (wh_config.balance) for the uneven batch: its 1536
+# one-planet-per-lane wavefronts of three costs run in windows of 1024
+# equal-work wavefronts (+15% over two planets per lane, whose 769 heavy
+# wavefronts leave a quarter of the SIMDs idle).  The GR batch's 4096 pair
+# wavefronts of one cost measured the same with and without windows.
+DEFAULT_BALANCE = {"large8gr": 0, "uneven2to8": 1, "uniform8": 0, "single8": 0, "adjoint8": 0}
 KERNEL_NAME = {"pair": "k_step_pair (persistent step kernel, two planets per lane)",
                "split": "k_step_split (persistent step kernel, two lanes per planet)",
                "serial": "k_step_serial (persistent step kernel, one lane per system)"}
@@ -63,28 +75,23 @@ KERNEL_NAME = {"pair": "k_step_pair (persistent step kernel, two planets per lan
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None,
-                    help="timed Wisdom-Holman steps (default: 1e5 for adjoint8 and single8, 1e6 otherwise)")
-    ap.add_argument("--warmup", type=int, default=4096, help="untimed steps before the timed region")
-    ap.add_argument("--workload", default="uniform8", choices=sorted(WORKLOAD_TEXT))
-    ap.add_argument("--packing", default=None,
-                    help="auto|pow2|g8|pair|split|serial|tuned (default: tuned for uneven2to8, pair for large8gr, whose "
-                         "batch fills more wavefronts than the chip has SIMDs, split for uniform8 and single8, which "
-                         "fill fewer; auto otherwise)")
-    ap.add_argument("--block-waves", type=int, default=None,
-                    help="wavefronts per workgroup (default 4 for uniform8: one four-wave workgroup per CU puts "
-                         "exactly one of its 1024 wavefronts on each SIMD; 1 otherwise)")
-    ap.add_argument("--chunk", type=int, default=4096)
+    ap.add_argument("--steps", type=int, default=60,
+                    help="timed bench steps; one bench step = one launch of --chunk Wisdom-Holman steps of the batch")
+    ap.add_argument("--warmup", type=int, default=4, help="untimed bench steps before the timed region")
+    ap.add_argument("--workload", default="large8gr", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--packing", default=None, help="auto|pow2|g8|pair|split|serial (default: per workload)")
+    ap.add_argument("--block-waves", type=int, default=None)
+    ap.add_argument("--balance", type=int, default=None, choices=[0, 1],
+                    help="balanced launch windows (default: per workload)")
+    ap.add_argument("--chunk", type=int, default=4096, help="Wisdom-Holman steps per launch")
     ap.add_argument("--exchange", default="auto", choices=["auto", "dpp", "lds"])
     ap.add_argument("--scheme", default=None, choices=["dkd", "kdk", "saba2", "saba3", "saba4"],
                     help="step composition (default: the workload's, drift-kick-drift)")
-    ap.add_argument("--coords", default="dhc", choices=["dhc", "jacobi"],
-                    help="splitting coordinates: democratic heliocentric (the paper's) or Jacobi")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
-    ap.add_argument("--cpu-steps", type=int, default=80000)
+    ap.add_argument("--coords", default="dhc", choices=["dhc", "jacobi"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--no-legs", action="store_true", help="skip the uniform, uneven, adjoint and single legs")
+    ap.add_argument("--cpu-steps", type=int, default=40000, help="steps of the oracle's multi-thread sample")
     ap.add_argument("--cpu-systems", type=int, default=256)
-    ap.add_argument("--plain-steps", type=int, default=2000, help="steps of the per-size reference path")
-    ap.add_argument("--ckpt-every", type=int, default=1000, help="checkpoint interval of the adjoint workload")
     ap.add_argument("--save-state", default=None,
                     help="write the final synchronized states and per-system energy errors to this .npz file")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -119,7 +126,9 @@ def measured_counters(workload: str, chunk: int, coords: str = "dhc", packing: s
 
 
 def flops_per_system_step(n_planets: np.ndarray, gr: bool, coords: str = "dhc", scheme: str = "dkd") -> float:
-    """A SABA_n step is n drifts and n kicks: n times the counted step."""
+    """Algorithmic FP64 operations of one step of the batch (the oracle's count
+    of the paper's fixed-iteration step); a SABA_n step is n drifts and n
+    kicks: n times the counted step."""
     from paper_2307_05683_amd.flops import ALGO_FLOPS, ALGO_FLOPS_GR, ALGO_FLOPS_JACOBI, ALGO_FLOPS_JACOBI_GR
     if coords == "jacobi":
         table = ALGO_FLOPS_JACOBI_GR if gr else ALGO_FLOPS_JACOBI
@@ -129,66 +138,206 @@ def flops_per_system_step(n_planets: np.ndarray, gr: bool, coords: str = "dhc", 
     return float(stages * sum(table[int(n)] for n in n_planets))
 
 
-def _cpu_model() -> str:
+def _cpu_model() -> dict:
+    """CPU model and topology as the host reports them (/proc/cpuinfo, lscpu)."""
+    out = {"model": "unknown"}
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+                out["model"] = line.split(":", 1)[1].strip()
+                break
     except OSError:
         pass
-    return "unknown"
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            k = k.strip()
+            if k in ("Model name", "CPU(s)", "Thread(s) per core", "Core(s) per socket", "Socket(s)",
+                     "CPU max MHz", "Vendor ID", "CPU family", "Model"):
+                out["lscpu " + k] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        out["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except OSError:
+        pass
+    return out
 
 
 def cpu_baseline(systems, args, gr_c, scheme="dkd"):
-    """The oracle (double, converged Kepler solves) on a bounded sample of the
-    same workload, on all host threads and on one."""
+    """The oracle as it stands (double precision, Kepler solved to
+    convergence, OpenMP over systems) on bounded samples: the headline
+    workload on all host threads and on one, the uneven batch, the
+    one-system configuration in full, and the long-double parity reference."""
     import oracle
-    sub = systems.subset(np.arange(min(args.cpu_systems, systems.S)))
+    from paper_2307_05683_amd import inputs
     threads = oracle.max_threads()
 
-    def run(s, n, nthreads):
+    def run(s, n, nthreads, precision="d", sch=scheme, gr=gr_c):
         t0 = time.perf_counter()
         if args.coords == "jacobi":
-            oracle.jacobi_integrate(s, n, scheme=scheme, precision="d", nthreads=nthreads, gr_c=gr_c)
+            oracle.jacobi_integrate(s, n, scheme=sch, precision=precision, nthreads=nthreads, gr_c=gr)
         else:
-            oracle.integrate(s, n, scheme=scheme, gr_c=gr_c, precision="d", nthreads=nthreads)
+            oracle.integrate(s, n, scheme=sch, gr_c=gr, precision=precision, nthreads=nthreads)
         return time.perf_counter() - t0
 
+    sub = systems.subset(np.arange(min(args.cpu_systems, systems.S)))
     dt = run(sub, args.cpu_steps, threads)
     one = sub.subset(np.arange(min(16, sub.S)))
     n1 = max(1, args.cpu_steps // 8)
     dt1 = run(one, n1, 1)
-    return {
+    out = {
         "value": sub.S * args.cpu_steps / dt,
         "unit": "system-steps/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": "%d systems of the same workload x %d steps, FP64, converged Kepler solves, OpenMP over systems "
-                  "(%.1f s wall)" % (sub.S, args.cpu_steps, dt),
+        "sample": "%d systems of the headline workload (%s) x %d steps, FP64, converged Kepler solves, OpenMP "
+                  "over systems on %d threads (%.1f s wall)" % (sub.S, "GR" if gr_c > 0 else "no GR",
+                                                                 args.cpu_steps, threads, dt),
         "value_1core": one.S * n1 / dt1,
         "sample_1core": "%d systems x %d steps on one thread (%.1f s wall)" % (one.S, n1, dt1),
-        "cpu_model": _cpu_model(),
+        "cpu": _cpu_model(),
     }
+    if not args.no_legs and args.coords == "dhc":
+        unev = inputs.workload("uneven2to8").subset(np.arange(args.cpu_systems))
+        n_u = args.cpu_steps // 4
+        t_u = run(unev, n_u, threads, gr=0.0)
+        out["uneven2to8"] = {"value": unev.S * n_u / t_u, "sample": "%d systems x %d steps, %d threads (%.1f s)"
+                             % (unev.S, n_u, threads, t_u)}
+        single = inputs.workload("single8")
+        t_s = run(single, 100_000, 1, sch="kdk", gr=0.0)
+        out["single8"] = {"value": 1e5 / t_s, "sample": "1 system x 1e5 steps (the whole configuration), "
+                          "kick-drift-kick, one thread (%.2f s)" % t_s}
+        ld = sub.subset(np.arange(16))
+        t_ld = run(ld, 2000, 1, precision="ld")
+        out["long_double_1core"] = {"value": ld.S * 2000 / t_ld,
+                                    "sample": "16 systems x 2000 steps in long double on one thread (the parity "
+                                              "reference, not the baseline; %.1f s)" % t_ld}
+    return out
 
 
-def adjoint_cost(systems, args, dev, stream, t_plain, gr_c, scheme, opts):
-    """Forward with checkpoints + adjoint, against the plain forward of the
-    same steps (the cost ratio of reverse mode), with the scheme and packing
-    of the forward run.  A short run first loads every kernel involved; the
-    loss seed dL/dQ_T = 2 Q_T is formed outside the timed intervals."""
+def warm(ens, n_launch, chunk):
+    """Untimed launches; at least one graph's worth, so that the HIP graph of
+    the step loop is captured before any timed region.  Returns the count."""
+    n = max(n_launch, int(ens.cfg.graph_launches))
+    ens.step(n * chunk)
+    return n
+
+
+def timed_chunks(ens, n_launch, chunk, stream):
+    """Run n_launch launches of chunk steps; seconds between events recorded
+    on the kernels' stream."""
     import torch
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    ens.step(n_launch * chunk)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / 1e3
+
+
+def leg_uniform(dev, stream, chunk):
+    from paper_2307_05683_amd import inputs
     from paper_2307_05683_amd.ensemble import Ensemble
-    w = Ensemble.from_systems(systems.subset(np.arange(min(64, systems.S))), device=dev, gr_c=gr_c, scheme=scheme,
-                              **opts)
+    s = inputs.workload("uniform8")
+    e = Ensemble.from_systems(s, device=dev, packing="split", block_waves=4, chunk_steps=chunk)
+    warm(e, 1, chunk)
+    n = 8
+    t = timed_chunks(e, n, chunk, stream)
+    e.close()
+    fl = flops_per_system_step(s.n_planets, False)
+    return {"workload": WORKLOAD_TEXT["uniform8"], "packing": "split", "value": s.S * n * chunk / t,
+            "unit": "system-steps/s", "steps": n * chunk, "avg_launch_ms": t * 1e3 / n,
+            "frac": fl * chunk / (t / n) / 1e12 / FP64_PEAK_TFLOPS,
+            "kernel": KERNEL_NAME["split"]}
+
+
+def leg_uneven(dev, stream, chunk):
+    """Fused persistent launch (fixed packing) vs the plain per-size-launch
+    kernel (one 8-lane group per system, one launch per planet count per step,
+    state through HBM every step, no graph) and vs one persistent context per
+    planet count run one after the other."""
+    import torch
+    from paper_2307_05683_amd import inputs
+    from paper_2307_05683_amd.ensemble import Ensemble
+    s = inputs.workload("uneven2to8")
+    pk, bw, bal = DEFAULT_PACKING["uneven2to8"], DEFAULT_BLOCK_WAVES["uneven2to8"], DEFAULT_BALANCE["uneven2to8"]
+    e = Ensemble.from_systems(s, device=dev, packing=pk, block_waves=bw, chunk_steps=chunk, balance=bal)
+    windows = e.launch_windows[0]
+    warm(e, 1, chunk)
+    n = 8
+    t = timed_chunks(e, n, chunk, stream)
+    e.close()
+    fused = s.S * n * chunk / t
+    fl = flops_per_system_step(s.n_planets, False)
+    plain = Ensemble.from_systems(s, device=dev, packing="g8")
+    plain.step_plain(10)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_plain = 512
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    plain.step_plain(n_plain)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    tp = ev0.elapsed_time(ev1) / 1e3
+    plain.close()
+    subs = [Ensemble.from_systems(s.subset(np.flatnonzero(s.n_planets == k)), packing="g8", device=dev,
+                                  chunk_steps=chunk)
+            for k in range(1, 9) if (s.n_planets == k).any()]
+    for sub in subs:
+        sub.step(64)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for sub in subs:
+        sub.step(chunk)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ts = ev0.elapsed_time(ev1) / 1e3
+    for sub in subs:
+        sub.close()
+    return {"workload": WORKLOAD_TEXT["uneven2to8"], "packing": pk, "block_waves": bw, "balance": bal,
+            "launches_per_chunk": windows, "value": fused,
+            "unit": "system-steps/s", "steps": n * chunk, "avg_launch_ms": t * 1e3 / n,
+            "frac": fl * chunk / (t / n) / 1e12 / FP64_PEAK_TFLOPS, "kernel": KERNEL_NAME.get(pk, "k_step"),
+            "plain_per_size": {"value": s.S * n_plain / tp, "steps": n_plain},
+            "speedup_fused_over_plain": fused / (s.S * n_plain / tp),
+            "per_size_persistent": {"value": s.S * chunk / ts, "steps": chunk},
+            "speedup_fused_over_per_size_persistent": fused / (s.S * chunk / ts)}
+
+
+def leg_adjoint(dev, stream, n_steps=20000, every=1000):
+    """Reverse-mode cost on the adjoint configuration's batch: (forward with
+    checkpoints + adjoint) over the plain forward of the same steps, all in
+    the packing that fills the most SIMDs for this batch.  A short run first
+    loads every kernel involved; the loss seed dL/dQ_T = 2 Q_T is formed
+    outside the timed intervals."""
+    import torch
+    from paper_2307_05683_amd import inputs
+    from paper_2307_05683_amd.ensemble import Ensemble
+    s = inputs.workload("adjoint8")
+    opts = dict(packing=DEFAULT_PACKING["adjoint8"], block_waves=DEFAULT_BLOCK_WAVES["adjoint8"])
+    w = Ensemble.from_systems(s.subset(np.arange(64)), device=dev, **opts)
     w.forward_ckpt(4, 2)
     QT, VT = w.state()
     w.adjoint(2 * QT, torch.zeros_like(VT))
+    w.step(64)
     torch.cuda.synchronize()
     w.close()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    e = Ensemble.from_systems(systems, device=dev, gr_c=gr_c, scheme=scheme, **opts)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    f = Ensemble.from_systems(s, device=dev, **opts)
+    torch.cuda.synchronize()
+    ev[4].record(stream)
+    f.step(n_steps)
+    ev[5].record(stream)
+    torch.cuda.synchronize()
+    f.close()
+    e = Ensemble.from_systems(s, device=dev, **opts)
+    torch.cuda.synchronize()
     ev[0].record(stream)
-    e.forward_ckpt(args.steps, args.ckpt_every)
+    e.forward_ckpt(n_steps, every)
     ev[1].record(stream)
     QT, VT = e.state()
     gQ, gV = 2 * QT, torch.zeros_like(VT)
@@ -197,27 +346,52 @@ def adjoint_cost(systems, args, dev, stream, t_plain, gr_c, scheme, opts):
     g = e.adjoint(gQ, gV)
     ev[3].record(stream)
     torch.cuda.synchronize()
+    t_plain = ev[4].elapsed_time(ev[5]) / 1e3
     t_ckpt = ev[0].elapsed_time(ev[1]) / 1e3
     t_adj = ev[2].elapsed_time(ev[3]) / 1e3
     finite = bool(all(torch.isfinite(x).all().item() for x in g))
     e.close()
-    return {"steps": args.steps, "ckpt_every": args.ckpt_every, "forward_s": t_plain, "forward_ckpt_s": t_ckpt,
-            "adjoint_s": t_adj, "cost_ratio": (t_ckpt + t_adj) / t_plain, "backward_over_forward": t_adj / t_plain,
-            "gradients_finite": finite}
+    fl = flops_per_system_step(s.n_planets, False)
+    return {"workload": WORKLOAD_TEXT["adjoint8"], "packing": opts["packing"], "steps": n_steps,
+            "ckpt_every": every, "forward_s": t_plain, "forward_frac": fl * n_steps / t_plain / 1e12 / FP64_PEAK_TFLOPS,
+            "forward_ckpt_s": t_ckpt, "adjoint_s": t_adj, "cost_ratio": (t_ckpt + t_adj) / t_plain,
+            "backward_over_forward": t_adj / t_plain, "gradients_finite": finite}
+
+
+def leg_single(dev, stream):
+    import torch
+    from paper_2307_05683_amd import inputs
+    from paper_2307_05683_amd.ensemble import Ensemble
+    s = inputs.workload("single8")
+    e = Ensemble.from_systems(s, device=dev, packing="split", scheme="kdk")
+    e.step(4096)
+    E0 = e.energy()
+    n = 100_000
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    e.step(n)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t = ev0.elapsed_time(ev1) / 1e3
+    dE = float(((e.energy() - E0) / E0).abs().item())
+    e.close()
+    return {"workload": WORKLOAD_TEXT["single8"], "packing": "split", "steps": n, "value": n / t,
+            "unit": "steps/s", "rel_energy_error": dE}
 
 
 def main():
     args = parse()
-    if args.packing is None:
-        args.packing = DEFAULT_PACKING.get(args.workload, "auto")
-    if args.block_waves is None:
-        args.block_waves = 4 if args.workload == "uniform8" else 1
-    if args.steps is None:
-        args.steps = DEFAULT_STEPS.get(args.workload, 1_000_000)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (systems are independent; "
               "see the sharding design notes). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.warmup < 0 or args.chunk < 1:
+        print("--steps must be >= 1, --warmup >= 0 and --chunk >= 1", file=sys.stderr)
+        sys.exit(2)
+    packing = args.packing or DEFAULT_PACKING.get(args.workload, "auto")
+    block_waves = args.block_waves or DEFAULT_BLOCK_WAVES.get(args.workload, 1)
+    balance = DEFAULT_BALANCE.get(args.workload, 0) if args.balance is None else args.balance
     import torch
     from paper_2307_05683_amd import inputs
     from paper_2307_05683_amd.ensemble import Ensemble
@@ -226,39 +400,27 @@ def main():
     scheme = args.scheme or ("kdk" if args.workload == "single8" else "dkd")
     systems = inputs.workload(args.workload)
     dev = torch.device("cuda:0")
-    opts = dict(packing=args.packing, block_waves=args.block_waves, chunk_steps=args.chunk, exchange=args.exchange,
-                coords=args.coords)
-    tune_table = None
-    if args.packing == "tuned":
-        from paper_2307_05683_amd.autotune import autotune
-        print("[bench] autotuning the lane packing ...", file=sys.stderr, flush=True)
-        best, tune_table = autotune(systems, gr_c=gr_c, scheme=scheme, device=dev, coords=args.coords)
-        opts.update(best)
-        print("[bench] chosen: %s" % best, file=sys.stderr, flush=True)
+    chunk = args.chunk
+    opts = dict(packing=packing, block_waves=block_waves, chunk_steps=chunk, exchange=args.exchange,
+                coords=args.coords, balance=balance)
     ens = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, device=dev, **opts)
+    windows, window_slots = ens.launch_windows
     E0 = ens.energy()        # initial energy of every system (outside the timed region)
-    print("[bench] %s: S=%d, warmup %d steps" % (args.workload, systems.S, args.warmup), file=sys.stderr, flush=True)
+    print("[bench] %s: S=%d, packing %s, warmup %d x %d steps" % (args.workload, systems.S, packing, args.warmup,
+                                                                  chunk), file=sys.stderr, flush=True)
     if args.copy_probe_mb:
         x = torch.ones(args.copy_probe_mb << 17, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    if args.warmup:
-        ens.step(args.warmup)
-    torch.cuda.synchronize()
+    warm_run = warm(ens, args.warmup, chunk)
     stream = torch.cuda.current_stream(dev)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    ev0.record(stream)
-    ens.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
+    gpu_s = timed_chunks(ens, args.steps, chunk, stream)
     wall = time.perf_counter() - t0
-    gpu_s = ev0.elapsed_time(ev1) / 1e3
-    print("[bench] timed %d steps: %.3f s (events), %.3f s (wall)" % (args.steps, gpu_s, wall), file=sys.stderr,
-          flush=True)
+    print("[bench] timed %d launches x %d steps: %.3f s (events), %.3f s (wall)" % (args.steps, chunk, gpu_s, wall),
+          file=sys.stderr, flush=True)
     flags = ens.flags().cpu().numpy()
     E1 = ens.energy()
     dE = ((E1 - E0) / E0).abs().cpu().numpy()
@@ -266,12 +428,13 @@ def main():
     if args.save_state:
         Q, V = ens.state()
         np.savez(args.save_state, Q=Q.cpu().numpy(), V=V.cpu().numpy(), rel_energy_error=dE, flags=flags,
-                 n_planets=systems.n_planets, steps=args.warmup + args.steps)
-    sys_steps = systems.S * args.steps
-    value = sys_steps / gpu_s
-    n_launch = -(-args.steps // opts["chunk_steps"])
+                 n_planets=systems.n_planets, steps=(warm_run + args.steps) * chunk)
+    ens.close()
+    wh_steps = args.steps * chunk
+    value = systems.S * wh_steps / gpu_s
+    avg_launch = gpu_s / args.steps
     flops_step = flops_per_system_step(systems.n_planets, gr_c > 0, args.coords, scheme)
-    achieved = flops_step * args.steps / gpu_s / 1e12
+    achieved = flops_step * chunk / avg_launch / 1e12
     out = {
         "metric": "system-steps/s (8-planet FP64)" if "8" in args.workload else "system-steps/s (FP64)",
         "value": value,
@@ -279,7 +442,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": gpu_s * 1e3 / args.steps,
+        "ms_per_step": avg_launch * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -287,19 +450,23 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "%s: %s" % (args.workload, WORKLOAD_TEXT[args.workload]),
+            "wh_steps_per_step": chunk,
+            "warmup_launches_run": warm_run,
             "systems": systems.S,
             "planets_total": int(systems.n_planets.sum()),
-            "packing": opts["packing"],
-            "chunk_steps": opts["chunk_steps"],
-            "block_waves": opts["block_waves"],
-            "exchange": opts["exchange"],
+            "packing": packing,
+            "block_waves": block_waves,
+            "balance": balance,
+            "launches_per_chunk": windows,
+            "wavefronts_per_window": window_slots,
+            "exchange": args.exchange,
             "coords": args.coords,
             "scheme": scheme,
             "flagged_systems": int((flags != 0).sum()),
         },
         # relative energy error |E(T) - E(0)| / |E(0)| per system after the warmup and timed steps (unflagged)
         "energy_error": {
-            "steps": args.warmup + args.steps,
+            "steps": (warm_run + args.steps) * chunk,
             "median": float(np.median(dE[ok])) if ok.any() else None,
             "p90": float(np.percentile(dE[ok], 90)) if ok.any() else None,
             "p99": float(np.percentile(dE[ok], 99)) if ok.any() else None,
@@ -314,61 +481,30 @@ def main():
             "frac": achieved / FP64_PEAK_TFLOPS,
             "traffic": None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
-            "kernel": KERNEL_NAME.get(opts["packing"], "k_step (persistent step kernel)"),
-            "algorithmic_flops_per_step": flops_step,
-            "avg_launch_ms": gpu_s * 1e3 / n_launch,
-            "launches": n_launch,
+            "kernel": KERNEL_NAME.get(packing, "k_step (persistent step kernel)"),
+            "algorithmic_flops_per_launch": flops_step * chunk,
+            "avg_launch_ms": avg_launch * 1e3,
+            "launches": args.steps,
         },
     }
-    counters = measured_counters(args.workload, opts["chunk_steps"], args.coords, opts["packing"])
+    counters = measured_counters(args.workload, chunk, args.coords, packing)
     if counters and scheme == "dkd":
         out["roofline"]["traffic"] = counters["traffic"]
         if counters["hw_flops"]:
-            # FP64 flops the hardware executed (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes, FMA = 2, per step of a
-            # counted launch) over the timed steps: the kernel's own issue efficiency, beside the
-            # algorithmic fraction
-            hw = counters["hw_flops"] / opts["chunk_steps"] * args.steps / gpu_s / 1e12
+            # FP64 flops the hardware executed per launch (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes, FMA = 2)
+            # over the measured launch: the kernel's issue efficiency, beside the algorithmic fraction
+            hw = counters["hw_flops"] / avg_launch / 1e12
             out["roofline"]["achieved_hardware"] = hw
             out["roofline"]["frac_hardware"] = hw / FP64_PEAK_TFLOPS
-    if tune_table is not None:
-        out["config"]["autotune"] = [dict(r["opts"], rate=r["system_steps_per_s"]) for r in tune_table]
-    if args.workload == "adjoint8":
-        out["adjoint"] = adjoint_cost(systems, args, dev, stream, gpu_s, gr_c, scheme, opts)
-    if args.workload == "uneven2to8" and args.plain_steps > 0:
-        plain = Ensemble.from_systems(systems, gr_c=gr_c, scheme=scheme, packing="g8", coords=args.coords,
-                                      device=dev)
-        plain.step_plain(10)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        plain.step_plain(args.plain_steps)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ps = ev0.elapsed_time(ev1) / 1e3
-        out["plain_per_size"] = {"value": systems.S * args.plain_steps / ps, "steps": args.plain_steps,
-                                 "speedup_fused_over_plain": value / (systems.S * args.plain_steps / ps)}
-        plain.close()
-        # the stronger variant: one persistent context per planet count (the
-        # same 8-lane groups, each size's steps in chunked launches), run one
-        # after the other -- separates the gain of packing from that of
-        # persistence
-        subs = [Ensemble.from_systems(systems.subset(np.flatnonzero(systems.n_planets == n)), gr_c=gr_c,
-                                      scheme=scheme, packing="g8", coords=args.coords, device=dev)
-                for n in range(1, 9) if (systems.n_planets == n).any()]
-        n_sub = 8 * args.plain_steps
-        for sub in subs:
-            sub.step(64)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        for sub in subs:
-            sub.step(n_sub)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ts = ev0.elapsed_time(ev1) / 1e3
-        out["per_size_persistent"] = {"value": systems.S * n_sub / ts, "steps": n_sub,
-                                      "speedup_fused_over_it": value / (systems.S * n_sub / ts)}
-        for sub in subs:
-            sub.close()
-    ens.close()
+    if not args.no_legs:
+        legs = {}
+        for name, fn in (("uniform8", lambda: leg_uniform(dev, stream, chunk)),
+                         ("uneven2to8", lambda: leg_uneven(dev, stream, chunk)),
+                         ("adjoint8", lambda: leg_adjoint(dev, stream)),
+                         ("single8", lambda: leg_single(dev, stream))):
+            print("[bench] leg %s ..." % name, file=sys.stderr, flush=True)
+            legs[name] = fn()
+        out["legs"] = legs
     if not args.no_cpu:
         print("[bench] CPU baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(systems, args, gr_c, scheme)
