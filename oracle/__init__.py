@@ -32,9 +32,10 @@ def lib():
     """Load the oracle library, building it first if it is not there."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = os.environ.get("WH_ORACLE_LIB", _build.LIB)    # e.g. a sanitizer build of the same sources
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        L = C.CDLL(_build.LIB)
+        L = C.CDLL(path)
         i, l, ld, d = C.c_int, C.c_long, C.c_longdouble, C.c_double
         sig = {
             "or_max_threads": ([], i),

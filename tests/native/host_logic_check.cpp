@@ -1,0 +1,171 @@
+// Checks of the library's host logic (wh_host.h: lane packings, workspace
+// layout, configuration checks, SABA_n coefficients, tape sizes, launch
+// windows), built with AddressSanitizer and UndefinedBehaviorSanitizer by
+// tests/test_sanitizers.py.  Prints "host logic ok" and exits 0, or reports
+// the first failed check and exits 1.
+#include <cstdio>
+#include <cstring>
+#include <cstdlib>
+#include <random>
+
+#include "wh_host.h"
+
+using namespace wh_host;
+
+static int g_fail = 0;
+#define CHECK(cond)                                                            \
+  do {                                                                         \
+    if (!(cond)) {                                                             \
+      std::fprintf(stderr, "check failed at line %d: %s\n", __LINE__, #cond);  \
+      if (++g_fail > 20) std::exit(1);                                         \
+    }                                                                          \
+  } while (0)
+
+static void check_packing(const std::vector<int32_t>& np, int packing) {
+  const int S = (int)np.size();
+  Packing P;
+  std::string why;
+  const int eff = packing == WH_PACK_AUTO ? WH_PACK_POW2 : packing;
+  CHECK(make_packing(S, np.data(), eff, P, &why));
+  CHECK(P.ns == (int)P.slot_sys.size() && P.ns == (int)P.slot_pl.size());
+  CHECK(P.ns == slots_needed(S, np.data(), eff));
+  CHECK(P.ns == P.nwaves * (P.pair ? 128 : 64));
+  CHECK(P.w1 <= P.w2 && P.w2 <= P.w4 && P.w4 <= P.w8 && P.w8 <= P.nwaves);
+  // every planet of every system sits in exactly one slot (two in the split
+  // layout, whose two lanes per planet are copies); padding slots are -1
+  std::vector<int> seen((size_t)S * 8, 0);
+  for (int i = 0; i < P.ns; ++i) {
+    const int s = P.slot_sys[i], p = P.slot_pl[i];
+    CHECK(s >= -1 && s < S);
+    if (p >= 0) {
+      CHECK(s >= 0 && p < np[s]);
+      if (s >= 0 && p < 8) seen[(size_t)s * 8 + p]++;
+    }
+  }
+  const int copies = P.split ? 2 : 1;
+  for (int s = 0; s < S; ++s)
+    for (int p = 0; p < 8; ++p) CHECK(seen[(size_t)s * 8 + p] == (p < np[s] ? copies : 0));
+  // a system never straddles a wavefront, and in the one-planet layouts its
+  // planets fill an aligned group of group_size lanes from the group's start
+  if (!P.pair && !P.split) {
+    for (int i = 0; i < P.ns; ++i) {
+      const int s = P.slot_sys[i];
+      if (s < 0) continue;
+      const int G = group_size(np[s], eff);
+      const int base = i & ~(G - 1);
+      CHECK(P.slot_sys[base] == s);
+      CHECK((i - base) < G);
+      if (P.slot_pl[i] >= 0) CHECK(P.slot_pl[i] == i - base);
+    }
+  }
+  // the layout's regions are 256-byte aligned and disjoint
+  wh_config cfg;
+  config_defaults(&cfg, S);
+  cfg.packing = packing;
+  cfg.balance = 1;
+  const size_t cap = plan_capacity(&cfg, P);
+  const Layout L = make_layout(S, P.ns, cap);
+  const size_t offs[] = {L.st, L.m0s, L.dts, L.slot_sys, L.slot_pl, L.flags, L.synced, L.plan_wave, L.plan_steps,
+                         L.total};
+  for (int k = 0; k + 1 < 10; ++k) {
+    CHECK(offs[k] % 256 == 0);
+    CHECK(offs[k] <= offs[k + 1]);
+  }
+  CHECK(L.m0s - L.st >= sizeof(double) * WH_STATE_ROWS * (size_t)P.ns);
+  CHECK(L.plan_steps - L.plan_wave >= sizeof(int) * cap);
+  CHECK(cap == (P.serial ? 0 : (size_t)P.nwaves * (PLAN_Q + 2)));
+}
+
+static void check_plan(std::mt19937_64& rng) {
+  for (int trial = 0; trial < 60; ++trial) {
+    const int W = 1 + (int)(rng() % 3000);
+    const int slots = 1 + (int)(rng() % 1200);
+    const int R = trial % 3 == 0 ? 1 + (int)(rng() % 9) : 1 + (int)(rng() % 5000);
+    std::vector<double> cost(W);
+    static const double classes[] = {293, 326, 372, 478, 611, 704, 831};
+    for (auto& c : cost) c = classes[rng() % 7];
+    std::vector<int> hw, hs, off;
+    plan_windows(cost, R, slots, PLAN_Q, hw, hs, off);
+    CHECK(hw.size() == hs.size());
+    CHECK(!off.empty() && off.front() == 0 && off.back() == (int)hw.size());
+    CHECK(hw.size() <= (size_t)W * (PLAN_Q + 2));
+    std::vector<long> total(W, 0);
+    std::vector<int> last(W, -1);
+    double cmax = 0;
+    for (double c : cost) cmax = std::max(cmax, c);
+    for (size_t k = 0; k + 1 < off.size(); ++k) {
+      CHECK(off[k + 1] > off[k]);
+      CHECK(off[k + 1] - off[k] <= slots);
+      for (int e = off[k]; e < off[k + 1]; ++e) {
+        const int w = hw[e];
+        CHECK(w >= 0 && w < W);
+        if (w < 0 || w >= W) continue;
+        CHECK(last[w] != (int)k);         // a wave at most once per window
+        last[w] = (int)k;
+        CHECK(hs[e] >= 1);
+        // a wave's share of a window costs at most the window budget (or
+        // one step, when the budget is below a step)
+        CHECK(hs[e] == 1 || hs[e] * cost[w] <= cmax * R / PLAN_Q * (1 + 1e-12));
+        total[w] += hs[e];
+      }
+    }
+    for (int w = 0; w < W; ++w) CHECK(total[w] == R);
+  }
+}
+
+int main() {
+  std::mt19937_64 rng(12345);
+  // configuration checks
+  wh_config c;
+  config_defaults(&c, 10);
+  std::string why;
+  CHECK(config_ok(&c, why));
+  wh_config bad = c; bad.G = 2.0; CHECK(!config_ok(&bad, why));
+  bad = c; bad.n_systems = 0; CHECK(!config_ok(&bad, why));
+  bad = c; bad.scheme = 9; CHECK(!config_ok(&bad, why));
+  bad = c; bad.packing = 7; CHECK(!config_ok(&bad, why));
+  bad = c; bad.block_waves = 3; CHECK(!config_ok(&bad, why));
+  bad = c; bad.balance = 2; CHECK(!config_ok(&bad, why));
+  bad = c; bad.scheme = WH_SABA2; bad.gr_c = 10.0; CHECK(!config_ok(&bad, why));
+  // packings of random batches
+  for (int S : {1, 2, 7, 64, 65, 1000, 4099}) {
+    std::vector<int32_t> np(S);
+    for (auto& n : np) n = 1 + (int)(rng() % 8);
+    for (int pk : {WH_PACK_AUTO, WH_PACK_POW2, WH_PACK_G8, WH_PACK_PAIR, WH_PACK_SPLIT, WH_PACK_SERIAL})
+      check_packing(np, pk);
+  }
+  {
+    std::vector<int32_t> np(5, 9);
+    Packing P;
+    CHECK(!make_packing(5, np.data(), WH_PACK_POW2, P, &why));
+    np.assign(5, 0);
+    Packing P2;
+    CHECK(!make_packing(5, np.data(), WH_PACK_POW2, P2, &why));
+  }
+  // tape sizes: the formula, and sizes that would wrap size_t give 0
+  {
+    const TapeLayout T = tape_layout(640, 1000, 100, 1);
+    CHECK(T.n_seg == 10);
+    CHECK(T.total >= sizeof(double) * (12 * 640 * 11 + 2 * WH_TAPE_ROWS * 640 * 100 + 8 * 640));
+    CHECK(tape_layout(640, 1001, 100, 1).n_seg == 11);
+    CHECK(tape_layout(640, (int64_t(1) << 62) + 3, 1, 1).total == 0);
+    CHECK(tape_layout(1 << 27, INT64_MAX, 2, 1).total == 0);
+    CHECK(tape_layout(1 << 27, 10, int64_t(1) << 40, 4).total == 0);
+    CHECK(tape_layout(64, 0, 1, 1).n_seg == 0);
+  }
+  // SABA_n coefficients: drift and kick weights each sum to one, symmetric
+  for (int n = 1; n <= 4; ++n) {
+    double cc[5], d[4];
+    saba_coefficients(n, cc, d);
+    double sc = 0, sd = 0;
+    for (int k = 0; k <= n; ++k) sc += cc[k];
+    for (int k = 0; k < n; ++k) sd += d[k];
+    CHECK(std::fabs(sc - 1.0) < 1e-15 && std::fabs(sd - 1.0) < 1e-15);
+    for (int k = 0; k < n; ++k) CHECK(std::fabs(d[k] - d[n - 1 - k]) < 1e-15);
+  }
+  // launch windows
+  check_plan(rng);
+  if (g_fail) return 1;
+  std::printf("host logic ok\n");
+  return 0;
+}
