@@ -26,7 +26,10 @@ parts of the metric:
   legs.adjoint8   -- 1024 x 8 planets, 2e4 steps, checkpoints every 1000:
                      reverse-mode cost over the plain forward of the same run;
   legs.single8    -- the one-system configuration (1 x 8 planets, 1e5 steps,
-                     kick-drift-kick): steps/s on one 16-lane group.
+                     kick-drift-kick): steps/s on one 16-lane group;
+  legs.explorer_counts -- the headline batch with the Kepler iteration
+                     counts the autotuner picks after validating the cheaper
+                     compiled set with the envelope explorer (App. A).
 """
 from __future__ import annotations
 
@@ -125,13 +128,18 @@ def measured_counters(workload: str, chunk: int, coords: str = "dhc", packing: s
     return {"traffic": rec["bytes_per_launch"][key], "hw_flops": rec.get("hw_flops_per_launch", {}).get(key)}
 
 
-def flops_per_system_step(n_planets: np.ndarray, gr: bool, coords: str = "dhc", scheme: str = "dkd") -> float:
+def flops_per_system_step(n_planets: np.ndarray, gr: bool, coords: str = "dhc", scheme: str = "dkd",
+                          kepler_counts: int = 0) -> float:
     """Algorithmic FP64 operations of one step of the batch (the oracle's count
-    of the paper's fixed-iteration step); a SABA_n step is n drifts and n
-    kicks: n times the counted step."""
-    from paper_2307_05683_amd.flops import ALGO_FLOPS, ALGO_FLOPS_GR, ALGO_FLOPS_JACOBI, ALGO_FLOPS_JACOBI_GR
+    of the fixed-iteration step with the count set that ran: the paper's, or
+    kepler_counts = 1); a SABA_n step is n drifts and n kicks: n times the
+    counted step."""
+    from paper_2307_05683_amd.flops import (ALGO_FLOPS, ALGO_FLOPS_GR, ALGO_FLOPS_GR_KC1, ALGO_FLOPS_JACOBI,
+                                            ALGO_FLOPS_JACOBI_GR, ALGO_FLOPS_KC1)
     if coords == "jacobi":
         table = ALGO_FLOPS_JACOBI_GR if gr else ALGO_FLOPS_JACOBI
+    elif kepler_counts == 1:
+        table = ALGO_FLOPS_GR_KC1 if gr else ALGO_FLOPS_KC1
     else:
         table = ALGO_FLOPS_GR if gr else ALGO_FLOPS
     stages = int(scheme[4:]) if scheme.startswith("saba") else 1
@@ -358,6 +366,32 @@ def leg_adjoint(dev, stream, n_steps=20000, every=1000):
             "backward_over_forward": t_adj / t_plain, "gradients_finite": finite}
 
 
+def leg_counts(systems, dev, stream, chunk):
+    """The headline batch with the Kepler count set the autotuner picks: the
+    cheaper compiled set (one Halley step with 3 terms, two Newton steps)
+    after the envelope explorer has validated it on the batch's own orbits
+    within App. A's bound, else the paper's.  Its frac counts the flops of
+    the set that ran."""
+    from paper_2307_05683_amd import inputs
+    from paper_2307_05683_amd.autotune import choose_kepler_counts
+    from paper_2307_05683_amd.envelope import INTEGRATOR_COUNTS
+    from paper_2307_05683_amd.ensemble import Ensemble
+    opts = dict(packing=DEFAULT_PACKING["large8gr"], block_waves=DEFAULT_BLOCK_WAVES["large8gr"])
+    kc, worst, z = choose_kepler_counts(systems, opts, "dkd", "dhc", dev)
+    e = Ensemble.from_systems(systems, device=dev, gr_c=inputs.GR_C, chunk_steps=chunk, kepler_counts=kc, **opts)
+    warm(e, 1, chunk)
+    n = 8
+    t = timed_chunks(e, n, chunk, stream)
+    flags = int((e.flags().cpu().numpy() != 0).sum())
+    e.close()
+    fl = flops_per_system_step(systems.n_planets, True, kepler_counts=kc)
+    return {"workload": WORKLOAD_TEXT["large8gr"], "packing": opts["packing"],
+            "kepler_counts": list(INTEGRATOR_COUNTS[kc]), "validation_worst_da_over_a": worst,
+            "validation_max_z": z, "value": systems.S * n * chunk / t, "unit": "system-steps/s",
+            "steps": n * chunk, "avg_launch_ms": t * 1e3 / n,
+            "frac": fl * chunk / (t / n) / 1e12 / FP64_PEAK_TFLOPS, "flagged_systems": flags}
+
+
 def leg_single(dev, stream):
     import torch
     from paper_2307_05683_amd import inputs
@@ -462,6 +496,7 @@ def main():
             "exchange": args.exchange,
             "coords": args.coords,
             "scheme": scheme,
+            "kepler_counts": [2, 2, 4, 8],
             "flagged_systems": int((flags != 0).sum()),
         },
         # relative energy error |E(T) - E(0)| / |E(0)| per system after the warmup and timed steps (unflagged)
@@ -498,10 +533,13 @@ def main():
             out["roofline"]["frac_hardware"] = hw / FP64_PEAK_TFLOPS
     if not args.no_legs:
         legs = {}
-        for name, fn in (("uniform8", lambda: leg_uniform(dev, stream, chunk)),
-                         ("uneven2to8", lambda: leg_uneven(dev, stream, chunk)),
-                         ("adjoint8", lambda: leg_adjoint(dev, stream)),
-                         ("single8", lambda: leg_single(dev, stream))):
+        todo = [("uniform8", lambda: leg_uniform(dev, stream, chunk)),
+                ("uneven2to8", lambda: leg_uneven(dev, stream, chunk)),
+                ("adjoint8", lambda: leg_adjoint(dev, stream)),
+                ("single8", lambda: leg_single(dev, stream))]
+        if args.workload == "large8gr" and args.coords == "dhc" and scheme == "dkd":
+            todo.append(("explorer_counts", lambda: leg_counts(systems, dev, stream, chunk)))
+        for name, fn in todo:
             print("[bench] leg %s ..." % name, file=sys.stderr, flush=True)
             legs[name] = fn()
         out["legs"] = legs

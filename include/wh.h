@@ -142,6 +142,14 @@ typedef struct {
                           work in every window.  Results are bitwise those of balance = 0 (a launch
                           boundary only stores and reloads the state).  WH_PACK_SERIAL ignores it.
                           0: one launch per chunk. */
+  int32_t kepler_counts; /* iteration counts of the step's Kepler solve (Sec. 3.2, App. A): 0 the paper's
+                            (2 Halley steps with 4 series terms, then 2 Newton steps with 8); 1 one Halley
+                            step with 3 terms, then the same 2 Newton steps -- the cheapest set the envelope
+                            explorer finds within App. A's accuracy bound for eccentricities up to 0.6 at
+                            App. A's step (validate it on a batch first: autotune does).  Set 1: DHC
+                            drift-kick-drift or kick-drift-kick with the DPP exchange in the POW2, G8, PAIR
+                            and SPLIT packings, forward stepping only (no reverse mode: WH_ESTATE); the
+                            synchronized outputs' closing half drift keeps the paper's counts. */
 } wh_config;
 
 /* Fills *cfg with the defaults above (DKD, no GR, auto packing, DHC). */

@@ -16,6 +16,10 @@ OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 
 def main():
     plain = {n: oracle.count_ops(n)["flops"] for n in range(1, 9)}
     gr = {n: oracle.count_ops(n, gr=True)["flops"] for n in range(1, 9)}
+    # the integrator's second count set (wh_config.kepler_counts = 1): one
+    # Halley step with 3 series terms, then 2 Newton steps with 8
+    kc1 = {n: oracle.count_ops(n, n_halley=1, terms_halley=3)["flops"] for n in range(1, 9)}
+    kc1_gr = {n: oracle.count_ops(n, gr=True, n_halley=1, terms_halley=3)["flops"] for n in range(1, 9)}
     jac = {n: oracle.count_ops_jacobi(n)["flops"] for n in range(1, 9)}
     jac_gr = {n: oracle.count_ops_jacobi(n, gr=True)["flops"] for n in range(1, 9)}
     with open(OUT, "w") as f:
@@ -31,6 +35,9 @@ def main():
         f.write("ALGO_FLOPS_GR = %r\n" % gr)
         f.write("ALGO_FLOPS_JACOBI = %r\n" % jac)
         f.write("ALGO_FLOPS_JACOBI_GR = %r\n" % jac_gr)
+        f.write("# kepler_counts = 1: one Halley step with 3 series terms, then 2 Newton steps with 8\n")
+        f.write("ALGO_FLOPS_KC1 = %r\n" % kc1)
+        f.write("ALGO_FLOPS_GR_KC1 = %r\n" % kc1_gr)
     print(OUT, plain, gr, jac, jac_gr)
 
 

@@ -45,6 +45,7 @@ class Config(C.Structure):
         ("exchange", C.c_int32),
         ("coords", C.c_int32),
         ("balance", C.c_int32),
+        ("kepler_counts", C.c_int32),
     ]
 
 

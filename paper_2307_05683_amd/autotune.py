@@ -87,11 +87,27 @@ def time_candidate(systems, opts, gr_c, scheme, steps, warmup, device, coords="d
         e.close()
 
 
+def choose_kepler_counts(systems, opts, scheme: str = "dkd", coords: str = "dhc", device="cuda"):
+    """The cheaper compiled count set (wh_config.kepler_counts = 1) if the
+    layout can run it and the envelope explorer validates it on this batch's
+    own orbits within App. A's bound (envelope.validate_counts), else the
+    paper's (0).  Returns (kepler_counts, worst |da/a| of set 1, its largest z)."""
+    from .envelope import INTEGRATOR_COUNTS, validate_counts
+    runs_it = (coords == "dhc" and scheme in ("dkd", "kdk") and opts.get("packing") != "serial"
+               and opts.get("exchange", "auto") != "lds")
+    if not runs_it:
+        return 0, None, None
+    ok, worst, z = validate_counts(systems, INTEGRATOR_COUNTS[1], device=device)
+    return (1 if ok else 0), worst, z
+
+
 def autotune(systems, gr_c: float = 0.0, scheme: str = "dkd", steps: int = 1024, warmup: int = 64,
-             device="cuda", use_cache: bool = True, candidates=None, verbose: bool = False, coords: str = "dhc"):
+             device="cuda", use_cache: bool = True, candidates=None, verbose: bool = False, coords: str = "dhc",
+             counts: bool = False):
     """Return (best_options, table) for this batch; best_options can be passed
-    to Ensemble(...) as keyword arguments."""
-    key = shape_key(systems.n_planets, gr_c > 0, scheme, coords)
+    to Ensemble(...) as keyword arguments.  counts=True also picks the Kepler
+    count set (choose_kepler_counts) for the winning layout."""
+    key = shape_key(systems.n_planets, gr_c > 0, scheme, coords) + ("|counts" if counts else "")
     cache = _load() if use_cache else {}
     if use_cache and key in cache:
         return cache[key]["best"], cache[key]["table"]
@@ -113,7 +129,12 @@ def autotune(systems, gr_c: float = 0.0, scheme: str = "dkd", steps: int = 1024,
         table.append({"opts": opts, "system_steps_per_s": rate})
         if verbose:
             print("autotune %s: %.4g system-steps/s" % (opts, rate), flush=True)
-    best = max(table, key=lambda r: r["system_steps_per_s"])["opts"]
+    best = dict(max(table, key=lambda r: r["system_steps_per_s"])["opts"])
+    if counts:
+        kc, worst, z = choose_kepler_counts(systems, best, scheme, coords, device)
+        best["kepler_counts"] = kc
+        if verbose:
+            print("autotune: kepler_counts %d (set 1: worst |da/a| %s, largest z %s)" % (kc, worst, z), flush=True)
     if use_cache:
         cache[key] = {"best": best, "table": table}
         _save(cache)

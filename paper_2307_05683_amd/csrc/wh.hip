@@ -166,9 +166,12 @@ __device__ __forceinline__ void add_hi(double& s, double& c, double h, double l)
 // the rounded values; the increment (f-1)Q + gV, f'Q + (g'-1)V is formed in
 // double-double (lin2_dd) and c is carried through the same linear map.
 // Returns the anomaly X.
+// KC selects the iteration counts of the solve (KepSet, wh_device.h).
+template <int KC = 0>
 __device__ __forceinline__ double drift(Lane& L, double mu, double tau, KepDiag& dg) {
   KepCoef k;
-  double X = kepler_coeffs<KEP_NH, KEP_NN, KEP_KH, KEP_KN>(L.qx, L.qy, L.qz, L.vx, L.vy, L.vz, mu, tau, dg, k);
+  double X = kepler_coeffs<KepSet<KC>::NH, KepSet<KC>::NN, KepSet<KC>::KH, KepSet<KC>::KN>(L.qx, L.qy, L.qz, L.vx,
+                                                                                          L.vy, L.vz, mu, tau, dg, k);
   double hqx, hqy, hqz, hvx, hvy, hvz, lqx, lqy, lqz, lvx, lvy, lvz;
   lin2_dd(k.fm1, L.qx, k.g, L.vx, hqx, lqx);
   lin2_dd(k.fm1, L.qy, k.g, L.vy, hqy, lqy);
@@ -386,7 +389,7 @@ template <int G> __device__ __forceinline__ void dhc_to_jacobi(Lane& L, int p) {
 //
 // In Jacobi coordinates (JAC) the loop bodies are K(tk) . I(dt) (DKD) and
 // I(ti) . K(dt) (KDK), each planet drifting about mu = G M_i, with no jump.
-template <int G, bool GR, int SCHEME, int EXCH, bool JAC = false>
+template <int G, bool GR, int SCHEME, int EXCH, bool JAC = false, int KC = 0>
 __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane) {
   Exch<G, EXCH> ex;
   ex.init(lane, L.m);
@@ -441,7 +444,7 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
   } else if (SCHEME == WH_DKD) {
     double tk = L.first ? h : dt;
     for (int s = 0; s < p.n_steps; ++s) {
-      drift(L, L.m0, tk, dg);
+      drift<KC>(L, L.m0, tk, dg);
       tk = dt;
       kick_block<G, GR, EXCH>(L, ex, inv_m0, kg, h, dt, h, vkx, vky, vkz);
     }
@@ -452,7 +455,7 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
       kick_block<G, GR, EXCH>(L, ex, inv_m0, kg, ta, ti, h, vkx, vky, vkz);
       ta = h;
       ti = dt;
-      drift(L, L.m0, dt, dg);
+      drift<KC>(L, L.m0, dt, dg);
     }
   }
   int f = 0;
@@ -470,17 +473,17 @@ __device__ __forceinline__ void step_lane(const StepParams& p, Lane& L, int lane
   }
 }
 
-template <int G, bool GR, int SCHEME, int EXCH, bool JAC>
+template <int G, bool GR, int SCHEME, int EXCH, bool JAC, int KC = 0>
 __device__ void step_group(const StepParams& p, int slot, int lane) {
   Lane L = load_lane(p, slot);
-  step_lane<G, GR, SCHEME, EXCH, JAC>(p, L, lane);
+  step_lane<G, GR, SCHEME, EXCH, JAC, KC>(p, L, lane);
   store_lane(p, slot, L);
 }
 
 // The compiler fits every variant in 128 VGPRs without spills, so four
 // wavefronts stay resident per SIMD; a launch holds one wave per 64 lanes of
 // the packed ensemble and each wave runs its whole chunk of steps.
-template <bool GR, int SCHEME, int EXCH, bool JAC = false>
+template <bool GR, int SCHEME, int EXCH, bool JAC = false, int KC = 0>
 __global__ __launch_bounds__(256) void k_step(StepParams p) {
   const int lane = threadIdx.x & 63;
   int wave;
@@ -488,10 +491,10 @@ __global__ __launch_bounds__(256) void k_step(StepParams p) {
                    p.n_steps))
     return;
   const int slot = wave * 64 + lane;
-  if (wave < p.w1) step_group<1, GR, SCHEME, EXCH, JAC>(p, slot, lane);
-  else if (wave < p.w2) step_group<2, GR, SCHEME, EXCH, JAC>(p, slot, lane);
-  else if (wave < p.w4) step_group<4, GR, SCHEME, EXCH, JAC>(p, slot, lane);
-  else step_group<8, GR, SCHEME, EXCH, JAC>(p, slot, lane);
+  if (wave < p.w1) step_group<1, GR, SCHEME, EXCH, JAC, KC>(p, slot, lane);
+  else if (wave < p.w2) step_group<2, GR, SCHEME, EXCH, JAC, KC>(p, slot, lane);
+  else if (wave < p.w4) step_group<4, GR, SCHEME, EXCH, JAC, KC>(p, slot, lane);
+  else step_group<8, GR, SCHEME, EXCH, JAC, KC>(p, slot, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -550,7 +553,7 @@ __device__ __forceinline__ int lane_flags(const Lane& L, const KepDiag& dg, doub
   return f;
 }
 
-template <int G, bool GR, int SCHEME>
+template <int G, bool GR, int SCHEME, int KC = 0>
 __device__ __forceinline__ void step_lane_pair(const StepParams& p, Lane& A, Lane& B, int lane) {
   const PairMass pm = make_pair_mass<G>(A.m, B.m);
   const double dt = A.dt;
@@ -582,8 +585,8 @@ __device__ __forceinline__ void step_lane_pair(const StepParams& p, Lane& A, Lan
   } else if (SCHEME == WH_DKD) {
     double tk = A.first ? h : dt;
     for (int s = 0; s < p.n_steps; ++s) {
-      drift(A, A.m0, tk, dga);
-      drift(B, B.m0, tk, dgb);
+      drift<KC>(A, A.m0, tk, dga);
+      drift<KC>(B, B.m0, tk, dgb);
       tk = dt;
       kick_block_pair<G, GR>(A, B, pm, inv_m0, kg, h, dt, h, vka, vkb);
     }
@@ -594,8 +597,8 @@ __device__ __forceinline__ void step_lane_pair(const StepParams& p, Lane& A, Lan
       kick_block_pair<G, GR>(A, B, pm, inv_m0, kg, ta, ti, h, vka, vkb);
       ta = h;
       ti = dt;
-      drift(A, A.m0, dt, dga);
-      drift(B, B.m0, dt, dgb);
+      drift<KC>(A, A.m0, dt, dga);
+      drift<KC>(B, B.m0, dt, dgb);
     }
   }
   int f = group_or<G>(lane_flags(A, dga, p.zlim) | lane_flags(B, dgb, p.zlim));
@@ -605,15 +608,16 @@ __device__ __forceinline__ void step_lane_pair(const StepParams& p, Lane& A, Lan
   }
 }
 
-template <int G, bool GR, int SCHEME> __device__ void step_group_pair(const StepParams& p, int sa, int lane) {
+template <int G, bool GR, int SCHEME, int KC = 0>
+__device__ void step_group_pair(const StepParams& p, int sa, int lane) {
   Lane A = load_lane(p, sa);
   Lane B = load_lane(p, sa + 64);
-  step_lane_pair<G, GR, SCHEME>(p, A, B, lane);
+  step_lane_pair<G, GR, SCHEME, KC>(p, A, B, lane);
   store_lane(p, sa, A);
   store_lane(p, sa + 64, B);
 }
 
-template <bool GR, int SCHEME>
+template <bool GR, int SCHEME, int KC = 0>
 __global__ __launch_bounds__(256) void k_step_pair(StepParams p) {
   const int lane = threadIdx.x & 63;
   int wave;
@@ -621,9 +625,9 @@ __global__ __launch_bounds__(256) void k_step_pair(StepParams p) {
                    p.n_steps))
     return;
   const int sa = wave * 128 + lane;
-  if (wave < p.w1) step_group_pair<1, GR, SCHEME>(p, sa, lane);
-  else if (wave < p.w2) step_group_pair<2, GR, SCHEME>(p, sa, lane);
-  else step_group_pair<4, GR, SCHEME>(p, sa, lane);
+  if (wave < p.w1) step_group_pair<1, GR, SCHEME, KC>(p, sa, lane);
+  else if (wave < p.w2) step_group_pair<2, GR, SCHEME, KC>(p, sa, lane);
+  else step_group_pair<4, GR, SCHEME, KC>(p, sa, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -631,14 +635,14 @@ __global__ __launch_bounds__(256) void k_step_pair(StepParams p) {
 // 16-lane groups, one system each, planet p in lanes 2p and 2p + 1.  The step
 // is the one-planet step with the split interaction and the planet sums of
 // that layout.
-template <bool GR, int SCHEME>
+template <bool GR, int SCHEME, int KC = 0>
 __global__ __launch_bounds__(256) void k_step_split(StepParams p) {
   const int lane = threadIdx.x & 63;
   int wave;
   if (!launch_wave(p, (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), wave,
                    p.n_steps))
     return;
-  step_group<G_SPLIT, GR, SCHEME, 1, false>(p, wave * 64 + lane, lane);
+  step_group<G_SPLIT, GR, SCHEME, 1, false, KC>(p, wave * 64 + lane, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -2689,6 +2693,20 @@ template <int EXCH> const void* step_kernel_exch(const wh_ctx* c) {
   const bool gr = c->cfg.gr_c > 0;
   const bool jac = c->cfg.coords == WH_COORDS_JACOBI;
   const bool saba = c->cfg.scheme >= WH_SABA2, dkd = c->cfg.scheme == WH_DKD;
+  if (c->cfg.kepler_counts == 1) {
+    // the cheaper count set: DHC drift-kick-drift / kick-drift-kick in the
+    // DPP-exchange layouts (config_ok refuses the rest)
+    if (c->P.pair) {
+      if (dkd) return gr ? (const void*)k_step_pair<true, WH_DKD, 1> : (const void*)k_step_pair<false, WH_DKD, 1>;
+      return gr ? (const void*)k_step_pair<true, WH_KDK, 1> : (const void*)k_step_pair<false, WH_KDK, 1>;
+    }
+    if (c->P.split) {
+      if (dkd) return gr ? (const void*)k_step_split<true, WH_DKD, 1> : (const void*)k_step_split<false, WH_DKD, 1>;
+      return gr ? (const void*)k_step_split<true, WH_KDK, 1> : (const void*)k_step_split<false, WH_KDK, 1>;
+    }
+    if (dkd) return gr ? (const void*)k_step<true, WH_DKD, 1, false, 1> : (const void*)k_step<false, WH_DKD, 1, false, 1>;
+    return gr ? (const void*)k_step<true, WH_KDK, 1, false, 1> : (const void*)k_step<false, WH_KDK, 1, false, 1>;
+  }
   if (c->P.pair) {
     if (saba) return (const void*)k_step_pair<false, SCHEME_SABA>;
     if (dkd) return gr ? (const void*)k_step_pair<true, WH_DKD> : (const void*)k_step_pair<false, WH_DKD>;
@@ -3242,6 +3260,8 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
   if (((uintptr_t)tape & 255) != 0) return fail(WH_EINVAL, "tape must be 256-byte aligned");
   if (c->cfg.scheme != WH_DKD && c->cfg.scheme != WH_KDK && c->cfg.scheme < WH_SABA2)
     return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD, WH_KDK and WH_SABA2..4");
+  if (c->cfg.kepler_counts != 0)
+    return fail(WH_ESTATE, "reverse mode runs the paper's Kepler counts (kepler_counts = 0)");
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
   if (ckpt_every * tape_units(c) > (1 << 30)) return fail(WH_EINVAL, "ckpt_every too large for this scheme");
   TapeLayout T = tape_layout(c->P.ns, n_steps, ckpt_every, tape_units(c));

@@ -305,6 +305,18 @@ __device__ __forceinline__ void dd_add(double& s, double& c, double d, double e)
 // with 8 terms (Sec. 3.2).
 constexpr int KEP_NH = 2, KEP_NN = 2, KEP_KH = 4, KEP_KN = 8;
 
+// Count sets of the integrator's solve (wh_config.kepler_counts): 0 the
+// paper's; 1 one Halley step with 3 series terms then the paper's two Newton
+// steps with 8, the cheapest combination the envelope explorer finds within
+// App. A's bound (relative a-error < 1e-13 over 10 years of 5-day steps for
+// a test particle at a = 0.387) for every eccentricity up to 0.6.
+template <int KC> struct KepSet {
+  static constexpr int NH = KEP_NH, NN = KEP_NN, KH = KEP_KH, KN = KEP_KN;
+};
+template <> struct KepSet<1> {
+  static constexpr int NH = 1, NN = 2, KH = 3, KN = 8;
+};
+
 // ---------------------------------------------------------------------------
 // Interaction kick (Sec. 3.3, acceleration equation) inside a G-lane group,
 // using Newton's third law: round k = 1..G/2 pairs lane p with lane

@@ -39,6 +39,7 @@ inline void config_defaults(wh_config* cfg, int32_t n_systems) {
   cfg->exchange = WH_EXCH_AUTO;
   cfg->coords = WH_COORDS_DHC;
   cfg->balance = 0;
+  cfg->kepler_counts = 0;
 }
 
 struct Packing {
@@ -240,6 +241,14 @@ inline bool config_ok(const wh_config* c, std::string& why) {
   }
   if (c->chunk_steps < 0) { why = "chunk_steps must be >= 0"; return false; }
   if (c->balance != 0 && c->balance != 1) { why = "balance must be 0 or 1"; return false; }
+  if (c->kepler_counts != 0 && c->kepler_counts != 1) { why = "kepler_counts must be 0 or 1"; return false; }
+  if (c->kepler_counts == 1 &&
+      (c->coords != WH_COORDS_DHC || (c->scheme != WH_DKD && c->scheme != WH_KDK) ||
+       c->packing == WH_PACK_SERIAL || c->exchange == WH_EXCH_LDS)) {
+    why = "kepler_counts = 1 runs DHC drift-kick-drift or kick-drift-kick with the DPP exchange in the POW2, G8, "
+          "PAIR or SPLIT packing";
+    return false;
+  }
   if (!(c->z_max >= 0.0)) { why = "z_max must be >= 0"; return false; }
   if (c->exchange < WH_EXCH_AUTO || c->exchange > WH_EXCH_DPP) { why = "unknown exchange"; return false; }
   if (c->coords != WH_COORDS_DHC && c->coords != WH_COORDS_JACOBI) { why = "unknown coordinates"; return false; }

@@ -26,6 +26,9 @@ from .ensemble import _stream
 from .inputs import DT_5_DAYS, make_test_particles
 
 PAPER_COUNTS = (2, 2, 4, 8)      # Halley steps, Newton steps, Halley terms, Newton terms (Sec. 3.2)
+# The integrator's compiled count sets (wh_config.kepler_counts): 0 the
+# paper's, 1 the cheapest set the App. A search finds for e <= 0.6.
+INTEGRATOR_COUNTS = {0: PAPER_COUNTS, 1: (1, 2, 3, 8)}
 
 
 def kepler_envelope(Q, V, mu, tau, n_steps: int, counts=PAPER_COUNTS, device="cuda", return_state=False):
@@ -117,3 +120,25 @@ def search_counts(a=0.387, e_max=0.7, n_e=15, n_phase=8, dt=DT_5_DAYS, years=10.
     passing = sorted((r for r in table if np.isfinite(r["worst"]) and r["worst"] < bound), key=lambda r: r["cost"])
     best = passing[0]["counts"] if passing else None
     return passing, best, table
+
+
+def validate_counts(systems, counts, n_steps=1000, bound=1e-13, z_max=1.0, device="cuda"):
+    """Whether a count set solves every Kepler drift of this batch within
+    App. A's accuracy bound: each planet of each system, taken as a test
+    particle about its star (its own Q, V, mu = m0 and step dt, the drift the
+    integrator applies), runs n_steps fixed-count drifts; the set passes if
+    every |da/a| < bound, every state stays finite and the largest Stumpff
+    argument stays within z_max (the integrator's WH_F_ZMAX guard).  The
+    interaction kicks move the planets between drifts, so this checks the
+    solver on the batch's own orbits, not the whole map.  Returns
+    (ok, worst |da/a|, largest z)."""
+    live = np.arange(8)[None, :] < systems.n_planets[:, None]
+    Q = systems.Q[live]
+    V = systems.V[live]
+    mu = np.repeat(systems.m0, systems.n_planets)
+    tau = np.repeat(systems.dt, systems.n_planets)
+    err, zmax = kepler_envelope(Q, V, mu, tau, n_steps, counts, device)
+    ok_finite = bool(torch.isfinite(err).all().item())
+    worst = float(err.abs().max().item()) if ok_finite else float("nan")
+    z = float(zmax.max().item())
+    return ok_finite and worst < bound and z <= z_max, worst, z

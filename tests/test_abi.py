@@ -141,3 +141,18 @@ def test_noalloc_entry_point_rejects_oversized_batches_before_any_device_call():
     assert b"scratch" in L.wh_last_error()
     rc = L.wh_integrate_noalloc(C.byref(cfg), p, None, None, None, None, None, -1, 8, 8, None)
     assert rc == _lib.WH_EINVAL
+
+
+@pytest.mark.parametrize("bad", [dict(packing=_lib.WH_PACK_SERIAL), dict(coords=_lib.WH_COORDS_JACOBI),
+                                 dict(scheme=_lib.WH_SABA2), dict(exchange=_lib.WH_EXCH_LDS), dict(kepler_counts=2)])
+def test_cheaper_kepler_counts_only_where_compiled(bad):
+    L = _lib.load()
+    cfg = _lib.default_config(4)
+    cfg.kepler_counts = 1
+    for k, v in bad.items():
+        setattr(cfg, k, v)
+    npl = np.full(4, 3, dtype=np.int32)
+    assert L.wh_workspace_bytes(C.byref(cfg), npl.ctypes.data_as(C.POINTER(C.c_int32))) == 0
+    cfg = _lib.default_config(4)
+    cfg.kepler_counts = 1
+    assert L.wh_workspace_bytes(C.byref(cfg), npl.ctypes.data_as(C.POINTER(C.c_int32))) > 0
