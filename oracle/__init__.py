@@ -64,6 +64,9 @@ def lib():
             "or_jacobi_kick_direct_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, ld, ld], None),
             "or_count_ops_jacobi": ([i, i, i, i, i, i, _PL], None),
             "or_saba_coeffs": ([i, _PLD, _PLD], None),
+            "or_corrector_coeffs": ([i, i, i, _PLD, _PLD], None),
+            "or_corrector_F_series": ([i, i, _PLD], None),
+            "or_jacobi_corrector_ld": ([i, i, _PI, _PLD, _PLD, _PLD, _PLD, _PLD, i, i, i, i, ld, i], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -301,3 +304,40 @@ def saba_coeffs(n):
     c = np.zeros(n + 1, dtype=LD); d = np.zeros(n, dtype=LD)
     lib().or_saba_coeffs(int(n), c, d)
     return c, d
+
+
+CORRECTOR_SIGN = 1     # the direction of the change of variables (pinned by the corrected energy error)
+
+
+def corrector_coeffs(stages, scheme="dkd", sign=None):
+    """(a, b) of the n-stage symplectic corrector (order 2n + 1) of the Jacobi
+    map, scheme "dkd" or "kdk"."""
+    a = np.zeros(stages, dtype=LD)
+    b = np.zeros(stages, dtype=LD)
+    lib().or_corrector_coeffs(int(stages), SCHEMES[scheme], CORRECTOR_SIGN if sign is None else int(sign), a, b)
+    return a, b
+
+
+def corrector_F_series(scheme, kmax):
+    f = np.zeros(kmax + 1, dtype=LD)
+    lib().or_corrector_F_series(SCHEMES[scheme], int(kmax), f)
+    return f
+
+
+def jacobi_corrector(sysm, stages, scheme="dkd", inverse=False, Q=None, V=None, gr_c=0.0, sign=None, nthreads=0):
+    """The corrector C (or C^-1) of the Jacobi map on DHC states: mapping
+    coordinates -> real coordinates (inverse: real -> mapping)."""
+    S = sysm.S
+    Qa = _ld(sysm.Q if Q is None else Q).copy(); Va = _ld(sysm.V if V is None else V).copy()
+    lib().or_jacobi_corrector_ld(S, 8, _i(sysm.n_planets), _ld(sysm.m0), _ld(sysm.m), Qa, Va, _ld(sysm.dt),
+                                 int(stages), SCHEMES[scheme], CORRECTOR_SIGN if sign is None else int(sign),
+                                 int(bool(inverse)), LD(gr_c), nthreads)
+    return Qa, Va
+
+
+def jacobi_integrate_corrected(sysm, n_steps, stages, scheme="dkd", gr_c=0.0, sign=None):
+    """The corrected Jacobi map: C^-1 at the start, n_steps of the map, C at
+    the output; DHC in and out."""
+    Q, V = jacobi_corrector(sysm, stages, scheme, inverse=True, gr_c=gr_c, sign=sign)
+    Q, V = jacobi_integrate(sysm, n_steps, scheme=scheme, Q=Q, V=V, gr_c=gr_c)
+    return jacobi_corrector(sysm, stages, scheme, inverse=False, Q=Q, V=V, gr_c=gr_c, sign=sign)

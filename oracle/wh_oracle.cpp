@@ -163,15 +163,29 @@ template <class T> struct KepEq {
 };
 
 // Converged root of Kepler's equation in the real type: safeguarded Newton
-// (bisection whenever a Newton step leaves the bracket [lo, hi]).
+// (bisection whenever a Newton step leaves the bracket [lo, hi]).  F rises
+// with X (F' = r > 0) and F(0) = -tau, so the root lies on the side of 0 that
+// tau's sign gives; the bracket grows from 0 towards it (tau < 0: a backward
+// drift, the exact flow run backwards).
 template <class R> R solve_universal(const KepEq<R>& e) {
   R F, dF, G[4];
-  R lo = 0, hi = e.tau / e.r0;
-  for (int k = 0; k < 400; ++k) {   // grow the bracket until F(hi) > 0
-    e.eval(hi, F, dF, G);
-    if (F > 0) break;
-    lo = hi;
-    hi *= 2;
+  R lo = 0, hi = 0;
+  if (e.tau >= 0) {
+    hi = e.tau / e.r0;
+    for (int k = 0; k < 400; ++k) {   // grow the bracket until F(hi) > 0
+      e.eval(hi, F, dF, G);
+      if (F > 0) break;
+      lo = hi;
+      hi *= 2;
+    }
+  } else {
+    lo = e.tau / e.r0;
+    for (int k = 0; k < 400; ++k) {   // grow it downwards until F(lo) < 0
+      e.eval(lo, F, dF, G);
+      if (F < 0) break;
+      hi = lo;
+      lo *= 2;
+    }
   }
   R X = e.tau / e.r0;
   if (!(X > lo && X < hi)) X = (lo + hi) / 2;
@@ -820,6 +834,94 @@ template <class A> void jac_store(const JSys<ld>& s, int idx, int nmax, A* Q, A*
     }
 }
 
+// ---- Symplectic correctors for the Jacobi map --------------------------
+// (Wisdom, Holman & Touma 1996; derived here, coefficients computed.)
+// To first order in the perturbation B = H_I, the drift-kick-drift map of
+// step h is the time-h flow of A + F(x) B with A the Kepler part and
+// x = h ad_A (the first-order-in-B part of the symmetric BCH formula):
+//   drift-kick-drift  F(x) = (x/2) / sinh(x/2),
+//   kick-drift-kick   F(x) = (x/2) cosh(x/2) / sinh(x/2).
+// A near-identity canonical change of variables generated by h Psi(x) B with
+// Psi(x) = (1 - F(x)) / x (odd in x) turns that flow into the flow of A + B,
+// up to O(B^2).  The kernel X(a, b): drift a h, kick b h, drift -a h (a kick
+// carried by the Kepler flow) and Z(a, b) = X(a, b) then X(-a, -b) generate
+// 2 b h sinh(a x) B, so n stages Z(a_i, b_i) with
+//   sum_i 2 b_i a_i^(2k-1) / (2k-1)! = sigma [x^(2k-1)] Psi(x),   k = 1..n
+// remove the first-order error terms through h^(2n) (a corrector of order
+// 2n + 1).  sigma = +1 or -1 fixes which way the change is applied (the
+// pins choose it: the corrected energy error must fall).  The a_i are
+// i / (2n) (no drift of a stage longer than one step) and the b_i solve the
+// n x n system.  Z(a, b)^-1 = Z(-a, b) exactly.
+struct Corr {
+  int n;
+  ld a[8], b[8];
+};
+
+// Taylor coefficients f_k of F (F = sum_k f_k x^(2k)), k = 0..kmax, by power
+// series division of  y cosh y  (kick-drift-kick) or y  (drift-kick-drift)
+// by  sinh y = sum_k y^(2k+1) / (2k+1)!,  then y = x / 2.
+void corrector_F_series(int scheme, int kmax, ld* f) {
+  ld num[16], den[16], q[16];
+  for (int k = 0; k <= kmax; ++k) {
+    ld fac2k = 1, fac2k1 = 1;
+    for (int j = 2; j <= 2 * k; ++j) fac2k *= j;
+    fac2k1 = fac2k * (2 * k + 1);
+    den[k] = 1 / fac2k1;                        // sinh(y) / y
+    num[k] = scheme == 1 ? 1 / fac2k : (k == 0 ? 1 : 0);   // cosh(y) or 1
+  }
+  for (int k = 0; k <= kmax; ++k) {             // q = num / den
+    ld s = num[k];
+    for (int j = 1; j <= k; ++j) s -= den[j] * q[k - j];
+    q[k] = s / den[0];
+  }
+  for (int k = 0; k <= kmax; ++k) f[k] = q[k] / std::pow(2.0L, 2 * k);   // y^(2k) = x^(2k) / 4^k
+}
+
+Corr corrector_coeffs(int stages, int scheme, int sigma) {
+  Corr c;
+  c.n = stages;
+  ld f[16];
+  corrector_F_series(scheme, stages, f);
+  ld M[8][9];
+  for (int i = 0; i < stages; ++i) c.a[i] = (ld)(i + 1) / (2 * stages);
+  for (int k = 1; k <= stages; ++k) {
+    ld fac = 1;
+    for (int j = 2; j <= 2 * k - 1; ++j) fac *= j;
+    for (int i = 0; i < stages; ++i) M[k - 1][i] = 2 * std::pow(c.a[i], (ld)(2 * k - 1)) / fac;
+    M[k - 1][stages] = sigma * (-f[k]);         // [x^(2k-1)] Psi = -f_k
+  }
+  for (int col = 0; col < stages; ++col) {      // Gauss-Jordan with partial pivoting
+    int piv = col;
+    for (int r = col + 1; r < stages; ++r)
+      if (std::fabs(M[r][col]) > std::fabs(M[piv][col])) piv = r;
+    for (int j = 0; j <= stages; ++j) std::swap(M[col][j], M[piv][j]);
+    for (int r = 0; r < stages; ++r) {
+      if (r == col) continue;
+      ld g = M[r][col] / M[col][col];
+      for (int j = col; j <= stages; ++j) M[r][j] -= g * M[col][j];
+    }
+  }
+  for (int i = 0; i < stages; ++i) c.b[i] = M[i][stages] / M[i][i];
+  return c;
+}
+
+void jac_corr_stage(JSys<ld>& s, ld h, ld a, ld b) {     // Z(a, b)
+  jac_drift(s, a * h);
+  jac_kick(s, b * h);
+  jac_drift(s, -2 * a * h);
+  jac_kick(s, -b * h);
+  jac_drift(s, a * h);
+}
+
+// The change of variables C (inverse: C^-1): mapping coordinates -> real
+// coordinates.  C applies Z(a_n, b_n) first and Z(a_1, b_1) last.
+void jac_corrector(JSys<ld>& s, ld h, const Corr& c, bool inverse) {
+  if (!inverse)
+    for (int i = c.n - 1; i >= 0; --i) jac_corr_stage(s, h, c.a[i], c.b[i]);
+  else
+    for (int i = 0; i < c.n; ++i) jac_corr_stage(s, h, -c.a[i], c.b[i]);
+}
+
 template <class A> void jac_integrate_arrays(int S, int nmax, const int* np, const A* m0, const A* m, A* Q, A* V,
                                              const A* dt, long n_steps, int scheme, ld gr_c, int nthreads) {
   if (nthreads <= 0) nthreads = omp_get_max_threads();
@@ -906,6 +1008,29 @@ void or_jacobi_integrate_d(int S, int nmax, const int* np, const double* m0, con
                            const double* dt, long n_steps, int scheme, double gr_c, int nthreads) {
   jac_integrate_arrays(S, nmax, np, m0, m, Q, V, dt, n_steps, scheme, (ld)gr_c, nthreads);
 }
+// Symplectic corrector coefficients (a_i, b_i) of an n-stage corrector
+// (order 2n + 1) of scheme 0 (drift-kick-drift) or 1 (kick-drift-kick).
+void or_corrector_coeffs(int stages, int scheme, int sigma, ld* a, ld* b) {
+  Corr c = corrector_coeffs(stages, scheme, sigma);
+  for (int i = 0; i < stages; ++i) { a[i] = c.a[i]; b[i] = c.b[i]; }
+}
+// Taylor coefficients of F (for the pins).
+void or_corrector_F_series(int scheme, int kmax, ld* f) { corrector_F_series(scheme, kmax, f); }
+// Apply the corrector C (inverse != 0: C^-1) with step dt[k] to DHC states.
+void or_jacobi_corrector_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, ld* Q, ld* V, const ld* dt,
+                            int stages, int scheme, int sigma, int inverse, ld gr_c, int nthreads) {
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+  const Corr c = corrector_coeffs(stages, scheme, sigma);
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+  for (int k = 0; k < S; ++k) {
+    JSys<ld> s;
+    jac_load(s, k, nmax, np, m0, m, Q, V);
+    s.gr_c = gr_c;
+    jac_corrector(s, dt[k], c, inverse != 0);
+    jac_store(s, k, nmax, Q, V);
+  }
+}
+
 // Jacobi coordinates of DHC states (xp, vp: [S][nmax][3]).
 void or_jacobi_from_dhc_ld(int S, int nmax, const int* np, const ld* m0, const ld* m, const ld* Q, const ld* V,
                            ld* xp, ld* vp) {
