@@ -150,6 +150,15 @@ typedef struct {
                             drift-kick-drift or kick-drift-kick with the DPP exchange in the POW2, G8, PAIR
                             and SPLIT packings, forward stepping only (no reverse mode: WH_ESTATE); the
                             synchronized outputs' closing half drift keeps the paper's counts. */
+  int32_t corrector;   /* symplectic corrector stages (Wisdom, Holman & Touma 1996) of the Jacobi map: 0 none,
+                          n = 1..3 a corrector of order 2n + 1.  The integration runs in mapping coordinates:
+                          wh_init applies the inverse change of variables to the input state and every output
+                          (state, energy, elements, angular momentum) applies the change to its synchronized
+                          copy, removing the map's first-order-in-mass error terms through dt^(2n).  Each stage
+                          is a kick carried by the Kepler flow: drift a dt, kick b dt, drift -2a dt, kick -b dt,
+                          drift a dt, with a_i = i/(2n) and b_i from the conditions on the series of
+                          (x/2)/sinh(x/2) (drift-kick-drift) or (x/2)coth(x/2) (kick-drift-kick).  Needs
+                          WH_COORDS_JACOBI with WH_DKD or WH_KDK; forward only (reverse mode: WH_ESTATE). */
 } wh_config;
 
 /* Fills *cfg with the defaults above (DKD, no GR, auto packing, DHC). */

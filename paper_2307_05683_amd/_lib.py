@@ -46,6 +46,7 @@ class Config(C.Structure):
         ("coords", C.c_int32),
         ("balance", C.c_int32),
         ("kepler_counts", C.c_int32),
+        ("corrector", C.c_int32),
     ]
 
 

@@ -66,6 +66,9 @@ struct StepParams {
   const int* plan_wave;
   const int* plan_steps;
   int plan_n;
+  // symplectic corrector of the Jacobi map: stages and their coefficients
+  int corr_n;
+  double corr_a[3], corr_b[3];
 };
 
 // Wave of the packing and step count of launch wavefront k (k uniform over
@@ -923,6 +926,37 @@ __device__ __forceinline__ void planet_angmom(const Lane& L, double& lx, double&
   lz = L.m * (L.qx * L.vy - L.qy * L.vx);
 }
 
+// Symplectic corrector of the Jacobi map on a lane's (compensated) state:
+// the change from mapping to real coordinates C, or its inverse.  A stage
+// Z(a, b) drifts a dt, kicks b dt, drifts -2a dt, kicks -b dt and drifts a dt
+// (a kick carried by the Kepler flow and back); C applies the stages from
+// the last to the first, C^-1 the first to the last with a negated, which is
+// the exact inverse.  Coefficients from the host (corrector_coefficients).
+template <int G, bool GR>
+__device__ void apply_corrector(const StepParams& p, Lane& L, int lane, bool inverse) {
+  const int pg = lane & (G - 1);
+  const JacConst jc = jac_const<G>(L.m0, L.m, pg);
+  Exch<G, 0> ex;
+  ex.init(lane, L.m);
+  const double kg = GR ? p.kgr * L.m0 * L.m0 : 0.0;
+  KepDiag dg{0.0, 1.0e300};
+  double vkx, vky, vkz;
+  const double h = L.dt;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k < p.corr_n) {
+      const int i = inverse ? k : p.corr_n - 1 - k;
+      const double a = (inverse ? -p.corr_a[i] : p.corr_a[i]) * h;
+      const double b = p.corr_b[i] * h;
+      drift(L, jc.Mi, a, dg);
+      kick_jacobi<G, 0, GR>(L, ex, jc, pg, b, vkx, vky, vkz, kg);
+      drift(L, jc.Mi, -2.0 * a, dg);
+      kick_jacobi<G, 0, GR>(L, ex, jc, pg, -b, vkx, vky, vkz, kg);
+      drift(L, jc.Mi, a, dg);
+    }
+  }
+}
+
 template <int G, bool GR, int SCHEME, bool JAC = false>
 __device__ void sync_lane(const StepParams& p, Lane& L, int lane) {
   const int pg = lane & (G - 1);
@@ -944,6 +978,10 @@ __device__ void sync_lane(const StepParams& p, Lane& L, int lane) {
       else kick_block<G, GR, 0>(L, ex, 1.0 / L.m0, GR ? p.kgr * L.m0 * L.m0 : 0.0, h, h, 0.0, vkx, vky, vkz);
     }
   }
+  // the output is in real coordinates: the corrector takes the synchronized
+  // mapping coordinates there (uniform over the group: one system)
+  if constexpr (JAC)
+    if (p.corr_n > 0) apply_corrector<G, GR>(p, L, lane, false);
   L.qx += L.cqx; L.qy += L.cqy; L.qz += L.cqz;
   L.vx += L.cvx; L.vy += L.cvy; L.vz += L.cvz;
   if constexpr (JAC) jacobi_to_dhc<G>(L, pg);
@@ -1157,6 +1195,24 @@ template <int G> __device__ void to_jacobi_group(const StepParams& p, int slot, 
   dhc_to_jacobi<G>(L, lane & (G - 1));
   store_lane(p, slot, L);
 }
+// Inverse corrector at set-up: real -> mapping coordinates (Jacobi state).
+template <int G, bool GR> __device__ void corrector_in_group(const StepParams& p, int slot, int lane) {
+  Lane L = load_lane(p, slot);
+  apply_corrector<G, GR>(p, L, lane, true);
+  renorm_all(L);
+  store_lane(p, slot, L);
+}
+template <bool GR> __global__ __launch_bounds__(256) void k_corrector_in(StepParams p) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  const int slot = wave * 64 + lane;
+  if (wave < p.w1) corrector_in_group<1, GR>(p, slot, lane);
+  else if (wave < p.w2) corrector_in_group<2, GR>(p, slot, lane);
+  else if (wave < p.w4) corrector_in_group<4, GR>(p, slot, lane);
+  else corrector_in_group<8, GR>(p, slot, lane);
+}
+
 __global__ __launch_bounds__(256) void k_to_jacobi(StepParams p) {
   const int lane = threadIdx.x & 63;
   const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -2678,6 +2734,9 @@ StepParams step_params(const wh_ctx* c, int n_steps) {
   p.plan_wave = nullptr;
   p.plan_steps = nullptr;
   p.plan_n = 0;
+  p.corr_n = c->cfg.corrector;
+  for (int k = 0; k < 3; ++k) p.corr_a[k] = p.corr_b[k] = 0.0;
+  if (p.corr_n > 0) corrector_coefficients(p.corr_n, c->cfg.scheme, p.corr_a, p.corr_b);
   for (int k = 0; k < 5; ++k) p.sc[k] = 0.0;
   for (int k = 0; k < 4; ++k) p.sd[k] = 0.0;
   if (c->cfg.scheme >= WH_SABA2) {
@@ -3067,6 +3126,10 @@ wh_status wh_init(wh_ctx** out, const wh_config* cfg, const int32_t* n_planets, 
   hipLaunchKernelGGL(k_fill_u32, dim3((S + 255) / 256), dim3(256), 0, stream, (uint32_t*)c->synced, 1u, S);
   if (cfg->coords == WH_COORDS_JACOBI)
     hipLaunchKernelGGL(k_to_jacobi, dim3(c->P.nwaves), dim3(64), 0, stream, step_params(c, 0));
+  if (cfg->coords == WH_COORDS_JACOBI && cfg->corrector > 0) {
+    if (cfg->gr_c > 0) hipLaunchKernelGGL(k_corrector_in<true>, dim3(c->P.nwaves), dim3(64), 0, stream, step_params(c, 0));
+    else hipLaunchKernelGGL(k_corrector_in<false>, dim3(c->P.nwaves), dim3(64), 0, stream, step_params(c, 0));
+  }
   if ((st = hip_check(hipGetLastError(), "init kernels"))) return abandon(st);
   // the slot tables live in the context and must outlive the async copies;
   // synchronize so the caller may free the input arrays right away
@@ -3262,6 +3325,7 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
     return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD, WH_KDK and WH_SABA2..4");
   if (c->cfg.kepler_counts != 0)
     return fail(WH_ESTATE, "reverse mode runs the paper's Kepler counts (kepler_counts = 0)");
+  if (c->cfg.corrector != 0) return fail(WH_ESTATE, "reverse mode is not implemented with symplectic correctors");
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
   if (ckpt_every * tape_units(c) > (1 << 30)) return fail(WH_EINVAL, "ckpt_every too large for this scheme");
   TapeLayout T = tape_layout(c->P.ns, n_steps, ckpt_every, tape_units(c));

@@ -40,6 +40,7 @@ inline void config_defaults(wh_config* cfg, int32_t n_systems) {
   cfg->coords = WH_COORDS_DHC;
   cfg->balance = 0;
   cfg->kepler_counts = 0;
+  cfg->corrector = 0;
 }
 
 struct Packing {
@@ -249,6 +250,11 @@ inline bool config_ok(const wh_config* c, std::string& why) {
           "PAIR or SPLIT packing";
     return false;
   }
+  if (c->corrector < 0 || c->corrector > 3) { why = "corrector must be 0..3 stages"; return false; }
+  if (c->corrector > 0 && (c->coords != WH_COORDS_JACOBI || (c->scheme != WH_DKD && c->scheme != WH_KDK))) {
+    why = "symplectic correctors need Jacobi coordinates with WH_DKD or WH_KDK";
+    return false;
+  }
   if (!(c->z_max >= 0.0)) { why = "z_max must be >= 0"; return false; }
   if (c->exchange < WH_EXCH_AUTO || c->exchange > WH_EXCH_DPP) { why = "unknown exchange"; return false; }
   if (c->coords != WH_COORDS_DHC && c->coords != WH_COORDS_JACOBI) { why = "unknown coordinates"; return false; }
@@ -297,6 +303,52 @@ inline void saba_coefficients(int n, double* c, double* d) {
   for (int k = 0; k < n; ++k) d[k] = (double)w[k];
 }
 
+
+// Symplectic corrector of the Jacobi map, n stages (order 2n + 1), scheme
+// WH_DKD or WH_KDK.  To first order in the perturbation the map of step h is
+// the flow of A + F(h ad_A) B, F(x) = (x/2)/sinh(x/2) (drift-kick-drift) or
+// (x/2) cosh(x/2)/sinh(x/2) (kick-drift-kick); a stage Z(a, b) (drift a h,
+// kick b h, drift -2a h, kick -b h, drift a h) generates 2 b h sinh(a h ad_A)
+// B, so with a_i = i/(2n) the b_i solve
+//   sum_i 2 b_i a_i^(2k-1)/(2k-1)! = -f_k,  k = 1..n,
+// f_k the coefficient of x^(2k) in F: the change of variables h Psi B,
+// Psi = (1 - F(x))/x, that takes the map's flow to that of A + B.
+inline void corrector_coefficients(int n, int scheme, double* a, double* b) {
+  // F = (x/2) g(x/2)/ (sinh(y)/y) with y = x/2: numerator 1 or cosh y,
+  // denominator sinh(y)/y, both as series in y^2; divide term by term.
+  double num[8], den[8], q[8];
+  double fact = 1.0;                       // (2k)!
+  for (int k = 0; k <= n; ++k) {
+    if (k > 0) fact *= (2.0 * k - 1.0) * (2.0 * k);
+    den[k] = 1.0 / (fact * (2.0 * k + 1.0));
+    num[k] = scheme == WH_KDK ? 1.0 / fact : (k == 0 ? 1.0 : 0.0);
+  }
+  for (int k = 0; k <= n; ++k) {
+    double s = num[k];
+    for (int j = 1; j <= k; ++j) s -= den[j] * q[k - j];
+    q[k] = s / den[0];
+  }
+  double M[3][4];
+  for (int i = 0; i < n; ++i) a[i] = (i + 1.0) / (2.0 * n);
+  for (int k = 1; k <= n; ++k) {
+    double f = 1.0;                        // (2k-1)!
+    for (int j = 2; j <= 2 * k - 1; ++j) f *= j;
+    for (int i = 0; i < n; ++i) M[k - 1][i] = 2.0 * std::pow(a[i], 2 * k - 1) / f;
+    M[k - 1][n] = -q[k] / std::pow(4.0, k);   // f_k: y^(2k) = x^(2k) / 4^k
+  }
+  for (int col = 0; col < n; ++col) {      // Gauss-Jordan, partial pivoting
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(M[r][col]) > std::fabs(M[piv][col])) piv = r;
+    for (int j = 0; j <= n; ++j) std::swap(M[col][j], M[piv][j]);
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double g = M[r][col] / M[col][col];
+      for (int j = col; j <= n; ++j) M[r][j] -= g * M[col][j];
+    }
+  }
+  for (int i = 0; i < n; ++i) b[i] = M[i][n] / M[i][i];
+}
 
 struct TapeLayout {
   int64_t n_seg = 0;       // segments

@@ -41,7 +41,7 @@ class Ensemble:
 
     def __init__(self, n_planets, m0, m, Q, V, dt, *, gr_c=0.0, scheme="dkd", packing="auto", block_waves=1,
                  chunk_steps=4096, graph_launches=8, z_max=1.0, exchange="auto", coords="dhc", balance=0,
-                 kepler_counts=0, device="cuda"):
+                 kepler_counts=0, corrector=0, device="cuda"):
         L = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("Ensemble needs a GPU (no CPU path exists)")
@@ -62,6 +62,7 @@ class Ensemble:
         cfg.coords = COORDS[coords] if isinstance(coords, str) else int(coords)
         cfg.balance = int(balance)
         cfg.kepler_counts = int(kepler_counts)
+        cfg.corrector = int(corrector)
         self.cfg = cfg
         self.gr_c = float(gr_c)
         self.scheme = scheme

@@ -163,6 +163,27 @@ int main() {
     CHECK(std::fabs(sc - 1.0) < 1e-15 && std::fabs(sd - 1.0) < 1e-15);
     for (int k = 0; k < n; ++k) CHECK(std::fabs(d[k] - d[n - 1 - k]) < 1e-15);
   }
+  // symplectic corrector coefficients: a_i = i/(2n) and the stages'
+  // generator sum_i 2 b_i sinh(a_i x) meets (1 - F(x))/x to order x^(2n-1),
+  // so doubling x multiplies the difference by ~2^(2n+1)
+  for (int scheme : {WH_DKD, WH_KDK})
+    for (int n = 1; n <= 3; ++n) {
+      double a[3], b[3];
+      corrector_coefficients(n, scheme, a, b);
+      double d[2];
+      for (int j = 0; j < 2; ++j) {
+        const double x = 0.16 * (1 << j), y = x / 2;
+        const double F = scheme == WH_DKD ? y / std::sinh(y) : y * std::cosh(y) / std::sinh(y);
+        double g = 0;
+        for (int i = 0; i < n; ++i) {
+          CHECK(std::fabs(a[i] - (i + 1.0) / (2.0 * n)) < 1e-15);
+          g += 2 * b[i] * std::sinh(a[i] * x);
+        }
+        d[j] = std::fabs(g - (1 - F) / x);
+      }
+      const double r = d[1] / d[0], want = std::pow(2.0, 2 * n + 1);
+      CHECK(r > 0.7 * want && r < 1.3 * want);
+    }
   // launch windows
   check_plan(rng);
   if (g_fail) return 1;

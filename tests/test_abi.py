@@ -156,3 +156,17 @@ def test_cheaper_kepler_counts_only_where_compiled(bad):
     cfg = _lib.default_config(4)
     cfg.kepler_counts = 1
     assert L.wh_workspace_bytes(C.byref(cfg), npl.ctypes.data_as(C.POINTER(C.c_int32))) > 0
+
+
+@pytest.mark.parametrize("bad", [dict(coords=_lib.WH_COORDS_DHC), dict(scheme=_lib.WH_SABA2), dict(corrector=4),
+                                 dict(corrector=-1)])
+def test_correctors_need_jacobi_and_a_second_order_scheme(bad):
+    L = _lib.load()
+    npl = np.full(4, 3, dtype=np.int32)
+    cfg = _lib.default_config(4)
+    cfg.coords = _lib.WH_COORDS_JACOBI
+    cfg.corrector = 2
+    assert L.wh_workspace_bytes(C.byref(cfg), npl.ctypes.data_as(C.POINTER(C.c_int32))) > 0
+    for k, v in bad.items():
+        setattr(cfg, k, v)
+    assert L.wh_workspace_bytes(C.byref(cfg), npl.ctypes.data_as(C.POINTER(C.c_int32))) == 0
