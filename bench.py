@@ -102,9 +102,10 @@ def parse():
     return ap.parse_args()
 
 
-def measured_counters(workload: str, chunk: int, coords: str = "dhc", packing: str = "auto"):
-    """HBM bytes and hardware FP64 flops per launch from the committed counter
-    summary, if the kernel sources are still the ones it was taken on (else
+def measured_counters(workload: str, chunk: int, coords: str = "dhc", packing: str = "auto", windows: int = 1):
+    """HBM bytes and hardware FP64 flops per launch (per chunk of balanced
+    windows when windows > 1) from the committed counter summary, if the
+    kernel and host-planner sources are still the ones it was taken on (else
     None)."""
     import hashlib
     import re
@@ -122,7 +123,7 @@ def measured_counters(workload: str, chunk: int, coords: str = "dhc", packing: s
             return None
     if chunk != rec["chunk_steps"] or coords != "dhc":
         return None
-    key = "%s/%s" % (workload, "pow2" if packing == "auto" else packing)
+    key = "%s/%s%s" % (workload, "pow2" if packing == "auto" else packing, "+windows" if windows > 1 else "")
     if key not in rec["bytes_per_launch"]:
         return None
     return {"traffic": rec["bytes_per_launch"][key], "hw_flops": rec.get("hw_flops_per_launch", {}).get(key)}
@@ -515,14 +516,15 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
             "traffic": None,
-            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
+            "traffic_unit": "HBM bytes per bench step: one launch, or one chunk of balanced windows "
+                            "(rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
             "kernel": KERNEL_NAME.get(packing, "k_step (persistent step kernel)"),
             "algorithmic_flops_per_launch": flops_step * chunk,
             "avg_launch_ms": avg_launch * 1e3,
             "launches": args.steps,
         },
     }
-    counters = measured_counters(args.workload, chunk, args.coords, packing)
+    counters = measured_counters(args.workload, chunk, args.coords, packing, windows)
     if counters and scheme == "dkd":
         out["roofline"]["traffic"] = counters["traffic"]
         if counters["hw_flops"]:

@@ -60,8 +60,9 @@ def test_envelope_map_agrees_with_oracle_and_tf():
     solver forms g' from the Wronskian identity, and so does the oracle run
     here: cells the oracle resolves to rounding are converged on the GPU,
     cells where its solve fails outright (>= 1e-3) fail on the GPU, and in
-    between (partial convergence, where the error is a sum of truncation
-    biases) the two agree within 1.5 decades.  The oracle with the direct
+    between (partial convergence) the two agree within a tenth of a decade
+    where truncation decides the error (>= 1e-10) and within a decade
+    where amplified rounding does (1e-13 .. 1e-10).  The oracle with the direct
     g' converges in no cell where the GPU does not.  Every cell with
     T_f < dt fails and every cell with T_f >= 8 dt converges."""
     a_v = np.geomspace(0.05, 1.0, 12); e_v = np.linspace(0, 0.95, 12)
@@ -82,8 +83,12 @@ def test_envelope_map_agrees_with_oracle_and_tf():
           "\noracle (direct g')\n", np.log10(wd), flush=True)
     assert np.all(wg[wo < 1e-14] < 1e-13)
     assert np.all(wg[wo >= 1e-3] >= 1e-6)
-    mid = (wo >= 1e-13) & (wo < 1e-3)
-    assert np.all(np.abs(np.log10(wg[mid]) - np.log10(wo[mid])) <= 1.5)
+    gap = np.abs(np.log10(wg) - np.log10(wo))
+    trunc = (wo >= 1e-10) & (wo < 1e-3)
+    rounding = (wo >= 1e-13) & (wo < 1e-10)
+    assert trunc.sum() >= 10 and rounding.sum() >= 5
+    assert np.all(gap[trunc] <= 0.1), gap[trunc].max()
+    assert np.all(gap[rounding] <= 1.0), gap[rounding].max()
     assert np.all(wg[wd < 1e-14] < 1e-13)
     spt = m["steps_per_Tf"]
     assert np.all(wg[spt < 1] > 1e-3)
