@@ -129,6 +129,26 @@ def measured_counters(workload: str, chunk: int, coords: str = "dhc", packing: s
     return {"traffic": rec["bytes_per_launch"][key], "hw_flops": rec.get("hw_flops_per_launch", {}).get(key)}
 
 
+def fp64_issue_probe() -> dict | None:
+    """Run the standalone FP64 issue-rate probe (built beside the library) as
+    a child process: the FMA rate the chip sustains at 8 wavefronts per SIMD
+    and the issue cost of a reciprocal seed, context for the roofline
+    fractions.  None if the probe is not built or fails."""
+    exe = os.path.join(ROOT, "paper_2307_05683_amd", "fp64_issue_probe")
+    if not os.access(exe, os.X_OK):
+        return None
+    try:
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    except (OSError, subprocess.SubprocessError):
+        return None
+    if r.returncode != 0:
+        return None
+    try:
+        return json.loads(r.stdout.strip().splitlines()[-1])
+    except (ValueError, IndexError):
+        return None
+
+
 def flops_per_system_step(n_planets: np.ndarray, gr: bool, coords: str = "dhc", scheme: str = "dkd",
                           kepler_counts: int = 0) -> float:
     """Algorithmic FP64 operations of one step of the batch (the oracle's count
@@ -533,6 +553,13 @@ def main():
             hw = counters["hw_flops"] / avg_launch / 1e12
             out["roofline"]["achieved_hardware"] = hw
             out["roofline"]["frac_hardware"] = hw / FP64_PEAK_TFLOPS
+    probe = fp64_issue_probe()
+    if probe:
+        # the FP64 FMA rate the chip sustains under full load (its clock drops
+        # below the 2.4 GHz of the published peak), beside the published peak
+        out["roofline"]["sustained_fma_tflops"] = probe["fma_tflops"]
+        out["roofline"]["frac_of_sustained_fma"] = achieved / probe["fma_tflops"]
+        out["roofline"]["issue_probe"] = probe
     if not args.no_legs:
         legs = {}
         todo = [("uniform8", lambda: leg_uniform(dev, stream, chunk)),

@@ -19,16 +19,28 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc"] + FLAGS + list(extra) + [SRC, "-o", tmp]
+PROBE_SRC = os.path.join(PKG, "csrc", "fp64_issue_probe.hip")
+PROBE = os.path.join(PKG, "fp64_issue_probe")
+
+
+def _hipcc(cmd, out, verbose):
+    tmp = out + ".tmp"
+    cmd = cmd + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    _hipcc(["hipcc"] + FLAGS + list(extra) + [SRC], LIB, verbose)
+    # the FP64 issue-rate probe bench.py reports beside the roofline (a
+    # standalone program, not part of the library)
+    probe_flags = [f for f in FLAGS if f not in ("-fPIC", "-shared")]
+    _hipcc(["hipcc"] + probe_flags + [PROBE_SRC], PROBE, verbose)
     return LIB
 
 
