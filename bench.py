@@ -197,8 +197,9 @@ def _cpu_model() -> dict:
 def cpu_baseline(systems, args, gr_c, scheme="dkd"):
     """The oracle as it stands (double precision, Kepler solved to
     convergence, OpenMP over systems) on bounded samples: the headline
-    workload on all host threads and on one, the uneven batch, the
-    one-system configuration in full, and the long-double parity reference."""
+    workload on all host threads and on one, the uniform and uneven
+    batches, the one-system configuration in full, and the long-double
+    parity reference."""
     import oracle
     from paper_2307_05683_amd import inputs
     threads = oracle.max_threads()
@@ -229,6 +230,11 @@ def cpu_baseline(systems, args, gr_c, scheme="dkd"):
         "cpu": _cpu_model(),
     }
     if not args.no_legs and args.coords == "dhc":
+        uni = inputs.workload("uniform8").subset(np.arange(args.cpu_systems))
+        n_uni = args.cpu_steps // 4
+        t_uni = run(uni, n_uni, threads, gr=0.0)
+        out["uniform8"] = {"value": uni.S * n_uni / t_uni, "sample": "%d systems x %d steps, %d threads (%.1f s)"
+                           % (uni.S, n_uni, threads, t_uni)}
         unev = inputs.workload("uneven2to8").subset(np.arange(args.cpu_systems))
         n_u = args.cpu_steps // 4
         t_u = run(unev, n_u, threads, gr=0.0)
@@ -238,11 +244,11 @@ def cpu_baseline(systems, args, gr_c, scheme="dkd"):
         t_s = run(single, 100_000, 1, sch="kdk", gr=0.0)
         out["single8"] = {"value": 1e5 / t_s, "sample": "1 system x 1e5 steps (the whole configuration), "
                           "kick-drift-kick, one thread (%.2f s)" % t_s}
-        ld = sub.subset(np.arange(16))
+        ld = sub.subset(np.arange(min(16, sub.S)))
         t_ld = run(ld, 2000, 1, precision="ld")
         out["long_double_1core"] = {"value": ld.S * 2000 / t_ld,
-                                    "sample": "16 systems x 2000 steps in long double on one thread (the parity "
-                                              "reference, not the baseline; %.1f s)" % t_ld}
+                                    "sample": "%d systems x 2000 steps in long double on one thread (the parity "
+                                              "reference, not the baseline; %.1f s)" % (ld.S, t_ld)}
     return out
 
 
