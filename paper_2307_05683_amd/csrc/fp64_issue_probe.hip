@@ -1,4 +1,4 @@
-// FP64 issue-rate probe: what one MI355X sustains on plain FP64 vector work,
+// FP64 issue-rate probe: the rate of plain FP64 vector streams on one MI355X,
 // measured the same way the step kernels are (HIP events around launches of
 // 8 wavefronts per SIMD), as context for their roofline fractions.
 //
@@ -7,7 +7,7 @@
 //         of the Kepler solve and the interaction kick)
 //   mix   per chain one v_rcp_f64 followed by eight v_fma_f64
 //
-// Prints one JSON line: the sustained FMA rate in TFLOP/s (2 flops per FMA
+// Prints one JSON line: the FMA stream's rate in TFLOP/s (2 flops per FMA
 // lane), the time per wave64 instruction per SIMD of each stream, and the
 // issue cost of a reciprocal seed inside an FMA stream in FMA units.
 // Standalone program (no library, no inputs); exits non-zero on any HIP error.
