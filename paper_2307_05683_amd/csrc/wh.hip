@@ -1417,6 +1417,20 @@ __device__ void adj_record_lane(const AdjParams& q, int slot, int lane) {
   }
 }
 
+// One step's row of a segment tape (TAPE_ROWS values of one slot).
+struct TapeRow {
+  double v[TAPE_ROWS];
+};
+__device__ __forceinline__ void load_tape_row(const double* row, int ns, TapeRow& r) {
+#pragma unroll
+  for (int i = 0; i < TAPE_ROWS; ++i) r.v[i] = row[(size_t)i * ns];
+}
+// The two slots of a pair-layout lane: slot 128 w + l and slot 128 w + 64 + l.
+__device__ __forceinline__ void load_tape_rows_pair(const double* ra, int ns, TapeRow& a, TapeRow& b) {
+  load_tape_row(ra, ns, a);
+  load_tape_row(ra + 64, ns, b);
+}
+
 // Reverse sweep of a recorded segment: the adjoint state is carried back
 // through the transposed Jacobian of every sub-step.
 template <int G, bool GR, int SCH = WH_DKD>
@@ -1437,16 +1451,20 @@ __device__ void adj_sweep_lane(const AdjParams& q, int slot, int lane) {
   if constexpr (SCH == SCHEME_SABA) {
     const int nu = p.saba_n;
     const double c1dt = p.sc[0] * dt;
-    for (int u = q.n_seg * nu - 1; u >= 0; --u) {
+    const int nunits = q.n_seg * nu;
+    TapeRow nxt;
+    if (nunits > 0) load_tape_row(q.tape + (size_t)(nunits - 1) * TAPE_ROWS * ns + slot, ns, nxt);
+    for (int u = nunits - 1; u >= 0; --u) {
       const int s = u / nu, k = u - s * nu;
-      const double* row = q.tape + (size_t)u * TAPE_ROWS * ns + slot;
-      const double q0x = row[0], q0y = row[ns], q0z = row[2 * ns];
-      const double v0x = row[3 * ns], v0y = row[4 * ns], v0z = row[5 * ns];
-      const double vkx = row[7 * ns], vky = row[8 * ns], vkz = row[9 * ns];
+      const TapeRow cur = nxt;
+      if (u > 0) load_tape_row(q.tape + (size_t)(u - 1) * TAPE_ROWS * ns + slot, ns, nxt);
+      const double q0x = cur.v[0], q0y = cur.v[1], q0z = cur.v[2];
+      const double v0x = cur.v[3], v0y = cur.v[4], v0z = cur.v[5];
+      const double vkx = cur.v[7], vky = cur.v[8], vkz = cur.v[9];
       const double tau = k > 0 ? p.sc[k] * dt : (q.first_synced && s == 0 ? c1dt : 2.0 * c1dt);
       const double tb = p.sd[k] * dt;
       KepFwd kf;
-      kepler_at_X(q0x, q0y, q0z, v0x, v0y, v0z, m0, tau, row[6 * ns], kf);
+      kepler_at_X(q0x, q0y, q0z, v0x, v0y, v0z, m0, tau, cur.v[6], kf);
       const double q1x = kf.f * q0x + kf.g * v0x, q1y = kf.f * q0y + kf.g * v0y, q1z = kf.f * q0z + kf.g * v0z;
       const double v1x = kf.fd * q0x + kf.gd * v0x, v1y = kf.fd * q0y + kf.gd * v0y, v1z = kf.fd * q0z + kf.gd * v0z;
       kick_block_vjp<G, false>(a, ex, m, m0, inv_m0, 0.0, q1x, q1y, q1z, v1x, v1y, v1z, vkx, vky, vkz, 0.5 * tb, tb,
@@ -1460,12 +1478,15 @@ __device__ void adj_sweep_lane(const AdjParams& q, int slot, int lane) {
   }
   if constexpr (SCH == WH_KDK) {
     // step = kick block (ta, ti, h) then K(dt): the drift's adjoint first
+    TapeRow nxt;
+    if (q.n_seg > 0) load_tape_row(q.tape + (size_t)(q.n_seg - 1) * TAPE_ROWS * ns + slot, ns, nxt);
     for (int s = q.n_seg - 1; s >= 0; --s) {
-      const double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
-      const double q0x = row[0], q0y = row[ns], q0z = row[2 * ns];
-      const double v0x = row[3 * ns], v0y = row[4 * ns], v0z = row[5 * ns];
-      const double X = row[6 * ns];
-      const double vkx = row[7 * ns], vky = row[8 * ns], vkz = row[9 * ns];
+      const TapeRow cur = nxt;
+      if (s > 0) load_tape_row(q.tape + (size_t)(s - 1) * TAPE_ROWS * ns + slot, ns, nxt);
+      const double q0x = cur.v[0], q0y = cur.v[1], q0z = cur.v[2];
+      const double v0x = cur.v[3], v0y = cur.v[4], v0z = cur.v[5];
+      const double X = cur.v[6];
+      const double vkx = cur.v[7], vky = cur.v[8], vkz = cur.v[9];
       const bool first = q.first_synced && s == 0;
       const double ta = first ? 0.0 : h, ti = first ? h : dt;
       // the drift's starting point: positions after both jumps
@@ -1493,12 +1514,18 @@ __device__ void adj_sweep_lane(const AdjParams& q, int slot, int lane) {
     store_grad(q.grad, ns, slot, a);
     return;
   }
+  // The tape row of step s - 1 is loaded while step s is swept, so the
+  // loads' latency hides behind a step's arithmetic (one wavefront per SIMD
+  // has nothing else to switch to).
+  TapeRow nxt;
+  if (q.n_seg > 0) load_tape_row(q.tape + (size_t)(q.n_seg - 1) * TAPE_ROWS * ns + slot, ns, nxt);
   for (int s = q.n_seg - 1; s >= 0; --s) {
-    const double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
-    double q0x = row[0], q0y = row[ns], q0z = row[2 * ns];
-    double v0x = row[3 * ns], v0y = row[4 * ns], v0z = row[5 * ns];
-    double X = row[6 * ns];
-    double vkx = row[7 * ns], vky = row[8 * ns], vkz = row[9 * ns];
+    const TapeRow cur = nxt;
+    if (s > 0) load_tape_row(q.tape + (size_t)(s - 1) * TAPE_ROWS * ns + slot, ns, nxt);
+    double q0x = cur.v[0], q0y = cur.v[1], q0z = cur.v[2];
+    double v0x = cur.v[3], v0y = cur.v[4], v0z = cur.v[5];
+    double X = cur.v[6];
+    double vkx = cur.v[7], vky = cur.v[8], vkz = cur.v[9];
     double tau = (q.first_synced && s == 0) ? h : dt;
     KepFwd k;
     kepler_at_X(q0x, q0y, q0z, v0x, v0y, v0z, m0, tau, X, k);
@@ -1656,18 +1683,21 @@ __device__ void adj_sweep_pair(const AdjParams& q, int sa, int lane) {
   if constexpr (SCH == SCHEME_SABA) {
     const int nu = p.saba_n;
     const double c1dt = p.sc[0] * dt;
-    for (int u = q.n_seg * nu - 1; u >= 0; --u) {
+    const int nunits = q.n_seg * nu;
+    TapeRow na, nb;
+    if (nunits > 0) load_tape_rows_pair(q.tape + (size_t)(nunits - 1) * TAPE_ROWS * ns + sa, ns, na, nb);
+    for (int u = nunits - 1; u >= 0; --u) {
       const int s = u / nu, k = u - s * nu;
-      const double* ra = q.tape + (size_t)u * TAPE_ROWS * ns + sa;
-      const double* rb = ra + 64;
-      const double q0a[3] = {ra[0], ra[ns], ra[2 * ns]}, v0a[3] = {ra[3 * ns], ra[4 * ns], ra[5 * ns]};
-      const double q0b[3] = {rb[0], rb[ns], rb[2 * ns]}, v0b[3] = {rb[3 * ns], rb[4 * ns], rb[5 * ns]};
-      const double vka[3] = {ra[7 * ns], ra[8 * ns], ra[9 * ns]}, vkb[3] = {rb[7 * ns], rb[8 * ns], rb[9 * ns]};
+      const TapeRow ca = na, cb = nb;
+      if (u > 0) load_tape_rows_pair(q.tape + (size_t)(u - 1) * TAPE_ROWS * ns + sa, ns, na, nb);
+      const double q0a[3] = {ca.v[0], ca.v[1], ca.v[2]}, v0a[3] = {ca.v[3], ca.v[4], ca.v[5]};
+      const double q0b[3] = {cb.v[0], cb.v[1], cb.v[2]}, v0b[3] = {cb.v[3], cb.v[4], cb.v[5]};
+      const double vka[3] = {ca.v[7], ca.v[8], ca.v[9]}, vkb[3] = {cb.v[7], cb.v[8], cb.v[9]};
       const double tau = k > 0 ? p.sc[k] * dt : (q.first_synced && s == 0 ? c1dt : 2.0 * c1dt);
       const double tb = p.sd[k] * dt;
       KepFwd ka, kb;
-      kepler_at_X(q0a[0], q0a[1], q0a[2], v0a[0], v0a[1], v0a[2], m0, tau, ra[6 * ns], ka);
-      kepler_at_X(q0b[0], q0b[1], q0b[2], v0b[0], v0b[1], v0b[2], m0, tau, rb[6 * ns], kb);
+      kepler_at_X(q0a[0], q0a[1], q0a[2], v0a[0], v0a[1], v0a[2], m0, tau, ca.v[6], ka);
+      kepler_at_X(q0b[0], q0b[1], q0b[2], v0b[0], v0b[1], v0b[2], m0, tau, cb.v[6], kb);
       double q1a[3], v1a[3], q1b[3], v1b[3];
       for (int c = 0; c < 3; ++c) {
         q1a[c] = ka.f * q0a[c] + ka.g * v0a[c]; v1a[c] = ka.fd * q0a[c] + ka.gd * v0a[c];
@@ -1687,12 +1717,14 @@ __device__ void adj_sweep_pair(const AdjParams& q, int sa, int lane) {
     return;
   }
   if constexpr (SCH == WH_KDK) {
+    TapeRow na, nb;
+    if (q.n_seg > 0) load_tape_rows_pair(q.tape + (size_t)(q.n_seg - 1) * TAPE_ROWS * ns + sa, ns, na, nb);
     for (int s = q.n_seg - 1; s >= 0; --s) {
-      const double* ra = q.tape + (size_t)s * TAPE_ROWS * ns + sa;
-      const double* rb = ra + 64;
-      const double q0a[3] = {ra[0], ra[ns], ra[2 * ns]}, v0a[3] = {ra[3 * ns], ra[4 * ns], ra[5 * ns]};
-      const double q0b[3] = {rb[0], rb[ns], rb[2 * ns]}, v0b[3] = {rb[3 * ns], rb[4 * ns], rb[5 * ns]};
-      const double vka[3] = {ra[7 * ns], ra[8 * ns], ra[9 * ns]}, vkb[3] = {rb[7 * ns], rb[8 * ns], rb[9 * ns]};
+      const TapeRow ca = na, cb = nb;
+      if (s > 0) load_tape_rows_pair(q.tape + (size_t)(s - 1) * TAPE_ROWS * ns + sa, ns, na, nb);
+      const double q0a[3] = {ca.v[0], ca.v[1], ca.v[2]}, v0a[3] = {ca.v[3], ca.v[4], ca.v[5]};
+      const double q0b[3] = {cb.v[0], cb.v[1], cb.v[2]}, v0b[3] = {cb.v[3], cb.v[4], cb.v[5]};
+      const double vka[3] = {ca.v[7], ca.v[8], ca.v[9]}, vkb[3] = {cb.v[7], cb.v[8], cb.v[9]};
       const bool first = q.first_synced && s == 0;
       const double ta = first ? 0.0 : h, ti = first ? h : dt;
       double s2[3], q3a[3], q3b[3];
@@ -1710,8 +1742,8 @@ __device__ void adj_sweep_pair(const AdjParams& q, int sa, int lane) {
         for (int k = 0; k < 3; ++k) { q3a[k] = q0a[k] + k2 * s2[k]; q3b[k] = q0b[k] + k2 * s2[k]; }
       }
       KepFwd ka, kb;
-      kepler_at_X(q3a[0], q3a[1], q3a[2], vka[0], vka[1], vka[2], m0, dt, ra[6 * ns], ka);
-      kepler_at_X(q3b[0], q3b[1], q3b[2], vkb[0], vkb[1], vkb[2], m0, dt, rb[6 * ns], kb);
+      kepler_at_X(q3a[0], q3a[1], q3a[2], vka[0], vka[1], vka[2], m0, dt, ca.v[6], ka);
+      kepler_at_X(q3b[0], q3b[1], q3b[2], vkb[0], vkb[1], vkb[2], m0, dt, cb.v[6], kb);
       double gmu = 0.0;
       kepler_vjp(ka, q3a[0], q3a[1], q3a[2], vka[0], vka[1], vka[2], m0, a.qx, a.qy, a.qz, a.vx, a.vy, a.vz, gmu);
       a.m0 += gmu;
@@ -1725,16 +1757,18 @@ __device__ void adj_sweep_pair(const AdjParams& q, int sa, int lane) {
     store_grad(q.grad, ns, sb, b);
     return;
   }
+  TapeRow na, nb;
+  if (q.n_seg > 0) load_tape_rows_pair(q.tape + (size_t)(q.n_seg - 1) * TAPE_ROWS * ns + sa, ns, na, nb);
   for (int s = q.n_seg - 1; s >= 0; --s) {
-    const double* ra = q.tape + (size_t)s * TAPE_ROWS * ns + sa;
-    const double* rb = ra + 64;
-    const double q0a[3] = {ra[0], ra[ns], ra[2 * ns]}, v0a[3] = {ra[3 * ns], ra[4 * ns], ra[5 * ns]};
-    const double q0b[3] = {rb[0], rb[ns], rb[2 * ns]}, v0b[3] = {rb[3 * ns], rb[4 * ns], rb[5 * ns]};
-    const double vka[3] = {ra[7 * ns], ra[8 * ns], ra[9 * ns]}, vkb[3] = {rb[7 * ns], rb[8 * ns], rb[9 * ns]};
+    const TapeRow ca = na, cb = nb;
+    if (s > 0) load_tape_rows_pair(q.tape + (size_t)(s - 1) * TAPE_ROWS * ns + sa, ns, na, nb);
+    const double q0a[3] = {ca.v[0], ca.v[1], ca.v[2]}, v0a[3] = {ca.v[3], ca.v[4], ca.v[5]};
+    const double q0b[3] = {cb.v[0], cb.v[1], cb.v[2]}, v0b[3] = {cb.v[3], cb.v[4], cb.v[5]};
+    const double vka[3] = {ca.v[7], ca.v[8], ca.v[9]}, vkb[3] = {cb.v[7], cb.v[8], cb.v[9]};
     const double tau = (q.first_synced && s == 0) ? h : dt;
     KepFwd ka, kb;
-    kepler_at_X(q0a[0], q0a[1], q0a[2], v0a[0], v0a[1], v0a[2], m0, tau, ra[6 * ns], ka);
-    kepler_at_X(q0b[0], q0b[1], q0b[2], v0b[0], v0b[1], v0b[2], m0, tau, rb[6 * ns], kb);
+    kepler_at_X(q0a[0], q0a[1], q0a[2], v0a[0], v0a[1], v0a[2], m0, tau, ca.v[6], ka);
+    kepler_at_X(q0b[0], q0b[1], q0b[2], v0b[0], v0b[1], v0b[2], m0, tau, cb.v[6], kb);
     double q1a[3], v1a[3], q1b[3], v1b[3];
     for (int k = 0; k < 3; ++k) {
       q1a[k] = ka.f * q0a[k] + ka.g * v0a[k]; v1a[k] = ka.fd * q0a[k] + ka.gd * v0a[k];
@@ -2212,38 +2246,48 @@ __device__ void adj_sweep_jac(const AdjParams& q, int slot, int lane) {
   if constexpr (SCH == SCHEME_SABA) {
     const int nu = p.saba_n;
     const double c1dt = p.sc[0] * dt;
-    for (int u = q.n_seg * nu - 1; u >= 0; --u) {
+    const int nunits = q.n_seg * nu;
+    TapeRow nxt;
+    if (nunits > 0) load_tape_row(q.tape + (size_t)(nunits - 1) * TAPE_ROWS * ns + slot, ns, nxt);
+    for (int u = nunits - 1; u >= 0; --u) {
       const int s = u / nu, kk = u - s * nu;
-      const double* row = q.tape + (size_t)u * TAPE_ROWS * ns + slot;
+      const TapeRow cur = nxt;
+      if (u > 0) load_tape_row(q.tape + (size_t)(u - 1) * TAPE_ROWS * ns + slot, ns, nxt);
       const double tau = kk > 0 ? p.sc[kk] * dt : (q.first_synced && s == 0 ? c1dt : 2.0 * c1dt);
-      const double x0x = row[0], x0y = row[ns], x0z = row[2 * ns];
-      const double v0x = row[3 * ns], v0y = row[4 * ns], v0z = row[5 * ns];
-      kepler_at_X(x0x, x0y, x0z, v0x, v0y, v0z, jc.Mi, tau, row[6 * ns], k);
+      const double x0x = cur.v[0], x0y = cur.v[1], x0z = cur.v[2];
+      const double v0x = cur.v[3], v0y = cur.v[4], v0z = cur.v[5];
+      kepler_at_X(x0x, x0y, x0z, v0x, v0y, v0z, jc.Mi, tau, cur.v[6], k);
       const double x1x = k.f * x0x + k.g * v0x, x1y = k.f * x0y + k.g * v0y, x1z = k.f * x0z + k.g * v0z;
       kick_jacobi_vjp<G, GR>(a, gMim1, ex, jc, pg, m, m0, kg, x1x, x1y, x1z, p.sd[kk] * dt);
-      jac_drift_vjp(a, gMim1, jc.Mi, x0x, x0y, x0z, v0x, v0y, v0z, tau, row[6 * ns], k);
+      jac_drift_vjp(a, gMim1, jc.Mi, x0x, x0y, x0z, v0x, v0y, v0z, tau, cur.v[6], k);
       jac_fold_mim1<G>(a, gMim1, pg);
     }
   } else if constexpr (SCH == WH_KDK) {
+    TapeRow nxt;
+    if (q.n_seg > 0) load_tape_row(q.tape + (size_t)(q.n_seg - 1) * TAPE_ROWS * ns + slot, ns, nxt);
     for (int s = q.n_seg - 1; s >= 0; --s) {
-      const double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
-      const double x0x = row[0], x0y = row[ns], x0z = row[2 * ns];
+      const TapeRow cur = nxt;
+      if (s > 0) load_tape_row(q.tape + (size_t)(s - 1) * TAPE_ROWS * ns + slot, ns, nxt);
+      const double x0x = cur.v[0], x0y = cur.v[1], x0z = cur.v[2];
       const double ti = (q.first_synced && s == 0) ? h : dt;
       // K(dt) from (x0, V' after the kick), then the kick at x0
-      jac_drift_vjp(a, gMim1, jc.Mi, x0x, x0y, x0z, row[7 * ns], row[8 * ns], row[9 * ns], dt, row[6 * ns], k);
+      jac_drift_vjp(a, gMim1, jc.Mi, x0x, x0y, x0z, cur.v[7], cur.v[8], cur.v[9], dt, cur.v[6], k);
       kick_jacobi_vjp<G, GR>(a, gMim1, ex, jc, pg, m, m0, kg, x0x, x0y, x0z, ti);
       jac_fold_mim1<G>(a, gMim1, pg);
     }
   } else {
+    TapeRow nxt;
+    if (q.n_seg > 0) load_tape_row(q.tape + (size_t)(q.n_seg - 1) * TAPE_ROWS * ns + slot, ns, nxt);
     for (int s = q.n_seg - 1; s >= 0; --s) {
-      const double* row = q.tape + (size_t)s * TAPE_ROWS * ns + slot;
+      const TapeRow cur = nxt;
+      if (s > 0) load_tape_row(q.tape + (size_t)(s - 1) * TAPE_ROWS * ns + slot, ns, nxt);
       const double tau = (q.first_synced && s == 0) ? h : dt;
-      const double x0x = row[0], x0y = row[ns], x0z = row[2 * ns];
-      const double v0x = row[3 * ns], v0y = row[4 * ns], v0z = row[5 * ns];
-      kepler_at_X(x0x, x0y, x0z, v0x, v0y, v0z, jc.Mi, tau, row[6 * ns], k);
+      const double x0x = cur.v[0], x0y = cur.v[1], x0z = cur.v[2];
+      const double v0x = cur.v[3], v0y = cur.v[4], v0z = cur.v[5];
+      kepler_at_X(x0x, x0y, x0z, v0x, v0y, v0z, jc.Mi, tau, cur.v[6], k);
       const double x1x = k.f * x0x + k.g * v0x, x1y = k.f * x0y + k.g * v0y, x1z = k.f * x0z + k.g * v0z;
       kick_jacobi_vjp<G, GR>(a, gMim1, ex, jc, pg, m, m0, kg, x1x, x1y, x1z, dt);
-      jac_drift_vjp(a, gMim1, jc.Mi, x0x, x0y, x0z, v0x, v0y, v0z, tau, row[6 * ns], k);
+      jac_drift_vjp(a, gMim1, jc.Mi, x0x, x0y, x0z, v0x, v0y, v0z, tau, cur.v[6], k);
       jac_fold_mim1<G>(a, gMim1, pg);   // per step, so the sums do not depend on the segments
     }
   }
