@@ -128,7 +128,7 @@ def test_paper_combination_at_mercury():
 
 
 def test_search_agrees_with_oracle():
-    """App. A search on a subset of combinations: the GPU's pass/fail verdict
+    """App. A search on a subset of combinations: the GPU's pass/fail outcome
     matches the oracle's wherever the oracle's worst error is not within a
     factor 3 of the bound, and the cheapest passing combination passes the
     oracle too."""
