@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--balance", type=int, default=None, choices=[0, 1],
                     help="balanced launch windows (default: per workload)")
     ap.add_argument("--chunk", type=int, default=4096, help="Wisdom-Holman steps per launch")
+    ap.add_argument("--systems", type=int, default=0,
+                    help="run only the workload's first N systems (0: all; an occupancy scan, not the headline)")
     ap.add_argument("--exchange", default="auto", choices=["auto", "dpp", "lds"])
     ap.add_argument("--scheme", default=None, choices=["dkd", "kdk", "saba2", "saba3", "saba4"],
                     help="step composition (default: the workload's, drift-kick-drift)")
@@ -460,6 +462,12 @@ def main():
     gr_c = inputs.GR_C if args.workload == "large8gr" else 0.0
     scheme = args.scheme or ("kdk" if args.workload == "single8" else "dkd")
     systems = inputs.workload(args.workload)
+    full_S = systems.S
+    if args.systems:
+        if not 1 <= args.systems <= full_S:
+            print("--systems must be in 1..%d for %s" % (full_S, args.workload), file=sys.stderr)
+            sys.exit(2)
+        systems = systems.subset(np.arange(args.systems))
     dev = torch.device("cuda:0")
     chunk = args.chunk
     opts = dict(packing=packing, block_waves=block_waves, chunk_steps=chunk, exchange=args.exchange,
@@ -510,7 +518,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "%s: %s" % (args.workload, WORKLOAD_TEXT[args.workload]),
+            "workload": "%s: %s%s" % (args.workload, WORKLOAD_TEXT[args.workload],
+                                      "" if systems.S == full_S else " (first %d systems only)" % systems.S),
             "wh_steps_per_step": chunk,
             "warmup_launches_run": warm_run,
             "systems": systems.S,
@@ -550,7 +559,8 @@ def main():
             "launches": args.steps,
         },
     }
-    counters = measured_counters(args.workload, chunk, args.coords, packing, windows)
+    # the committed counters describe the whole batch
+    counters = measured_counters(args.workload, chunk, args.coords, packing, windows) if systems.S == full_S else None
     if counters and scheme == "dkd":
         out["roofline"]["traffic"] = counters["traffic"]
         if counters["hw_flops"]:

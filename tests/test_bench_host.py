@@ -24,6 +24,12 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout.strip() == ""
 
 
+def test_systems_subset_is_bounded():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "uniform8", "--systems",
+                        "5000"], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2 and "--systems must be in 1..4096" in r.stderr
+
+
 def test_cpu_baseline_fields():
     s = inputs.make_systems(8, 3, n_planets=8)
     args = argparse.Namespace(cpu_systems=4, cpu_steps=40, coords="dhc", no_legs=True)
