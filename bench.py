@@ -345,17 +345,19 @@ def leg_uneven(dev, stream, chunk):
             "speedup_fused_over_per_size_persistent": fused / (s.S * chunk / ts)}
 
 
-def leg_adjoint(dev, stream, n_steps=20000, every=1000):
-    """Reverse-mode cost on the adjoint configuration's batch: (forward with
-    checkpoints + adjoint) over the plain forward of the same steps, all in
-    the packing that fills the most SIMDs for this batch.  A short run first
-    loads every kernel involved; the loss seed dL/dQ_T = 2 Q_T is formed
-    outside the timed intervals."""
+def leg_adjoint(dev, stream, workload="adjoint8", n_steps=20000, every=1000):
+    """Reverse-mode cost: (forward with checkpoints + adjoint) over the plain
+    forward of the same steps, all in the workload's packing (the one that
+    fills the most SIMDs for it).  The adjoint configuration's batch (1024 x
+    8) fills a quarter of the SIMDs; the uniform batch (4096 x 8, two lanes
+    per planet) fills all of them.  A short run first loads every kernel
+    involved; the loss seed dL/dQ_T = 2 Q_T is formed outside the timed
+    intervals."""
     import torch
     from paper_2307_05683_amd import inputs
     from paper_2307_05683_amd.ensemble import Ensemble
-    s = inputs.workload("adjoint8")
-    opts = dict(packing=DEFAULT_PACKING["adjoint8"], block_waves=DEFAULT_BLOCK_WAVES["adjoint8"])
+    s = inputs.workload(workload)
+    opts = dict(packing=DEFAULT_PACKING[workload], block_waves=DEFAULT_BLOCK_WAVES[workload])
     w = Ensemble.from_systems(s.subset(np.arange(64)), device=dev, **opts)
     w.forward_ckpt(4, 2)
     QT, VT = w.state()
@@ -389,7 +391,10 @@ def leg_adjoint(dev, stream, n_steps=20000, every=1000):
     finite = bool(all(torch.isfinite(x).all().item() for x in g))
     e.close()
     fl = flops_per_system_step(s.n_planets, False)
-    return {"workload": WORKLOAD_TEXT["adjoint8"], "packing": opts["packing"], "steps": n_steps,
+    text = WORKLOAD_TEXT[workload]
+    if workload != "adjoint8":
+        text += "; reverse mode with checkpoints every %d steps, loss sum |Q(T)|^2" % every
+    return {"workload": text, "packing": opts["packing"], "steps": n_steps,
             "ckpt_every": every, "forward_s": t_plain, "forward_frac": fl * n_steps / t_plain / 1e12 / FP64_PEAK_TFLOPS,
             "forward_ckpt_s": t_ckpt, "adjoint_s": t_adj, "cost_ratio": (t_ckpt + t_adj) / t_plain,
             "backward_over_forward": t_adj / t_plain, "gradients_finite": finite}
@@ -582,6 +587,7 @@ def main():
         todo = [("uniform8", lambda: leg_uniform(dev, stream, chunk)),
                 ("uneven2to8", lambda: leg_uneven(dev, stream, chunk)),
                 ("adjoint8", lambda: leg_adjoint(dev, stream)),
+                ("adjoint_uniform8", lambda: leg_adjoint(dev, stream, "uniform8")),
                 ("single8", lambda: leg_single(dev, stream))]
         if args.workload == "large8gr" and args.coords == "dhc" and scheme == "dkd":
             todo.append(("explorer_counts", lambda: leg_counts(systems, dev, stream, chunk)))
