@@ -158,7 +158,8 @@ typedef struct {
                           is a kick carried by the Kepler flow: drift a dt, kick b dt, drift -2a dt, kick -b dt,
                           drift a dt, with a_i = i/(2n) and b_i from the conditions on the series of
                           (x/2)/sinh(x/2) (drift-kick-drift) or (x/2)coth(x/2) (kick-drift-kick).  Needs
-                          WH_COORDS_JACOBI with WH_DKD or WH_KDK; forward only (reverse mode: WH_ESTATE). */
+                          WH_COORDS_JACOBI with WH_DKD or WH_KDK.  Reverse mode differentiates through both
+                          changes of variables (the input's inverse and the output's). */
 } wh_config;
 
 /* Fills *cfg with the defaults above (DKD, no GR, auto packing, DHC). */

@@ -957,6 +957,37 @@ __device__ void apply_corrector(const StepParams& p, Lane& L, int lane, bool inv
   }
 }
 
+// Substep j of the corrector's sequence in the order C (or C^-1) applies
+// them (as apply_corrector: stage by stage, D(a) K(b) D(-2a) K(-b) D(a) in
+// units of dt).  Returns true for a drift; tau is the substep's time.
+__device__ __forceinline__ bool corrector_substep(const StepParams& p, int j, bool inverse, double h, double& tau) {
+  const int k = j / 5, sub = j - 5 * k;
+  const int i = inverse ? k : p.corr_n - 1 - k;
+  const double a = (inverse ? -p.corr_a[i] : p.corr_a[i]) * h;
+  const double b = p.corr_b[i] * h;
+  if (sub == 0 || sub == 4) { tau = a; return true; }
+  if (sub == 2) { tau = -2.0 * a; return true; }
+  tau = sub == 1 ? b : -b;
+  return false;
+}
+
+// The first n_sub substeps of C (or C^-1) on a lane's compensated state.
+template <int G, bool GR>
+__device__ void corrector_run(const StepParams& p, Lane& L, int lane, bool inverse, int n_sub) {
+  const int pg = lane & (G - 1);
+  const JacConst jc = jac_const<G>(L.m0, L.m, pg);
+  Exch<G, 0> ex;
+  ex.init(lane, L.m);
+  const double kg = GR ? p.kgr * L.m0 * L.m0 : 0.0;
+  KepDiag dg{0.0, 1.0e300};
+  double vkx, vky, vkz;
+  for (int j = 0; j < n_sub; ++j) {
+    double tau;
+    if (corrector_substep(p, j, inverse, L.dt, tau)) drift(L, jc.Mi, tau, dg);
+    else kick_jacobi<G, 0, GR>(L, ex, jc, pg, tau, vkx, vky, vkz, kg);
+  }
+}
+
 template <int G, bool GR, int SCHEME, bool JAC = false>
 __device__ void sync_lane(const StepParams& p, Lane& L, int lane) {
   const int pg = lane & (G - 1);
@@ -2315,6 +2346,35 @@ template <bool GR, int SCH> __global__ __launch_bounds__(256) void k_adj_segment
   }
 }
 
+// Adjoint of the corrector C (or C^-1) entered at the lane state L0: a.q,
+// a.v hold dL/d(its output) on entry and dL/d(its input) on return; mass
+// terms go to a.m, a.m0 and gMim1.  The substeps' inputs are recomputed
+// from L0 (the sequence is at most 15 substeps long, and this runs once per
+// reverse pass).
+template <int G, bool GR>
+__device__ void corrector_vjp(const StepParams& p, const Lane& L0, int lane, bool inverse, Grad& a,
+                              double& gMim1) {
+  const int pg = lane & (G - 1);
+  const JacConst jc = jac_const<G>(L0.m0, L0.m, pg);
+  Exch<G, 1> ex;
+  ex.init(lane, L0.m);
+  const double kg = GR ? p.kgr * L0.m0 * L0.m0 : 0.0;
+  for (int j = 5 * p.corr_n - 1; j >= 0; --j) {
+    Lane L = L0;
+    corrector_run<G, GR>(p, L, lane, inverse, j);   // the state entering substep j
+    double tau;
+    if (corrector_substep(p, j, inverse, L0.dt, tau)) {
+      Lane Lx = L;
+      KepDiag dg{0.0, 1.0e300};
+      const double X = drift(Lx, jc.Mi, tau, dg);
+      KepFwd k;
+      jac_drift_vjp(a, gMim1, jc.Mi, L.qx, L.qy, L.qz, L.vx, L.vy, L.vz, tau, X, k);
+    } else {
+      kick_jacobi_vjp<G, GR>(a, gMim1, ex, jc, pg, L.m, L.m0, kg, L.qx, L.qy, L.qz, tau);
+    }
+  }
+}
+
 // The synchronized output of a Jacobi context: the pending operation (K(h),
 // K(c_1 dt) or the half kick) on the stored state, then the transform to
 // DHC.  The grad rows hold the caller's dL/dQ_T, dL/dV_T on entry and
@@ -2330,6 +2390,8 @@ template <int G, bool GR, int SCH> __device__ void adj_init_jac_lane(const AdjPa
   load_ck(q.ck, ns, slot, L);
   L.m = p.st[6 * ns + slot];
   const double m0 = p.m0s[slot], dt = p.dts[slot];
+  L.m0 = m0;
+  L.dt = dt;
   const double kg = GR ? p.kgr * m0 * m0 : 0.0;
   const JacConst jc = jac_const<G>(m0, L.m, pg);
   Exch<G, 1> ex;
@@ -2347,8 +2409,13 @@ template <int G, bool GR, int SCH> __device__ void adj_init_jac_lane(const AdjPa
       X = drift(L, jc.Mi, tau, dg);
     }
   }
+  // the output's corrector C (real coordinates) sits between the pending
+  // operation and the transform
+  const Lane Lp = L;
+  if (p.corr_n > 0) apply_corrector<G, GR>(p, L, lane, false);
   jac_to_dhc_vjp<G>(a, gMim1, jc, pg, L.m, m0, L.qx + L.cqx, L.qy + L.cqy, L.qz + L.cqz, L.vx + L.cvx,
                     L.vy + L.cvy, L.vz + L.cvz);
+  if (p.corr_n > 0) corrector_vjp<G, GR>(p, Lp, lane, false, a, gMim1);
   if (!synced) {
     if (SCH == WH_KDK) {
       kick_jacobi_vjp<G, GR>(a, gMim1, ex, jc, pg, L.m, m0, kg, x0x, x0y, x0z, 0.5 * dt);
@@ -2375,8 +2442,10 @@ template <bool GR, int SCH> __global__ __launch_bounds__(256) void k_adj_init_ja
 
 // Before the outputs: the grad rows hold dL/d(initial Jacobi state); the
 // input transform's adjoint at the initial DHC state (rebuilt from the first
-// checkpoint) turns them into dL/d(Q0, V0) and adds the mass terms.
-template <int G> __device__ void adj_in_jac_lane(const AdjParams& q, int slot, int lane) {
+// checkpoint) turns them into dL/d(Q0, V0) and adds the mass terms.  With a
+// corrector the stored initial state is C^-1 of the transformed input: C
+// rebuilds that input (to rounding) and C^-1's adjoint runs first.
+template <int G, bool GR> __device__ void adj_in_jac_lane(const AdjParams& q, int slot, int lane) {
   const StepParams& p = q.sp;
   const int ns = p.ns;
   const int pg = lane & (G - 1);
@@ -2386,26 +2455,31 @@ template <int G> __device__ void adj_in_jac_lane(const AdjParams& q, int slot, i
   load_ck(q.ck, ns, slot, L);
   L.m = p.st[6 * ns + slot];
   L.m0 = p.m0s[slot];
+  L.dt = p.dts[slot];
+  double gMim1 = 0.0;
+  if (p.corr_n > 0) {
+    apply_corrector<G, GR>(p, L, lane, false);
+    corrector_vjp<G, GR>(p, L, lane, true, a, gMim1);
+  }
   L.qx += L.cqx; L.qy += L.cqy; L.qz += L.cqz;
   L.vx += L.cvx; L.vy += L.cvy; L.vz += L.cvz;
   const JacConst jc = jac_const<G>(L.m0, L.m, pg);
   jacobi_to_dhc<G>(L, pg);
-  double gMim1 = 0.0;
   dhc_to_jac_vjp<G>(a, gMim1, jc, pg, L.m, L.m0, L.qx, L.qy, L.qz, L.vx, L.vy, L.vz);
   jac_fold_mim1<G>(a, gMim1, pg);
   store_grad(q.grad, ns, slot, a);
 }
 
-__global__ __launch_bounds__(256) void k_adj_in_jac(AdjParams q) {
+template <bool GR> __global__ __launch_bounds__(256) void k_adj_in_jac(AdjParams q) {
   const StepParams& p = q.sp;
   const int lane = threadIdx.x & 63;
   const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (wave >= p.w8) return;
   const int slot = wave * 64 + lane;
-  if (wave < p.w1) adj_in_jac_lane<1>(q, slot, lane);
-  else if (wave < p.w2) adj_in_jac_lane<2>(q, slot, lane);
-  else if (wave < p.w4) adj_in_jac_lane<4>(q, slot, lane);
-  else adj_in_jac_lane<8>(q, slot, lane);
+  if (wave < p.w1) adj_in_jac_lane<1, GR>(q, slot, lane);
+  else if (wave < p.w2) adj_in_jac_lane<2, GR>(q, slot, lane);
+  else if (wave < p.w4) adj_in_jac_lane<4, GR>(q, slot, lane);
+  else adj_in_jac_lane<8, GR>(q, slot, lane);
 }
 
 // Adjoint of the closing drift of the synchronized output (K(h), or K(c_1 dt)
@@ -3369,7 +3443,6 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
     return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD, WH_KDK and WH_SABA2..4");
   if (c->cfg.kepler_counts != 0)
     return fail(WH_ESTATE, "reverse mode runs the paper's Kepler counts (kepler_counts = 0)");
-  if (c->cfg.corrector != 0) return fail(WH_ESTATE, "reverse mode is not implemented with symplectic correctors");
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
   if (ckpt_every * tape_units(c) > (1 << 30)) return fail(WH_EINVAL, "ckpt_every too large for this scheme");
   TapeLayout T = tape_layout(c->P.ns, n_steps, ckpt_every, tape_units(c));
@@ -3505,7 +3578,8 @@ wh_status wh_adjoint_n(wh_ctx* c, void* tape, size_t tape_bytes, const double* g
   }
   if (jac) {
     q.ck = ck;   // the first checkpoint: the initial state the input transform is differentiated at
-    hipLaunchKernelGGL(k_adj_in_jac, dim3(nw), dim3(64), 0, stream, q);
+    if (c->cfg.gr_c > 0) hipLaunchKernelGGL(k_adj_in_jac<true>, dim3(nw), dim3(64), 0, stream, q);
+    else hipLaunchKernelGGL(k_adj_in_jac<false>, dim3(nw), dim3(64), 0, stream, q);
   }
   if (c->P.pair) hipLaunchKernelGGL(k_adj_finish_pair, dim3(nw), dim3(64), 0, stream, q);
   else if (c->P.split) hipLaunchKernelGGL(k_adj_finish<true>, dim3(nw), dim3(64), 0, stream, q);

@@ -3,9 +3,10 @@ against the oracle's corrected map: the inverse change of variables at set-up,
 the map in mapping coordinates, the change on every synchronized output."""
 import numpy as np
 import pytest
+import torch
 
 import oracle
-from paper_2307_05683_amd import _lib, inputs
+from paper_2307_05683_amd import inputs
 from paper_2307_05683_amd.ensemble import Ensemble
 
 pytestmark = pytest.mark.gpu
@@ -59,10 +60,91 @@ def test_corrector_lowers_the_energy_error():
     assert worst[1] < worst[0] / 5 and worst[2] < worst[1] / 3
 
 
-def test_reverse_mode_refuses_correctors():
-    s = inputs.make_systems(4, 98, n_planets=3)
-    e = Ensemble.from_systems(s, coords="jacobi", corrector=1)
-    with pytest.raises(_lib.WHError) as ei:
-        e.forward_ckpt(10, 5)
-    assert ei.value.code == _lib.WH_ESTATE
+def oracle_corrected_gradients(s, n_steps, stages, scheme, gr_c):
+    """dL/d(Q0, V0, m, m0) of L = sum_i |Q_i(T)|^2 under the oracle's
+    corrected map in long double, by Richardson-extrapolated central
+    differences [4 D(h/2) - D(h)] / 3 (error O(h^4)): h = 1e-5 |Q_i| (|V_i|)
+    for a state component, 1e-3 m_i for a planet mass, 1e-5 m0 for the star
+    mass.  Every perturbed copy integrates as one batch."""
+    lm = np.arange(8)[None, :] < s.n_planets[:, None]
+    cases = []                      # (system, kind, planet, component, h)
+    for i in range(s.S):
+        for p in range(int(s.n_planets[i])):
+            for c in range(3):
+                cases.append((i, "Q", p, c, 1e-5 * np.linalg.norm(s.Q[i, p])))
+                cases.append((i, "V", p, c, 1e-5 * np.linalg.norm(s.V[i, p])))
+            cases.append((i, "m", p, 0, 1e-3 * s.m[i, p]))
+        cases.append((i, "m0", 0, 0, 1e-5 * s.m0[i]))
+    rows, shifts = [], []
+    for ci, (i, kind, p, c, h) in enumerate(cases):
+        for f in (1.0, -1.0, 0.5, -0.5):
+            rows.append(i)
+            shifts.append((ci, f * h))
+    rep = s.subset(rows)
+    for r, (ci, d) in enumerate(shifts):
+        i, kind, p, c, h = cases[ci]
+        if kind == "Q": rep.Q[r, p, c] += d
+        elif kind == "V": rep.V[r, p, c] += d
+        elif kind == "m": rep.m[r, p] += d
+        else: rep.m0[r] += d
+    Q, _ = oracle.jacobi_integrate_corrected(rep, n_steps, stages, scheme=scheme, gr_c=gr_c)
+    L = np.where(lm[rows][:, :, None], Q, 0).astype(np.longdouble)
+    L = (L * L).sum(axis=(1, 2))
+    gQ = np.zeros((s.S, 8, 3)); gV = np.zeros((s.S, 8, 3)); gm = np.zeros((s.S, 8)); gm0 = np.zeros(s.S)
+    for ci, (i, kind, p, c, h) in enumerate(cases):
+        Lp, Lm, Lp2, Lm2 = L[4 * ci: 4 * ci + 4]
+        d1 = (Lp - Lm) / (2 * h)
+        d2 = (Lp2 - Lm2) / h
+        r = float((4 * d2 - d1) / 3)
+        if kind == "Q": gQ[i, p, c] = r
+        elif kind == "V": gV[i, p, c] = r
+        elif kind == "m": gm[i, p] = r
+        else: gm0[i] = r
+    return gQ, gV, gm, gm0
+
+
+@pytest.mark.parametrize("stages", [1, 2, 3])
+@pytest.mark.parametrize("scheme,gr_c", [("dkd", 0.0), ("kdk", 40.0), ("dkd", 10065.0)])
+def test_corrected_gradients_match_the_oracles_differences(stages, scheme, gr_c):
+    """Reverse mode through both changes of variables (C^-1 at set-up, C on
+    the output): every gradient component of L = sum |Q(T)|^2 against
+    central differences of the oracle's corrected map (long double,
+    Richardson), to 1e-6 relative with a floor of 1e-8 of the system's
+    gradient block."""
+    s = inputs.make_systems(4, 99, n_planets=None, n_range=(2, 8))
+    n_steps, every = 120, 40
+    print("case: corrector %d %s gr_c=%g" % (stages, scheme, gr_c), flush=True)
+    e = Ensemble.from_systems(s, coords="jacobi", scheme=scheme, gr_c=gr_c, corrector=stages)
+    e.forward_ckpt(n_steps, every)
+    QT, VT = e.state()
+    g = [x.cpu().numpy() for x in e.adjoint(2 * QT, torch.zeros_like(VT))]
     e.close()
+    ref = oracle_corrected_gradients(s, n_steps, stages, scheme, gr_c)
+    lm = np.arange(8)[None, :] < s.n_planets[:, None]
+    worst = 0.0
+    for name, a, r in zip(("dQ0", "dV0", "dm", "dm0"), g, ref):
+        for i in range(s.S):
+            if name in ("dQ0", "dV0"):
+                ai, ri = a[i][lm[i]].ravel(), r[i][lm[i]].ravel()
+            elif name == "dm":
+                ai, ri = a[i][lm[i]], r[i][lm[i]]
+            else:
+                ai, ri = np.atleast_1d(a[i]), np.atleast_1d(r[i])
+            floor = 1e-8 * np.linalg.norm(ri)
+            err = np.abs(ai - ri) / (np.abs(ri) + floor)
+            worst = max(worst, err.max())
+            assert np.all(err < 1e-6), (name, i, err.max())
+    print("worst relative difference %.2e" % worst, flush=True)
+
+
+def test_corrected_gradients_do_not_depend_on_the_checkpoint_interval():
+    s = inputs.make_systems(8, 98, n_planets=None, n_range=(1, 8))
+    out = []
+    for every in (7, 50):
+        e = Ensemble.from_systems(s, coords="jacobi", corrector=2)
+        e.forward_ckpt(100, every)
+        QT, VT = e.state()
+        out.append([x.cpu().numpy() for x in e.adjoint(2 * QT, torch.zeros_like(VT))])
+        e.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
