@@ -218,11 +218,15 @@ inline Layout make_layout(int S, int ns, size_t plan_cap = 0) {
 }
 
 // Balanced launch windows.  A chunk of R steps is cut so that the heaviest
-// wave runs in PLAN_Q windows of R / PLAN_Q steps; a wave appears in at most
-// PLAN_Q + 1 windows of a chunk, so PLAN_Q + 2 entries per wave bound the plan.
+// wave runs in about PLAN_Q windows of R / PLAN_Q steps.  Every appearance of
+// a wave but its last runs at least max(1, floor(R / PLAN_Q)) steps, so a wave
+// appears in at most 2 PLAN_Q - 1 windows of a chunk (R < PLAN_Q: R windows;
+// PLAN_Q <= R < 2 PLAN_Q: one step each; beyond, floor(R / PLAN_Q) >= 2 and
+// R / floor(R / PLAN_Q) < 1.5 PLAN_Q), and 2 PLAN_Q entries per wave bound
+// the plan.
 constexpr int PLAN_Q = 16;
 inline size_t plan_capacity(const wh_config* cfg, const Packing& P) {
-  return cfg->balance == 1 && !P.serial ? (size_t)P.nwaves * (PLAN_Q + 2) : 0;
+  return cfg->balance == 1 && !P.serial ? (size_t)P.nwaves * 2 * PLAN_Q : 0;
 }
 
 inline bool config_ok(const wh_config* c, std::string& why) {
@@ -412,8 +416,9 @@ inline double wave_step_cost(const Packing& P, bool with_gr, int w) {
 // cost about B = (heaviest wave's cost) x R / Q, so that every SIMD carries
 // about the same work in every window and all waves finish the chunk
 // together.  Output: window k holds entries [off[k], off[k+1]) of (hw: wave,
-// hs: steps); every wave's steps add up to R; a wave appears in at most Q + 1
-// windows (floor(B / cost) >= R / Q steps each time).
+// hs: steps); every wave's steps add up to R; a wave appears in at most
+// 2 Q - 1 windows (max(1, floor(B / cost)) >= max(1, floor(R / Q)) steps each
+// time but the last).
 inline void plan_windows(const std::vector<double>& cost, int R, int slots, int Q, std::vector<int>& hw,
                          std::vector<int>& hs, std::vector<int>& off) {
   const int W = (int)cost.size();

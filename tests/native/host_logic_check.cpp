@@ -73,14 +73,18 @@ static void check_packing(const std::vector<int32_t>& np, int packing) {
   }
   CHECK(L.m0s - L.st >= sizeof(double) * WH_STATE_ROWS * (size_t)P.ns);
   CHECK(L.plan_steps - L.plan_wave >= sizeof(int) * cap);
-  CHECK(cap == (P.serial ? 0 : (size_t)P.nwaves * (PLAN_Q + 2)));
+  CHECK(cap == (P.serial ? 0 : (size_t)P.nwaves * 2 * PLAN_Q));
 }
 
 static void check_plan(std::mt19937_64& rng) {
   for (int trial = 0; trial < 60; ++trial) {
     const int W = 1 + (int)(rng() % 3000);
     const int slots = 1 + (int)(rng() % 1200);
-    const int R = trial % 3 == 0 ? 1 + (int)(rng() % 9) : 1 + (int)(rng() % 5000);
+    // short chunks, chunks from Q to about 3 Q (one or two steps per
+    // appearance: the most windows per wave), and long ones
+    const int R = trial % 4 == 0   ? 1 + (int)(rng() % 9)
+                  : trial % 4 == 1 ? PLAN_Q + (int)(rng() % (2 * PLAN_Q + 8))
+                                   : 1 + (int)(rng() % 5000);
     std::vector<double> cost(W);
     static const double classes[] = {293, 326, 372, 478, 611, 704, 831};
     for (auto& c : cost) c = classes[rng() % 7];
@@ -88,9 +92,9 @@ static void check_plan(std::mt19937_64& rng) {
     plan_windows(cost, R, slots, PLAN_Q, hw, hs, off);
     CHECK(hw.size() == hs.size());
     CHECK(!off.empty() && off.front() == 0 && off.back() == (int)hw.size());
-    CHECK(hw.size() <= (size_t)W * (PLAN_Q + 2));
+    CHECK(hw.size() <= (size_t)W * 2 * PLAN_Q);
     std::vector<long> total(W, 0);
-    std::vector<int> last(W, -1);
+    std::vector<int> last(W, -1), seen(W, 0);
     double cmax = 0;
     for (double c : cost) cmax = std::max(cmax, c);
     for (size_t k = 0; k + 1 < off.size(); ++k) {
@@ -107,9 +111,20 @@ static void check_plan(std::mt19937_64& rng) {
         // one step, when the budget is below a step)
         CHECK(hs[e] == 1 || hs[e] * cost[w] <= cmax * R / PLAN_Q * (1 + 1e-12));
         total[w] += hs[e];
+        ++seen[w];
       }
     }
-    for (int w = 0; w < W; ++w) CHECK(total[w] == R);
+    for (int w = 0; w < W; ++w) CHECK(total[w] == R && seen[w] <= 2 * PLAN_Q - 1);
+  }
+  // the chunk length with the most windows per wave: every wave at the
+  // largest cost and R = 2 Q - 1 (one step per appearance); the old bound of
+  // Q + 2 entries per wave did not hold it
+  {
+    std::vector<double> cost(100, 478.0);
+    std::vector<int> hw, hs, off;
+    plan_windows(cost, 2 * PLAN_Q - 1, 40, PLAN_Q, hw, hs, off);
+    CHECK(hw.size() == cost.size() * (2 * PLAN_Q - 1));
+    CHECK(hw.size() <= cost.size() * 2 * PLAN_Q);
   }
 }
 

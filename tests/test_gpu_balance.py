@@ -87,3 +87,17 @@ def test_no_plan_when_the_batch_fits():
     e.step(100)
     torch.cuda.synchronize()
     e.close()
+
+
+def test_short_chunks_fit_the_plan():
+    """A chunk of 31 steps (one step per window for the heaviest waves: each
+    appears in 31 windows of a chunk) plans within the workspace and equals
+    one launch per chunk bit for bit."""
+    s = inputs.workload("uneven2to8")
+    n = 2 * 31 + 7
+    (Qa, Va, fa, Ea), wa = run(s, n, chunk=31, balance=1, block_waves=4)
+    (Qb, Vb, fb, Eb), wb = run(s, n, chunk=31, balance=0, block_waves=4)
+    print("windows per chunk: %d" % wa[0], flush=True)
+    assert wa[0] >= 31 and wb == (1, 0)
+    assert np.array_equal(Qa, Qb) and np.array_equal(Va, Vb)
+    assert np.array_equal(fa, fb) and np.array_equal(Ea, Eb)
