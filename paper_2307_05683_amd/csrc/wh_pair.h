@@ -22,8 +22,7 @@ namespace wh {
 
 // 1/|d|^3 for the separation d
 __device__ __forceinline__ double inv_r3(double dx, double dy, double dz) {
-  const double ir = rsqrt_full(fma(dx, dx, fma(dy, dy, dz * dz)));
-  return ir * ir * ir;
+  return rsqrt3_full(fma(dx, dx, fma(dy, dy, dz * dz)));
 }
 
 // Partner masses of the rounds (constant, Sec. 3.5).
