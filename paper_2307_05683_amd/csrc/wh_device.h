@@ -30,17 +30,20 @@ __device__ __forceinline__ double rsqrt_full(double x) {
   return fma(y * e, c, y);
 }
 // x^(-3/2), the 1/r^3 of the kicks, from the same seed in one step:
-// (1 - e)^(-3/2) = 1 + 3e/2 + 15e^2/8 + O(e^3) with e = 1 - x y^2, applied to
-// y^3.  One instruction fewer and a shorter dependency chain than cubing
-// rsqrt_full, and closer (within 2.5 units of 2^-53 against 5.6, over 2e7
-// arguments with seeds off by up to 2^-21, against long double).
+// (1 - e)^(-3/2) = 1 + (3e/2)(1 + 5e/4) + O(e^3) with e = 1 - x y^2, applied
+// to y^3.  As many instructions as cubing rsqrt_full, and closer (within 2.5
+// units of 2^-53 against 5.6, over 2e7 arguments with seeds off by up to
+// 2^-21, against long double).  Every instruction takes at most one
+// constant that is not an inline one (1.25, 1.5): the single form
+// fma(15/8, e, 3/2) needs both in one instruction, which the VALU's one
+// scalar operand turns into two register moves per evaluation.
 __device__ __forceinline__ double rsqrt3_full(double x) {
   double y = __builtin_amdgcn_rsq(x);
   double y2 = y * y;
   double e = fma(-x, y2, 1.0);
   double y3 = y2 * y;
-  double c = fma(1.875, e, 1.5);
-  return fma(y3 * e, c, y3);
+  double s = fma(1.25, e, 1.0);
+  return fma(1.5 * (y3 * e), s, y3);
 }
 
 // ---------------------------------------------------------------------------
