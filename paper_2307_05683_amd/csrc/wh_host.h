@@ -395,9 +395,14 @@ inline TapeLayout tape_layout(int ns, int64_t n_steps, int64_t every, int units)
 }
 
 
-// Relative cost of one step of wave w of the packing: VALU instructions per
-// lane-step of the compiled drift-kick-drift step loop for the wave's group
-// size (gfx950; without and with GR).  Only the proportions matter.
+// Relative cost of one step of wave w of the packing (gfx950; without and
+// with GR; only the proportions matter).  One planet per lane: the measured
+// time of a drift-kick-drift step of a wavefront alone on its SIMD, for each
+// group size, scaled to the 8-lane group's VALU instructions per lane-step
+// (1024 one-size wavefronts: 0.662 / 0.692 / 0.791 of the 8-lane step for
+// 1, 2, 4 lanes without GR, 0.627 / 0.698 / 0.790 with; the instruction
+// counts, 293 / 326 / 372 / 478, had the 4-lane waves 1.6% too cheap).  Two
+// planets per lane: VALU instructions per lane-step.
 inline double wave_step_cost(const Packing& P, bool with_gr, int w) {
   const int gr = with_gr ? 1 : 0;
   if (P.split) return 1.0;
@@ -405,7 +410,7 @@ inline double wave_step_cost(const Packing& P, bool with_gr, int w) {
     static const double t[2][3] = {{611, 704, 831}, {653, 755, 891}};
     return t[gr][w < P.w1 ? 0 : w < P.w2 ? 1 : 2];
   }
-  static const double t[2][4] = {{293, 326, 372, 478}, {314, 356, 411, 526}};
+  static const double t[2][4] = {{316, 331, 378, 478}, {330, 367, 416, 526}};
   return t[gr][w < P.w1 ? 0 : w < P.w2 ? 1 : w < P.w4 ? 2 : 3];
 }
 
