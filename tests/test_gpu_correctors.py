@@ -103,9 +103,11 @@ def oracle_corrected_gradients(s, n_steps, stages, scheme, gr_c):
     return gQ, gV, gm, gm0
 
 
-@pytest.mark.parametrize("stages", [1, 2, 3])
-@pytest.mark.parametrize("scheme,gr_c", [("dkd", 0.0), ("kdk", 40.0), ("dkd", 10065.0)])
-def test_corrected_gradients_match_the_oracles_differences(stages, scheme, gr_c):
+@pytest.mark.parametrize("stages,scheme,gr_c,packing",
+                         [(n, sch, c, "auto") for n in (1, 2, 3)
+                          for sch, c in (("dkd", 0.0), ("kdk", 40.0), ("dkd", 10065.0))]
+                         + [(2, "kdk", 40.0, "g8"), (3, "dkd", 10065.0, "g8")])
+def test_corrected_gradients_match_the_oracles_differences(stages, scheme, gr_c, packing):
     """Reverse mode through both changes of variables (C^-1 at set-up, C on
     the output): every gradient component of L = sum |Q(T)|^2 against
     central differences of the oracle's corrected map (long double,
@@ -113,8 +115,8 @@ def test_corrected_gradients_match_the_oracles_differences(stages, scheme, gr_c)
     gradient block."""
     s = inputs.make_systems(4, 99, n_planets=None, n_range=(2, 8))
     n_steps, every = 120, 40
-    print("case: corrector %d %s gr_c=%g" % (stages, scheme, gr_c), flush=True)
-    e = Ensemble.from_systems(s, coords="jacobi", scheme=scheme, gr_c=gr_c, corrector=stages)
+    print("case: corrector %d %s gr_c=%g %s" % (stages, scheme, gr_c, packing), flush=True)
+    e = Ensemble.from_systems(s, coords="jacobi", scheme=scheme, gr_c=gr_c, corrector=stages, packing=packing)
     e.forward_ckpt(n_steps, every)
     QT, VT = e.state()
     g = [x.cpu().numpy() for x in e.adjoint(2 * QT, torch.zeros_like(VT))]
@@ -137,11 +139,12 @@ def test_corrected_gradients_match_the_oracles_differences(stages, scheme, gr_c)
     print("worst relative difference %.2e" % worst, flush=True)
 
 
-def test_corrected_gradients_do_not_depend_on_the_checkpoint_interval():
+@pytest.mark.parametrize("packing", ["auto", "g8"])
+def test_corrected_gradients_do_not_depend_on_the_checkpoint_interval(packing):
     s = inputs.make_systems(8, 98, n_planets=None, n_range=(1, 8))
     out = []
     for every in (7, 50):
-        e = Ensemble.from_systems(s, coords="jacobi", corrector=2)
+        e = Ensemble.from_systems(s, coords="jacobi", corrector=2, packing=packing)
         e.forward_ckpt(100, every)
         QT, VT = e.state()
         out.append([x.cpu().numpy() for x in e.adjoint(2 * QT, torch.zeros_like(VT))])
