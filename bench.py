@@ -87,6 +87,9 @@ def parse():
     ap.add_argument("--balance", type=int, default=None, choices=[0, 1],
                     help="balanced launch windows (default: per workload)")
     ap.add_argument("--chunk", type=int, default=4096, help="Wisdom-Holman steps per launch")
+    ap.add_argument("--planets", type=int, default=0,
+                    help="draw the workload's systems with N planets each instead of its own count (1..8; the "
+                         "uniform-count workloads only): throughput by planet count, not the headline")
     ap.add_argument("--systems", type=int, default=0,
                     help="run only the workload's first N systems (0: all; an occupancy scan, not the headline)")
     ap.add_argument("--exchange", default="auto", choices=["auto", "dpp", "lds"])
@@ -466,7 +469,15 @@ def main():
 
     gr_c = inputs.GR_C if args.workload == "large8gr" else 0.0
     scheme = args.scheme or ("kdk" if args.workload == "single8" else "dkd")
-    systems = inputs.workload(args.workload)
+    if args.planets:
+        kw = dict(inputs.WORKLOADS[args.workload])
+        if not 1 <= args.planets <= 8 or kw.get("n_planets") is None:
+            print("--planets must be in 1..8, for a workload with one planet count per system", file=sys.stderr)
+            sys.exit(2)
+        kw["n_planets"] = args.planets
+        systems = inputs.make_systems(**kw)
+    else:
+        systems = inputs.workload(args.workload)
     full_S = systems.S
     if args.systems:
         if not 1 <= args.systems <= full_S:
@@ -510,7 +521,8 @@ def main():
     flops_step = flops_per_system_step(systems.n_planets, gr_c > 0, args.coords, scheme)
     achieved = flops_step * chunk / avg_launch / 1e12
     out = {
-        "metric": "system-steps/s (8-planet FP64)" if "8" in args.workload else "system-steps/s (FP64)",
+        "metric": ("system-steps/s (%d-planet FP64)" % args.planets if args.planets
+                   else "system-steps/s (8-planet FP64)" if "8" in args.workload else "system-steps/s (FP64)"),
         "value": value,
         "unit": "system-steps/s",
         "n_gpus": 1,
@@ -523,8 +535,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "%s: %s%s" % (args.workload, WORKLOAD_TEXT[args.workload],
-                                      "" if systems.S == full_S else " (first %d systems only)" % systems.S),
+            "workload": "%s: %s%s%s" % (args.workload, WORKLOAD_TEXT[args.workload],
+                                        " (with %d planets per system)" % args.planets if args.planets else "",
+                                        "" if systems.S == full_S else " (first %d systems only)" % systems.S),
             "wh_steps_per_step": chunk,
             "warmup_launches_run": warm_run,
             "systems": systems.S,
@@ -565,7 +578,8 @@ def main():
         },
     }
     # the committed counters describe the whole batch
-    counters = measured_counters(args.workload, chunk, args.coords, packing, windows) if systems.S == full_S else None
+    counters = (measured_counters(args.workload, chunk, args.coords, packing, windows)
+                if systems.S == full_S and not args.planets else None)
     if counters and scheme == "dkd":
         out["roofline"]["traffic"] = counters["traffic"]
         if counters["hw_flops"]:

@@ -30,6 +30,13 @@ def test_systems_subset_is_bounded():
     assert r.returncode == 2 and "--systems must be in 1..4096" in r.stderr
 
 
+def test_planet_count_option_is_bounded():
+    for argv in (["--planets", "9"], ["--planets", "3", "--workload", "uneven2to8"]):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + argv, capture_output=True, text=True,
+                           timeout=300)
+        assert r.returncode == 2 and "--planets must be in 1..8" in r.stderr, argv
+
+
 def test_cpu_baseline_fields():
     s = inputs.make_systems(8, 3, n_planets=8)
     args = argparse.Namespace(cpu_systems=4, cpu_steps=40, coords="dhc", no_legs=True)

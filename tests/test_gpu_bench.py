@@ -52,3 +52,16 @@ def test_bench_uneven_runs_in_windows():
     assert cfg["packing"] == "pow2" and cfg["balance"] == 1
     assert cfg["launches_per_chunk"] > 1 and cfg["wavefronts_per_window"] >= 256
     assert cfg["flagged_systems"] == 0
+
+
+def test_bench_by_planet_count():
+    """--planets N: the workload's recipe with N planets per system, its own
+    flop count in the roofline, no counter-derived traffic (the committed
+    counters are for the workload's own count)."""
+    out = run_bench("--workload", "uniform8", "--planets", "3")
+    assert out["metric"] == "system-steps/s (3-planet FP64)"
+    assert "with 3 planets per system" in out["config"]["workload"]
+    assert out["config"]["planets_total"] == 3 * 4096
+    rf = out["roofline"]
+    assert rf["algorithmic_flops_per_launch"] == 898 * 4096 * 4096
+    assert rf["traffic"] is None
