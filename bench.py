@@ -59,20 +59,24 @@ WORKLOAD_TEXT = {
 # Lane packing per workload.  Two planets per lane pays once the one-planet
 # layout has more wavefronts than the chip has SIMDs (fewer, heavier waves
 # with more independent work); two lanes per planet pays when it has fewer.
-DEFAULT_PACKING = {"large8gr": "pair", "uneven2to8": "pow2", "uniform8": "split", "single8": "split",
+DEFAULT_PACKING = {"large8gr": "pair", "uneven2to8": "mixed", "uniform8": "split", "single8": "split",
                    "adjoint8": "split"}
 # Wavefronts per workgroup: four-wave workgroups put one wave of each
 # workgroup on each SIMD of a CU.
 DEFAULT_BLOCK_WAVES = {"large8gr": 1, "uneven2to8": 4, "uniform8": 4, "single8": 1, "adjoint8": 4}
-# Balanced launch windows (wh_config.balance) for the uneven batch: its 1536
-# one-planet-per-lane wavefronts of three costs run in windows of 1024
-# equal-work wavefronts (+15% over two planets per lane, whose 769 heavy
-# wavefronts leave a quarter of the SIMDs idle).  The GR batch's 4096 pair
-# wavefronts of one cost measured the same with and without windows.
+# Balanced launch windows (wh_config.balance) for the uneven batch: its
+# one-planet-per-lane wavefronts of several costs (1322 with two systems
+# sharing the 8-lane groups of 5+3 and 6+2 planets, 1535 without) run in
+# windows of 1024 equal-work wavefronts (+15% over two planets per lane,
+# whose 769 heavy wavefronts leave a quarter of the SIMDs idle; the shared
+# groups add 6%).  The GR batch's 4096 pair wavefronts of one cost measured
+# the same with and without windows.
 DEFAULT_BALANCE = {"large8gr": 0, "uneven2to8": 1, "uniform8": 0, "single8": 0, "adjoint8": 0}
 KERNEL_NAME = {"pair": "k_step_pair (persistent step kernel, two planets per lane)",
                "split": "k_step_split (persistent step kernel, two lanes per planet)",
-               "serial": "k_step_serial (persistent step kernel, one lane per system)"}
+               "serial": "k_step_serial (persistent step kernel, one lane per system)",
+               "mixed": "k_step_mixed (persistent step kernel, one planet per lane, two systems in some 8-lane "
+                        "groups)"}
 
 
 def parse():

@@ -89,9 +89,15 @@ enum {
   WH_PACK_SPLIT = 3, /* two lanes per planet: a 16-lane group per system whatever N, the interaction kick
                         divided between the two copies of each planet (for ensembles with fewer
                         wavefronts than the GPU has SIMDs); DHC only */
-  WH_PACK_SERIAL = 4 /* one lane per system: the storage of WH_PACK_G8, but one thread runs all planets of
-                        a system (every pair visited once, no cross-lane traffic; 64 systems per wave, for
-                        very large ensembles); DHC only */
+  WH_PACK_SERIAL = 4, /* one lane per system: the storage of WH_PACK_G8, but one thread runs all planets of
+                         a system (every pair visited once, no cross-lane traffic; 64 systems per wave, for
+                         very large ensembles); DHC only */
+  WH_PACK_MIXED = 5   /* WH_PACK_POW2, except that a 5-planet system shares an 8-lane group with a 3- or
+                         2-planet one and a 6-planet system with a 2-planet one (the larger system in the
+                         group's first lanes): the sums and the interaction kick of a group keep the two
+                         systems apart, and a non-finite state in one never reaches the other.  DHC with
+                         WH_DKD or WH_KDK, the DPP exchange and kepler_counts 0; forward only (reverse
+                         mode: WH_ESTATE) */
 };
 
 /* Partner exchange of the interaction kick inside a lane group. */

@@ -17,7 +17,7 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "wh.h")
 WH_OK, WH_EINVAL, WH_EWORKSPACE, WH_EHIP, WH_ESTATE = 0, -1, -2, -3, -4
 WH_DKD, WH_KDK = 0, 1
 WH_SABA2, WH_SABA3, WH_SABA4 = 2, 3, 4
-WH_PACK_AUTO, WH_PACK_POW2, WH_PACK_G8, WH_PACK_PAIR, WH_PACK_SPLIT, WH_PACK_SERIAL = -1, 0, 1, 2, 3, 4
+WH_PACK_AUTO, WH_PACK_POW2, WH_PACK_G8, WH_PACK_PAIR, WH_PACK_SPLIT, WH_PACK_SERIAL, WH_PACK_MIXED = -1, 0, 1, 2, 3, 4, 5
 WH_F_NONFINITE, WH_F_HYPERBOLIC, WH_F_ZMAX = 1, 2, 4
 WH_EXCH_AUTO, WH_EXCH_LDS, WH_EXCH_DPP = 0, 1, 2
 WH_COORDS_DHC, WH_COORDS_JACOBI = 0, 1

@@ -1,8 +1,9 @@
 """Autotuner for the lane packing of an ensemble.
 
 Candidates: packing (1/2/4/8-lane groups, always 8 lanes, two planets per
-lane in 1/2/4-lane groups, two lanes per planet in 16-lane groups, or one
-lane per system), partner exchange (DPP or LDS crossbar; the last three
+lane in 1/2/4-lane groups, two lanes per planet in 16-lane groups, one
+lane per system, or 1/2/4/8-lane groups with two systems sharing some 8-lane
+groups), partner exchange (DPP or LDS crossbar; the last three
 layouts have a single schedule), wavefronts per workgroup, steps per
 launch and balanced launch windows (on or off) (the splitting coordinates are the caller's choice, not a candidate:
 they change the results, not just the speed).  Each candidate integrates the real batch for a short run; the
@@ -27,7 +28,7 @@ from . import _lib
 from .ensemble import Ensemble
 
 CANDIDATES = {
-    "packing": ["pow2", "g8", "pair", "split", "serial"],
+    "packing": ["pow2", "g8", "pair", "split", "serial", "mixed"],
     "exchange": ["dpp", "lds"],
     "block_waves": [1, 4],
     "chunk_steps": [1024, 4096],
@@ -118,6 +119,8 @@ def autotune(systems, gr_c: float = 0.0, scheme: str = "dkd", steps: int = 1024,
         opts = dict(zip(names, values))
         if opts.get("packing") in ("pair", "split", "serial") and opts.get("exchange") == "lds":
             continue              # same kernel as the DPP candidate
+        if opts.get("packing") == "mixed" and opts.get("exchange") == "lds":
+            continue              # shared groups run the DPP rounds only
         if opts.get("packing") == "serial" and opts.get("balance"):
             continue              # the serial layout ignores the launch plan
         # the steps of a probe must cover a few launches of the candidate's chunk

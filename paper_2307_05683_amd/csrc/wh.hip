@@ -54,6 +54,7 @@ struct StepParams {
   int* synced;           // [S] 1 while the stored state is synchronized
   int wave0;             // first wave of this launch
   int w1, w2, w4, w8;    // wave ranges [0,w1) G=1, [w1,w2) G=2, [w2,w4) G=4, [w4,w8) G=8
+  int wm;                // [wm, w8): 8-lane groups of two systems (mixed packing; wm = w8 otherwise)
   int n_steps;
   double kgr;            // 6 / c^2, or 0 without GR
   double zlim;           // WH_F_ZMAX threshold
@@ -208,6 +209,10 @@ template <int G, int EXCH> struct Exch;
 template <int G> struct Exch<G, 0> {
   GroupTopo<G> t;
   __device__ __forceinline__ void init(int lane, double m) { make_topo<G>(t, lane, m); }
+  __device__ __forceinline__ void momentum(double m, double vx, double vy, double vz, double& sx, double& sy,
+                                           double& sz) const {
+    group_momentum<G>(m, vx, vy, vz, sx, sy, sz);
+  }
   __device__ __forceinline__ void accel(double qx, double qy, double qz, double m, double& ax, double& ay,
                                         double& az) const {
     interaction_accel<G>(t, qx, qy, qz, m, ax, ay, az);
@@ -216,6 +221,10 @@ template <int G> struct Exch<G, 0> {
 template <int G> struct Exch<G, 1> {
   DppMass t;
   __device__ __forceinline__ void init(int, double m) { make_dpp_mass<G>(t, m); }
+  __device__ __forceinline__ void momentum(double m, double vx, double vy, double vz, double& sx, double& sy,
+                                           double& sz) const {
+    group_momentum<G>(m, vx, vy, vz, sx, sy, sz);
+  }
   __device__ __forceinline__ void accel(double qx, double qy, double qz, double m, double& ax, double& ay,
                                         double& az) const {
     interaction_accel_dpp<G>(t, qx, qy, qz, m, ax, ay, az);
@@ -226,6 +235,10 @@ template <int G> struct Exch<G, 1> {
 struct ExchSplit {
   SplitMass t;
   __device__ __forceinline__ void init(int lane, double m) { t = make_split_mass(lane, m); }
+  __device__ __forceinline__ void momentum(double m, double vx, double vy, double vz, double& sx, double& sy,
+                                           double& sz) const {
+    group_momentum<G_SPLIT>(m, vx, vy, vz, sx, sy, sz);
+  }
   __device__ __forceinline__ void accel(double qx, double qy, double qz, double m, double& ax, double& ay,
                                         double& az) const {
     accel_split(t, qx, qy, qz, m, ax, ay, az);
@@ -233,6 +246,92 @@ struct ExchSplit {
 };
 template <> struct Exch<G_SPLIT, 0> : ExchSplit {};
 template <> struct Exch<G_SPLIT, 1> : ExchSplit {};
+
+// Two systems in one 8-lane group (the mixed packing): system a in the
+// group's first lanes, system b after it (padding lanes belong to b).  The
+// DPP rounds of the one-system kick run over all eight lanes; a pair across
+// the two systems gets zero partner mass and zero reaction weight, its
+// squared distance is kept above 1e-200 (planets of two systems may
+// coincide) and every position is taken finite, so that neither system's
+// planets feel the other's and a non-finite state stays in its own system.
+// Sums over the group run twice, once per system, each with the other
+// system's lanes replaced by zeros (a select, which does not carry a NaN
+// across).  System a meets the partners of its own 8-lane group in the same
+// order; with the selects the compiler's contractions differ, so its results
+// agree with that group's to rounding, not bit for bit.
+struct ExchMixed {
+  DppMass t;          // partner masses of the rounds, zero across the systems
+  double r1, r3;      // own mass for the reactions of rounds 1 and 3, zero across
+  bool a;             // the lane belongs to the group's first system
+  // pl: the lane's planet index (-1: padding); p: its lane in the group
+  __device__ __forceinline__ void init_mixed(double m, int pl, int p) {
+    a = pl == p;
+    make_dpp_mass<8>(t, m);
+    const int s = a ? 1 : 0;
+    const int s0 = dpp_i<QP_NEXT>(s), s1 = dpp_i<DPP_XOR2>(s), sm = dpp_i<DPP_HALF_MIRROR>(s);
+    const int s2 = dpp_i<QP_R3>(sm), s3 = dpp_i<QP_R4>(sm), s4 = dpp_i<QP_R5>(sm);
+    t.m[0] = s0 == s ? t.m[0] : 0.0;
+    t.m[1] = s1 == s ? t.m[1] : 0.0;
+    t.m[2] = s2 == s ? t.m[2] : 0.0;
+    t.m[3] = s3 == s ? t.m[3] : 0.0;
+    t.m[4] = s4 == s ? t.m[4] : 0.0;
+    r1 = s0 == s ? m : 0.0;
+    r3 = s2 == s ? m : 0.0;
+  }
+  __device__ __forceinline__ double sum(double v) const {
+    const double sa = group_sum<8>(a ? v : 0.0);
+    const double sb = group_sum<8>(a ? 0.0 : v);
+    return a ? sa : sb;
+  }
+  __device__ __forceinline__ int any(int f) const {
+    const int fa = group_or<8>(a ? f : 0);
+    const int fb = group_or<8>(a ? 0 : f);
+    return a ? fa : fb;
+  }
+  __device__ __forceinline__ void momentum(double m, double vx, double vy, double vz, double& sx, double& sy,
+                                           double& sz) const {
+    sx = sum(m * vx);
+    sy = sum(m * vy);
+    sz = sum(m * vz);
+  }
+  static __device__ __forceinline__ double pair(double qx, double qy, double qz, double px, double py, double pz,
+                                                double mj, double& ax, double& ay, double& az, double& dx, double& dy,
+                                                double& dz) {
+    dx = qx - px; dy = qy - py; dz = qz - pz;
+    const double r2 = fmax(fma(dx, dx, fma(dy, dy, dz * dz)), 1.0e-200);
+    const double ir3 = rsqrt3_full(r2);
+    const double w = mj * ir3;
+    ax = fma(-w, dx, ax);
+    ay = fma(-w, dy, ay);
+    az = fma(-w, dz, az);
+    return ir3;
+  }
+  // the rounds of interaction_accel_dpp<8>
+  __device__ __forceinline__ void accel(double qx, double qy, double qz, double, double& ax, double& ay,
+                                        double& az) const {
+    qx = __builtin_isfinite(qx) ? qx : 0.0;
+    qy = __builtin_isfinite(qy) ? qy : 0.0;
+    qz = __builtin_isfinite(qz) ? qz : 0.0;
+    ax = 0.0; ay = 0.0; az = 0.0;
+    double dx, dy, dz;
+    double ir3 = pair(qx, qy, qz, dpp<QP_NEXT>(qx), dpp<QP_NEXT>(qy), dpp<QP_NEXT>(qz), t.m[0], ax, ay, az, dx, dy,
+                      dz);
+    double wi = r1 * ir3;
+    ax += dpp<QP_PREV>(wi * dx);
+    ay += dpp<QP_PREV>(wi * dy);
+    az += dpp<QP_PREV>(wi * dz);
+    pair(qx, qy, qz, dpp<DPP_XOR2>(qx), dpp<DPP_XOR2>(qy), dpp<DPP_XOR2>(qz), t.m[1], ax, ay, az, dx, dy, dz);
+    const double mx = dpp<DPP_HALF_MIRROR>(qx), my = dpp<DPP_HALF_MIRROR>(qy), mz = dpp<DPP_HALF_MIRROR>(qz);
+    ir3 = pair(qx, qy, qz, dpp<QP_R3>(mx), dpp<QP_R3>(my), dpp<QP_R3>(mz), t.m[2], ax, ay, az, dx, dy, dz);
+    wi = r3 * ir3;
+    ax += dpp<QP_R3_BACK>(dpp<DPP_HALF_MIRROR>(wi * dx));
+    ay += dpp<QP_R3_BACK>(dpp<DPP_HALF_MIRROR>(wi * dy));
+    az += dpp<QP_R3_BACK>(dpp<DPP_HALF_MIRROR>(wi * dz));
+    pair(qx, qy, qz, dpp<QP_R4>(mx), dpp<QP_R4>(my), dpp<QP_R4>(mz), t.m[3], ax, ay, az, dx, dy, dz);
+    pair(qx, qy, qz, dpp<QP_R5>(mx), dpp<QP_R5>(my), dpp<QP_R5>(mz), t.m[4], ax, ay, az, dx, dy, dz);
+  }
+};
+template <> struct Exch<8, 2> : ExchMixed {};
 
 // Kick block of the loop on the compensated state.  With GR:
 // J(ta) [I + GR](ti) J(tc); without GR the jumps commute with I and merge:
@@ -244,7 +343,7 @@ __device__ __forceinline__ void kick_block(Lane& L, const Exch<G, EXCH>& ex, dou
                                            double ti, double tc, double& vkx, double& vky, double& vkz) {
   double ax, ay, az, sx, sy, sz;
   if (GR) {
-    group_momentum<G>(L.m, L.vx, L.vy, L.vz, sx, sy, sz);
+    ex.momentum(L.m, L.vx, L.vy, L.vz, sx, sy, sz);
     double k1 = ta * inv_m0;
     double dqx = k1 * sx, dqy = k1 * sy, dqz = k1 * sz;
     L.cqx += dqx; L.cqy += dqy; L.cqz += dqz;
@@ -259,7 +358,7 @@ __device__ __forceinline__ void kick_block(Lane& L, const Exch<G, EXCH>& ex, dou
   double dvx = ti * ax, dvy = ti * ay, dvz = ti * az;
   L.cvx += dvx; L.cvy += dvy; L.cvz += dvz;
   vkx = L.vx + dvx; vky = L.vy + dvy; vkz = L.vz + dvz;
-  group_momentum<G>(L.m, vkx, vky, vkz, sx, sy, sz);
+  ex.momentum(L.m, vkx, vky, vkz, sx, sy, sz);
   double k2 = (GR ? tc : ta + tc) * inv_m0;
   L.cqx += k2 * sx; L.cqy += k2 * sy; L.cqz += k2 * sz;
   renorm_all(L);
@@ -629,6 +728,62 @@ __global__ __launch_bounds__(256) void k_step_pair(StepParams p) {
   if (wave < p.w1) step_group_pair<1, GR, SCHEME, KC>(p, sa, lane);
   else if (wave < p.w2) step_group_pair<2, GR, SCHEME, KC>(p, sa, lane);
   else step_group_pair<4, GR, SCHEME, KC>(p, sa, lane);
+}
+
+// ---------------------------------------------------------------------------
+// The mixed packing (WH_PACK_MIXED): waves [wm, w8) hold two systems per
+// 8-lane group (ExchMixed); the other waves are those of the one-planet
+// layout.  DHC, drift-kick-drift or kick-drift-kick, the paper's Kepler
+// counts.  Each system's flags are written from its planet 0.
+template <bool GR, int SCHEME>
+__device__ __forceinline__ void step_lane_mixed(const StepParams& p, Lane& L, int lane) {
+  Exch<8, 2> ex;
+  ex.init_mixed(L.m, L.pl, lane & 7);
+  const double dt = L.dt;
+  const double h = 0.5 * dt;
+  const double inv_m0 = 1.0 / L.m0;
+  const double kg = GR ? p.kgr * L.m0 * L.m0 : 0.0;
+  KepDiag dg{0.0, 1.0e300};
+  double vkx, vky, vkz;
+  if (SCHEME == WH_DKD) {
+    double tk = L.first ? h : dt;
+    for (int s = 0; s < p.n_steps; ++s) {
+      drift(L, L.m0, tk, dg);
+      tk = dt;
+      kick_block<8, GR, 2>(L, ex, inv_m0, kg, h, dt, h, vkx, vky, vkz);
+    }
+  } else {
+    double ta = L.first ? 0.0 : h;
+    double ti = L.first ? h : dt;
+    for (int s = 0; s < p.n_steps; ++s) {
+      kick_block<8, GR, 2>(L, ex, inv_m0, kg, ta, ti, h, vkx, vky, vkz);
+      ta = h;
+      ti = dt;
+      drift(L, L.m0, dt, dg);
+    }
+  }
+  const int f = ex.any(lane_flags(L, dg, p.zlim));
+  if (L.pl == 0 && L.sys >= 0) {
+    p.flags[L.sys] |= (uint32_t)f;
+    p.synced[L.sys] = 0;
+  }
+}
+
+template <bool GR, int SCHEME>
+__global__ __launch_bounds__(256) void k_step_mixed(StepParams p) {
+  const int lane = threadIdx.x & 63;
+  int wave;
+  if (!launch_wave(p, (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), wave, p.n_steps)) return;
+  const int slot = wave * 64 + lane;
+  if (wave < p.w1) step_group<1, GR, SCHEME, 1, false>(p, slot, lane);
+  else if (wave < p.w2) step_group<2, GR, SCHEME, 1, false>(p, slot, lane);
+  else if (wave < p.w4) step_group<4, GR, SCHEME, 1, false>(p, slot, lane);
+  else if (wave < p.wm) step_group<8, GR, SCHEME, 1, false>(p, slot, lane);
+  else {
+    Lane L = load_lane(p, slot);
+    step_lane_mixed<GR, SCHEME>(p, L, lane);
+    store_lane(p, slot, L);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1125,6 +1280,89 @@ __device__ __forceinline__ double planet_energy(const Lane& L, double kgr) {
   double e = 0.5 * L.m * (L.vx * L.vx + L.vy * L.vy + L.vz * L.vz) - L.m0 * L.m / sqrt(r2);
   if (kgr > 0) e -= 0.5 * kgr * L.m0 * L.m0 * L.m / r2;
   return e;
+}
+
+// Synchronized copy of a shared 8-lane group (the mixed packing): as
+// sync_group, with the pending half kick, the energy's pair terms and every
+// sum kept within each system; results written from each system's planet 0.
+template <bool GR, int SCHEME> __device__ void sync_group_mixed(const SyncParams& q, int slot, int lane) {
+  const StepParams& p = q.sp;
+  Lane L = load_lane(p, slot);
+  Exch<8, 2> ex;
+  ex.init_mixed(L.m, L.pl, lane & 7);
+  if (!L.first) {
+    const double h = 0.5 * L.dt;
+    if (SCHEME == WH_DKD) {
+      KepDiag dg{0.0, 1.0e300};
+      drift(L, L.m0, h, dg);
+    } else {
+      double vkx, vky, vkz;
+      kick_block<8, GR, 2>(L, ex, 1.0 / L.m0, GR ? p.kgr * L.m0 * L.m0 : 0.0, h, h, 0.0, vkx, vky, vkz);
+    }
+  }
+  L.qx += L.cqx; L.qy += L.cqy; L.qz += L.cqz;
+  L.vx += L.cvx; L.vy += L.cvy; L.vz += L.cvz;
+  const bool writer = L.sys >= 0 && L.pl >= 0;
+  if (q.Q_out && writer) {
+    size_t o = ((size_t)L.sys * 8 + L.pl) * 3;
+    q.Q_out[o] = L.qx; q.Q_out[o + 1] = L.qy; q.Q_out[o + 2] = L.qz;
+    q.V_out[o] = L.vx; q.V_out[o + 1] = L.vy; q.V_out[o + 2] = L.vz;
+  }
+  if (q.E_out) {
+    const double r2 = L.qx * L.qx + L.qy * L.qy + L.qz * L.qz;
+    double e = 0.5 * L.m * (L.vx * L.vx + L.vy * L.vy + L.vz * L.vz) - L.m0 * L.m / sqrt(r2);
+    if (GR) e -= 0.5 * p.kgr * L.m0 * L.m0 * L.m / r2;
+    const int own = ex.a ? 1 : 0;
+    double pair = 0.0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+      const int src = (lane ^ k) << 2;
+      const double px = bperm(src, L.qx), py = bperm(src, L.qy), pz = bperm(src, L.qz), pm = bperm(src, L.m);
+      const bool same = __builtin_amdgcn_ds_bpermute(src, own) == own;
+      const double dx = L.qx - px, dy = L.qy - py, dz = L.qz - pz;
+      const double d2 = same ? dx * dx + dy * dy + dz * dz : 1.0;
+      pair += (same ? pm : 0.0) / sqrt(d2);
+    }
+    e -= 0.5 * L.m * pair;
+    e = ex.sum(e);
+    double sx, sy, sz;
+    ex.momentum(L.m, L.vx, L.vy, L.vz, sx, sy, sz);
+    const double E = e + (sx * sx + sy * sy + sz * sz) / (2.0 * L.m0);
+    if (L.pl == 0 && L.sys >= 0) q.E_out[L.sys] = E;
+  }
+  if (q.L_out) {
+    double lx, ly, lz;
+    planet_angmom(L, lx, ly, lz);
+    lx = ex.sum(lx); ly = ex.sum(ly); lz = ex.sum(lz);
+    if (L.pl == 0 && L.sys >= 0) {
+      q.L_out[(size_t)L.sys * 3] = lx; q.L_out[(size_t)L.sys * 3 + 1] = ly; q.L_out[(size_t)L.sys * 3 + 2] = lz;
+    }
+  }
+  if (q.a_out) {
+    double sx, sy, sz;
+    ex.momentum(L.m, L.vx, L.vy, L.vz, sx, sy, sz);
+    double a, e;
+    osculating(L, sx, sy, sz, a, e);
+    if (writer) {
+      size_t o = (size_t)L.sys * 8 + L.pl;
+      q.a_out[o] = a;
+      q.e_out[o] = e;
+    }
+  }
+}
+
+template <bool GR, int SCHEME>
+__global__ __launch_bounds__(256) void k_sync_mixed(SyncParams q) {
+  const StepParams& p = q.sp;
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wave >= p.w8) return;
+  const int slot = wave * 64 + lane;
+  if (wave < p.w1) sync_group<1, GR, SCHEME, false>(q, slot, lane);
+  else if (wave < p.w2) sync_group<2, GR, SCHEME, false>(q, slot, lane);
+  else if (wave < p.w4) sync_group<4, GR, SCHEME, false>(q, slot, lane);
+  else if (wave < p.wm) sync_group<8, GR, SCHEME, false>(q, slot, lane);
+  else sync_group_mixed<GR, SCHEME>(q, slot, lane);
 }
 
 template <int G, bool GR> __device__ double group_energy_pair(const StepParams& p, const Lane& A, const Lane& B,
@@ -2843,6 +3081,7 @@ StepParams step_params(const wh_ctx* c, int n_steps) {
   p.synced = c->synced;
   p.wave0 = 0;
   p.w1 = c->P.w1; p.w2 = c->P.w2; p.w4 = c->P.w4; p.w8 = c->P.w8;
+  p.wm = c->P.wm;
   p.n_steps = n_steps;
   p.kgr = c->cfg.gr_c > 0 ? 6.0 / (c->cfg.gr_c * c->cfg.gr_c) : 0.0;
   p.zlim = c->cfg.z_max > 0 ? c->cfg.z_max : 1.0;
@@ -2912,6 +3151,11 @@ template <int EXCH> const void* step_kernel_exch(const wh_ctx* c) {
 }
 
 const void* step_kernel(const wh_ctx* c) {
+  if (c->P.mixed) {
+    const bool gr = c->cfg.gr_c > 0;
+    if (c->cfg.scheme == WH_DKD) return gr ? (const void*)k_step_mixed<true, WH_DKD> : (const void*)k_step_mixed<false, WH_DKD>;
+    return gr ? (const void*)k_step_mixed<true, WH_KDK> : (const void*)k_step_mixed<false, WH_KDK>;
+  }
   return c->exchange == WH_EXCH_LDS ? step_kernel_exch<0>(c) : step_kernel_exch<1>(c);
 }
 
@@ -3012,7 +3256,15 @@ wh_status launch_sync(wh_ctx* c, double* Q, double* V, double* E, hipStream_t st
   q.L_out = L;
   dim3 block(64), grid(c->P.nwaves);
   const bool gr = c->cfg.gr_c > 0;
-  if (c->P.pair) {
+  if (c->P.mixed) {
+    if (c->cfg.scheme == WH_DKD) {
+      if (gr) hipLaunchKernelGGL((k_sync_mixed<true, WH_DKD>), grid, block, 0, st, q);
+      else hipLaunchKernelGGL((k_sync_mixed<false, WH_DKD>), grid, block, 0, st, q);
+    } else {
+      if (gr) hipLaunchKernelGGL((k_sync_mixed<true, WH_KDK>), grid, block, 0, st, q);
+      else hipLaunchKernelGGL((k_sync_mixed<false, WH_KDK>), grid, block, 0, st, q);
+    }
+  } else if (c->P.pair) {
     if (c->cfg.scheme >= WH_SABA2) {
       hipLaunchKernelGGL((k_sync_pair<false, SCHEME_SABA>), grid, block, 0, st, q);
     } else if (c->cfg.scheme == WH_DKD) {
@@ -3441,6 +3693,7 @@ wh_status wh_forward_ckpt(wh_ctx* c, int64_t n_steps, int64_t ckpt_every, void* 
     return fail(WH_ESTATE, "reverse mode is implemented for WH_DKD, WH_KDK and WH_SABA2..4");
   if (c->cfg.kepler_counts != 0)
     return fail(WH_ESTATE, "reverse mode runs the paper's Kepler counts (kepler_counts = 0)");
+  if (c->P.mixed) return fail(WH_ESTATE, "reverse mode does not run the mixed packing");
   if (c->steps_done != 0) return fail(WH_ESTATE, "wh_forward_ckpt must start from the initial state (no steps taken)");
   if (ckpt_every * tape_units(c) > (1 << 30)) return fail(WH_EINVAL, "ckpt_every too large for this scheme");
   TapeLayout T = tape_layout(c->P.ns, n_steps, ckpt_every, tape_units(c));

@@ -47,8 +47,9 @@ struct Packing {
   bool pair = false;   // WH_PACK_PAIR: two slots (planets) per lane, 128 slots per wave
   bool split = false;  // WH_PACK_SPLIT: two lanes (copies) per planet, 16 lanes per system
   bool serial = false; // WH_PACK_SERIAL: the G8 storage, one thread per system in the step
+  bool mixed = false;  // WH_PACK_MIXED: waves [wm, w8) hold two systems per 8-lane group
   int ns = 0, nwaves = 0;
-  int w1 = 0, w2 = 0, w4 = 0, w8 = 0;
+  int w1 = 0, w2 = 0, w4 = 0, wm = 0, w8 = 0;
   int plain_begin[9] = {0}, plain_end[9] = {0};   // G8 packing: waves of each planet count
   std::vector<int32_t> slot_sys, slot_pl;
 };
@@ -56,6 +57,37 @@ struct Packing {
 inline int group_size(int n, int packing) {
   if (packing == WH_PACK_G8 || packing == WH_PACK_SERIAL) return 8;
   return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : 8;
+}
+
+// Systems that share an 8-lane group in the mixed packing: each 5-planet
+// system takes the next unpaired 3-planet one, else the next 2-planet one;
+// each 6-planet system the next 2-planet one (index order throughout).  A
+// shared group's step costs about 1.12 of a one-system 8-lane group's, less
+// than the 2- or 4-lane group the smaller system would otherwise take; a
+// 1-planet partner (64 per wave) would not pay.
+struct MixedPairs {
+  std::vector<int> a, b;          // the groups: larger system a, smaller b
+  std::vector<char> paired;       // per system
+};
+inline MixedPairs mixed_pairs(int S, const int32_t* np) {
+  MixedPairs M;
+  M.paired.assign(S, 0);
+  std::vector<int> by[9];
+  for (int s = 0; s < S; ++s) by[np[s]].push_back(s);
+  size_t i3 = 0, i2 = 0;
+  for (int s : by[5]) {
+    int t = -1;
+    if (i3 < by[3].size()) t = by[3][i3++];
+    else if (i2 < by[2].size()) t = by[2][i2++];
+    if (t < 0) break;
+    M.a.push_back(s); M.b.push_back(t);
+  }
+  for (int s : by[6]) {
+    if (i2 >= by[2].size()) break;
+    M.a.push_back(s); M.b.push_back(by[2][i2++]);
+  }
+  for (size_t k = 0; k < M.a.size(); ++k) M.paired[M.a[k]] = M.paired[M.b[k]] = 1;
+  return M;
 }
 
 // Device indexing is 32-bit: row r of a [rows][ns] array sits at r * ns, with
@@ -77,6 +109,14 @@ inline int64_t slots_needed(int S, const int32_t* np, int packing) {
     int64_t w = 0;
     for (int n = 1; n <= 8; ++n) w += waves(cnt[n], 8);
     return w * 64;
+  }
+  if (packing == WH_PACK_MIXED) {
+    // the pairing rule of mixed_pairs, on the counts
+    const int64_t p53 = std::min(cnt[5], cnt[3]);
+    const int64_t p52 = std::min(cnt[5] - p53, cnt[2]);
+    const int64_t p62 = std::min(cnt[6], cnt[2] - p52);
+    return (waves(cnt[1], 64) + waves(cnt[2] - p52 - p62, 32) + waves(cnt[3] - p53 + cnt[4], 16) +
+            waves(cnt[5] - p53 - p52 + cnt[6] - p62 + cnt[7] + cnt[8], 8) + waves(p53 + p52 + p62, 8)) * 64;
   }
   return (waves(cnt[1], 64) + waves(cnt[2], 32) + waves(cnt[3] + cnt[4], 16) +
           waves(cnt[5] + cnt[6] + cnt[7] + cnt[8], 8)) * 64;
@@ -174,17 +214,43 @@ inline bool make_packing(int S, const int32_t* np, int packing, Packing& P, std:
     P.w8 = P.nwaves;
     P.serial = packing == WH_PACK_SERIAL;
   } else {
+    MixedPairs M;
+    if (packing == WH_PACK_MIXED) M = mixed_pairs(S, np);
     int ends[4];
     const int Gs[4] = {1, 2, 4, 8};
     for (int gi = 0; gi < 4; ++gi) {
       std::vector<int> cls;
       for (int s = 0; s < S; ++s)
-        if (group_size(np[s], packing) == Gs[gi]) cls.push_back(s);
+        if (group_size(np[s], packing) == Gs[gi] && (M.paired.empty() || !M.paired[s])) cls.push_back(s);
       add_wave_block(cls, Gs[gi]);
       ends[gi] = P.nwaves;
     }
-    P.w1 = ends[0]; P.w2 = ends[1]; P.w4 = ends[2]; P.w8 = ends[3];
+    P.w1 = ends[0]; P.w2 = ends[1]; P.w4 = ends[2]; P.wm = ends[3];
+    if (packing == WH_PACK_MIXED) {
+      // shared 8-lane groups: system a in lanes 0..Na-1, b in Na..Na+Nb-1,
+      // padding lanes after them belong to b (its star and step)
+      const int ng = (int)M.a.size(), nw = (ng + 7) / 8;
+      for (int g = 0; g < nw * 8; ++g) {
+        const int a = g < ng ? M.a[g] : -1, b = g < ng ? M.b[g] : -1;
+        for (int l = 0; l < 8; ++l) {
+          if (a < 0) {
+            P.slot_sys.push_back(-1);
+            P.slot_pl.push_back(-1);
+          } else if (l < np[a]) {
+            P.slot_sys.push_back(a);
+            P.slot_pl.push_back(l);
+          } else {
+            P.slot_sys.push_back(b);
+            P.slot_pl.push_back(l - np[a] < np[b] ? l - np[a] : -1);
+          }
+        }
+      }
+      P.nwaves += nw;
+      P.mixed = true;
+    }
+    P.w8 = P.nwaves;
   }
+  if (!P.mixed) P.wm = P.w8;
   P.ns = P.nwaves * (P.pair ? 128 : 64);
   // every wave holds exactly 64 (pair layout: 128) slots; the device tables are copied at ns
   if ((int)P.slot_sys.size() != P.ns || (int)P.slot_pl.size() != P.ns || P.ns != slots_needed(S, np, packing)) {
@@ -240,7 +306,14 @@ inline bool config_ok(const wh_config* c, std::string& why) {
   if (c->scheme >= WH_SABA2 && c->gr_c > 0 && c->coords != WH_COORDS_JACOBI) {
     why = "SABA_n with GR needs Jacobi coordinates: in DHC the GR and jump flows do not commute"; return false;
   }
-  if (c->packing < WH_PACK_AUTO || c->packing > WH_PACK_SERIAL) { why = "unknown packing"; return false; }
+  if (c->packing < WH_PACK_AUTO || c->packing > WH_PACK_MIXED) { why = "unknown packing"; return false; }
+  if (c->packing == WH_PACK_MIXED &&
+      (c->coords != WH_COORDS_DHC || (c->scheme != WH_DKD && c->scheme != WH_KDK) || c->exchange == WH_EXCH_LDS ||
+       c->kepler_counts != 0)) {
+    why = "the mixed packing runs DHC drift-kick-drift or kick-drift-kick with the DPP exchange and the paper's "
+          "Kepler counts";
+    return false;
+  }
   if (c->block_waves != 0 && c->block_waves != 1 && c->block_waves != 2 && c->block_waves != 4) {
     why = "block_waves must be 0, 1, 2 or 4"; return false;
   }
@@ -411,6 +484,8 @@ inline double wave_step_cost(const Packing& P, bool with_gr, int w) {
     return t[gr][w < P.w1 ? 0 : w < P.w2 ? 1 : 2];
   }
   static const double t[2][4] = {{316, 331, 378, 478}, {330, 367, 416, 526}};
+  static const double mixed[2] = {543, 598};
+  if (P.mixed && w >= P.wm) return mixed[gr];
   return t[gr][w < P.w1 ? 0 : w < P.w2 ? 1 : w < P.w4 ? 2 : 3];
 }
 

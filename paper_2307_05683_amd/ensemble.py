@@ -16,7 +16,7 @@ from ._lib import check
 SCHEMES = {"dkd": _lib.WH_DKD, "kdk": _lib.WH_KDK, "saba2": _lib.WH_SABA2, "saba3": _lib.WH_SABA3,
            "saba4": _lib.WH_SABA4}
 PACKINGS = {"auto": _lib.WH_PACK_AUTO, "pow2": _lib.WH_PACK_POW2, "g8": _lib.WH_PACK_G8, "pair": _lib.WH_PACK_PAIR,
-            "split": _lib.WH_PACK_SPLIT, "serial": _lib.WH_PACK_SERIAL}
+            "split": _lib.WH_PACK_SPLIT, "serial": _lib.WH_PACK_SERIAL, "mixed": _lib.WH_PACK_MIXED}
 EXCHANGES = {"auto": _lib.WH_EXCH_AUTO, "lds": _lib.WH_EXCH_LDS, "dpp": _lib.WH_EXCH_DPP}
 COORDS = {"dhc": _lib.WH_COORDS_DHC, "jacobi": _lib.WH_COORDS_JACOBI}
 

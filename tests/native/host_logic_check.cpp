@@ -30,7 +30,9 @@ static void check_packing(const std::vector<int32_t>& np, int packing) {
   CHECK(P.ns == (int)P.slot_sys.size() && P.ns == (int)P.slot_pl.size());
   CHECK(P.ns == slots_needed(S, np.data(), eff));
   CHECK(P.ns == P.nwaves * (P.pair ? 128 : 64));
-  CHECK(P.w1 <= P.w2 && P.w2 <= P.w4 && P.w4 <= P.w8 && P.w8 <= P.nwaves);
+  CHECK(P.w1 <= P.w2 && P.w2 <= P.w4 && P.w4 <= P.wm && P.wm <= P.w8 && P.w8 <= P.nwaves);
+  CHECK(P.mixed == (eff == WH_PACK_MIXED));
+  CHECK(P.mixed || P.wm == P.w8);
   // every planet of every system sits in exactly one slot (two in the split
   // layout, whose two lanes per planet are copies); padding slots are -1
   std::vector<int> seen((size_t)S * 8, 0);
@@ -51,6 +53,21 @@ static void check_packing(const std::vector<int32_t>& np, int packing) {
     for (int i = 0; i < P.ns; ++i) {
       const int s = P.slot_sys[i];
       if (s < 0) continue;
+      if (P.mixed && i >= P.wm * 64) {
+        // a shared 8-lane group: system a from the group's first lane, then
+        // system b, then b's padding; a has 5 or 6 planets, b 2 or 3
+        const int base = i & ~7;
+        const int a = P.slot_sys[base];
+        CHECK(a >= 0 && (np[a] == 5 || np[a] == 6));
+        if (a < 0) continue;
+        const int b = P.slot_sys[base + np[a]];
+        CHECK(b >= 0 && b != a && (np[b] == 2 || np[b] == 3) && np[a] + np[b] <= 8);
+        if (b < 0) continue;
+        const int l = i - base;
+        if (l < np[a]) CHECK(s == a && P.slot_pl[i] == l);
+        else CHECK(s == b && P.slot_pl[i] == (l - np[a] < np[b] ? l - np[a] : -1));
+        continue;
+      }
       const int G = group_size(np[s], eff);
       const int base = i & ~(G - 1);
       CHECK(P.slot_sys[base] == s);
@@ -139,6 +156,12 @@ int main() {
   bad = c; bad.n_systems = 0; CHECK(!config_ok(&bad, why));
   bad = c; bad.scheme = 9; CHECK(!config_ok(&bad, why));
   bad = c; bad.packing = 7; CHECK(!config_ok(&bad, why));
+  bad = c; bad.packing = WH_PACK_MIXED; CHECK(config_ok(&bad, why));
+  bad.scheme = WH_SABA2; CHECK(!config_ok(&bad, why));
+  bad = c; bad.packing = WH_PACK_MIXED; bad.coords = WH_COORDS_JACOBI; CHECK(!config_ok(&bad, why));
+  bad = c; bad.packing = WH_PACK_MIXED; bad.exchange = WH_EXCH_LDS; CHECK(!config_ok(&bad, why));
+  bad = c; bad.packing = WH_PACK_MIXED; bad.kepler_counts = 1; CHECK(!config_ok(&bad, why));
+  bad = c; bad.packing = WH_PACK_MIXED + 1; CHECK(!config_ok(&bad, why));
   bad = c; bad.block_waves = 3; CHECK(!config_ok(&bad, why));
   bad = c; bad.balance = 2; CHECK(!config_ok(&bad, why));
   bad = c; bad.scheme = WH_SABA2; bad.gr_c = 10.0; CHECK(!config_ok(&bad, why));
@@ -146,7 +169,8 @@ int main() {
   for (int S : {1, 2, 7, 64, 65, 1000, 4099}) {
     std::vector<int32_t> np(S);
     for (auto& n : np) n = 1 + (int)(rng() % 8);
-    for (int pk : {WH_PACK_AUTO, WH_PACK_POW2, WH_PACK_G8, WH_PACK_PAIR, WH_PACK_SPLIT, WH_PACK_SERIAL})
+    for (int pk : {WH_PACK_AUTO, WH_PACK_POW2, WH_PACK_G8, WH_PACK_PAIR, WH_PACK_SPLIT, WH_PACK_SERIAL,
+                   WH_PACK_MIXED})
       check_packing(np, pk);
   }
   {

@@ -102,7 +102,7 @@ def test_pair_split_and_serial_packings_need_dhc(packing):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(G=2.0), dict(scheme=5), dict(packing=5), dict(packing=7), dict(block_waves=3), dict(chunk_steps=-1), dict(n_systems=0),
+    dict(G=2.0), dict(scheme=5), dict(packing=6), dict(packing=7), dict(block_waves=3), dict(chunk_steps=-1), dict(n_systems=0),
     dict(exchange=9),
 ])
 def test_invalid_configs_rejected(bad):
@@ -110,6 +110,23 @@ def test_invalid_configs_rejected(bad):
     for k, v in bad.items():
         setattr(cfg, k, v)
     assert _ws(cfg, [2, 2, 2]) == 0
+
+
+def test_mixed_packing_configurations():
+    # shared 8-lane groups: DHC drift-kick-drift or kick-drift-kick, the DPP
+    # exchange, the paper's Kepler counts; a 5- and a 3-planet system share
+    # a group (one wave), the 8-planet system has its own
+    cfg = _lib.default_config(3)
+    cfg.packing = _lib.WH_PACK_MIXED
+    assert _ws(cfg, [5, 3, 8]) > 0
+    cfg.scheme = _lib.WH_KDK
+    assert _ws(cfg, [5, 3, 8]) > 0
+    for k, v in (("scheme", _lib.WH_SABA2), ("coords", _lib.WH_COORDS_JACOBI), ("exchange", _lib.WH_EXCH_LDS),
+                 ("kepler_counts", 1)):
+        c = _lib.default_config(3)
+        c.packing = _lib.WH_PACK_MIXED
+        setattr(c, k, v)
+        assert _ws(c, [5, 3, 8]) == 0, k
 
 
 @pytest.mark.parametrize("counts", [[0, 2], [9], [3, -1]])

@@ -49,7 +49,7 @@ def test_bench_line_contract():
 def test_bench_uneven_runs_in_windows():
     out = run_bench("--workload", "uneven2to8")
     cfg = out["config"]
-    assert cfg["packing"] == "pow2" and cfg["balance"] == 1
+    assert cfg["packing"] == "mixed" and cfg["balance"] == 1
     assert cfg["launches_per_chunk"] > 1 and cfg["wavefronts_per_window"] >= 256
     assert cfg["flagged_systems"] == 0
 

@@ -115,6 +115,10 @@ def test_uneven_batch_every_system_two_planets_per_lane():
     check_batch("uneven2to8", 16384, "pair", 4)
 
 
+def test_uneven_batch_every_system_one_planet_per_lane():
+    check_batch("uneven2to8", 16384, "pow2", 4, 1)
+
+
 def test_gr_batch_2048_systems_bench_layout():
     check_batch("large8gr", 2048, bench.DEFAULT_PACKING["large8gr"], bench.DEFAULT_BLOCK_WAVES["large8gr"],
                 bench.DEFAULT_BALANCE["large8gr"])
