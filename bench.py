@@ -65,7 +65,7 @@ DEFAULT_PACKING = {"large8gr": "pair", "uneven2to8": "mixed", "uniform8": "split
 # workgroup on each SIMD of a CU.
 DEFAULT_BLOCK_WAVES = {"large8gr": 1, "uneven2to8": 4, "uniform8": 4, "single8": 1, "adjoint8": 4}
 # Balanced launch windows (wh_config.balance) for the uneven batch: its
-# one-planet-per-lane wavefronts of several costs (1322 with two systems
+# one-planet-per-lane wavefronts of several costs (1315 with two systems
 # sharing the 8-lane groups of 5+3 and 6+2 planets, 1535 without) run in
 # windows of 1024 equal-work wavefronts (+15% over two planets per lane,
 # whose 769 heavy wavefronts leave a quarter of the SIMDs idle; the shared
