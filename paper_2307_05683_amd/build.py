@@ -51,7 +51,10 @@ def build(verbose: bool = False, extra=()) -> str:
         jobs = []
         for src, more in ((SRC, []), (PAIR_SRC, PAIR_FLAGS)):
             obj = os.path.join(tmp, os.path.basename(src) + ".o")
-            cmd = ["hipcc", "-c"] + cflags + more + [src, "-o", obj]
+            # a fixed compilation-unit id: the default one hashes the
+            # temporary object path, which would make every build differ
+            cuid = "-cuid=" + os.path.splitext(os.path.basename(src))[0]
+            cmd = ["hipcc", "-c", cuid] + cflags + more + [src, "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             jobs.append((obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
