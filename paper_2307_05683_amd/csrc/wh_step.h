@@ -162,12 +162,12 @@ __device__ __forceinline__ double drift(Lane& L, double mu, double tau, KepDiag&
   lin2_dd(k.gdm1, L.vx, k.fd, L.qx, hvx, lvx);
   lin2_dd(k.gdm1, L.vy, k.fd, L.qy, hvy, lvy);
   lin2_dd(k.gdm1, L.vz, k.fd, L.qz, hvz, lvz);
-  lqx += fma(k.fm1, L.cqx, k.g * L.cvx);
-  lqy += fma(k.fm1, L.cqy, k.g * L.cvy);
-  lqz += fma(k.fm1, L.cqz, k.g * L.cvz);
-  lvx += fma(k.fd, L.cqx, k.gdm1 * L.cvx);
-  lvy += fma(k.fd, L.cqy, k.gdm1 * L.cvy);
-  lvz += fma(k.fd, L.cqz, k.gdm1 * L.cvz);
+  lqx = fma(k.fm1, L.cqx, fma(k.g, L.cvx, lqx));
+  lqy = fma(k.fm1, L.cqy, fma(k.g, L.cvy, lqy));
+  lqz = fma(k.fm1, L.cqz, fma(k.g, L.cvz, lqz));
+  lvx = fma(k.fd, L.cqx, fma(k.gdm1, L.cvx, lvx));
+  lvy = fma(k.fd, L.cqy, fma(k.gdm1, L.cvy, lvy));
+  lvz = fma(k.fd, L.cqz, fma(k.gdm1, L.cvz, lvz));
   add_hi(L.qx, L.cqx, hqx, lqx);
   add_hi(L.qy, L.cqy, hqy, lqy);
   add_hi(L.qz, L.cqz, hqz, lqz);
