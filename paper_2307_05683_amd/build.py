@@ -20,10 +20,11 @@ FLAGS = [
     "-I", os.path.join(PKG, "csrc"),
 ]
 # The pair layout's step kernel (wh_pair_step.hip) is scheduled for
-# instruction latency rather than occupancy: at its two to three resident
-# wavefronts per SIMD that measured 1.4% faster on 65536 eight-planet systems
-# with GR, while the one-planet kernels in wh.hip, one wavefront per SIMD in
-# their launches, measured slower with it.
+# instruction latency rather than occupancy: at 238 VGPRs, two resident
+# wavefronts per SIMD (three with the default schedule), it measured 1.6-2.4%
+# faster on 65536 eight-planet systems with GR, while the one-planet and split
+# kernels in wh.hip, one wavefront per SIMD in their launches, measured
+# slower with it.
 PAIR_FLAGS = ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
 
 

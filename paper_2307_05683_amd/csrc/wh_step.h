@@ -3,9 +3,8 @@
 // Kepler drift of that state, and the pair layout's kick and step (two
 // planets per lane).  wh.hip holds every other kernel and the C ABI;
 // wh_pair_step.hip holds the pair layout's step kernel, compiled with the
-// instruction scheduler set for latency (it runs at two to three resident
-// wavefronts per SIMD, where the default occupancy-first schedule measured
-// slower).
+// instruction scheduler set for latency (two resident wavefronts per SIMD;
+// the default occupancy-first schedule, three resident, measured slower).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
