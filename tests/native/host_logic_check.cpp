@@ -143,6 +143,35 @@ static void check_plan(std::mt19937_64& rng) {
     CHECK(hw.size() == cost.size() * (2 * PLAN_Q - 1));
     CHECK(hw.size() <= cost.size() * 2 * PLAN_Q);
   }
+  // quality of the plan on an uneven batch in the mixed packing (16384
+  // systems of 2..8 planets, 1024 slots, a 4096-step chunk): with one wave
+  // per slot a window lasts as long as its longest share, and the windows
+  // together stay within 3% of the chunk's work divided evenly over the
+  // slots (98.1% measured without GR, 98.3% with)
+  for (int gr = 0; gr < 2; ++gr) {
+    std::mt19937_64 r2(2024 + gr);
+    std::vector<int32_t> np(16384);
+    for (auto& n : np) n = 2 + (int)(r2() % 7);
+    Packing P;
+    std::string why;
+    CHECK(make_packing((int)np.size(), np.data(), WH_PACK_MIXED, P, &why));
+    std::vector<double> cost(P.nwaves);
+    double work = 0.0;
+    const int R = 4096, slots = 1024;
+    for (int w = 0; w < P.nwaves; ++w) {
+      cost[w] = wave_step_cost(P, gr == 1, w);
+      work += cost[w] * R;
+    }
+    std::vector<int> hw, hs, off;
+    plan_windows(cost, R, slots, PLAN_Q, hw, hs, off);
+    double span = 0.0;
+    for (size_t k = 0; k + 1 < off.size(); ++k) {
+      double longest = 0.0;
+      for (int e = off[k]; e < off[k + 1]; ++e) longest = std::max(longest, hs[e] * cost[hw[e]]);
+      span += longest;
+    }
+    CHECK(span > 0.0 && work / slots / span >= 0.97);
+  }
 }
 
 int main() {
