@@ -20,9 +20,24 @@
 
 namespace wh {
 
-// 1/|d|^3 for the separation d
+// 1/|d|^3 for the separation d: rsqrt3_full's refinement with its two
+// constants in one FMA, (1 - e)^(-3/2) = 1 + e (3/2 + (15/8) e) + O(e^3).
+// An instruction takes one scalar operand, so 15/8 is held in a register
+// across the step loop: the empty asm statement hides its value from the
+// compiler, which would otherwise re-create it at every use.  One
+// instruction fewer per evaluation than rsqrt3_full, within the pair
+// layout's register budget (two resident wavefronts per SIMD); the
+// one-planet kernels keep rsqrt3_full, where the extra live register would
+// cost occupancy.
 __device__ __forceinline__ double inv_r3(double dx, double dy, double dz) {
-  return rsqrt3_full(fma(dx, dx, fma(dy, dy, dz * dz)));
+  const double x = fma(dx, dx, fma(dy, dy, dz * dz));
+  const double y = __builtin_amdgcn_rsq(x);
+  const double y2 = y * y;
+  const double e = fma(-x, y2, 1.0);
+  const double y3 = y2 * y;
+  double c = 1.875;
+  __asm__("" : "+v"(c));
+  return fma(y3 * e, fma(c, e, 1.5), y3);
 }
 
 // Partner masses of the rounds (constant, Sec. 3.5).
