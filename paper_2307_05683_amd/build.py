@@ -20,7 +20,7 @@ FLAGS = [
     "-I", os.path.join(PKG, "csrc"),
 ]
 # The pair layout's step kernel (wh_pair_step.hip) is scheduled for
-# instruction latency rather than occupancy: at 238 VGPRs, two resident
+# instruction latency rather than occupancy: at 242 VGPRs, two resident
 # wavefronts per SIMD (three with the default schedule), it measured 1.6-2.4%
 # faster on 65536 eight-planet systems with GR, while the one-planet and split
 # kernels in wh.hip, one wavefront per SIMD in their launches, measured
